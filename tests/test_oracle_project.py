@@ -1,0 +1,123 @@
+"""Pins for the oracle's projection step (CPU only).
+
+* quaternion -> rotation against scipy's Rotation (a library routine);
+* the EWA Jacobian against central differences of the pinhole projection;
+* a single isotropic Gaussian on the optical axis: Sigma' = ((f s/d)^2 + 0.3) I;
+* the footprint box is conservative: sampled pixel centres outside it have
+  alpha < 1/255 (the property that makes tile binning result-neutral);
+* the float32 depth sequence against a scalar float32 evaluation.
+"""
+import math
+
+import numpy as np
+from scipy.spatial.transform import Rotation
+
+from oracle import project
+from paper_2503_18402_amd import scenes
+
+
+def test_quat_matches_scipy():
+    rng = np.random.default_rng(0)
+    q = rng.normal(size=(100, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    R = project.quat_to_rot(q)
+    ref = Rotation.from_quat(q[:, [1, 2, 3, 0]]).as_matrix()  # scipy takes (x,y,z,w)
+    assert np.abs(R - ref).max() < 1e-12
+
+
+def test_jacobian_fd():
+    sc = scenes.make_scene(20, seed=3)
+    cam = scenes.look_at((0.3, -0.2, -3.0), (0, 0, 0), 64, 48, 70.0, fy=65.0)
+    P = project.project(sc, cam)
+    xc = P["xc"]
+    f = lambda v: np.stack([cam.fx * v[:, 0] / v[:, 2], cam.fy * v[:, 1] / v[:, 2]], 1)
+    h = 1e-6
+    for j in range(3):
+        e = np.zeros(3)
+        e[j] = h
+        fd = (f(xc + e) - f(xc - e)) / (2 * h)
+        assert np.abs(fd - P["J"][:, :, j]).max() < 1e-6
+
+
+def _single(d=3.0, s=0.05, logit=0.0, W=32, H=32, f=40.0):
+    sc = dict(means=np.zeros((1, 3), np.float32),
+              log_scales=np.full((1, 3), math.log(s), np.float32),
+              quats=np.array([[1, 0, 0, 0]], np.float32),
+              opacity_logits=np.array([logit], np.float32),
+              sh=np.zeros((1, 16, 3), np.float32))
+    cam = scenes.look_at((0, 0, -d), (0, 0, 0), W, H, f)
+    return sc, cam
+
+
+def test_isotropic_covariance_closed_form():
+    d, s, f = 3.0, 0.05, 40.0
+    sc, cam = _single(d, s, f=f)
+    P = project.project(sc, cam)
+    s32 = math.exp(float(np.float32(math.log(s))))
+    var = (f * s32 / d) ** 2 + 0.3
+    assert abs(P["cov2d"][0, 0] - var) < 1e-12 and abs(P["cov2d"][0, 2] - var) < 1e-12
+    assert abs(P["cov2d"][0, 1]) < 1e-15
+    assert np.allclose(P["conic"][0], [1 / var, 0, 1 / var], rtol=1e-12, atol=1e-15)
+    assert np.allclose(P["mean2d"][0], [cam.cx, cam.cy])
+
+
+def test_box_is_conservative():
+    sc = scenes.make_scene(300, seed=4, mean_range=1.0, ls_mu=-3.0, ls_sigma=0.6)
+    cam = scenes.look_at((0.0, 0.0, -3.0), (0, 0, 0), 96, 80, 90.0)
+    P = project.project(sc, cam, tile=8)
+    rng = np.random.default_rng(5)
+    checked = 0
+    for i in np.nonzero(P["live"])[0]:
+        px = rng.integers(0, cam.width, size=400)
+        py = rng.integers(0, cam.height, size=400)
+        x0, y0, x1, y1 = P["px_box"][i]
+        inside = (P["tiles_touched"][i] > 0) & (px >= x0) & (px <= x1) & (py >= y0) & (py <= y1)
+        dx = px + 0.5 - P["mean2d"][i, 0]
+        dy = py + 0.5 - P["mean2d"][i, 1]
+        a, b, c = P["conic"][i]
+        power = -0.5 * (a * dx * dx + c * dy * dy) - b * dx * dy
+        alpha = P["opacity"][i] * np.exp(power)
+        assert np.all(alpha[~inside] < 1.0 / 255.0)
+        checked += (~inside).sum()
+        # the tile rectangle covers the pixel box
+        if P["tiles_touched"][i] > 0:
+            assert P["rect"][i, 0] == x0 // 8 and P["rect"][i, 2] == x1 // 8
+    assert checked > 1000
+
+
+def test_box_is_tight_axis_extent():
+    # the half-width is sqrt(2 ln(255 o) S00) up to the small widening margin
+    sc, cam = _single(d=3.0, s=0.2, logit=2.0, W=200, H=200, f=100.0)
+    P = project.project(sc, cam, tile=8)
+    o = P["opacity"][0]
+    ext = math.sqrt(2 * math.log(255 * o) * P["cov2d"][0, 0])
+    x0, _, x1, _ = P["px_box"][0]
+    mx = P["mean2d"][0, 0]
+    assert x0 == math.ceil(mx - ext * (1 + project.EXT_REL) - project.EXT_ABS - 0.5)
+    assert x1 == math.floor(mx + ext * (1 + project.EXT_REL) + project.EXT_ABS - 0.5)
+
+
+def test_depth_f32_sequence():
+    rng = np.random.default_rng(6)
+    m = rng.normal(size=(50, 3)).astype(np.float32)
+    cam = scenes.look_at((1.0, 2.0, -5.0), (0, 0, 0), 10, 10, 10.0)
+    z = project.depth_f32(m, cam.R, cam.t)
+    f = np.float32
+    for i in range(50):
+        acc = f(f(m[i, 0]) * f(cam.R[2, 0]))
+        acc = f(acc + f(f(m[i, 1]) * f(cam.R[2, 1])))
+        acc = f(acc + f(f(m[i, 2]) * f(cam.R[2, 2])))
+        acc = f(acc + f(cam.t[2]))
+        assert acc.view(np.uint32) == z[i].view(np.uint32)
+    zf = (m.astype(np.float64) @ cam.R[2].astype(np.float64)) + float(cam.t[2])
+    assert np.abs(z - zf).max() < 1e-5
+
+
+def test_culls():
+    sc = scenes.make_scene(4, seed=7)
+    sc["means"][:] = [[0, 0, -3.0], [0, 0, -2.85], [0, 0, 0], [0, 0, 0]]  # behind, too near, ok, ok
+    sc["opacity_logits"][:] = [0, 0, 0, -8.0]                              # last: o < 1/255
+    cam = scenes.look_at((0, 0, -3.0), (0, 0, 0), 32, 32, 30.0)
+    P = project.project(sc, cam)
+    assert list(P["live"]) == [False, False, True, False]
+    assert list(P["tiles_touched"] > 0) == [False, False, True, False]
