@@ -1,0 +1,195 @@
+/*
+ * gs.h -- C ABI of the MI355X (gfx950) differentiable tile-based Gaussian
+ * rasterizer: the per-iteration hot path of 3DGS optimisation that
+ * DashGaussian's resolution and primitive schedules make cheaper.
+ *
+ * The paper states the rendering model (Sec. 3, Eq. 1):
+ *     C(u) = sum_i T_i(u) w_i(u) c_i,   T_i(u) = prod_{j<i} (1 - w_j(u)),
+ *     w_i(u) = o_i G2D_i(u),
+ * evaluated once per rendered pixel, back-propagated to the Gaussian
+ * parameters, followed by a primitive (Adam) update (Sec. 1, Sec. 5.2).
+ * Everything else below (EWA splatting, SH colour, 1/255 cutoff, 0.99 clamp,
+ * T < 1e-4 exit, 16x16 tiles) is the rasterizer convention the paper relies
+ * on without restating it.
+ *
+ * Common rules
+ * ------------
+ * - Every array pointer is a DEVICE pointer unless marked "host".  Arrays are
+ *   FP32 (unless typed otherwise), contiguous, row-major.  The caller owns and
+ *   allocates every buffer; the library allocates no device memory.
+ * - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *   Every call only enqueues work on `stream` and returns; none synchronises,
+ *   so all of them may be captured into a HIP graph.
+ * - Argument errors are reported synchronously through the return value and
+ *   nothing is enqueued.  Device-side capacity overflow is reported through
+ *   *n_pairs_dev > capacity_pairs (see gs_bin_sort).  NaN inputs are not
+ *   checked; they propagate.
+ * - Gaussians that fail a cull (depth <= near, det <= 0, opacity < 1/255, or a
+ *   footprint outside the image) are dropped silently: no pairs, zero
+ *   gradients.
+ * - Several views per call (n_views > 1, at most GS_MAX_VIEWS, resolutions
+ *   may differ) run as ONE launch per kernel over all views: the batched form.
+ *   Per-view outputs are concatenated view after view.
+ */
+#ifndef GS_H
+#define GS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GS_MAX_VIEWS 32
+#define GS_SH_COEFFS 16 /* sh arrays always hold 16 coefficients x 3 channels */
+
+typedef enum {
+  GS_OK = 0,
+  GS_ERR_ARG = 1,         /* invalid argument; nothing was enqueued          */
+  GS_ERR_CAPACITY = 2,    /* a workspace or capacity is too small           */
+  GS_ERR_DEVICE = 3,      /* a HIP launch failed                            */
+  GS_ERR_UNSUPPORTED = 4  /* valid request the library does not implement   */
+} gs_status;
+
+/* Pinhole camera.  x_cam = R x_world + t with OpenCV axes (x right, y down,
+ * z forward); R is row-major.  Pixel (px, py) has its centre at
+ * (px + 0.5, py + 0.5); mean2D = (fx x/z + cx, fy y/z + cy).  width and
+ * height are in [1, 16384]; near_plane > 0 (0.2 in the conventions above). */
+typedef struct {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  float near_plane;
+} gs_camera;
+
+/* Raster configuration.  tile in {8, 16, 32} pixels; lds_batch in
+ * {128, 256, 512} Gaussians staged in LDS per step of the blend kernels;
+ * bg is the background colour added as T_final * bg.  The image does not
+ * depend on tile or lds_batch (binning is result-neutral). */
+typedef struct {
+  int32_t tile;
+  int32_t lds_batch;
+  float bg[3];
+} gs_raster_cfg;
+
+/* ---------------------------------------------------------------------------
+ * gs_preprocess: 3D -> 2D splatting of every Gaussian into every view
+ * (Sec. 3: G_i is splatted to G2D_i; colour c_i from SH coefficients).
+ *   means [n,3], log_scales [n,3], quats [n,4] (w,x,y,z, need not be unit),
+ *   opacity_logits [n], sh [n,16,3] (coefficient-major; only the first
+ *   (sh_degree+1)^2 are read), sh_degree in 0..3.
+ *   cams: host array [n_views]; cfg: host.
+ *   proj: output, gs_proj_bytes(n_views, n) bytes, opaque per-view records
+ *   (screen mean, conic, opacity, colour, depth, footprint box, tile count,
+ *   clamp flags), consumed by the calls below with the same n_views, cams,
+ *   cfg and n.  0 <= n < 2^31 / n_views.
+ * ------------------------------------------------------------------------- */
+size_t gs_proj_bytes(int32_t n_views, int32_t n);
+gs_status gs_preprocess(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
+                        int32_t n, const float* means, const float* log_scales,
+                        const float* quats, const float* opacity_logits, const float* sh,
+                        int32_t sh_degree, void* proj, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * gs_bin_sort: one (tile, Gaussian) pair per tile of each Gaussian's
+ * footprint, keyed key = (tile_id << 32) | bits(depth_f32), sorted ascending
+ * and stably (equal keys keep ascending Gaussian index), then per-tile ranges.
+ * With several views tile ids run view after view (view 0's tiles first).
+ *   capacity_pairs: length of keys/vals (>= 0, < 2^32).
+ *   ws: workspace of gs_bin_sort_workspace_bytes(...) bytes.
+ *   keys [capacity] u64: may be NULL (the blend kernels need only vals).
+ *   vals [capacity] u32: Gaussian index of each sorted pair.
+ *   ranges [total_tiles, 2] u32: [start, end) into vals, [0,0) when empty;
+ *     total_tiles = sum over views of ceil(W/tile) * ceil(H/tile).
+ *   n_pairs_dev [1] i64: number of pairs, always written.  If it exceeds
+ *     capacity_pairs, keys/vals/ranges are NOT valid: grow and call again.
+ * ------------------------------------------------------------------------- */
+size_t gs_bin_sort_workspace_bytes(int32_t n_views, int32_t n, int64_t capacity_pairs);
+gs_status gs_bin_sort(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
+                      int32_t n, const void* proj, int64_t capacity_pairs, void* ws,
+                      size_t ws_bytes, uint64_t* keys, uint32_t* vals, uint32_t* ranges,
+                      int64_t* n_pairs_dev, void* stream);
+
+/* Total tiles over the views for this cfg (host helper for sizing ranges). */
+int64_t gs_total_tiles(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg);
+
+/* ---------------------------------------------------------------------------
+ * gs_render_fwd: front-to-back blend of Eq. 1 for every pixel of every view.
+ * Per pixel, over its tile's sorted list: alpha = min(0.99, o G2D(u)),
+ * Gaussians with alpha < 1/255 are skipped, and the first Gaussian that would
+ * take the transmittance below 1e-4 stops the pixel without being blended.
+ *   image [3,H,W] per view, final_T [H,W] per view, last_contrib [H,W] per
+ *   view (number of list entries up to and including the last blended one,
+ *   0 if none), all concatenated over views.
+ * ------------------------------------------------------------------------- */
+gs_status gs_render_fwd(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
+                        int32_t n, const void* proj, const uint32_t* ranges,
+                        const uint32_t* vals, float* image, float* final_T,
+                        uint32_t* last_contrib, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * gs_render_bwd: back-propagation of Eq. 1 to the Gaussian parameters
+ * (Sec. 3: the process is differentiable and G_i is optimised from the loss).
+ * Each pixel replays its list back to front from last_contrib, recovering
+ * T_i = T_{i+1} / (1 - alpha_i) from final_T, so no per-pixel history is
+ * stored.  Per (tile, Gaussian) gradients land in a deterministic per-pair
+ * slot of the workspace (no float atomics), then one kernel chains them to
+ * the 3D parameters and sums over views.
+ *   Inputs: the parameters given to gs_preprocess, its proj, the ranges/vals
+ *   of gs_bin_sort (which must not have overflowed), the forward's final_T
+ *   and last_contrib, and dL_dimage (same layout as image).
+ *   Outputs (ACCUMULATED, +=; zero them per iteration): d_means [n,3],
+ *   d_log_scales [n,3], d_quats [n,4], d_opacity_logits [n], d_sh [n,16,3]
+ *   (coefficients above sh_degree untouched), d_mean2d_abs [n] (nullable:
+ *   sum over views of |dL/dmean2D|, the densification statistic).
+ *   ws: gs_render_bwd_workspace_bytes(n_views, n, capacity_pairs) bytes.
+ * ------------------------------------------------------------------------- */
+size_t gs_render_bwd_workspace_bytes(int32_t n_views, int32_t n, int64_t capacity_pairs);
+gs_status gs_render_bwd(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
+                        int32_t n, const float* means, const float* log_scales,
+                        const float* quats, const float* opacity_logits, const float* sh,
+                        int32_t sh_degree, const void* proj, const uint32_t* ranges,
+                        const uint32_t* vals, const float* final_T,
+                        const uint32_t* last_contrib, const float* dL_dimage, float* d_means,
+                        float* d_log_scales, float* d_quats, float* d_opacity_logits,
+                        float* d_sh, float* d_mean2d_abs, int64_t capacity_pairs, void* ws,
+                        size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * gs_adam_step: fused Adam over several parameter groups in one launch
+ * (the primitive update, Sec. 1 / Sec. 5.2):
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   p -= lr * (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps).
+ * groups: host array [n_groups], 1 <= n_groups <= GS_MAX_ADAM_GROUPS, each
+ * with device p, g, m, v of numel elements (numel >= 0); step >= 1.
+ * ------------------------------------------------------------------------- */
+#define GS_MAX_ADAM_GROUPS 8
+typedef struct {
+  float* p;
+  const float* g;
+  float* m;
+  float* v;
+  int64_t numel;
+  float lr;
+} gs_adam_group;
+gs_status gs_adam_step(const gs_adam_group* groups, int32_t n_groups, int32_t step,
+                       float beta1, float beta2, float eps, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * gs_l1_loss_grad: L1 photometric loss of the backbones.
+ *   dL_dimage[i] = scale * sign(image[i] - target[i])  (sign(0) = 0), numel
+ *   elements; if loss_sum (device, [1]) is non-NULL, scale * sum|image-target|
+ *   is ADDED to it.  scale = 1/numel gives the mean.
+ * ------------------------------------------------------------------------- */
+gs_status gs_l1_loss_grad(int64_t numel, const float* image, const float* target, float scale,
+                          float* dL_dimage, float* loss_sum, void* stream);
+
+const char* gs_status_str(gs_status s);
+int32_t gs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GS_H */

@@ -147,6 +147,7 @@ def render_bwd_2d(P: dict, dL_dC: np.ndarray, bg=(0.0, 0.0, 0.0), pixels=None,
     d_con = np.zeros((len(order), 3))
     d_op = np.zeros(len(order))
     d_rgb = np.zeros((len(order), 3))
+    abs2d = np.zeros((len(order), 9))
     contrib = np.zeros(len(order), bool)
     for s in range(0, pix.shape[0], chunk):
         blk = pix[s:s + chunk]
@@ -172,11 +173,19 @@ def render_bwd_2d(P: dict, dL_dC: np.ndarray, bg=(0.0, 0.0, 0.0), pixels=None,
         d_con[:, 0] += (dL_dpow * (-0.5 * dx * dx)).sum(axis=0)
         d_con[:, 1] += (dL_dpow * (-dx * dy)).sum(axis=0)
         d_con[:, 2] += (dL_dpow * (-0.5 * dy * dy)).sum(axis=0)
-        d_mean[:, 0] += (dL_dpow * (a[None, :] * dx + b[None, :] * dy)).sum(axis=0)
-        d_mean[:, 1] += (dL_dpow * (b[None, :] * dx + c[None, :] * dy)).sum(axis=0)
+        terms = [dL_dpow * (a[None, :] * dx + b[None, :] * dy),
+                 dL_dpow * (b[None, :] * dx + c[None, :] * dy),
+                 dL_dpow * (-0.5 * dx * dx), dL_dpow * (-dx * dy), dL_dpow * (-0.5 * dy * dy),
+                 np.where(unclamped, dL_dalpha * G, 0.0),
+                 w * g[:, 0:1], w * g[:, 1:2], w * g[:, 2:3]]
+        d_mean[:, 0] += terms[0].sum(axis=0)
+        d_mean[:, 1] += terms[1].sum(axis=0)
+        for k in range(9):
+            abs2d[:, k] += np.abs(terms[k]).sum(axis=0)
         contrib |= keep.any(axis=0)
     out = dict(d_mean2d=np.zeros((n, 2)), d_conic=np.zeros((n, 3)), d_opacity=np.zeros(n),
-               d_rgb=np.zeros((n, 3)), contrib=np.zeros(n, bool))
+               d_rgb=np.zeros((n, 3)), contrib=np.zeros(n, bool), abs2d=np.zeros((n, 9)))
+    out["abs2d"][order] = abs2d
     out["d_mean2d"][order] = d_mean
     out["d_conic"][order] = d_con
     out["d_opacity"][order] = d_op
@@ -270,12 +279,76 @@ def chain_to_3d(scene: dict, P: dict, g2: dict) -> dict:
     return out
 
 
+def chain_abs_bound(scene: dict, P: dict, abs2d: np.ndarray) -> dict:
+    """Running error scale of every parameter gradient.
+
+    ``chain_to_3d`` evaluated on absolute values: every input, matrix entry
+    and intermediate replaced by its magnitude and every difference by a sum,
+    fed with the per-Gaussian sums over pixels of the absolute 2D terms
+    (``abs2d``).  The result bounds the sum of the magnitudes of all products
+    that a floating-point evaluation adds up into each gradient element, so a
+    float32 result that cancels from large terms has an error proportional to
+    it (the usual forward error bound |fl(s) - s| <= gamma * sum |terms|).
+    """
+    n = P["mean2d"].shape[0]
+    A = np.abs
+    x, y = A(P["xc"][:, 0]), A(P["xc"][:, 1])
+    z = np.where(P["live"], P["xc"][:, 2], 1.0)
+    fx, fy = P["fx"], P["fy"]
+    gm = abs2d[:, 0:2]
+    ga, gb, gc = abs2d[:, 2], abs2d[:, 3], abs2d[:, 4]
+    a, b, c = A(P["conic"][:, 0]), A(P["conic"][:, 1]), A(P["conic"][:, 2])
+    Q = np.stack([np.stack([a, b], -1), np.stack([b, c], -1)], -2)
+    GQ = np.stack([np.stack([ga, 0.5 * gb], -1), np.stack([0.5 * gb, gc], -1)], -2)
+    GS2 = Q @ GQ @ Q
+    Tm, Sigma, Rc = A(P["Tm"]), A(P["Sigma"]), A(P["Rc"])
+    GSigma = np.transpose(Tm, (0, 2, 1)) @ GS2 @ Tm
+    GJ = (2.0 * GS2 @ Tm @ Sigma) @ Rc.T
+    gx = gm[:, 0] * fx / z + GJ[:, 0, 2] * fx / (z * z)
+    gy = gm[:, 1] * fy / z + GJ[:, 1, 2] * fy / (z * z)
+    gz = (gm[:, 0] * fx * x / (z * z) + gm[:, 1] * fy * y / (z * z)
+          + GJ[:, 0, 0] * fx / (z * z) + GJ[:, 0, 2] * 2.0 * fx * x / z ** 3
+          + GJ[:, 1, 1] * fy / (z * z) + GJ[:, 1, 2] * 2.0 * fy * y / z ** 3)
+    d_means = np.stack([gx, gy, gz], 1) @ Rc
+    s, Rq = P["scales"], A(P["Rq"])
+    M = Rq * s[:, None, :]
+    GM = 2.0 * GSigma @ M
+    d_ls = np.einsum("nik,nik->nk", GM, Rq) * s
+    GR = GM * s[:, None, :]
+    qn = A(P["qn"])
+    gqn = np.einsum("nij,nijk->nk", GR, A(_dR_dq(P["qn"])))
+    d_q = (gqn + qn * np.sum(qn * gqn, axis=1, keepdims=True)) / P["qnorm"][:, None]
+    o = P["opacity"]
+    d_logit = abs2d[:, 5] * o * (1.0 - o)
+    deg = P["sh_degree"]
+    K = _sh.n_coeffs(deg)
+    grgb = abs2d[:, 6:9]
+    d_sh = np.zeros((n, 16, 3))
+    d_sh[:, :K, :] = A(P["Y"])[:, :, None] * grgb[:, None, :]
+    dY = A(_sh.basis_grad(P["dirs"], deg))
+    shc = A(np.asarray(scene["sh"], F64)[:, :K, :])
+    gdir = np.einsum("nc,nkc,nkj->nj", grgb, shc, dY)
+    d = A(P["dirs"])
+    d_means = d_means + (gdir + d * np.sum(d * gdir, axis=1, keepdims=True)) / P["dist"][:, None]
+    out = dict(d_means=d_means, d_log_scales=d_ls, d_quats=d_q, d_opacity_logits=d_logit,
+               d_sh=d_sh)
+    for k in out:
+        out[k][~P["live"]] = 0.0
+    return out
+
+
 def render_bwd(scene: dict, P: dict, dL_dC: np.ndarray, bg=(0.0, 0.0, 0.0), pixels=None,
-               chunk: int = 256) -> dict:
-    """Full backward: 2D gradients then the chain to the parameters."""
+               chunk: int = 256, with_bound: bool = False) -> dict:
+    """Full backward: 2D gradients then the chain to the parameters.
+
+    With ``with_bound`` also returns ``bound``: the per-element term scale of
+    ``chain_abs_bound`` for every parameter gradient.
+    """
     g2 = render_bwd_2d(P, dL_dC, bg=bg, pixels=pixels, chunk=chunk)
     out = chain_to_3d(scene, P, g2)
     out["g2d"] = g2
+    if with_bound:
+        out["bound"] = chain_abs_bound(scene, P, g2["abs2d"])
     return out
 
 

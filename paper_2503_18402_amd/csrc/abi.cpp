@@ -1,0 +1,187 @@
+// C ABI of the rasterizer library: argument checks, view tables, dispatch.
+// Every entry point validates its arguments before enqueuing anything and
+// never throws; kernels are enqueued on the caller's stream only.
+#include <cmath>
+#include <cstring>
+
+#include "gs_internal.hpp"
+
+namespace gsk {
+
+bool build_views(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg, Views* out) {
+  if (!cams || !cfg || !out || n_views < 1 || n_views > GS_MAX_VIEWS) return false;
+  if (cfg->tile != 8 && cfg->tile != 16 && cfg->tile != 32) return false;
+  if (cfg->lds_batch != 128 && cfg->lds_batch != 256 && cfg->lds_batch != 512) return false;
+  std::memset(out, 0, sizeof(Views));
+  out->n_views = n_views;
+  out->tile = cfg->tile;
+  int64_t tiles = 0, pix = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const gs_camera& c = cams[v];
+    if (c.width < 1 || c.height < 1 || c.width > 16384 || c.height > 16384) return false;
+    if (!(c.near_plane > 0.0f) || !std::isfinite(c.fx) || !std::isfinite(c.fy)) return false;
+    DevView& d = out->v[v];
+    for (int k = 0; k < 9; ++k) d.R[k] = c.R[k];
+    for (int k = 0; k < 3; ++k) d.t[k] = c.t[k];
+    for (int k = 0; k < 3; ++k)  // -R^T t in double, rounded once
+      d.campos[k] = float(-(double(c.R[k]) * c.t[0] + double(c.R[3 + k]) * c.t[1] +
+                            double(c.R[6 + k]) * c.t[2]));
+    d.fx = c.fx;
+    d.fy = c.fy;
+    d.cx = c.cx;
+    d.cy = c.cy;
+    d.near_plane = c.near_plane;
+    d.W = c.width;
+    d.H = c.height;
+    d.gw = (c.width + cfg->tile - 1) / cfg->tile;
+    d.gh = (c.height + cfg->tile - 1) / cfg->tile;
+    d.tile_base = int32_t(tiles);
+    d.pix_base = pix;
+    tiles += int64_t(d.gw) * d.gh;
+    pix += int64_t(c.width) * c.height;
+  }
+  if (tiles >= (int64_t(1) << 31)) return false;
+  out->total_tiles = int32_t(tiles);
+  return true;
+}
+
+}  // namespace gsk
+
+using namespace gsk;
+
+namespace {
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+gs_status from_hip(hipError_t e) { return e == hipSuccess ? GS_OK : GS_ERR_DEVICE; }
+
+bool n_ok(int32_t n_views, int32_t n) {
+  return n >= 0 && n_views >= 1 && int64_t(n) * n_views < (int64_t(1) << 31);
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t gs_version(void) { return 1; }
+
+const char* gs_status_str(gs_status s) {
+  switch (s) {
+    case GS_OK: return "ok";
+    case GS_ERR_ARG: return "invalid argument";
+    case GS_ERR_CAPACITY: return "workspace or capacity too small";
+    case GS_ERR_DEVICE: return "HIP launch failed";
+    case GS_ERR_UNSUPPORTED: return "unsupported request";
+  }
+  return "unknown status";
+}
+
+size_t gs_proj_bytes(int32_t n_views, int32_t n) {
+  if (!n_ok(n_views, n) || n_views > GS_MAX_VIEWS) return 0;
+  return size_t(n_views) * ProjLayout(n).stride;
+}
+
+int64_t gs_total_tiles(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg) {
+  Views V;
+  if (!build_views(n_views, cams, cfg, &V)) return -1;
+  return V.total_tiles;
+}
+
+gs_status gs_preprocess(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
+                        int32_t n, const float* means, const float* log_scales,
+                        const float* quats, const float* opacity_logits, const float* sh,
+                        int32_t sh_degree, void* proj, void* stream) {
+  Views V;
+  if (!n_ok(n_views, n) || !build_views(n_views, cams, cfg, &V)) return GS_ERR_ARG;
+  if (sh_degree < 0 || sh_degree > 3) return GS_ERR_ARG;
+  if (n > 0 && (!means || !log_scales || !quats || !opacity_logits || !sh || !proj))
+    return GS_ERR_ARG;
+  if (n > 0 && (!aligned16(quats) || !aligned16(proj))) return GS_ERR_ARG;
+  return from_hip(launch_preprocess(V, n, sh_degree, means, log_scales, quats, opacity_logits, sh,
+                                    static_cast<char*>(proj), as_stream(stream)));
+}
+
+size_t gs_bin_sort_workspace_bytes(int32_t n_views, int32_t n, int64_t capacity_pairs) {
+  if (!n_ok(n_views, n) || capacity_pairs < 0 || capacity_pairs >= (int64_t(1) << 32)) return 0;
+  return bin_sort_ws_bytes(n_views, n, capacity_pairs);
+}
+
+gs_status gs_bin_sort(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
+                      int32_t n, const void* proj, int64_t capacity_pairs, void* ws,
+                      size_t ws_bytes, uint64_t* keys, uint32_t* vals, uint32_t* ranges,
+                      int64_t* n_pairs_dev, void* stream) {
+  Views V;
+  if (!n_ok(n_views, n) || !build_views(n_views, cams, cfg, &V)) return GS_ERR_ARG;
+  if (capacity_pairs < 0 || capacity_pairs >= (int64_t(1) << 32)) return GS_ERR_ARG;
+  if (!ws || !ranges || !n_pairs_dev || (n > 0 && !proj) || (capacity_pairs > 0 && !vals))
+    return GS_ERR_ARG;
+  if (ws_bytes < bin_sort_ws_bytes(n_views, n, capacity_pairs)) return GS_ERR_CAPACITY;
+  if (!aligned16(ws) || (n > 0 && !aligned16(proj))) return GS_ERR_ARG;
+  return from_hip(launch_bin_sort(V, n, static_cast<const char*>(proj), capacity_pairs, ws, keys,
+                                  vals, ranges, n_pairs_dev, as_stream(stream)));
+}
+
+gs_status gs_render_fwd(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
+                        int32_t n, const void* proj, const uint32_t* ranges,
+                        const uint32_t* vals, float* image, float* final_T,
+                        uint32_t* last_contrib, void* stream) {
+  Views V;
+  if (!n_ok(n_views, n) || !build_views(n_views, cams, cfg, &V)) return GS_ERR_ARG;
+  if (!ranges || !image || !final_T || !last_contrib || (n > 0 && !proj)) return GS_ERR_ARG;
+  if (n > 0 && !aligned16(proj)) return GS_ERR_ARG;
+  return from_hip(launch_render_fwd(V, n, *cfg, static_cast<const char*>(proj), ranges, vals,
+                                    image, final_T, last_contrib, as_stream(stream)));
+}
+
+size_t gs_render_bwd_workspace_bytes(int32_t n_views, int32_t n, int64_t capacity_pairs) {
+  if (!n_ok(n_views, n) || capacity_pairs < 0 || capacity_pairs >= (int64_t(1) << 32)) return 0;
+  return render_bwd_ws_bytes(n_views, n, capacity_pairs);
+}
+
+gs_status gs_render_bwd(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
+                        int32_t n, const float* means, const float* log_scales,
+                        const float* quats, const float* opacity_logits, const float* sh,
+                        int32_t sh_degree, const void* proj, const uint32_t* ranges,
+                        const uint32_t* vals, const float* final_T,
+                        const uint32_t* last_contrib, const float* dL_dimage, float* d_means,
+                        float* d_log_scales, float* d_quats, float* d_opacity_logits,
+                        float* d_sh, float* d_mean2d_abs, int64_t capacity_pairs, void* ws,
+                        size_t ws_bytes, void* stream) {
+  Views V;
+  if (!n_ok(n_views, n) || !build_views(n_views, cams, cfg, &V)) return GS_ERR_ARG;
+  if (sh_degree < 0 || sh_degree > 3) return GS_ERR_ARG;
+  if (capacity_pairs < 0 || capacity_pairs >= (int64_t(1) << 32)) return GS_ERR_ARG;
+  if (!ranges || !final_T || !last_contrib || !dL_dimage || !ws) return GS_ERR_ARG;
+  if (n > 0 && (!means || !log_scales || !quats || !opacity_logits || !sh || !proj || !d_means ||
+                !d_log_scales || !d_quats || !d_opacity_logits || !d_sh))
+    return GS_ERR_ARG;
+  if (n > 0 && (!aligned16(quats) || !aligned16(d_quats) || !aligned16(proj) || !aligned16(ws)))
+    return GS_ERR_ARG;
+  if (ws_bytes < render_bwd_ws_bytes(n_views, n, capacity_pairs)) return GS_ERR_CAPACITY;
+  return from_hip(launch_render_bwd(V, n, *cfg, means, log_scales, quats, opacity_logits, sh,
+                                    sh_degree, static_cast<const char*>(proj), ranges, vals,
+                                    final_T, last_contrib, dL_dimage, d_means, d_log_scales,
+                                    d_quats, d_opacity_logits, d_sh, d_mean2d_abs,
+                                    capacity_pairs, ws, as_stream(stream)));
+}
+
+gs_status gs_adam_step(const gs_adam_group* groups, int32_t n_groups, int32_t step, float beta1,
+                       float beta2, float eps, void* stream) {
+  if (!groups || n_groups < 1 || n_groups > GS_MAX_ADAM_GROUPS || step < 1) return GS_ERR_ARG;
+  if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps >= 0.0f))
+    return GS_ERR_ARG;
+  for (int k = 0; k < n_groups; ++k) {
+    const gs_adam_group& g = groups[k];
+    if (g.numel < 0) return GS_ERR_ARG;
+    if (g.numel > 0 && (!g.p || !g.g || !g.m || !g.v)) return GS_ERR_ARG;
+  }
+  return from_hip(launch_adam(groups, n_groups, step, beta1, beta2, eps, as_stream(stream)));
+}
+
+gs_status gs_l1_loss_grad(int64_t numel, const float* image, const float* target, float scale,
+                          float* dL_dimage, float* loss_sum, void* stream) {
+  if (numel < 0 || (numel > 0 && (!image || !target || !dL_dimage))) return GS_ERR_ARG;
+  return from_hip(launch_l1(numel, image, target, scale, dL_dimage, loss_sum, as_stream(stream)));
+}
+
+}  // extern "C"

@@ -1,0 +1,611 @@
+// Backward of Eq. 1 and the chain rule to the Gaussian parameters.
+//
+// k_blend_bwd: one workgroup per tile replays the tile's list back to front
+// in LDS-staged batches.  Each pixel starts at its own last contributor with
+// T = final_T and recovers T_i = T_{i+1} / (1 - alpha_i); the colour behind a
+// Gaussian is carried as its dot product with dL/dC.  Per (tile, Gaussian) the
+// nine 2D gradients (mean2D x/y, conic a/b/c, opacity, rgb) are summed over
+// the tile's pixels in a fixed order (wave butterfly, then waves in order)
+// and written to that pair's own slot: the pair slots of a Gaussian are
+// contiguous (ordered by Gaussian index, then by tile inside its footprint),
+// so no float atomics are needed and gradients are bit-reproducible.
+//
+// k_chain: one thread per Gaussian sums its pair slots per view and chains the
+// 2D gradients through the EWA projection, the covariance, the quaternion,
+// the sigmoid and the SH colour back to the parameters, accumulating over
+// views in registers before one read-modify-write of the outputs.
+#include "blend_common.hpp"
+#include "scan.hpp"
+
+namespace gsk {
+namespace {
+
+constexpr int kG = 9;  // 2D gradient components per (tile, Gaussian)
+constexpr float kLn2 = 0.69314718055994530942f;
+
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+  return x;
+}
+
+template <int TILE, int BATCH>
+__global__ __launch_bounds__(TileShape<TILE>::kThreads) void k_blend_bwd(
+    RViews RV, int n, const char* __restrict__ proj, size_t stride,
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
+    const float* __restrict__ final_T, const uint32_t* __restrict__ last_contrib,
+    const float* __restrict__ dL_dimage, const uint32_t* __restrict__ grad_off,
+    float* __restrict__ pair_grad, int64_t cap, float bg0, float bg1, float bg2) {
+  using S = TileShape<TILE>;
+  constexpr int NT = S::kThreads, NW = S::kWaves, R = S::kRegion, SUB = S::kSub, P = S::kPix;
+  __shared__ float4 s_r0[BATCH];
+  __shared__ float4 s_r1[BATCH];
+  __shared__ float s_b[BATCH];
+  __shared__ uint32_t s_mask[BATCH];
+  __shared__ uint32_t s_pidx[BATCH];
+  __shared__ uint16_t s_list[NW][BATCH];
+  __shared__ float s_acc[NW][kG][BATCH];
+  __shared__ uint32_t s_max;
+
+  const int t = blockIdx.x;
+  const int v = view_of_tile(RV, t);
+  const int lt = t - RV.tile_base[v];
+  const int gw = RV.gw[v], W = RV.W[v], H = RV.H[v];
+  const int tx = lt % gw, ty = lt / gw;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wx = (NW == 1) ? 0 : (w & 1), wy = (NW == 1) ? 0 : (w >> 1);
+  const int rx0 = tx * TILE + wx * R, ry0 = ty * TILE + wy * R;
+  const int lx = lane & 7, ly = lane >> 3;
+  const uint64_t ltmask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t pb = RV.pix_base[v];
+  const int64_t plane = int64_t(W) * H;
+
+  if (tid == 0) s_max = 0;
+  float pxc[P], pyc[P], T[P], g0[P], g1[P], g2[P], SdL[P];
+  uint32_t last[P];
+  uint32_t mylast = 0;
+#pragma unroll
+  for (int j = 0; j < SUB; ++j)
+#pragma unroll
+    for (int i = 0; i < SUB; ++i) {
+      const int p = j * SUB + i;
+      const int x = rx0 + i * 8 + lx, y = ry0 + j * 8 + ly;
+      pxc[p] = float(x - tx * TILE) + 0.5f;  // pixel centre in the tile's frame
+      pyc[p] = float(y - ty * TILE) + 0.5f;
+      if (x < W && y < H) {
+        const int64_t o = int64_t(y) * W + x;
+        T[p] = final_T[pb + o];
+        last[p] = last_contrib[pb + o];
+        g0[p] = dL_dimage[3 * pb + o];
+        g1[p] = dL_dimage[3 * pb + plane + o];
+        g2[p] = dL_dimage[3 * pb + 2 * plane + o];
+      } else {
+        T[p] = 1.0f;
+        last[p] = 0;
+        g0[p] = g1[p] = g2[p] = 0.0f;
+      }
+      // colour behind the current Gaussian, dotted with dL/dC: starts at T_final * bg
+      SdL[p] = T[p] * fmaf(bg0, g0[p], fmaf(bg1, g1[p], bg2 * g2[p]));
+      mylast = max(mylast, last[p]);
+    }
+  __syncthreads();
+  atomicMax(&s_max, mylast);
+  __syncthreads();
+  const uint32_t start = ranges[2 * t];
+  const uint32_t stop = min(start + s_max, ranges[2 * t + 1]);
+  const float4* rec = reinterpret_cast<const float4*>(proj + size_t(v) * stride);
+  const uint32_t* goff = grad_off + size_t(v) * n;
+
+  for (uint32_t bend = stop; bend > start;) {
+    const uint32_t bstart = (bend - start > uint32_t(BATCH)) ? bend - BATCH : start;
+    const int nb = int(bend - bstart);
+    for (int k = tid; k < BATCH; k += NT) {
+      uint32_t msk = 0;
+      if (k < nb) {
+        const uint32_t g = vals[bstart + k];
+        const float4 r0 = rec[3 * size_t(g)];
+        const float4 r1 = rec[3 * size_t(g) + 1];
+        const float4 r2 = rec[3 * size_t(g) + 2];
+        const uint32_t lo = __float_as_uint(r2.z), hi = __float_as_uint(r2.w);
+        s_r0[k] = to_tile_frame<TILE>(r0, lo, tx, ty);
+        s_r1[k] = r1;
+        s_b[k] = r2.x;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) {
+          const int x0 = tx * TILE + ((NW == 1) ? 0 : (ww & 1) * R);
+          const int y0 = ty * TILE + ((NW == 1) ? 0 : (ww >> 1) * R);
+          msk |= box_overlaps(lo, hi, x0, y0, x0 + R - 1, y0 + R - 1) ? (1u << ww) : 0u;
+        }
+        const int tx0 = box_x(lo) / TILE, ty0 = box_y(lo) / TILE, tx1 = box_x(hi) / TILE;
+        s_pidx[k] = goff[g] + uint32_t((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww)
+#pragma unroll
+          for (int c = 0; c < kG; ++c) s_acc[ww][c][k] = 0.0f;
+      }
+      s_mask[k] = msk;
+    }
+    __syncthreads();
+    int cnt = 0;
+    for (int c = 0; c < nb; c += 64) {
+      const int k = c + lane;
+      const bool m = (k < nb) && ((s_mask[k] >> w) & 1u);
+      const uint64_t bal = __ballot(m);
+      if (m) s_list[w][cnt + __popcll(bal & ltmask)] = uint16_t(k);
+      cnt += __popcll(bal);
+    }
+    for (int q = cnt - 1; q >= 0; --q) {
+      const int k = s_list[w][q];
+      const float4 r0 = s_r0[k];
+      const float4 r1 = s_r1[k];
+      const float cb = s_b[k];
+      const float o = r1.y;
+      const uint32_t pos = bstart - start + uint32_t(k) + 1u;
+      float acc[kG];
+#pragma unroll
+      for (int c = 0; c < kG; ++c) acc[c] = 0.0f;
+      bool hit = false;
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        if (pos <= last[p]) {
+          float a, G, dx, dy;
+          if (eval_alpha(r0, r1.x, o, pxc[p], pyc[p], a, G, dx, dy)) {
+            hit = true;
+            const float inv = 1.0f / (1.0f - a);
+            const float Ti = T[p] * inv;
+            const float wgt = a * Ti;
+            const float cg = fmaf(r1.z, g0[p], fmaf(r1.w, g1[p], cb * g2[p]));
+            const float dLda = Ti * cg - SdL[p] * inv;
+            SdL[p] = fmaf(wgt, cg, SdL[p]);
+            T[p] = Ti;
+            acc[6] = fmaf(wgt, g0[p], acc[6]);
+            acc[7] = fmaf(wgt, g1[p], acc[7]);
+            acc[8] = fmaf(wgt, g2[p], acc[8]);
+            if (o * G <= kAlphaMax) {
+              acc[5] = fmaf(dLda, G, acc[5]);
+              const float dpow = dLda * o * G;
+              const float dpx = dpow * dx, dpy = dpow * dy;
+              acc[2] = fmaf(dpx, dx, acc[2]);
+              acc[3] = fmaf(dpx, dy, acc[3]);
+              acc[4] = fmaf(dpy, dy, acc[4]);
+              // (2A dx + B dy), (B dx + 2C dy): derivative of p2 w.r.t. -mean2D
+              acc[0] = fmaf(dpow, fmaf(2.0f * r0.z, dx, r0.w * dy), acc[0]);
+              acc[1] = fmaf(dpow, fmaf(r0.w, dx, 2.0f * r1.x * dy), acc[1]);
+            }
+          }
+        }
+      }
+      if (__ballot(hit) != 0ull) {
+#pragma unroll
+        for (int c = 0; c < kG; ++c) {
+          const float sum = wave_sum(acc[c]);
+          if (lane == 0) s_acc[w][c][k] = sum;
+        }
+      }
+    }
+    __syncthreads();
+    for (int k = tid; k < nb; k += NT) {
+      float sum[kG];
+      bool nz = false;
+#pragma unroll
+      for (int c = 0; c < kG; ++c) {
+        float s = s_acc[0][c][k];
+#pragma unroll
+        for (int ww = 1; ww < NW; ++ww) s += s_acc[ww][c][k];
+        sum[c] = s;
+        nz |= (s != 0.0f);
+      }
+      const uint32_t idx = s_pidx[k];
+      if (nz && int64_t(idx) < cap) {
+        // natural-unit conic / mean gradients from the base-2 accumulators
+        float* dst = pair_grad + size_t(idx) * kG;
+        dst[0] = -kLn2 * sum[0];
+        dst[1] = -kLn2 * sum[1];
+        dst[2] = -0.5f * sum[2];
+        dst[3] = -sum[3];
+        dst[4] = -0.5f * sum[4];
+        dst[5] = sum[5];
+        dst[6] = sum[6];
+        dst[7] = sum[7];
+        dst[8] = sum[8];
+      }
+    }
+    __syncthreads();
+    bend = bstart;
+  }
+}
+
+// -------------------------------------------------------------- chain rule
+constexpr float SH0 = 0.28209479177387814f;
+constexpr float SH1 = 0.48860251190291992f;
+constexpr float SH2a = 1.0925484305920792f;
+constexpr float SH2b = 0.31539156525252005f;
+constexpr float SH2c = 0.54627421529603959f;
+constexpr float SH3a = 0.59004358992664352f;
+constexpr float SH3b = 2.8906114426405538f;
+constexpr float SH3c = 0.45704579946446572f;
+constexpr float SH3d = 0.37317633259011540f;
+constexpr float SH3e = 1.4453057213202769f;
+
+__device__ inline void sh_basis_b(float x, float y, float z, int deg, float* Y) {
+  Y[0] = SH0;
+  if (deg < 1) return;
+  Y[1] = -SH1 * y;
+  Y[2] = SH1 * z;
+  Y[3] = -SH1 * x;
+  if (deg < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = SH2a * (x * y);
+  Y[5] = -SH2a * (y * z);
+  Y[6] = SH2b * (2.0f * zz - xx - yy);
+  Y[7] = -SH2a * (x * z);
+  Y[8] = SH2c * (xx - yy);
+  if (deg < 3) return;
+  Y[9] = -SH3a * y * (3.0f * xx - yy);
+  Y[10] = SH3b * (x * y) * z;
+  Y[11] = -SH3c * y * (4.0f * zz - xx - yy);
+  Y[12] = SH3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+  Y[13] = -SH3c * x * (4.0f * zz - xx - yy);
+  Y[14] = SH3e * z * (xx - yy);
+  Y[15] = -SH3a * x * (xx - 3.0f * yy);
+}
+
+// sum_k wk dY_k/d(x,y,z) for the polynomial form of the basis
+__device__ inline void sh_dir_grad(float x, float y, float z, int deg, const float* wk,
+                                   float& gx, float& gy, float& gz) {
+  gx = gy = gz = 0.0f;
+  if (deg < 1) return;
+  gy -= SH1 * wk[1];
+  gz += SH1 * wk[2];
+  gx -= SH1 * wk[3];
+  if (deg < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  gx += SH2a * y * wk[4];          gy += SH2a * x * wk[4];
+  gy -= SH2a * z * wk[5];          gz -= SH2a * y * wk[5];
+  gx -= 2.0f * SH2b * x * wk[6];   gy -= 2.0f * SH2b * y * wk[6];   gz += 4.0f * SH2b * z * wk[6];
+  gx -= SH2a * z * wk[7];          gz -= SH2a * x * wk[7];
+  gx += 2.0f * SH2c * x * wk[8];   gy -= 2.0f * SH2c * y * wk[8];
+  if (deg < 3) return;
+  gx -= SH3a * 6.0f * x * y * wk[9];
+  gy -= SH3a * (3.0f * xx - 3.0f * yy) * wk[9];
+  gx += SH3b * y * z * wk[10];     gy += SH3b * x * z * wk[10];     gz += SH3b * x * y * wk[10];
+  gx += SH3c * 2.0f * x * y * wk[11];
+  gy -= SH3c * (4.0f * zz - xx - 3.0f * yy) * wk[11];
+  gz -= SH3c * 8.0f * y * z * wk[11];
+  gx -= SH3d * 6.0f * x * z * wk[12];
+  gy -= SH3d * 6.0f * y * z * wk[12];
+  gz += SH3d * (6.0f * zz - 3.0f * xx - 3.0f * yy) * wk[12];
+  gx -= SH3c * (4.0f * zz - 3.0f * xx - yy) * wk[13];
+  gy += SH3c * 2.0f * x * y * wk[13];
+  gz -= SH3c * 8.0f * x * z * wk[13];
+  gx += SH3e * 2.0f * x * z * wk[14];
+  gy -= SH3e * 2.0f * y * z * wk[14];
+  gz += SH3e * (xx - yy) * wk[14];
+  gx -= SH3a * (3.0f * xx - 3.0f * yy) * wk[15];
+  gy += SH3a * 6.0f * x * y * wk[15];
+}
+
+__global__ __launch_bounds__(128) void k_chain(
+    Views V, int n, int sh_degree, const float* __restrict__ means,
+    const float* __restrict__ log_scales, const float* __restrict__ quats,
+    const float* __restrict__ opacity_logits, const float* __restrict__ sh,
+    const char* __restrict__ proj, const uint32_t* __restrict__ grad_off,
+    const float* __restrict__ pair_grad, int64_t cap, float* __restrict__ d_means,
+    float* __restrict__ d_log_scales, float* __restrict__ d_quats,
+    float* __restrict__ d_opacity_logits, float* __restrict__ d_sh,
+    float* __restrict__ d_mean2d_abs) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const ProjLayout L(n);
+
+  // does any view have gradient slots for this Gaussian?
+  bool any = false;
+  for (int v = 0; v < V.n_views; ++v)
+    any |= reinterpret_cast<const uint32_t*>(proj + size_t(v) * L.stride + L.tt)[g] > 0u;
+  if (!any) return;
+
+  const float mx = means[3 * g + 0], my = means[3 * g + 1], mz = means[3 * g + 2];
+  const float s0 = expf(log_scales[3 * g + 0]);
+  const float s1 = expf(log_scales[3 * g + 1]);
+  const float s2 = expf(log_scales[3 * g + 2]);
+  const float4 q4 = reinterpret_cast<const float4*>(quats)[g];
+  const float qn2 = q4.x * q4.x + q4.y * q4.y + q4.z * q4.z + q4.w * q4.w;
+  const float qlen = sqrtf(qn2);
+  const float qinv = 1.0f / qlen;
+  const float qw = q4.x * qinv, qx = q4.y * qinv, qy = q4.z * qinv, qz = q4.w * qinv;
+  float Rq[9];
+  Rq[0] = 1.0f - 2.0f * (qy * qy + qz * qz);
+  Rq[1] = 2.0f * (qx * qy - qw * qz);
+  Rq[2] = 2.0f * (qx * qz + qw * qy);
+  Rq[3] = 2.0f * (qx * qy + qw * qz);
+  Rq[4] = 1.0f - 2.0f * (qx * qx + qz * qz);
+  Rq[5] = 2.0f * (qy * qz - qw * qx);
+  Rq[6] = 2.0f * (qx * qz - qw * qy);
+  Rq[7] = 2.0f * (qy * qz + qw * qx);
+  Rq[8] = 1.0f - 2.0f * (qx * qx + qy * qy);
+  const float sc[3] = {s0, s1, s2};
+  float M[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) M[3 * i + j] = Rq[3 * i + j] * sc[j];
+  float Sg[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      Sg[3 * i + j] = M[3 * i] * M[3 * j] + M[3 * i + 1] * M[3 * j + 1] + M[3 * i + 2] * M[3 * j + 2];
+  const float o = 1.0f / (1.0f + expf(-opacity_logits[g]));
+  const int K = (sh_degree + 1) * (sh_degree + 1);
+  const float* shg = sh + size_t(g) * GS_SH_COEFFS * 3;
+
+  float dm[3] = {0, 0, 0}, dS[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  float dop = 0.0f, m2abs = 0.0f;
+  float dshacc[GS_SH_COEFFS * 3];
+#pragma unroll
+  for (int k = 0; k < GS_SH_COEFFS * 3; ++k) dshacc[k] = 0.0f;
+
+  for (int v = 0; v < V.n_views; ++v) {
+    const char* base = proj + size_t(v) * L.stride;
+    const uint32_t tt = reinterpret_cast<const uint32_t*>(base + L.tt)[g];
+    if (tt == 0u) continue;
+    const uint32_t off = grad_off[size_t(v) * n + g];
+    if (int64_t(off) + tt > cap) continue;
+    float gr[kG] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const float* pg = pair_grad + size_t(off) * kG;
+    for (uint32_t k = 0; k < tt; ++k)
+#pragma unroll
+      for (int c = 0; c < kG; ++c) gr[c] += pg[size_t(k) * kG + c];
+    const uint32_t flags = reinterpret_cast<const uint32_t*>(base + L.flags)[g];
+    const DevView& cv = V.v[v];
+
+    // ---- recompute the projection of this view
+    const float xc = fmaf(cv.R[0], mx, fmaf(cv.R[1], my, fmaf(cv.R[2], mz, cv.t[0])));
+    const float yc = fmaf(cv.R[3], mx, fmaf(cv.R[4], my, fmaf(cv.R[5], mz, cv.t[1])));
+    const float zc = __fadd_rn(
+        __fadd_rn(__fadd_rn(__fmul_rn(cv.R[6], mx), __fmul_rn(cv.R[7], my)),
+                  __fmul_rn(cv.R[8], mz)),
+        cv.t[2]);
+    const float iz = 1.0f / zc, iz2 = iz * iz;
+    const float j00 = cv.fx * iz, j11 = cv.fy * iz;
+    const float j02 = -cv.fx * xc * iz2, j12 = -cv.fy * yc * iz2;
+    float Tm[6];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      Tm[k] = j00 * cv.R[k] + j02 * cv.R[6 + k];
+      Tm[3 + k] = j11 * cv.R[3 + k] + j12 * cv.R[6 + k];
+    }
+    float U[6];  // U = T Sigma
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        U[3 * a + j] = Tm[3 * a] * Sg[j] + Tm[3 * a + 1] * Sg[3 + j] + Tm[3 * a + 2] * Sg[6 + j];
+    const float c00 = U[0] * Tm[0] + U[1] * Tm[1] + U[2] * Tm[2] + kDilation;
+    const float c01 = U[0] * Tm[3] + U[1] * Tm[4] + U[2] * Tm[5];
+    const float c11 = U[3] * Tm[3] + U[4] * Tm[4] + U[5] * Tm[5] + kDilation;
+    const float idet = 1.0f / (c00 * c11 - c01 * c01);
+    const float ca = c11 * idet, cb = -c01 * idet, cc = c00 * idet;
+
+    // ---- conic -> Sigma': G' = -Q GQ Q with GQ = [[ga, gb/2], [gb/2, gc]]
+    const float ga = gr[2], gbh = 0.5f * gr[3], gc = gr[4];
+    const float X00 = ga * ca + gbh * cb, X01 = ga * cb + gbh * cc;
+    const float X10 = gbh * ca + gc * cb, X11 = gbh * cb + gc * cc;
+    const float G00 = -(ca * X00 + cb * X10);
+    const float G01 = -0.5f * ((ca * X01 + cb * X11) + (cb * X00 + cc * X10));
+    const float G11 = -(cb * X01 + cc * X11);
+    // Sigma' = T Sigma T^T: dSigma += T^T G' T ; dT = 2 G' U
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const float a0 = G00 * Tm[j] + G01 * Tm[3 + j];
+        const float a1 = G01 * Tm[j] + G11 * Tm[3 + j];
+        dS[3 * i + j] += Tm[i] * a0 + Tm[3 + i] * a1;
+      }
+    float dT[6];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      dT[j] = 2.0f * (G00 * U[j] + G01 * U[3 + j]);
+      dT[3 + j] = 2.0f * (G01 * U[j] + G11 * U[3 + j]);
+    }
+    // T = J W: dJ = dT W^T (only J00, J02, J11, J12 vary)
+    const float dJ00 = dT[0] * cv.R[0] + dT[1] * cv.R[1] + dT[2] * cv.R[2];
+    const float dJ02 = dT[0] * cv.R[6] + dT[1] * cv.R[7] + dT[2] * cv.R[8];
+    const float dJ11 = dT[3] * cv.R[3] + dT[4] * cv.R[4] + dT[5] * cv.R[5];
+    const float dJ12 = dT[3] * cv.R[6] + dT[4] * cv.R[7] + dT[5] * cv.R[8];
+    const float gmx = gr[0], gmy = gr[1];
+    const float iz3 = iz2 * iz;
+    const float gxc = gmx * cv.fx * iz - dJ02 * cv.fx * iz2;
+    const float gyc = gmy * cv.fy * iz - dJ12 * cv.fy * iz2;
+    const float gzc = -gmx * cv.fx * xc * iz2 - gmy * cv.fy * yc * iz2 - dJ00 * cv.fx * iz2 +
+                      dJ02 * 2.0f * cv.fx * xc * iz3 - dJ11 * cv.fy * iz2 +
+                      dJ12 * 2.0f * cv.fy * yc * iz3;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dm[k] += cv.R[k] * gxc + cv.R[3 + k] * gyc + cv.R[6 + k] * gzc;
+
+    // ---- colour
+    float dx = mx - cv.campos[0], dy = my - cv.campos[1], dz = mz - cv.campos[2];
+    const float dlen = sqrtf(dx * dx + dy * dy + dz * dz);
+    const float dn = 1.0f / dlen;
+    dx *= dn; dy *= dn; dz *= dn;
+    float Y[GS_SH_COEFFS];
+#pragma unroll
+    for (int k = 0; k < GS_SH_COEFFS; ++k) Y[k] = 0.0f;
+    sh_basis_b(dx, dy, dz, sh_degree, Y);
+    const float grgb[3] = {(flags & 1u) ? 0.0f : gr[6], (flags & 2u) ? 0.0f : gr[7],
+                           (flags & 4u) ? 0.0f : gr[8]};
+    float wk[GS_SH_COEFFS];
+#pragma unroll
+    for (int k = 0; k < GS_SH_COEFFS; ++k) {
+      wk[k] = 0.0f;
+      if (k < K) {
+        wk[k] = grgb[0] * shg[3 * k] + grgb[1] * shg[3 * k + 1] + grgb[2] * shg[3 * k + 2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dshacc[3 * k + c] += grgb[c] * Y[k];
+      }
+    }
+    float gdx, gdy, gdz;
+    sh_dir_grad(dx, dy, dz, sh_degree, wk, gdx, gdy, gdz);
+    const float dd = dx * gdx + dy * gdy + dz * gdz;
+    dm[0] += (gdx - dx * dd) * dn;
+    dm[1] += (gdy - dy * dd) * dn;
+    dm[2] += (gdz - dz * dd) * dn;
+
+    dop += gr[5];
+    m2abs += sqrtf(gmx * gmx + gmy * gmy);
+  }
+
+  // ---- Sigma = M M^T -> scales and rotation
+  float dMm[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      dMm[3 * i + j] = 2.0f * (dS[3 * i] * M[j] + dS[3 * i + 1] * M[3 + j] + dS[3 * i + 2] * M[6 + j]);
+  float dls[3], dR[9];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    dls[j] = (dMm[j] * Rq[j] + dMm[3 + j] * Rq[3 + j] + dMm[6 + j] * Rq[6 + j]) * sc[j];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) dR[3 * i + j] = dMm[3 * i + j] * sc[j];
+  }
+  const float gw = -2.0f * qz * dR[1] + 2.0f * qy * dR[2] + 2.0f * qz * dR[3] -
+                   2.0f * qx * dR[5] - 2.0f * qy * dR[6] + 2.0f * qx * dR[7];
+  const float gx = 2.0f * qy * dR[1] + 2.0f * qz * dR[2] + 2.0f * qy * dR[3] - 4.0f * qx * dR[4] -
+                   2.0f * qw * dR[5] + 2.0f * qz * dR[6] + 2.0f * qw * dR[7] - 4.0f * qx * dR[8];
+  const float gy = -4.0f * qy * dR[0] + 2.0f * qx * dR[1] + 2.0f * qw * dR[2] +
+                   2.0f * qx * dR[3] + 2.0f * qz * dR[5] - 2.0f * qw * dR[6] +
+                   2.0f * qz * dR[7] - 4.0f * qy * dR[8];
+  const float gz = -4.0f * qz * dR[0] - 2.0f * qw * dR[1] + 2.0f * qx * dR[2] +
+                   2.0f * qw * dR[3] - 4.0f * qz * dR[4] + 2.0f * qy * dR[5] +
+                   2.0f * qx * dR[6] + 2.0f * qy * dR[7];
+  const float qd = qw * gw + qx * gx + qy * gy + qz * gz;
+  float4 dq4 = reinterpret_cast<float4*>(d_quats)[g];
+  dq4.x += (gw - qw * qd) * qinv;
+  dq4.y += (gx - qx * qd) * qinv;
+  dq4.z += (gy - qy * qd) * qinv;
+  dq4.w += (gz - qz * qd) * qinv;
+  reinterpret_cast<float4*>(d_quats)[g] = dq4;
+
+  d_means[3 * g + 0] += dm[0];
+  d_means[3 * g + 1] += dm[1];
+  d_means[3 * g + 2] += dm[2];
+  d_log_scales[3 * g + 0] += dls[0];
+  d_log_scales[3 * g + 1] += dls[1];
+  d_log_scales[3 * g + 2] += dls[2];
+  d_opacity_logits[g] += dop * o * (1.0f - o);
+  float* dshg = d_sh + size_t(g) * GS_SH_COEFFS * 3;
+#pragma unroll
+  for (int k = 0; k < GS_SH_COEFFS * 3; ++k)
+    if (k < 3 * K) dshg[k] += dshacc[k];
+  if (d_mean2d_abs) d_mean2d_abs[g] += m2abs;
+}
+
+struct TTSrc {  // tiles touched of item (view, Gaussian), index order
+  const char* proj;
+  size_t stride, tt_off;
+  int n;
+  __device__ uint32_t operator()(int64_t i) const {
+    const int64_t v = i / n, g = i - v * n;
+    return reinterpret_cast<const uint32_t*>(proj + v * stride + tt_off)[g];
+  }
+};
+struct GoffDst {
+  uint32_t* off;
+  __device__ void operator()(int64_t i, uint32_t pos, uint32_t) const { off[i] = pos; }
+};
+
+__global__ __launch_bounds__(256) void k_zero_pairs(float* __restrict__ p,
+                                                    const int64_t* __restrict__ total,
+                                                    int64_t cap) {
+  const int64_t np = (*total < cap) ? *total : cap;
+  const int64_t m = np * kG;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < m;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = 0.0f;
+}
+
+struct BwdWs {
+  size_t goff, bsum, total, pairs, bytes;
+  BwdWs(int64_t M, int64_t cap) {
+    size_t o = 0;
+    auto take = [&](size_t b) { size_t r = o; o += align256(b); return r; };
+    goff = take(4 * M);
+    bsum = take(4 * scan_block_sums(M));
+    total = take(8);
+    pairs = take(size_t(cap) * kG * 4);
+    bytes = o;
+  }
+};
+
+template <int TILE>
+void launch_bwd_tile(int batch, dim3 grid, const RViews& RV, int n, const char* proj,
+                     size_t stride, const uint32_t* ranges, const uint32_t* vals,
+                     const float* final_T, const uint32_t* last_contrib, const float* dL,
+                     const uint32_t* goff, float* pairs, int64_t cap, const float* bg,
+                     hipStream_t st) {
+  const dim3 block(TileShape<TILE>::kThreads);
+#define GS_BWD_LAUNCH(B)                                                                       \
+  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_blend_bwd<TILE, B>), grid, block, 0, st, RV, n, proj,   \
+                     stride, ranges, vals, final_T, last_contrib, dL, goff, pairs, cap, bg[0], \
+                     bg[1], bg[2])
+  switch (batch) {
+    case 128: GS_BWD_LAUNCH(128); break;
+    case 256: GS_BWD_LAUNCH(256); break;
+    default: GS_BWD_LAUNCH(512); break;
+  }
+#undef GS_BWD_LAUNCH
+}
+
+}  // namespace
+
+size_t render_bwd_ws_bytes(int n_views, int n, int64_t cap) {
+  return BwdWs(int64_t(n_views) * n, cap).bytes;
+}
+
+hipError_t launch_render_bwd(const Views& V, int n, const gs_raster_cfg& cfg,
+                             const float* means, const float* log_scales, const float* quats,
+                             const float* opacity_logits, const float* sh, int sh_degree,
+                             const char* proj, const uint32_t* ranges, const uint32_t* vals,
+                             const float* final_T, const uint32_t* last_contrib,
+                             const float* dL_dimage, float* d_means, float* d_log_scales,
+                             float* d_quats, float* d_opacity_logits, float* d_sh,
+                             float* d_mean2d_abs, int64_t cap, void* ws_, hipStream_t st) {
+  const int64_t M = int64_t(V.n_views) * n;
+  if (M == 0) return hipSuccess;
+  const BwdWs B(M, cap);
+  char* ws = static_cast<char*>(ws_);
+  uint32_t* goff = reinterpret_cast<uint32_t*>(ws + B.goff);
+  int64_t* total = reinterpret_cast<int64_t*>(ws + B.total);
+  float* pairs = reinterpret_cast<float*>(ws + B.pairs);
+  const ProjLayout L(n);
+  hipError_t e = scan_exclusive(TTSrc{proj, L.stride, L.tt, n}, GoffDst{goff}, Count{nullptr, M},
+                                M, reinterpret_cast<uint32_t*>(ws + B.bsum), total, nullptr, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_zero_pairs, dim3(2048), dim3(256), 0, st, pairs, total, cap);
+  if (V.total_tiles > 0) {
+    const RViews RV = make_rviews(V);
+    const dim3 grid(unsigned(V.total_tiles));
+    switch (cfg.tile) {
+      case 8:
+        launch_bwd_tile<8>(cfg.lds_batch, grid, RV, n, proj, L.stride, ranges, vals, final_T,
+                           last_contrib, dL_dimage, goff, pairs, cap, cfg.bg, st);
+        break;
+      case 16:
+        launch_bwd_tile<16>(cfg.lds_batch, grid, RV, n, proj, L.stride, ranges, vals, final_T,
+                            last_contrib, dL_dimage, goff, pairs, cap, cfg.bg, st);
+        break;
+      default:
+        launch_bwd_tile<32>(cfg.lds_batch, grid, RV, n, proj, L.stride, ranges, vals, final_T,
+                            last_contrib, dL_dimage, goff, pairs, cap, cfg.bg, st);
+        break;
+    }
+  }
+  hipLaunchKernelGGL(k_chain, dim3(unsigned((n + 127) / 128)), dim3(128), 0, st, V, n, sh_degree,
+                     means, log_scales, quats, opacity_logits, sh, proj, goff, pairs, cap,
+                     d_means, d_log_scales, d_quats, d_opacity_logits, d_sh, d_mean2d_abs);
+  return hipGetLastError();
+}
+
+}  // namespace gsk

@@ -1,0 +1,64 @@
+// Pieces shared by the forward and backward blend kernels.  The alpha of a
+// (pixel, Gaussian) evaluation is computed by ONE inline function so that the
+// backward replays exactly the forward's float32 decisions (cutoff, clamp,
+// early exit); the library is built without floating-point contraction and
+// every fused multiply-add here is explicit.
+#pragma once
+
+#include "gs_internal.hpp"
+
+namespace gsk {
+
+// Pixel layout inside a tile: one 64-lane wave owns an R x R square of the
+// tile (R = 8 for 8x8 and 16x16 tiles, 16 for 32x32 tiles); lane l sits at
+// (l % 8, l / 8) of every 8x8 sub-square, so a lane owns SUB x SUB pixels.
+template <int TILE>
+struct TileShape {
+  static constexpr int kThreads = (TILE == 8) ? 64 : 256;
+  static constexpr int kWaves = kThreads / 64;
+  static constexpr int kRegion = (TILE == 8) ? 8 : TILE / 2;
+  static constexpr int kSub = kRegion / 8;
+  static constexpr int kPix = kSub * kSub;
+};
+
+// alpha of Gaussian (r0 = (mx, my, A, B), C, o) at pixel centre (px, py).
+// Returns false when the Gaussian is skipped at this pixel.
+__device__ __forceinline__ bool eval_alpha(const float4 r0, const float C, const float o,
+                                           const float px, const float py, float& alpha,
+                                           float& G, float& dx, float& dy) {
+  dx = px - r0.x;
+  dy = py - r0.y;
+  const float t0 = r0.w * dy;
+  const float t1 = fmaf(r0.z, dx, t0);
+  const float t2 = C * dy;
+  const float t3 = t2 * dy;
+  const float p2 = fmaf(dx, t1, t3);
+  if (p2 > 0.0f) return false;
+  G = __builtin_amdgcn_exp2f(p2);
+  const float raw = o * G;
+  alpha = fminf(kAlphaMax, raw);
+  return alpha >= kAlphaMin;
+}
+
+// global tile id -> view (views are few; the loop runs on the scalar unit)
+__device__ __forceinline__ int view_of_tile(const RViews& RV, int t) {
+  int v = 0;
+  for (int k = 1; k < RV.n_views; ++k) v = (RV.tile_base[k] <= t) ? k : v;
+  return v;
+}
+
+// The record's mean is relative to the origin of the footprint's first tile;
+// move it to the frame of tile (tx, ty) so pixel offsets stay small numbers.
+template <int TILE>
+__device__ __forceinline__ float4 to_tile_frame(float4 r0, uint32_t lo, int tx, int ty) {
+  r0.x += float((box_x(lo) / TILE - tx) * TILE);
+  r0.y += float((box_y(lo) / TILE - ty) * TILE);
+  return r0;
+}
+
+__device__ __forceinline__ bool box_overlaps(uint32_t lo, uint32_t hi, int x0, int y0, int x1,
+                                             int y1) {
+  return box_x(lo) <= x1 && box_x(hi) >= x0 && box_y(lo) <= y1 && box_y(hi) >= y0;
+}
+
+}  // namespace gsk

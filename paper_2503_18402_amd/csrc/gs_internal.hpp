@@ -1,0 +1,133 @@
+// Internal definitions shared by the HIP kernels of the rasterizer library.
+// Everything here is device-side layout and constants; the public C ABI is
+// include/gs.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "gs.h"
+
+namespace gsk {
+
+// ----------------------------------------------------------------- constants
+// Rasterizer conventions (the paper's Eq. 1 plus its backbones' cutoffs).
+constexpr float kAlphaMin = 1.0f / 255.0f;  // skip a Gaussian below this alpha
+constexpr float kAlphaMax = 0.99f;          // alpha clamp
+constexpr float kTMin = 1.0e-4f;            // stop a pixel before T drops below this
+constexpr float kDilation = 0.3f;           // screen-space low-pass added to Sigma'
+constexpr float kLog2e = 1.44269504088896340736f;
+constexpr float kExtRel = 1.0e-3f;          // widening of the footprint box (relative)
+constexpr float kExtAbs = 1.0e-2f;          // and (pixels)
+
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------ view table
+// One entry per view, passed by value in kernel arguments (<= GS_MAX_VIEWS).
+struct DevView {
+  float R[9];
+  float t[3];
+  float campos[3];  // -R^T t, the camera centre in world space
+  float fx, fy, cx, cy, near_plane;
+  int32_t W, H, gw, gh;
+  int32_t tile_base;   // global id of this view's first tile
+  int32_t pad;
+  int64_t pix_base;    // first pixel of this view in concatenated per-pixel arrays
+};
+
+struct Views {
+  DevView v[GS_MAX_VIEWS];
+  int32_t n_views;
+  int32_t tile;
+  int32_t total_tiles;
+  int32_t pad;
+};
+
+// ----------------------------------------------------- projected records
+// Per view, for each Gaussian g (all FP32 unless noted):
+//   rec[3g+0] = (mx, my, A, B)       screen mean relative to the pixel origin of the
+//                                     first tile of the footprint box (tile size of the
+//                                     call); A = -a/2 log2e, B = -b log2e
+//   rec[3g+1] = (C, o, r, g)         C = -c/2 log2e; opacity; colour r, g
+//   rec[3g+2] = (b, depth, lo, hi)   colour b; z_f32; pixel box as two u32
+//                                     (x | y << 16) of its inclusive corners
+//   tt[g]     u32 tiles touched (0: culled or off-screen)
+//   flags[g]  u32 bit c: colour channel c was clamped at 0
+// so that the exponent of G2D in base 2 is p2 = A dx^2 + B dx dy + C dy^2.
+
+// Compact per-view raster info for the blend kernels.
+struct RViews {
+  int32_t W[GS_MAX_VIEWS], H[GS_MAX_VIEWS], gw[GS_MAX_VIEWS], tile_base[GS_MAX_VIEWS];
+  int64_t pix_base[GS_MAX_VIEWS];
+  int32_t n_views;
+  int32_t total_tiles;
+};
+
+inline RViews make_rviews(const Views& V) {
+  RViews r{};
+  for (int k = 0; k < V.n_views; ++k) {
+    r.W[k] = V.v[k].W;
+    r.H[k] = V.v[k].H;
+    r.gw[k] = V.v[k].gw;
+    r.tile_base[k] = V.v[k].tile_base;
+    r.pix_base[k] = V.v[k].pix_base;
+  }
+  r.n_views = V.n_views;
+  r.total_tiles = V.total_tiles;
+  return r;
+}
+
+__host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct ProjLayout {
+  size_t rec, tt, flags, stride;
+  __host__ __device__ ProjLayout(int n) {
+    rec = 0;
+    tt = align256(size_t(n) * 48);
+    flags = tt + align256(size_t(n) * 4);
+    stride = flags + align256(size_t(n) * 4);
+  }
+};
+
+__device__ inline uint32_t box_pack(int x, int y) { return uint32_t(x) | (uint32_t(y) << 16); }
+__device__ inline int box_x(uint32_t b) { return int(b & 0xffffu); }
+__device__ inline int box_y(uint32_t b) { return int(b >> 16); }
+
+// ----------------------------------------------------------- launch helpers
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// host-side builders (abi.cpp)
+bool build_views(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg, Views* out);
+
+// kernels' host launchers (one per translation unit)
+hipError_t launch_preprocess(const Views& V, int n, int sh_degree, const float* means,
+                             const float* log_scales, const float* quats,
+                             const float* opacity_logits, const float* sh, char* proj,
+                             hipStream_t st);
+
+size_t bin_sort_ws_bytes(int n_views, int n, int64_t cap);
+hipError_t launch_bin_sort(const Views& V, int n, const char* proj, int64_t cap, void* ws,
+                           uint64_t* keys, uint32_t* vals, uint32_t* ranges,
+                           int64_t* n_pairs_dev, hipStream_t st);
+
+hipError_t launch_render_fwd(const Views& V, int n, const gs_raster_cfg& cfg, const char* proj,
+                             const uint32_t* ranges, const uint32_t* vals, float* image,
+                             float* final_T, uint32_t* last_contrib, hipStream_t st);
+
+size_t render_bwd_ws_bytes(int n_views, int n, int64_t cap);
+hipError_t launch_render_bwd(const Views& V, int n, const gs_raster_cfg& cfg,
+                             const float* means, const float* log_scales, const float* quats,
+                             const float* opacity_logits, const float* sh, int sh_degree,
+                             const char* proj, const uint32_t* ranges, const uint32_t* vals,
+                             const float* final_T, const uint32_t* last_contrib,
+                             const float* dL_dimage, float* d_means, float* d_log_scales,
+                             float* d_quats, float* d_opacity_logits, float* d_sh,
+                             float* d_mean2d_abs, int64_t cap, void* ws, hipStream_t st);
+
+hipError_t launch_adam(const gs_adam_group* groups, int n_groups, int step, float beta1,
+                       float beta2, float eps, hipStream_t st);
+hipError_t launch_l1(int64_t numel, const float* image, const float* target, float scale,
+                     float* dL, float* loss_sum, hipStream_t st);
+
+}  // namespace gsk

@@ -1,0 +1,202 @@
+// Preprocess: splat every 3D Gaussian into every view (Sec. 3: G_i -> G2D_i)
+// and evaluate its view-dependent colour.  One thread per Gaussian; the
+// parameters (59 floats) are read once and the views are looped in registers,
+// so batched views cost one parameter read.  HBM-bound: 236 B in per Gaussian,
+// 56 B out per Gaussian and view.
+#include "gs_internal.hpp"
+
+namespace gsk {
+namespace {
+
+// Real SH basis with the Condon-Shortley sign kept, k = l*l + l + m.
+constexpr float SH0 = 0.28209479177387814f;   // 1/(2 sqrt(pi))
+constexpr float SH1 = 0.48860251190291992f;   // sqrt(3/(4 pi))
+constexpr float SH2a = 1.0925484305920792f;   // sqrt(15/pi)/2
+constexpr float SH2b = 0.31539156525252005f;  // sqrt(5/pi)/4
+constexpr float SH2c = 0.54627421529603959f;  // sqrt(15/pi)/4
+constexpr float SH3a = 0.59004358992664352f;  // sqrt(35/(2 pi))/4
+constexpr float SH3b = 2.8906114426405538f;   // sqrt(105/pi)/2
+constexpr float SH3c = 0.45704579946446572f;  // sqrt(21/(2 pi))/4
+constexpr float SH3d = 0.37317633259011540f;  // sqrt(7/pi)/4
+constexpr float SH3e = 1.4453057213202769f;   // sqrt(105/pi)/4
+
+__device__ inline void sh_basis(float x, float y, float z, int deg, float* Y) {
+  Y[0] = SH0;
+  if (deg < 1) return;
+  Y[1] = -SH1 * y;
+  Y[2] = SH1 * z;
+  Y[3] = -SH1 * x;
+  if (deg < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = SH2a * (x * y);
+  Y[5] = -SH2a * (y * z);
+  Y[6] = SH2b * (2.0f * zz - xx - yy);
+  Y[7] = -SH2a * (x * z);
+  Y[8] = SH2c * (xx - yy);
+  if (deg < 3) return;
+  Y[9] = -SH3a * y * (3.0f * xx - yy);
+  Y[10] = SH3b * (x * y) * z;
+  Y[11] = -SH3c * y * (4.0f * zz - xx - yy);
+  Y[12] = SH3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+  Y[13] = -SH3c * x * (4.0f * zz - xx - yy);
+  Y[14] = SH3e * z * (xx - yy);
+  Y[15] = -SH3a * x * (xx - 3.0f * yy);
+}
+
+__global__ __launch_bounds__(256) void k_preprocess(
+    Views V, int n, int sh_degree, const float* __restrict__ means,
+    const float* __restrict__ log_scales, const float* __restrict__ quats,
+    const float* __restrict__ opacity_logits, const float* __restrict__ sh,
+    char* __restrict__ proj) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const ProjLayout L(n);
+
+  const float mx = means[3 * g + 0], my = means[3 * g + 1], mz = means[3 * g + 2];
+  const float s0 = expf(log_scales[3 * g + 0]);
+  const float s1 = expf(log_scales[3 * g + 1]);
+  const float s2 = expf(log_scales[3 * g + 2]);
+  const float4 q4 = reinterpret_cast<const float4*>(quats)[g];
+  const float qinv = 1.0f / sqrtf(q4.x * q4.x + q4.y * q4.y + q4.z * q4.z + q4.w * q4.w);
+  const float qw = q4.x * qinv, qx = q4.y * qinv, qy = q4.z * qinv, qz = q4.w * qinv;
+  // rotation of the unit quaternion, times the scales (M = R diag(s))
+  const float m00 = (1.0f - 2.0f * (qy * qy + qz * qz)) * s0;
+  const float m01 = (2.0f * (qx * qy - qw * qz)) * s1;
+  const float m02 = (2.0f * (qx * qz + qw * qy)) * s2;
+  const float m10 = (2.0f * (qx * qy + qw * qz)) * s0;
+  const float m11 = (1.0f - 2.0f * (qx * qx + qz * qz)) * s1;
+  const float m12 = (2.0f * (qy * qz - qw * qx)) * s2;
+  const float m20 = (2.0f * (qx * qz - qw * qy)) * s0;
+  const float m21 = (2.0f * (qy * qz + qw * qx)) * s1;
+  const float m22 = (1.0f - 2.0f * (qx * qx + qy * qy)) * s2;
+  // Sigma = M M^T (symmetric)
+  const float S00 = m00 * m00 + m01 * m01 + m02 * m02;
+  const float S01 = m00 * m10 + m01 * m11 + m02 * m12;
+  const float S02 = m00 * m20 + m01 * m21 + m02 * m22;
+  const float S11 = m10 * m10 + m11 * m11 + m12 * m12;
+  const float S12 = m10 * m20 + m11 * m21 + m12 * m22;
+  const float S22 = m20 * m20 + m21 * m21 + m22 * m22;
+
+  const float o = 1.0f / (1.0f + expf(-opacity_logits[g]));
+  const bool opaque = o >= kAlphaMin;
+  const float k2 = fmaxf(0.0f, 2.0f * logf(255.0f * o));
+
+  const int K = (sh_degree + 1) * (sh_degree + 1);
+  float shc[GS_SH_COEFFS * 3];
+  const float* shg = sh + size_t(g) * GS_SH_COEFFS * 3;
+#pragma unroll
+  for (int k = 0; k < GS_SH_COEFFS * 3; ++k) shc[k] = (k < 3 * K) ? shg[k] : 0.0f;
+
+  for (int v = 0; v < V.n_views; ++v) {
+    const DevView& cv = V.v[v];
+    char* base = proj + size_t(v) * L.stride;
+    float4* rec = reinterpret_cast<float4*>(base + L.rec) + 3 * size_t(g);
+    uint32_t* tt = reinterpret_cast<uint32_t*>(base + L.tt);
+    uint32_t* fl = reinterpret_cast<uint32_t*>(base + L.flags);
+
+    // depth: the exact float32 sequence that defines the sort key
+    const float depth = __fadd_rn(
+        __fadd_rn(__fadd_rn(__fmul_rn(cv.R[6], mx), __fmul_rn(cv.R[7], my)),
+                  __fmul_rn(cv.R[8], mz)),
+        cv.t[2]);
+    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+    uint32_t count = 0, flags = 0;
+    if (opaque && depth > cv.near_plane) {
+      const float xc = fmaf(cv.R[0], mx, fmaf(cv.R[1], my, fmaf(cv.R[2], mz, cv.t[0])));
+      const float yc = fmaf(cv.R[3], mx, fmaf(cv.R[4], my, fmaf(cv.R[5], mz, cv.t[1])));
+      const float iz = 1.0f / depth;
+      const float j00 = cv.fx * iz, j11 = cv.fy * iz;
+      const float j02 = -cv.fx * xc * iz * iz, j12 = -cv.fy * yc * iz * iz;
+      // T = J W (2x3)
+      const float t00 = j00 * cv.R[0] + j02 * cv.R[6];
+      const float t01 = j00 * cv.R[1] + j02 * cv.R[7];
+      const float t02 = j00 * cv.R[2] + j02 * cv.R[8];
+      const float t10 = j11 * cv.R[3] + j12 * cv.R[6];
+      const float t11 = j11 * cv.R[4] + j12 * cv.R[7];
+      const float t12 = j11 * cv.R[5] + j12 * cv.R[8];
+      // U = T Sigma, Sigma' = U T^T + dilation
+      const float u00 = t00 * S00 + t01 * S01 + t02 * S02;
+      const float u01 = t00 * S01 + t01 * S11 + t02 * S12;
+      const float u02 = t00 * S02 + t01 * S12 + t02 * S22;
+      const float u10 = t10 * S00 + t11 * S01 + t12 * S02;
+      const float u11 = t10 * S01 + t11 * S11 + t12 * S12;
+      const float u12 = t10 * S02 + t11 * S12 + t12 * S22;
+      const float c00 = u00 * t00 + u01 * t01 + u02 * t02 + kDilation;
+      const float c01 = u00 * t10 + u01 * t11 + u02 * t12;
+      const float c11 = u10 * t10 + u11 * t11 + u12 * t12 + kDilation;
+      const float det = c00 * c11 - c01 * c01;
+      if (det > 0.0f) {
+        const float idet = 1.0f / det;
+        const float ca = c11 * idet, cb = -c01 * idet, cc = c00 * idet;
+        // screen mean in double: float32 spacing at 1000+ px (6e-5 px) would otherwise
+        // dominate the error of every pixel offset near the Gaussian
+        const double xd = double(cv.R[0]) * mx + double(cv.R[1]) * my + double(cv.R[2]) * mz +
+                          double(cv.t[0]);
+        const double yd = double(cv.R[3]) * mx + double(cv.R[4]) * my + double(cv.R[5]) * mz +
+                          double(cv.t[1]);
+        const double zd = double(cv.R[6]) * mx + double(cv.R[7]) * my + double(cv.R[8]) * mz +
+                          double(cv.t[2]);
+        const double mux = double(cv.fx) * xd / zd + double(cv.cx);
+        const double muy = double(cv.fy) * yd / zd + double(cv.cy);
+        // colour along the viewing direction
+        float dx = mx - cv.campos[0], dy = my - cv.campos[1], dz = mz - cv.campos[2];
+        const float dn = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+        dx *= dn; dy *= dn; dz *= dn;
+        float Y[GS_SH_COEFFS];
+#pragma unroll
+        for (int k = 0; k < GS_SH_COEFFS; ++k) Y[k] = 0.0f;
+        sh_basis(dx, dy, dz, sh_degree, Y);
+        float rgb[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          // coefficients above the degree are zero in shc and Y
+          float acc = 0.0f;
+#pragma unroll
+          for (int k = 0; k < GS_SH_COEFFS; ++k) acc = fmaf(Y[k], shc[3 * k + ch], acc);
+          acc += 0.5f;
+          if (acc < 0.0f) { flags |= 1u << ch; acc = 0.0f; }
+          rgb[ch] = acc;
+        }
+        // conservative footprint box of the alpha >= 1/255 ellipse
+        const double ex = double(sqrtf(k2 * c00) * (1.0f + kExtRel) + kExtAbs);
+        const double ey = double(sqrtf(k2 * c11) * (1.0f + kExtRel) + kExtAbs);
+        const double lox = (mux - ex) - 0.5, hix = (mux + ex) - 0.5;
+        const double loy = (muy - ey) - 0.5, hiy = (muy + ey) - 0.5;
+        const double Wd = double(cv.W), Hd = double(cv.H);
+        const int x0 = max(int(ceil(fmin(fmax(lox, -2.0), Wd + 2.0))), 0);
+        const int x1 = min(int(floor(fmin(fmax(hix, -2.0), Wd + 2.0))), cv.W - 1);
+        const int y0 = max(int(ceil(fmin(fmax(loy, -2.0), Hd + 2.0))), 0);
+        const int y1 = min(int(floor(fmin(fmax(hiy, -2.0), Hd + 2.0))), cv.H - 1);
+        const int T = V.tile;
+        if (x0 <= x1 && y0 <= y1) count = uint32_t((x1 / T - x0 / T + 1) * (y1 / T - y0 / T + 1));
+        // the mean is stored relative to the origin of the first tile of the footprint
+        const int ox = (x0 <= x1 ? x0 / T : 0) * T, oy = (y0 <= y1 ? y0 / T : 0) * T;
+        const float s = -0.5f * kLog2e;
+        r0 = make_float4(float(mux - double(ox)), float(muy - double(oy)), s * ca, -kLog2e * cb);
+        r1 = make_float4(s * cc, o, rgb[0], rgb[1]);
+        r2 = make_float4(rgb[2], depth, __uint_as_float(box_pack(x0 < 0 ? 0 : x0, y0 < 0 ? 0 : y0)),
+                         __uint_as_float(box_pack(x1 < 0 ? 0 : x1, y1 < 0 ? 0 : y1)));
+      }
+    }
+    rec[0] = r0;
+    rec[1] = r1;
+    rec[2] = r2;
+    tt[g] = count;
+    fl[g] = flags;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_preprocess(const Views& V, int n, int sh_degree, const float* means,
+                             const float* log_scales, const float* quats,
+                             const float* opacity_logits, const float* sh, char* proj,
+                             hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const int nb = (n + 255) / 256;
+  hipLaunchKernelGGL(k_preprocess, dim3(nb), dim3(256), 0, st, V, n, sh_degree, means,
+                     log_scales, quats, opacity_logits, sh, proj);
+  return hipGetLastError();
+}
+
+}  // namespace gsk

@@ -1,0 +1,202 @@
+"""Thin ctypes binding of ``include/gs.h``: same names, argument marshalling only.
+
+Every function here converts torch tensors to device pointers, calls the C
+entry point of ``libgsmi.so`` on the current HIP stream and raises
+``GsError`` on a non-OK status.  All arithmetic runs in the HIP kernels; if
+the library is missing this module raises instead of falling back.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_float, c_int32, c_int64, c_size_t, c_uint32, c_uint64, c_void_p
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgsmi.so")
+
+GS_MAX_VIEWS = 32
+GS_MAX_ADAM_GROUPS = 8
+STATUS = {0: "GS_OK", 1: "GS_ERR_ARG", 2: "GS_ERR_CAPACITY", 3: "GS_ERR_DEVICE",
+          4: "GS_ERR_UNSUPPORTED"}
+
+
+class GsError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        super().__init__(f"{fn} returned {STATUS.get(status, status)}")
+        self.status = status
+
+
+class GsCamera(ctypes.Structure):
+    _fields_ = [("R", c_float * 9), ("t", c_float * 3), ("fx", c_float), ("fy", c_float),
+                ("cx", c_float), ("cy", c_float), ("width", c_int32), ("height", c_int32),
+                ("near_plane", c_float)]
+
+
+class GsRasterCfg(ctypes.Structure):
+    _fields_ = [("tile", c_int32), ("lds_batch", c_int32), ("bg", c_float * 3)]
+
+
+class GsAdamGroup(ctypes.Structure):
+    _fields_ = [("p", c_void_p), ("g", c_void_p), ("m", c_void_p), ("v", c_void_p),
+                ("numel", c_int64), ("lr", c_float)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libgsmi.so (built by ``__graft_entry__.build()``); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first "
+                               "(python -m paper_2503_18402_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, sz = c_void_p, c_int32, c_int64, c_size_t
+        cam_p, cfg_p = POINTER(GsCamera), POINTER(GsRasterCfg)
+        sig = {
+            "gs_version": (i32, []),
+            "gs_status_str": (ctypes.c_char_p, [i32]),
+            "gs_proj_bytes": (sz, [i32, i32]),
+            "gs_total_tiles": (i64, [i32, cam_p, cfg_p]),
+            "gs_preprocess": (i32, [i32, cam_p, cfg_p, i32, vp, vp, vp, vp, vp, i32, vp, vp]),
+            "gs_bin_sort_workspace_bytes": (sz, [i32, i32, i64]),
+            "gs_bin_sort": (i32, [i32, cam_p, cfg_p, i32, vp, i64, vp, sz, vp, vp, vp, vp, vp]),
+            "gs_render_fwd": (i32, [i32, cam_p, cfg_p, i32, vp, vp, vp, vp, vp, vp, vp]),
+            "gs_render_bwd_workspace_bytes": (sz, [i32, i32, i64]),
+            "gs_render_bwd": (i32, [i32, cam_p, cfg_p, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp,
+                                    vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp, sz, vp]),
+            "gs_adam_step": (i32, [POINTER(GsAdamGroup), i32, i32, c_float, c_float, c_float, vp]),
+            "gs_l1_loss_grad": (i32, [i64, vp, vp, c_float, vp, vp, vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def is_available() -> bool:
+    return os.path.exists(LIB_PATH)
+
+
+# ----------------------------------------------------------------- helpers
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return c_void_p(stream.cuda_stream)
+
+
+def _check(fn: str, status: int):
+    if status != 0:
+        raise GsError(fn, status)
+
+
+def make_cameras(cams) -> ctypes.Array:
+    """Camera objects (attributes R, t, fx, fy, cx, cy, width, height, near) -> C array."""
+    arr = (GsCamera * len(cams))()
+    for k, c in enumerate(cams):
+        R = [float(x) for x in (c.R.reshape(-1) if hasattr(c.R, "reshape") else c.R)]
+        t = [float(x) for x in (c.t.reshape(-1) if hasattr(c.t, "reshape") else c.t)]
+        arr[k].R[:] = R
+        arr[k].t[:] = t
+        arr[k].fx, arr[k].fy, arr[k].cx, arr[k].cy = float(c.fx), float(c.fy), float(c.cx), float(c.cy)
+        arr[k].width, arr[k].height = int(c.width), int(c.height)
+        arr[k].near_plane = float(getattr(c, "near", 0.2))
+    return arr
+
+
+def make_cfg(tile: int = 16, lds_batch: int = 256, bg=(0.0, 0.0, 0.0)) -> GsRasterCfg:
+    c = GsRasterCfg()
+    c.tile, c.lds_batch = int(tile), int(lds_batch)
+    c.bg[:] = [float(x) for x in bg]
+    return c
+
+
+# ------------------------------------------------------ the C entry points
+
+def gs_version() -> int:
+    return int(lib().gs_version())
+
+
+def gs_status_str(status: int) -> str:
+    return lib().gs_status_str(int(status)).decode()
+
+
+def gs_proj_bytes(n_views: int, n: int) -> int:
+    return int(lib().gs_proj_bytes(n_views, n))
+
+
+def gs_total_tiles(cams_c, cfg) -> int:
+    return int(lib().gs_total_tiles(len(cams_c), cams_c, ctypes.byref(cfg)))
+
+
+def gs_preprocess(cams_c, cfg, n, means, log_scales, quats, opacity_logits, sh, sh_degree,
+                  proj, stream=None):
+    _check("gs_preprocess", lib().gs_preprocess(
+        len(cams_c), cams_c, ctypes.byref(cfg), int(n), _ptr(means), _ptr(log_scales),
+        _ptr(quats), _ptr(opacity_logits), _ptr(sh), int(sh_degree), _ptr(proj), _stream(stream)))
+
+
+def gs_bin_sort_workspace_bytes(n_views: int, n: int, capacity: int) -> int:
+    return int(lib().gs_bin_sort_workspace_bytes(n_views, n, capacity))
+
+
+def gs_bin_sort(cams_c, cfg, n, proj, capacity, ws, keys, vals, ranges, n_pairs_dev,
+                stream=None):
+    _check("gs_bin_sort", lib().gs_bin_sort(
+        len(cams_c), cams_c, ctypes.byref(cfg), int(n), _ptr(proj), int(capacity), _ptr(ws),
+        ws.numel() * ws.element_size(), _ptr(keys), _ptr(vals), _ptr(ranges), _ptr(n_pairs_dev),
+        _stream(stream)))
+
+
+def gs_render_fwd(cams_c, cfg, n, proj, ranges, vals, image, final_T, last_contrib,
+                  stream=None):
+    _check("gs_render_fwd", lib().gs_render_fwd(
+        len(cams_c), cams_c, ctypes.byref(cfg), int(n), _ptr(proj), _ptr(ranges), _ptr(vals),
+        _ptr(image), _ptr(final_T), _ptr(last_contrib), _stream(stream)))
+
+
+def gs_render_bwd_workspace_bytes(n_views: int, n: int, capacity: int) -> int:
+    return int(lib().gs_render_bwd_workspace_bytes(n_views, n, capacity))
+
+
+def gs_render_bwd(cams_c, cfg, n, means, log_scales, quats, opacity_logits, sh, sh_degree, proj,
+                  ranges, vals, final_T, last_contrib, dL_dimage, d_means, d_log_scales, d_quats,
+                  d_opacity_logits, d_sh, d_mean2d_abs, capacity, ws, stream=None):
+    _check("gs_render_bwd", lib().gs_render_bwd(
+        len(cams_c), cams_c, ctypes.byref(cfg), int(n), _ptr(means), _ptr(log_scales),
+        _ptr(quats), _ptr(opacity_logits), _ptr(sh), int(sh_degree), _ptr(proj), _ptr(ranges),
+        _ptr(vals), _ptr(final_T), _ptr(last_contrib), _ptr(dL_dimage), _ptr(d_means),
+        _ptr(d_log_scales), _ptr(d_quats), _ptr(d_opacity_logits), _ptr(d_sh),
+        _ptr(d_mean2d_abs), int(capacity), _ptr(ws), ws.numel() * ws.element_size(),
+        _stream(stream)))
+
+
+def gs_adam_step(groups, step: int, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
+    """groups: list of (p, g, m, v, lr) float32 device tensors (same numel per group)."""
+    arr = (GsAdamGroup * len(groups))()
+    for k, (p, g, m, v, lr) in enumerate(groups):
+        arr[k].p, arr[k].g, arr[k].m, arr[k].v = _ptr(p), _ptr(g), _ptr(m), _ptr(v)
+        arr[k].numel = p.numel()
+        arr[k].lr = float(lr)
+    _check("gs_adam_step", lib().gs_adam_step(arr, len(groups), int(step), float(beta1),
+                                              float(beta2), float(eps), _stream(stream)))
+
+
+def gs_l1_loss_grad(image, target, scale, dL_dimage, loss_sum=None, stream=None):
+    _check("gs_l1_loss_grad", lib().gs_l1_loss_grad(
+        image.numel(), _ptr(image), _ptr(target), float(scale), _ptr(dL_dimage), _ptr(loss_sum),
+        _stream(stream)))

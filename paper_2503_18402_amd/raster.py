@@ -1,0 +1,164 @@
+"""Rasterizer front end over the C ABI: buffer management and autograd.
+
+``render`` runs preprocess -> bin_sort -> render_fwd for one or several views
+(several views go into ONE launch per kernel: the batched form) and returns a
+``Frame`` holding every device buffer the backward needs.  ``render_backward``
+runs gs_render_bwd on that frame.  ``RasterizeFn`` wraps both as a
+``torch.autograd.Function``.  Nothing here computes: it allocates, calls the
+library, and checks the one device-side overflow count.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import torch
+
+from . import gsmi
+
+PARAM_NAMES = ("means", "log_scales", "quats", "opacity_logits", "sh")
+
+
+@dataclass
+class Frame:
+    cams_c: object
+    cfg: object
+    n: int
+    sh_degree: int
+    proj: torch.Tensor
+    vals: torch.Tensor
+    keys: torch.Tensor | None
+    ranges: torch.Tensor
+    n_pairs_dev: torch.Tensor
+    capacity: int
+    image: torch.Tensor          # [sum 3*H*W] concatenated per view
+    final_T: torch.Tensor
+    last_contrib: torch.Tensor
+    sizes: list = field(default_factory=list)   # (W, H) per view
+
+    def images(self):
+        """Per-view [3,H,W] views into the concatenated image."""
+        out, off = [], 0
+        for (W, H) in self.sizes:
+            out.append(self.image[off:off + 3 * W * H].view(3, H, W))
+            off += 3 * W * H
+        return out
+
+    def pixel_views(self, t):
+        out, off = [], 0
+        for (W, H) in self.sizes:
+            out.append(t[off:off + W * H].view(H, W))
+            off += W * H
+        return out
+
+
+def _aligned(t: torch.Tensor) -> torch.Tensor:
+    t = t.contiguous()
+    if t.data_ptr() % 16:
+        t = t.clone()
+    return t
+
+
+def default_capacity(n: int, n_views: int) -> int:
+    return max(1024, 8 * n * n_views)
+
+
+def render(params: dict, cams, tile: int = 16, lds_batch: int = 256, bg=(0.0, 0.0, 0.0),
+           sh_degree: int = 3, capacity: int | None = None, want_keys: bool = False,
+           check_capacity: bool = True, stream=None) -> Frame:
+    """Forward pass for the cameras ``cams`` (one launch per kernel for all views).
+
+    With ``check_capacity`` the pair count is read back once (one 8-byte copy)
+    and the sort is re-run with a larger buffer if it overflowed.
+    """
+    dev = params["means"].device
+    n = params["means"].shape[0]
+    cams_c = gsmi.make_cameras(cams)
+    cfg = gsmi.make_cfg(tile, lds_batch, bg)
+    nv = len(cams)
+    quats = _aligned(params["quats"])
+    proj = torch.empty(max(gsmi.gs_proj_bytes(nv, n), 16), dtype=torch.uint8, device=dev)
+    gsmi.gs_preprocess(cams_c, cfg, n, params["means"], params["log_scales"], quats,
+                       params["opacity_logits"], params["sh"], sh_degree, proj, stream)
+    cap = default_capacity(n, nv) if capacity is None else int(capacity)
+    total_tiles = gsmi.gs_total_tiles(cams_c, cfg)
+    ranges = torch.empty(2 * max(total_tiles, 1), dtype=torch.int32, device=dev)
+    n_pairs = torch.zeros(1, dtype=torch.int64, device=dev)
+    while True:
+        ws = torch.empty(max(gsmi.gs_bin_sort_workspace_bytes(nv, n, cap), 16), dtype=torch.uint8,
+                         device=dev)
+        vals = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        keys = torch.empty(max(cap, 1), dtype=torch.int64, device=dev) if want_keys else None
+        gsmi.gs_bin_sort(cams_c, cfg, n, proj, cap, ws, keys, vals, ranges, n_pairs, stream)
+        if not check_capacity:
+            break
+        np_ = int(n_pairs.item())
+        if np_ <= cap:
+            break
+        cap = int(np_ * 1.25) + 1024
+    del ws
+    npx = sum(int(c.width) * int(c.height) for c in cams)
+    image = torch.empty(3 * npx, dtype=torch.float32, device=dev)
+    final_T = torch.empty(npx, dtype=torch.float32, device=dev)
+    last = torch.empty(npx, dtype=torch.int32, device=dev)
+    gsmi.gs_render_fwd(cams_c, cfg, n, proj, ranges, vals, image, final_T, last, stream)
+    return Frame(cams_c=cams_c, cfg=cfg, n=n, sh_degree=sh_degree, proj=proj, vals=vals,
+                 keys=keys, ranges=ranges, n_pairs_dev=n_pairs, capacity=cap, image=image,
+                 final_T=final_T, last_contrib=last,
+                 sizes=[(int(c.width), int(c.height)) for c in cams])
+
+
+def zero_grads(params: dict) -> dict:
+    return {k: torch.zeros_like(params[k]) for k in PARAM_NAMES}
+
+
+def render_backward(params: dict, frame: Frame, dL_dimage: torch.Tensor, grads: dict | None = None,
+                    mean2d_abs: torch.Tensor | None = None, stream=None) -> dict:
+    """Accumulate the parameter gradients of L given dL/dimage (concatenated layout)."""
+    if grads is None:
+        grads = zero_grads(params)
+    n = frame.n
+    dev = params["means"].device
+    ws = torch.empty(max(gsmi.gs_render_bwd_workspace_bytes(len(frame.sizes), n, frame.capacity),
+                         16), dtype=torch.uint8, device=dev)
+    gsmi.gs_render_bwd(frame.cams_c, frame.cfg, n, params["means"], params["log_scales"],
+                       _aligned(params["quats"]), params["opacity_logits"], params["sh"],
+                       frame.sh_degree, frame.proj, frame.ranges, frame.vals, frame.final_T,
+                       frame.last_contrib, dL_dimage.contiguous(), grads["means"],
+                       grads["log_scales"], grads["quats"], grads["opacity_logits"], grads["sh"],
+                       mean2d_abs, frame.capacity, ws, stream)
+    return grads
+
+
+class RasterizeFn(torch.autograd.Function):
+    """image = RasterizeFn.apply(means, log_scales, quats, opacity_logits, sh, settings)
+
+    ``settings`` is a dict with ``cams`` and optionally tile, lds_batch, bg,
+    sh_degree.  The forward keeps only the frame buffers (projected records,
+    sorted pair values, ranges, final T and last contributor per pixel); the
+    backward recomputes each pixel's blend state from them.
+    """
+
+    @staticmethod
+    def forward(ctx, means, log_scales, quats, opacity_logits, sh, settings):
+        params = dict(means=means.detach().contiguous(), log_scales=log_scales.detach().contiguous(),
+                      quats=quats.detach().contiguous(),
+                      opacity_logits=opacity_logits.detach().contiguous(),
+                      sh=sh.detach().contiguous())
+        frame = render(params, settings["cams"], tile=settings.get("tile", 16),
+                       lds_batch=settings.get("lds_batch", 256),
+                       bg=settings.get("bg", (0.0, 0.0, 0.0)),
+                       sh_degree=settings.get("sh_degree", 3))
+        ctx.frame = frame
+        ctx.params = params
+        return frame.image.clone()
+
+    @staticmethod
+    def backward(ctx, dL_dimage):
+        g = render_backward(ctx.params, ctx.frame, dL_dimage.float())
+        return g["means"], g["log_scales"], g["quats"], g["opacity_logits"], g["sh"], None
+
+
+def to_device(scene: dict, device="cuda") -> dict:
+    """numpy scene -> contiguous float32 device tensors."""
+    return {k: torch.from_numpy(scene[k]).to(device=device, dtype=torch.float32).contiguous()
+            for k in PARAM_NAMES}

@@ -225,3 +225,19 @@ def test_clamped_alpha_has_zero_gradient():
     assert B["g2d"]["d_opacity"][0] == 0.0
     assert np.all(B["g2d"]["d_conic"][0] == 0.0)
     assert B["g2d"]["d_rgb"][0, 0] == pytest.approx(0.99)
+
+
+def test_error_scale_bounds_every_gradient():
+    # the absolute-value chain dominates the gradient it accompanies, element by element
+    sc = scenes.make_scene(6, seed=14, mean_range=0.3, ls_mu=-2.4, ls_sigma=0.3, rest_sigma=0.2)
+    cam = scenes.look_at((0.2, -0.1, -2.6), (0, 0, 0), 32, 28, 36.0)
+    P = project.project(sc, cam)
+    w = np.random.default_rng(6).uniform(-1, 1, size=(3, 28, 32))
+    B = render.render_bwd(sc, P, w, with_bound=True)
+    for k in ("d_means", "d_log_scales", "d_quats", "d_opacity_logits", "d_sh"):
+        assert np.all(B["bound"][k] >= np.abs(B[k]) * (1 - 1e-12))
+    # one Gaussian seen by one pixel: the 2D term magnitudes are the 2D gradients themselves
+    g = np.zeros((3, 28, 32))
+    g[0, 14, 16] = 1.0
+    B1 = render.render_bwd(sc, P, g)
+    assert np.allclose(B1["g2d"]["abs2d"][:, 6], np.abs(B1["g2d"]["d_rgb"][:, 0]))
