@@ -1,0 +1,299 @@
+"""Benchmark of the rasterizer hot path on one MI355X.
+
+A step is one full training iteration of the hot path on the paper-scale
+workload (1M Gaussians, one 1600x1064 view, FP32): preprocess, bin/sort,
+forward blend, L1 loss gradient, backward blend + chain rule, fused Adam.
+Inputs are resident in HBM before timing starts.  Prints ONE JSON line.
+
+Besides the headline (Mpix/s at full resolution) the line carries the
+per-level throughput at the schedule's downscale factors (8/4/2/1), the
+batched multi-resolution form vs 16 sequential plain calls (it/s), the
+roofline of the dominant kernel measured with HIP events on its stream, and
+the FP64 oracle timed on the host as a baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+# FP32 vector peak without packed-FP32 instructions (this build disables them):
+# 256 CUs x 64 lanes x 2 FLOP (FMA) x 2.4 GHz
+ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# algorithmic FLOPs per (pixel, Gaussian) evaluation of Eq. 1 in the forward:
+# offset (2), quadratic form (5 mul/fma = 8 FLOP), exp (1), o*G (1), clamp (1),
+# two cutoff tests (2), T(1-alpha) (2), alpha*T (1), colour (3 fma = 6)
+FWD_FLOP_PER_EVAL = 2 + 8 + 1 + 1 + 1 + 2 + 2 + 1 + 6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--lds-batch", type=int, default=256)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--cpu-pixels", type=int, default=16)
+    ap.add_argument("--no-extras", action="store_true", help="skip levels and batched form")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="only run warmup + this many steps (for rocprofv3), no extras")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (counter calibration)")
+    return ap.parse_args()
+
+
+def sha(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path shards by "
+              "views across GPUs but no multi-GPU run is part of this build.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2503_18402_amd import gsmi, raster, scenes
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    gsmi.lib()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    # ---------------------------------------------------------------- inputs
+    log("generating the 1M-Gaussian scene and target")
+    scene, cam = scenes.config1(level=1, n=args.n)
+    tscene = scenes.config1_target_scene(n=args.n)
+    params = raster.to_device(scene, dev)
+    tparams = raster.to_device(tscene, dev)
+    target = raster.render(tparams, [cam], tile=args.tile).image.clone()
+    del tparams
+    pipe = raster.Pipeline(params, [cam], target, tile=args.tile, lds_batch=args.lds_batch)
+    stream = torch.cuda.current_stream()
+    W, H = cam.width, cam.height
+
+    steps = args.profile_steps if args.profile_steps else args.steps
+    for _ in range(args.warmup):
+        pipe.step()
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps), timing {steps} steps")
+
+    # ------------------------------------------------------------ timed loop
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fwd_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        p = pipe.params
+        gsmi.gs_preprocess(pipe.cams_c, pipe.cfg, pipe.n, p["means"], p["log_scales"], p["quats"],
+                           p["opacity_logits"], p["sh"], pipe.sh_degree, pipe.proj)
+        gsmi.gs_bin_sort(pipe.cams_c, pipe.cfg, pipe.n, pipe.proj, pipe.capacity, pipe.sort_ws,
+                         None, pipe.vals, pipe.ranges, pipe.n_pairs)
+        fwd_ev[k][0].record(stream)
+        gsmi.gs_render_fwd(pipe.cams_c, pipe.cfg, pipe.n, pipe.proj, pipe.ranges, pipe.vals,
+                           pipe.image, pipe.final_T, pipe.last)
+        fwd_ev[k][1].record(stream)
+        pipe.backward()
+        pipe.adam()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1) / steps
+    assert not pipe.overflowed(), "pair capacity overflowed during timing"
+    fwd_ms = float(np.mean([a.elapsed_time(b) for a, b in fwd_ev]))
+    n_pairs = int(pipe.n_pairs.item())
+    mpix = W * H / (ms / 1e3) / 1e6
+    log(f"{ms:.3f} ms/step ({mpix:.1f} Mpix/s), forward blend {fwd_ms:.3f} ms, pairs {n_pairs}")
+
+    if args.copy_mib:
+        a = torch.empty(args.copy_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    if args.profile_steps:
+        print(json.dumps(dict(profile_only=True, ms_per_step=ms, pairs=n_pairs)))
+        return
+
+    # ------------------------------------------- forward-blend roofline (ALU)
+    # algorithmic evaluations: per pixel, the list entries up to and including its
+    # last blended Gaussian (a lower bound: the entries examined after it are not counted)
+    last = pipe.last.to(torch.int64)
+    fT = pipe.final_T
+    evals = int(last.sum().item())
+    flops = evals * FWD_FLOP_PER_EVAL
+    alu_achieved = flops / (fwd_ms / 1e3) / 1e12
+    prof = read_traffic("k_blend_fwd", ["paper_2503_18402_amd/csrc/blend_fwd.hip",
+                                        "paper_2503_18402_amd/csrc/blend_common.hpp"])
+    roofline = dict(kernel="k_blend_fwd", bound="alu", achieved=round(alu_achieved, 3),
+                    peak=round(ALU_PEAK_TFLOPS, 1), unit="TFLOP/s",
+                    frac=round(alu_achieved / ALU_PEAK_TFLOPS, 4),
+                    traffic=prof, evals=evals, flop_per_eval=FWD_FLOP_PER_EVAL,
+                    launch_ms=round(fwd_ms, 4),
+                    hbm_frac_algorithmic=round((40 * n_pairs + 20 * W * H) / (fwd_ms / 1e3)
+                                               / 1e9 / HBM_PEAK_GBS, 4))
+    del last, fT
+
+    extras = {}
+    if not args.no_extras:
+        extras["levels"] = level_sweep(torch, raster, scenes, params, tparams_scene=tscene,
+                                       tile=args.tile, lds=args.lds_batch)
+        extras["batched"] = batched_vs_plain(torch, raster, scenes, params, tscene)
+
+    cpu = None if args.no_cpu else cpu_baseline(scene, cam, args.cpu_pixels)
+
+    out = {
+        "metric": "fwd+bwd Mpix/s at 1M Gaussians 1600x1064; batched vs plain it/s at oracle tol",
+        "value": round(mpix, 2),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded 1M-Gaussian scene; target rendered from a second seeded scene)",
+        "config": {"workload": "1M Gaussians, one 1600x1064 view, full step: preprocess, "
+                               "bin/sort, blend fwd, L1, blend bwd + chain, Adam",
+                   "n_gaussians": args.n, "width": W, "height": H, "tile": args.tile,
+                   "lds_batch": args.lds_batch, "pairs": n_pairs, "wall_s": round(wall, 3)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    out.update(extras)
+    print(json.dumps(out))
+
+
+def read_traffic(kernel: str, sources):
+    """HBM bytes per launch of ``kernel`` from the committed counter summary, or
+    None when absent or taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_counters.md")
+    if not os.path.exists(path):
+        return None
+    want = sha(sources)
+    data = None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("traffic_json:"):
+                data = json.loads(line.split(":", 1)[1])
+    if not data or data.get("source_sha") != want:
+        return None
+    return data.get("bytes_per_launch")
+
+
+def time_pipe(torch, pipe, steps):
+    for _ in range(2):
+        pipe.step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        pipe.step()
+    e1.record()
+    torch.cuda.synchronize()
+    assert not pipe.overflowed()
+    return e0.elapsed_time(e1) / steps
+
+
+def level_sweep(torch, raster, scenes, params, tparams_scene, tile, lds):
+    out = {}
+    tparams = raster.to_device(tparams_scene, params["means"].device)
+    for r in (8, 4, 2, 1):
+        _, cam = scenes.config1(level=r, n=1)  # camera only
+        tgt = raster.render(tparams, [cam], tile=tile).image.clone()
+        p = {k: v.clone() for k, v in params.items()}
+        pipe = raster.Pipeline(p, [cam], tgt, tile=tile, lds_batch=lds)
+        ms = time_pipe(torch, pipe, 10)
+        out[f"r{r}"] = dict(width=cam.width, height=cam.height, ms_per_step=round(ms, 4),
+                            mpix_per_s=round(cam.width * cam.height / (ms / 1e3) / 1e6, 2))
+        log(f"level r={r}: {ms:.3f} ms/step")
+        del pipe, p
+    return out
+
+
+def batched_vs_plain(torch, raster, scenes, params, tscene):
+    """16 views at the four schedule resolutions: one batched step vs 16 plain steps."""
+    cams = scenes.config3_views()
+    tparams = raster.to_device(tscene, params["means"].device)
+    tgts = [raster.render(tparams, [c]).image.clone() for c in cams]
+    del tparams
+    p = {k: v.clone() for k, v in params.items()}
+    batched = raster.Pipeline(p, cams, torch.cat(tgts))
+    ms_b = time_pipe(torch, batched, 5)
+    del batched
+    plains = [raster.Pipeline(p, [c], t) for c, t in zip(cams, tgts)]
+    for pp in plains:
+        pp.step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3
+    e0.record()
+    for _ in range(reps):
+        for pp in plains:
+            pp.step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_p = e0.elapsed_time(e1) / reps
+    log(f"16 views: batched {ms_b:.3f} ms/it, plain {ms_p:.3f} ms/it")
+    return dict(views=16, batched_it_s=round(1e3 / ms_b, 2), plain_it_s=round(1e3 / ms_p, 2),
+                speedup=round(ms_p / ms_b, 3), pixels=sum(c.width * c.height for c in cams))
+
+
+def cpu_baseline(scene, cam, n_pix):
+    """The FP64 oracle on the host: projection and chain rule over all 1M
+    Gaussians timed whole, the per-pixel blend forward + backward timed on
+    ``n_pix`` random pixels and scaled to the full frame."""
+    from threadpoolctl import threadpool_limits
+    from oracle import project, render
+
+    rng = np.random.default_rng(0)
+    pix = rng.choice(cam.width * cam.height, n_pix, replace=False)
+    g = rng.uniform(-1.0, 1.0, size=(3, n_pix))
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        P = project.project(scene, cam)
+        t1 = time.perf_counter()
+        render.render_fwd(P, pixels=pix, chunk=4)
+        g2 = render.render_bwd_2d(P, g, pixels=pix, chunk=4)
+        t2 = time.perf_counter()
+        render.chain_to_3d(scene, P, g2)
+        t3 = time.perf_counter()
+    per_px = (t2 - t1) / n_pix
+    full = (t1 - t0) + (t3 - t2) + per_px * cam.width * cam.height
+    log(f"oracle: project {t1 - t0:.1f}s, {per_px:.3f} s/pixel, chain {t3 - t2:.1f}s")
+    return dict(value=round(cam.width * cam.height / full / 1e6, 8), unit="Mpix/s", cores=1,
+                kind="oracle",
+                sample=f"{n_pix} random pixels of the 1600x1064 view (1M Gaussians): projection "
+                       f"and chain rule over all Gaussians timed whole, per-pixel fwd+bwd "
+                       f"({per_px:.3f} s/pixel) scaled to {cam.width * cam.height} pixels",
+                seconds=round(t3 - t0, 2))
+
+
+if __name__ == "__main__":
+    main()

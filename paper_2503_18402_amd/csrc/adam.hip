@@ -129,7 +129,7 @@ hipError_t launch_l1(int64_t numel, const float* image, const float* target, flo
                      float* dL, float* loss_sum, hipStream_t st) {
   if (numel == 0) return hipSuccess;
   int64_t blocks = (numel + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
+  if (blocks > 1024) blocks = 1024;  // few blocks: one atomic each for the loss sum
   hipLaunchKernelGGL(k_l1, dim3(unsigned(blocks)), dim3(256), 0, st, numel, image, target, scale,
                      dL, loss_sum);
   return hipGetLastError();

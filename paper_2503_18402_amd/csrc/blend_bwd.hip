@@ -23,194 +23,186 @@ namespace {
 constexpr int kG = 9;  // 2D gradient components per (tile, Gaussian)
 constexpr float kLn2 = 0.69314718055994530942f;
 
-__device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+// ---- wave-wide sums of the nine gradient components, registers only.
+// Halving transposes: a 32-lane swap (v_permlane32_swap) pairs each value with
+// its partner half-wave, a 16-lane swap (v_permlane16_swap) pairs rows, and a
+// DPP prefix over each 16-lane row finishes.  Afterwards lane 16 r + 15 of
+// q[0] holds component kRow0[r], of q[1] component kRow1[r], of q[2] (rows 0, 1)
+// component 8.  About 30 VALU instructions for all nine sums, in a fixed order.
+template <int N>
+__device__ __forceinline__ float row_shr(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x110 + N, 0xF, 0xF,
+                                                    true));
+}
+__device__ __forceinline__ float row_sum16(float x) {
+  x += row_shr<1>(x);
+  x += row_shr<2>(x);
+  x += row_shr<4>(x);
+  x += row_shr<8>(x);
   return x;
+}
+__device__ __forceinline__ float swap32_add(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap16_add(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void wave_sum9(const float* v, float* q) {
+  const float r01 = swap32_add(v[0], v[1]);  // lanes 0-31: v0, 32-63: v1 (pair sums)
+  const float r23 = swap32_add(v[2], v[3]);
+  const float r45 = swap32_add(v[4], v[5]);
+  const float r67 = swap32_add(v[6], v[7]);
+  const float r8 = swap32_add(v[8], 0.0f);   // lanes 0-31: v8, 32-63: 0
+  q[0] = row_sum16(swap16_add(r01, r23));     // rows: v0, v2, v1, v3
+  q[1] = row_sum16(swap16_add(r45, r67));     // rows: v4, v6, v5, v7
+  q[2] = row_sum16(swap16_add(r8, r8));       // rows: v8, v8, 0, 0
 }
 
 template <int TILE, int BATCH>
-__global__ __launch_bounds__(TileShape<TILE>::kThreads) void k_blend_bwd(
+__global__ __launch_bounds__(64) void k_blend_bwd(
     RViews RV, int n, const char* __restrict__ proj, size_t stride,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const float* __restrict__ final_T, const uint32_t* __restrict__ last_contrib,
     const float* __restrict__ dL_dimage, const uint32_t* __restrict__ grad_off,
     float* __restrict__ pair_grad, int64_t cap, float bg0, float bg1, float bg2) {
-  using S = TileShape<TILE>;
-  constexpr int NT = S::kThreads, NW = S::kWaves, R = S::kRegion, SUB = S::kSub, P = S::kPix;
+  constexpr int GX = TileShape<TILE>::kGroupsX, Q = TileShape<TILE>::kGroups;
   __shared__ float4 s_r0[BATCH];
   __shared__ float4 s_r1[BATCH];
   __shared__ float s_b[BATCH];
   __shared__ uint32_t s_mask[BATCH];
   __shared__ uint32_t s_pidx[BATCH];
-  __shared__ uint16_t s_list[NW][BATCH];
-  __shared__ float s_acc[NW][kG][BATCH];
-  __shared__ uint32_t s_max;
 
   const int t = blockIdx.x;
   const int v = view_of_tile(RV, t);
   const int lt = t - RV.tile_base[v];
   const int gw = RV.gw[v], W = RV.W[v], H = RV.H[v];
   const int tx = lt % gw, ty = lt / gw;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wx = (NW == 1) ? 0 : (w & 1), wy = (NW == 1) ? 0 : (w >> 1);
-  const int rx0 = tx * TILE + wx * R, ry0 = ty * TILE + wy * R;
+  const int lane = threadIdx.x;
   const int lx = lane & 7, ly = lane >> 3;
-  const uint64_t ltmask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t pb = RV.pix_base[v];
   const int64_t plane = int64_t(W) * H;
 
-  if (tid == 0) s_max = 0;
-  float pxc[P], pyc[P], T[P], g0[P], g1[P], g2[P], SdL[P];
-  uint32_t last[P];
+  float T[Q], g0[Q], g1[Q], g2[Q], SdL[Q];
+  uint32_t last[Q];
+  uint32_t glast[Q];  // per group: the largest last contributor (wave-uniform)
   uint32_t mylast = 0;
 #pragma unroll
-  for (int j = 0; j < SUB; ++j)
-#pragma unroll
-    for (int i = 0; i < SUB; ++i) {
-      const int p = j * SUB + i;
-      const int x = rx0 + i * 8 + lx, y = ry0 + j * 8 + ly;
-      pxc[p] = float(x - tx * TILE) + 0.5f;  // pixel centre in the tile's frame
-      pyc[p] = float(y - ty * TILE) + 0.5f;
-      if (x < W && y < H) {
-        const int64_t o = int64_t(y) * W + x;
-        T[p] = final_T[pb + o];
-        last[p] = last_contrib[pb + o];
-        g0[p] = dL_dimage[3 * pb + o];
-        g1[p] = dL_dimage[3 * pb + plane + o];
-        g2[p] = dL_dimage[3 * pb + 2 * plane + o];
-      } else {
-        T[p] = 1.0f;
-        last[p] = 0;
-        g0[p] = g1[p] = g2[p] = 0.0f;
-      }
-      // colour behind the current Gaussian, dotted with dL/dC: starts at T_final * bg
-      SdL[p] = T[p] * fmaf(bg0, g0[p], fmaf(bg1, g1[p], bg2 * g2[p]));
-      mylast = max(mylast, last[p]);
+  for (int q = 0; q < Q; ++q) {
+    const int x = tx * TILE + (q % GX) * 8 + lx, y = ty * TILE + (q / GX) * 8 + ly;
+    if (x < W && y < H) {
+      const int64_t o = int64_t(y) * W + x;
+      T[q] = final_T[pb + o];
+      last[q] = last_contrib[pb + o];
+      g0[q] = dL_dimage[3 * pb + o];
+      g1[q] = dL_dimage[3 * pb + plane + o];
+      g2[q] = dL_dimage[3 * pb + 2 * plane + o];
+    } else {
+      T[q] = 1.0f;
+      last[q] = 0;
+      g0[q] = g1[q] = g2[q] = 0.0f;
     }
-  __syncthreads();
-  atomicMax(&s_max, mylast);
-  __syncthreads();
+    // colour behind the current Gaussian, dotted with dL/dC: starts at T_final * bg
+    SdL[q] = T[q] * fmaf(bg0, g0[q], fmaf(bg1, g1[q], bg2 * g2[q]));
+    uint32_t mx = last[q];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) mx = max(mx, uint32_t(__shfl_xor(int(mx), d, 64)));
+    glast[q] = __builtin_amdgcn_readfirstlane(mx);
+    mylast = max(mylast, glast[q]);
+  }
   const uint32_t start = ranges[2 * t];
-  const uint32_t stop = min(start + s_max, ranges[2 * t + 1]);
+  const uint32_t stop = min(start + mylast, ranges[2 * t + 1]);
   const float4* rec = reinterpret_cast<const float4*>(proj + size_t(v) * stride);
   const uint32_t* goff = grad_off + size_t(v) * n;
+  const float px0 = float(lx) + 0.5f, py0 = float(ly) + 0.5f;
 
   for (uint32_t bend = stop; bend > start;) {
     const uint32_t bstart = (bend - start > uint32_t(BATCH)) ? bend - BATCH : start;
     const int nb = int(bend - bstart);
-    for (int k = tid; k < BATCH; k += NT) {
-      uint32_t msk = 0;
-      if (k < nb) {
-        const uint32_t g = vals[bstart + k];
-        const float4 r0 = rec[3 * size_t(g)];
-        const float4 r1 = rec[3 * size_t(g) + 1];
-        const float4 r2 = rec[3 * size_t(g) + 2];
-        const uint32_t lo = __float_as_uint(r2.z), hi = __float_as_uint(r2.w);
-        s_r0[k] = to_tile_frame<TILE>(r0, lo, tx, ty);
-        s_r1[k] = r1;
-        s_b[k] = r2.x;
-#pragma unroll
-        for (int ww = 0; ww < NW; ++ww) {
-          const int x0 = tx * TILE + ((NW == 1) ? 0 : (ww & 1) * R);
-          const int y0 = ty * TILE + ((NW == 1) ? 0 : (ww >> 1) * R);
-          msk |= box_overlaps(lo, hi, x0, y0, x0 + R - 1, y0 + R - 1) ? (1u << ww) : 0u;
-        }
-        const int tx0 = box_x(lo) / TILE, ty0 = box_y(lo) / TILE, tx1 = box_x(hi) / TILE;
-        s_pidx[k] = goff[g] + uint32_t((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
-#pragma unroll
-        for (int ww = 0; ww < NW; ++ww)
-#pragma unroll
-          for (int c = 0; c < kG; ++c) s_acc[ww][c][k] = 0.0f;
-      }
-      s_mask[k] = msk;
+    __syncthreads();  // the previous batch is consumed
+    for (int k = lane; k < nb; k += 64) {
+      const uint32_t g = vals[bstart + k];
+      const float4 r0 = rec[3 * size_t(g)];
+      const float4 r1 = rec[3 * size_t(g) + 1];
+      const float4 r2 = rec[3 * size_t(g) + 2];
+      const uint32_t lo = __float_as_uint(r2.z), hi = __float_as_uint(r2.w);
+      s_r0[k] = to_tile_frame<TILE>(r0, lo, tx, ty);
+      s_r1[k] = r1;
+      s_b[k] = r2.x;
+      s_mask[k] = group_mask<TILE>(lo, hi, tx, ty);
+      const int tx0 = box_x(lo) / TILE, ty0 = box_y(lo) / TILE, tx1 = box_x(hi) / TILE;
+      s_pidx[k] = goff[g] + uint32_t((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
     }
     __syncthreads();
-    int cnt = 0;
-    for (int c = 0; c < nb; c += 64) {
-      const int k = c + lane;
-      const bool m = (k < nb) && ((s_mask[k] >> w) & 1u);
-      const uint64_t bal = __ballot(m);
-      if (m) s_list[w][cnt + __popcll(bal & ltmask)] = uint16_t(k);
-      cnt += __popcll(bal);
-    }
-    for (int q = cnt - 1; q >= 0; --q) {
-      const int k = s_list[w][q];
+    for (int k = nb - 1; k >= 0; --k) {
+      const uint32_t pos = bstart - start + uint32_t(k) + 1u;
+      uint32_t m = __builtin_amdgcn_readfirstlane(s_mask[k]);
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+        if (pos > glast[q]) m &= ~(1u << q);
+      if (m == 0u) continue;
       const float4 r0 = s_r0[k];
       const float4 r1 = s_r1[k];
       const float cb = s_b[k];
       const float o = r1.y;
-      const uint32_t pos = bstart - start + uint32_t(k) + 1u;
+      const float A2 = 2.0f * r0.z, C2 = 2.0f * r1.x;
       float acc[kG];
 #pragma unroll
       for (int c = 0; c < kG; ++c) acc[c] = 0.0f;
       bool hit = false;
 #pragma unroll
-      for (int p = 0; p < P; ++p) {
-        if (pos <= last[p]) {
-          float a, G, dx, dy;
-          if (eval_alpha(r0, r1.x, o, pxc[p], pyc[p], a, G, dx, dy)) {
-            hit = true;
-            const float inv = 1.0f / (1.0f - a);
-            const float Ti = T[p] * inv;
-            const float wgt = a * Ti;
-            const float cg = fmaf(r1.z, g0[p], fmaf(r1.w, g1[p], cb * g2[p]));
-            const float dLda = Ti * cg - SdL[p] * inv;
-            SdL[p] = fmaf(wgt, cg, SdL[p]);
-            T[p] = Ti;
-            acc[6] = fmaf(wgt, g0[p], acc[6]);
-            acc[7] = fmaf(wgt, g1[p], acc[7]);
-            acc[8] = fmaf(wgt, g2[p], acc[8]);
-            if (o * G <= kAlphaMax) {
-              acc[5] = fmaf(dLda, G, acc[5]);
-              const float dpow = dLda * o * G;
-              const float dpx = dpow * dx, dpy = dpow * dy;
-              acc[2] = fmaf(dpx, dx, acc[2]);
-              acc[3] = fmaf(dpx, dy, acc[3]);
-              acc[4] = fmaf(dpy, dy, acc[4]);
-              // (2A dx + B dy), (B dx + 2C dy): derivative of p2 w.r.t. -mean2D
-              acc[0] = fmaf(dpow, fmaf(2.0f * r0.z, dx, r0.w * dy), acc[0]);
-              acc[1] = fmaf(dpow, fmaf(r0.w, dx, 2.0f * r1.x * dy), acc[1]);
+      for (int q = 0; q < Q; ++q) {
+        if ((m >> q) & 1u) {
+          if (pos <= last[q]) {
+            float a, G, dx, dy;
+            const float px = px0 + float((q % GX) * 8), py = py0 + float((q / GX) * 8);
+            if (eval_alpha(r0, r1.x, o, px, py, a, G, dx, dy)) {
+              hit = true;
+              const float inv = __builtin_amdgcn_rcpf(1.0f - a);
+              const float Ti = T[q] * inv;
+              const float wgt = a * Ti;
+              const float cg = fmaf(r1.z, g0[q], fmaf(r1.w, g1[q], cb * g2[q]));
+              const float dLda = Ti * cg - SdL[q] * inv;
+              SdL[q] = fmaf(wgt, cg, SdL[q]);
+              T[q] = Ti;
+              acc[6] = fmaf(wgt, g0[q], acc[6]);
+              acc[7] = fmaf(wgt, g1[q], acc[7]);
+              acc[8] = fmaf(wgt, g2[q], acc[8]);
+              const float oG = o * G;
+              if (oG <= kAlphaMax) {
+                acc[5] = fmaf(dLda, G, acc[5]);
+                const float dpow = dLda * oG;
+                const float dpx = dpow * dx, dpy = dpow * dy;
+                acc[2] = fmaf(dpx, dx, acc[2]);
+                acc[3] = fmaf(dpx, dy, acc[3]);
+                acc[4] = fmaf(dpy, dy, acc[4]);
+                // (2A dx + B dy), (B dx + 2C dy): derivative of p2 w.r.t. -mean2D
+                acc[0] = fmaf(dpow, fmaf(A2, dx, r0.w * dy), acc[0]);
+                acc[1] = fmaf(dpow, fmaf(r0.w, dx, C2 * dy), acc[1]);
+              }
             }
           }
         }
       }
       if (__ballot(hit) != 0ull) {
-#pragma unroll
-        for (int c = 0; c < kG; ++c) {
-          const float sum = wave_sum(acc[c]);
-          if (lane == 0) s_acc[w][c][k] = sum;
+        float qv[3];
+        wave_sum9(acc, qv);
+        const uint32_t idx = s_pidx[k];
+        if ((lane & 15) == 15 && int64_t(idx) < cap) {
+          // natural-unit conic and mean gradients from the base-2 accumulators
+          const int row = lane >> 4;
+          const int c0 = ((row & 1) << 1) | (row >> 1);  // 0, 2, 1, 3
+          constexpr float kScale[kG] = {-kLn2, -kLn2, -0.5f, -1.0f, -0.5f, 1.0f, 1.0f, 1.0f, 1.0f};
+          float* dst = pair_grad + size_t(idx) * kG;
+          dst[c0] = kScale[c0] * qv[0];
+          dst[c0 + 4] = kScale[c0 + 4] * qv[1];
+          if (row == 0) dst[8] = qv[2];
         }
       }
     }
-    __syncthreads();
-    for (int k = tid; k < nb; k += NT) {
-      float sum[kG];
-      bool nz = false;
-#pragma unroll
-      for (int c = 0; c < kG; ++c) {
-        float s = s_acc[0][c][k];
-#pragma unroll
-        for (int ww = 1; ww < NW; ++ww) s += s_acc[ww][c][k];
-        sum[c] = s;
-        nz |= (s != 0.0f);
-      }
-      const uint32_t idx = s_pidx[k];
-      if (nz && int64_t(idx) < cap) {
-        // natural-unit conic / mean gradients from the base-2 accumulators
-        float* dst = pair_grad + size_t(idx) * kG;
-        dst[0] = -kLn2 * sum[0];
-        dst[1] = -kLn2 * sum[1];
-        dst[2] = -0.5f * sum[2];
-        dst[3] = -sum[3];
-        dst[4] = -0.5f * sum[4];
-        dst[5] = sum[5];
-        dst[6] = sum[6];
-        dst[7] = sum[7];
-        dst[8] = sum[8];
-      }
-    }
-    __syncthreads();
     bend = bstart;
   }
 }
@@ -545,7 +537,7 @@ void launch_bwd_tile(int batch, dim3 grid, const RViews& RV, int n, const char* 
                      const float* final_T, const uint32_t* last_contrib, const float* dL,
                      const uint32_t* goff, float* pairs, int64_t cap, const float* bg,
                      hipStream_t st) {
-  const dim3 block(TileShape<TILE>::kThreads);
+  const dim3 block(64);
 #define GS_BWD_LAUNCH(B)                                                                       \
   hipLaunchKernelGGL(HIP_KERNEL_NAME(k_blend_bwd<TILE, B>), grid, block, 0, st, RV, n, proj,   \
                      stride, ranges, vals, final_T, last_contrib, dL, goff, pairs, cap, bg[0], \

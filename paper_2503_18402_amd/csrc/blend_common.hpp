@@ -9,11 +9,20 @@
 
 namespace gsk {
 
-// Pixel layout inside a tile: one 64-lane wave owns an R x R square of the
-// tile (R = 8 for 8x8 and 16x16 tiles, 16 for 32x32 tiles); lane l sits at
-// (l % 8, l / 8) of every 8x8 sub-square, so a lane owns SUB x SUB pixels.
+// One 64-lane wave per tile.  The tile is cut into 8x8 groups; lane l owns the
+// pixel (l % 8, l / 8) of every group, so a lane holds kGroups pixels and a
+// Gaussian's footprint box selects whole groups with a wave-uniform mask.
 template <int TILE>
 struct TileShape {
+  static constexpr int kGroupsX = TILE / 8;
+  static constexpr int kGroups = kGroupsX * kGroupsX;
+};
+
+// Forward layout: several waves per tile, each owning an R x R square (R = 8 for
+// 8x8 and 16x16 tiles, 16 for 32x32 tiles); lane l sits at (l % 8, l / 8) of every
+// 8x8 sub-square of its wave, so a lane owns kSub x kSub pixels.
+template <int TILE>
+struct WaveShape {
   static constexpr int kThreads = (TILE == 8) ? 64 : 256;
   static constexpr int kWaves = kThreads / 64;
   static constexpr int kRegion = (TILE == 8) ? 8 : TILE / 2;
@@ -21,8 +30,13 @@ struct TileShape {
   static constexpr int kPix = kSub * kSub;
 };
 
-// alpha of Gaussian (r0 = (mx, my, A, B), C, o) at pixel centre (px, py).
-// Returns false when the Gaussian is skipped at this pixel.
+__device__ __forceinline__ bool box_overlaps(uint32_t lo, uint32_t hi, int x0, int y0, int x1,
+                                             int y1) {
+  return box_x(lo) <= x1 && box_x(hi) >= x0 && box_y(lo) <= y1 && box_y(hi) >= y0;
+}
+
+// alpha of Gaussian (r0 = (mx, my, A, B), C, o) at pixel centre (px, py), all in
+// the tile's frame.  Returns false when the Gaussian is skipped at this pixel.
 __device__ __forceinline__ bool eval_alpha(const float4 r0, const float C, const float o,
                                            const float px, const float py, float& alpha,
                                            float& G, float& dx, float& dy) {
@@ -56,9 +70,22 @@ __device__ __forceinline__ float4 to_tile_frame(float4 r0, uint32_t lo, int tx, 
   return r0;
 }
 
-__device__ __forceinline__ bool box_overlaps(uint32_t lo, uint32_t hi, int x0, int y0, int x1,
-                                             int y1) {
-  return box_x(lo) <= x1 && box_x(hi) >= x0 && box_y(lo) <= y1 && box_y(hi) >= y0;
+// Bit g set when the footprint box [lo, hi] touches 8x8 group g of tile (tx, ty).
+template <int TILE>
+__device__ __forceinline__ uint32_t group_mask(uint32_t lo, uint32_t hi, int tx, int ty) {
+  constexpr int GX = TILE / 8;
+  // box in group units relative to the tile, clamped to the tile's groups
+  const int gx0 = max((box_x(lo) - tx * TILE) >> 3, 0);
+  const int gx1 = min((box_x(hi) - tx * TILE) >> 3, GX - 1);
+  const int gy0 = max((box_y(lo) - ty * TILE) >> 3, 0);
+  const int gy1 = min((box_y(hi) - ty * TILE) >> 3, GX - 1);
+  if (gx0 > gx1 || gy0 > gy1) return 0u;
+  const uint32_t row = ((1u << (gx1 + 1)) - 1u) & ~((1u << gx0) - 1u);
+  uint32_t m = 0u;
+#pragma unroll
+  for (int gy = 0; gy < GX; ++gy)
+    if (gy >= gy0 && gy <= gy1) m |= row << (gy * GX);
+  return m;
 }
 
 }  // namespace gsk

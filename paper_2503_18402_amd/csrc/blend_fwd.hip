@@ -3,7 +3,8 @@
 // whole workgroup; each 64-lane wave owns an 8x8 (or 16x16) square of the
 // tile and compacts the batch to the Gaussians whose footprint box touches
 // its square (ballot + popcount), so waves skip Gaussians that cannot reach
-// their pixels.  A pixel stops at the first Gaussian that would take its
+// their pixels.  (The backward runs one wave per tile instead; both share the
+// float32 evaluation of alpha, so their decisions agree.)  A pixel stops at the first Gaussian that would take its
 // transmittance below 1e-4; a wave leaves the list when all its pixels have
 // stopped, the workgroup when all waves have.
 #include "blend_common.hpp"
@@ -12,11 +13,11 @@ namespace gsk {
 namespace {
 
 template <int TILE, int BATCH>
-__global__ __launch_bounds__(TileShape<TILE>::kThreads) void k_blend_fwd(
+__global__ __launch_bounds__(WaveShape<TILE>::kThreads) void k_blend_fwd(
     RViews RV, const char* __restrict__ proj, size_t stride, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ vals, float* __restrict__ image, float* __restrict__ final_T,
     uint32_t* __restrict__ last_contrib, float bg0, float bg1, float bg2) {
-  using S = TileShape<TILE>;
+  using S = WaveShape<TILE>;
   constexpr int NT = S::kThreads, NW = S::kWaves, R = S::kRegion, SUB = S::kSub, P = S::kPix;
   __shared__ float4 s_r0[BATCH];
   __shared__ float4 s_r1[BATCH];
@@ -146,7 +147,7 @@ template <int TILE>
 hipError_t launch_tile(int batch, const RViews& RV, const char* proj, size_t stride,
                        const uint32_t* ranges, const uint32_t* vals, float* image,
                        float* final_T, uint32_t* last_contrib, const float* bg, hipStream_t st) {
-  const dim3 grid(unsigned(RV.total_tiles)), block(TileShape<TILE>::kThreads);
+  const dim3 grid(unsigned(RV.total_tiles)), block(WaveShape<TILE>::kThreads);
   switch (batch) {
     case 128:
       hipLaunchKernelGGL(HIP_KERNEL_NAME(k_blend_fwd<TILE, 128>), grid, block, 0, st, RV, proj,

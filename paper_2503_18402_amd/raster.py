@@ -162,3 +162,97 @@ def to_device(scene: dict, device="cuda") -> dict:
     """numpy scene -> contiguous float32 device tensors."""
     return {k: torch.from_numpy(scene[k]).to(device=device, dtype=torch.float32).contiguous()
             for k in PARAM_NAMES}
+
+
+class Pipeline:
+    """Preallocated buffers for one training step over a fixed set of views.
+
+    ``step()`` enqueues the whole hot path on the current stream with no host
+    synchronisation and no allocation: preprocess, bin_sort, render_fwd, L1
+    loss gradient against ``targets``, render_bwd and one fused Adam step over
+    all parameter groups.  Every view of the set goes into one launch per
+    kernel.  ``overflowed()`` reads the pair count once to check the capacity
+    after the fact; a captured HIP graph of ``step()`` replays the same work.
+    """
+
+    def __init__(self, params: dict, cams, targets: torch.Tensor, tile: int = 16,
+                 lds_batch: int = 256, bg=(0.0, 0.0, 0.0), sh_degree: int = 3,
+                 capacity: int | None = None, lrs: dict | None = None,
+                 betas=(0.9, 0.999), eps: float = 1e-15):
+        self.params = params
+        self.cams = list(cams)
+        dev = params["means"].device
+        self.n = params["means"].shape[0]
+        self.nv = len(self.cams)
+        self.cams_c = gsmi.make_cameras(self.cams)
+        self.cfg = gsmi.make_cfg(tile, lds_batch, bg)
+        self.sh_degree = sh_degree
+        self.npx = sum(int(c.width) * int(c.height) for c in self.cams)
+        self.targets = targets.contiguous()
+        if capacity is None:
+            probe = render(params, self.cams, tile=tile, lds_batch=lds_batch, bg=bg,
+                           sh_degree=sh_degree)
+            capacity = int(int(probe.n_pairs_dev.item()) * 1.2) + 4096
+            del probe
+        self.capacity = int(capacity)
+        u8 = dict(dtype=torch.uint8, device=dev)
+        self.proj = torch.empty(max(gsmi.gs_proj_bytes(self.nv, self.n), 16), **u8)
+        self.sort_ws = torch.empty(
+            max(gsmi.gs_bin_sort_workspace_bytes(self.nv, self.n, self.capacity), 16), **u8)
+        self.bwd_ws = torch.empty(
+            max(gsmi.gs_render_bwd_workspace_bytes(self.nv, self.n, self.capacity), 16), **u8)
+        self.vals = torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev)
+        self.ranges = torch.empty(2 * max(gsmi.gs_total_tiles(self.cams_c, self.cfg), 1),
+                                  dtype=torch.int32, device=dev)
+        self.n_pairs = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.image = torch.empty(3 * self.npx, dtype=torch.float32, device=dev)
+        self.final_T = torch.empty(self.npx, dtype=torch.float32, device=dev)
+        self.last = torch.empty(self.npx, dtype=torch.int32, device=dev)
+        self.dL = torch.empty(3 * self.npx, dtype=torch.float32, device=dev)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.grads = zero_grads(params)
+        self.m = {k: torch.zeros_like(params[k]) for k in PARAM_NAMES}
+        self.v = {k: torch.zeros_like(params[k]) for k in PARAM_NAMES}
+        self.lrs = lrs or dict(means=1.6e-4, log_scales=5e-3, quats=1e-3, opacity_logits=5e-2,
+                               sh=2.5e-3)
+        self.betas, self.eps = betas, eps
+        self.step_no = 0
+
+    def forward(self, stream=None):
+        p = self.params
+        gsmi.gs_preprocess(self.cams_c, self.cfg, self.n, p["means"], p["log_scales"],
+                           p["quats"], p["opacity_logits"], p["sh"], self.sh_degree, self.proj,
+                           stream)
+        gsmi.gs_bin_sort(self.cams_c, self.cfg, self.n, self.proj, self.capacity, self.sort_ws,
+                         None, self.vals, self.ranges, self.n_pairs, stream)
+        gsmi.gs_render_fwd(self.cams_c, self.cfg, self.n, self.proj, self.ranges, self.vals,
+                           self.image, self.final_T, self.last, stream)
+
+    def backward(self, stream=None):
+        p, g = self.params, self.grads
+        for t in g.values():
+            t.zero_()
+        self.loss.zero_()
+        gsmi.gs_l1_loss_grad(self.image, self.targets, 1.0 / self.image.numel(), self.dL,
+                             self.loss, stream)
+        gsmi.gs_render_bwd(self.cams_c, self.cfg, self.n, p["means"], p["log_scales"],
+                           p["quats"], p["opacity_logits"], p["sh"], self.sh_degree, self.proj,
+                           self.ranges, self.vals, self.final_T, self.last, self.dL, g["means"],
+                           g["log_scales"], g["quats"], g["opacity_logits"], g["sh"], None,
+                           self.capacity, self.bwd_ws, stream)
+
+    def adam(self, stream=None, step: int | None = None):
+        if step is None:
+            self.step_no += 1
+            step = self.step_no
+        groups = [(self.params[k], self.grads[k], self.m[k], self.v[k], self.lrs[k])
+                  for k in PARAM_NAMES]
+        gsmi.gs_adam_step(groups, step, self.betas[0], self.betas[1], self.eps, stream)
+
+    def step(self, stream=None, adam_step: int | None = None):
+        self.forward(stream)
+        self.backward(stream)
+        self.adam(stream, adam_step)
+
+    def overflowed(self) -> bool:
+        return int(self.n_pairs.item()) > self.capacity
