@@ -33,6 +33,11 @@ ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 # offset (2), quadratic form (5 mul/fma = 8 FLOP), exp (1), o*G (1), clamp (1),
 # two cutoff tests (2), T(1-alpha) (2), alpha*T (1), colour (3 fma = 6)
 FWD_FLOP_PER_EVAL = 2 + 8 + 1 + 1 + 1 + 2 + 2 + 1 + 6
+# and in the backward: alpha again (13), T recovery 1-a, 1/x, T*inv (3), weight (1),
+# c.dL/dC (5), dL/dalpha (3), colour-behind update (2), colour grads (6), opacity
+# grad (2), dL/dpower and its products with the offsets (3), conic grads (6),
+# mean grads (10)
+BWD_FLOP_PER_EVAL = 13 + 3 + 1 + 5 + 3 + 2 + 6 + 2 + 3 + 6 + 10
 
 
 def parse():
@@ -41,7 +46,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--tile", type=int, default=16)
-    ap.add_argument("--lds-batch", type=int, default=256)
+    ap.add_argument("--lds-batch", type=int, default=128)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--cpu-pixels", type=int, default=16)
@@ -139,24 +144,36 @@ def main():
         print(json.dumps(dict(profile_only=True, ms_per_step=ms, pairs=n_pairs)))
         return
 
-    # ------------------------------------------- forward-blend roofline (ALU)
+    # per-kernel durations: the same steps again with every launch bracketed by HIP
+    # events on its own stream (separate from the timed loop above)
+    gsmi.gs_profile_enable(True)
+    for _ in range(steps):
+        pipe.step()
+    torch.cuda.synchronize()
+    kt = gsmi.gs_profile_collect()
+    gsmi.gs_profile_enable(False)
+    breakdown = {k: round(v[1] / steps, 4) for k, v in sorted(kt.items(), key=lambda kv: -kv[1][1])}
+    kernel_ms = {k: v[1] / v[0] for k, v in kt.items()}
+
+    # ------------------------------------------------- blend rooflines (ALU)
     # algorithmic evaluations: per pixel, the list entries up to and including its
-    # last blended Gaussian (a lower bound: the entries examined after it are not counted)
-    last = pipe.last.to(torch.int64)
-    fT = pipe.final_T
-    evals = int(last.sum().item())
-    flops = evals * FWD_FLOP_PER_EVAL
-    alu_achieved = flops / (fwd_ms / 1e3) / 1e12
-    prof = read_traffic("k_blend_fwd", ["paper_2503_18402_amd/csrc/blend_fwd.hip",
-                                        "paper_2503_18402_amd/csrc/blend_common.hpp"])
-    roofline = dict(kernel="k_blend_fwd", bound="alu", achieved=round(alu_achieved, 3),
+    # last blended Gaussian (the entries a pixel examines after it are not counted)
+    evals = int(pipe.last.to(torch.int64).sum().item())
+    srcs = ["paper_2503_18402_amd/csrc/blend_bwd.hip", "paper_2503_18402_amd/csrc/blend_common.hpp"]
+    bwd_ms = kernel_ms["k_blend_bwd"]
+    bwd_tf = evals * BWD_FLOP_PER_EVAL / (bwd_ms / 1e3) / 1e12
+    fwd_tf = evals * FWD_FLOP_PER_EVAL / (kernel_ms["k_blend_fwd"] / 1e3) / 1e12
+    algo_bytes = 40 * n_pairs + 24 * W * H   # records of the pairs + per-pixel state
+    roofline = dict(kernel="k_blend_bwd", bound="alu", achieved=round(bwd_tf, 3),
                     peak=round(ALU_PEAK_TFLOPS, 1), unit="TFLOP/s",
-                    frac=round(alu_achieved / ALU_PEAK_TFLOPS, 4),
-                    traffic=prof, evals=evals, flop_per_eval=FWD_FLOP_PER_EVAL,
-                    launch_ms=round(fwd_ms, 4),
-                    hbm_frac_algorithmic=round((40 * n_pairs + 20 * W * H) / (fwd_ms / 1e3)
-                                               / 1e9 / HBM_PEAK_GBS, 4))
-    del last, fT
+                    frac=round(bwd_tf / ALU_PEAK_TFLOPS, 4),
+                    traffic=read_traffic("k_blend_bwd", srcs), evals=evals,
+                    flop_per_eval=BWD_FLOP_PER_EVAL, launch_ms=round(bwd_ms, 4),
+                    hbm_frac_algorithmic=round(algo_bytes / (bwd_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                    fwd=dict(kernel="k_blend_fwd", achieved=round(fwd_tf, 3),
+                             frac=round(fwd_tf / ALU_PEAK_TFLOPS, 4),
+                             launch_ms=round(kernel_ms["k_blend_fwd"], 4),
+                             event_ms_in_timed_loop=round(fwd_ms, 4)))
 
     extras = {}
     if not args.no_extras:
@@ -185,6 +202,7 @@ def main():
                    "lds_batch": args.lds_batch, "pairs": n_pairs, "wall_s": round(wall, 3)},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "kernel_ms_per_step": breakdown,
     }
     out.update(extras)
     print(json.dumps(out))

@@ -135,15 +135,17 @@ gs_status gs_render_fwd(int32_t n_views, const gs_camera* cams, const gs_raster_
  * Each pixel replays its list back to front from last_contrib, recovering
  * T_i = T_{i+1} / (1 - alpha_i) from final_T, so no per-pixel history is
  * stored.  Per (tile, Gaussian) gradients land in a deterministic per-pair
- * slot of the workspace (no float atomics), then one kernel chains them to
- * the 3D parameters and sums over views.
+ * slot of the workspace (no float atomics); they are summed per Gaussian and
+ * view, then chained to the 3D parameters and summed over views.
  *   Inputs: the parameters given to gs_preprocess, its proj, the ranges/vals
  *   of gs_bin_sort (which must not have overflowed), the forward's final_T
  *   and last_contrib, and dL_dimage (same layout as image).
- *   Outputs (ACCUMULATED, +=; zero them per iteration): d_means [n,3],
- *   d_log_scales [n,3], d_quats [n,4], d_opacity_logits [n], d_sh [n,16,3]
- *   (coefficients above sh_degree untouched), d_mean2d_abs [n] (nullable:
- *   sum over views of |dL/dmean2D|, the densification statistic).
+ *   Outputs: d_means [n,3], d_log_scales [n,3], d_quats [n,4] (16-byte
+ *   aligned), d_opacity_logits [n], d_sh [n,16,3], d_mean2d_abs [n] (nullable:
+ *   sum over views of |dL/dmean2D|, the densification statistic).  With
+ *   accumulate != 0 they are ACCUMULATED (+=) and SH coefficients above
+ *   sh_degree are untouched; with accumulate == 0 every element is written
+ *   (=), zero where nothing contributes, including those coefficients.
  *   ws: gs_render_bwd_workspace_bytes(n_views, n, capacity_pairs) bytes.
  * ------------------------------------------------------------------------- */
 size_t gs_render_bwd_workspace_bytes(int32_t n_views, int32_t n, int64_t capacity_pairs);
@@ -154,8 +156,8 @@ gs_status gs_render_bwd(int32_t n_views, const gs_camera* cams, const gs_raster_
                         const uint32_t* vals, const float* final_T,
                         const uint32_t* last_contrib, const float* dL_dimage, float* d_means,
                         float* d_log_scales, float* d_quats, float* d_opacity_logits,
-                        float* d_sh, float* d_mean2d_abs, int64_t capacity_pairs, void* ws,
-                        size_t ws_bytes, void* stream);
+                        float* d_sh, float* d_mean2d_abs, int32_t accumulate,
+                        int64_t capacity_pairs, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * gs_adam_step: fused Adam over several parameter groups in one launch
@@ -185,6 +187,22 @@ gs_status gs_adam_step(const gs_adam_group* groups, int32_t n_groups, int32_t st
  * ------------------------------------------------------------------------- */
 gs_status gs_l1_loss_grad(int64_t numel, const float* image, const float* target, float scale,
                           float* dL_dimage, float* loss_sum, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Kernel timing (tracing aid, off by default).  While enabled, every kernel the
+ * library launches is bracketed by two hipEventRecord calls on the stream it
+ * is launched on.  gs_profile_collect waits for the recorded events, writes
+ * per-kernel aggregates (host array of at most max_entries) and clears the
+ * record; it returns the number of entries written, or -1 on a HIP error.
+ * Not thread-safe: enable, run and collect from one host thread.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  char name[48];     /* kernel name without template arguments */
+  int64_t launches;  /* launches recorded                      */
+  double total_ms;   /* summed event-to-event duration          */
+} gs_kernel_time;
+void gs_profile_enable(int32_t on);
+int32_t gs_profile_collect(gs_kernel_time* out, int32_t max_entries);
 
 const char* gs_status_str(gs_status s);
 int32_t gs_version(void);

@@ -3,10 +3,46 @@
 // never throws; kernels are enqueued on the caller's stream only.
 #include <cmath>
 #include <cstring>
+#include <string>
+#include <vector>
 
 #include "gs_internal.hpp"
 
 namespace gsk {
+
+// ------------------------------------------------------------ event tracing
+bool g_profile_on = false;
+namespace {
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+std::vector<ProfRec> g_recs;
+std::vector<hipEvent_t> g_pool;
+hipEvent_t take_event() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+}  // namespace
+
+void profile_begin(const char* name, hipStream_t st) {
+  ProfRec r{name, take_event(), nullptr};
+  if (r.a) hipEventRecord(r.a, st);
+  g_recs.push_back(r);
+}
+
+void profile_end(hipStream_t st) {
+  if (g_recs.empty()) return;
+  ProfRec& r = g_recs.back();
+  r.b = take_event();
+  if (r.b) hipEventRecord(r.b, st);
+}
 
 bool build_views(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg, Views* out) {
   if (!cams || !cfg || !out || n_views < 1 || n_views > GS_MAX_VIEWS) return false;
@@ -64,6 +100,38 @@ bool n_ok(int32_t n_views, int32_t n) {
 extern "C" {
 
 int32_t gs_version(void) { return 1; }
+
+void gs_profile_enable(int32_t on) { gsk::g_profile_on = on != 0; }
+
+int32_t gs_profile_collect(gs_kernel_time* out, int32_t max_entries) {
+  using gsk::g_recs;
+  std::vector<gs_kernel_time> agg;
+  bool err = false;
+  for (auto& r : g_recs) {
+    float ms = 0.0f;
+    if (!r.a || !r.b || hipEventSynchronize(r.b) != hipSuccess ||
+        hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+      err = true;
+    }
+    std::string nm(r.name);
+    size_t k = 0;
+    while (k < agg.size() && nm != agg[k].name) ++k;
+    if (k == agg.size()) {
+      gs_kernel_time t{};
+      std::strncpy(t.name, r.name, sizeof(t.name) - 1);
+      agg.push_back(t);
+    }
+    agg[k].launches += 1;
+    agg[k].total_ms += ms;
+    if (r.a) gsk::g_pool.push_back(r.a);
+    if (r.b) gsk::g_pool.push_back(r.b);
+  }
+  g_recs.clear();
+  if (err) return -1;
+  const int32_t n = int32_t(agg.size()) < max_entries ? int32_t(agg.size()) : max_entries;
+  for (int32_t i = 0; i < n && out; ++i) out[i] = agg[i];
+  return n;
+}
 
 const char* gs_status_str(gs_status s) {
   switch (s) {
@@ -145,8 +213,8 @@ gs_status gs_render_bwd(int32_t n_views, const gs_camera* cams, const gs_raster_
                         const uint32_t* vals, const float* final_T,
                         const uint32_t* last_contrib, const float* dL_dimage, float* d_means,
                         float* d_log_scales, float* d_quats, float* d_opacity_logits,
-                        float* d_sh, float* d_mean2d_abs, int64_t capacity_pairs, void* ws,
-                        size_t ws_bytes, void* stream) {
+                        float* d_sh, float* d_mean2d_abs, int32_t accumulate,
+                        int64_t capacity_pairs, void* ws, size_t ws_bytes, void* stream) {
   Views V;
   if (!n_ok(n_views, n) || !build_views(n_views, cams, cfg, &V)) return GS_ERR_ARG;
   if (sh_degree < 0 || sh_degree > 3) return GS_ERR_ARG;
@@ -162,7 +230,7 @@ gs_status gs_render_bwd(int32_t n_views, const gs_camera* cams, const gs_raster_
                                     sh_degree, static_cast<const char*>(proj), ranges, vals,
                                     final_T, last_contrib, dL_dimage, d_means, d_log_scales,
                                     d_quats, d_opacity_logits, d_sh, d_mean2d_abs,
-                                    capacity_pairs, ws, as_stream(stream)));
+                                    accumulate != 0, capacity_pairs, ws, as_stream(stream)));
 }
 
 gs_status gs_adam_step(const gs_adam_group* groups, int32_t n_groups, int32_t step, float beta1,

@@ -121,7 +121,7 @@ hipError_t launch_adam(const gs_adam_group* groups, int n_groups, int step, floa
   if (acc == 0) return hipSuccess;
   int64_t blocks = (acc / 4 + 255) / 256;
   if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_adam, dim3(unsigned(blocks)), dim3(256), 0, st, A);
+  GS_LAUNCH("k_adam", k_adam, dim3(unsigned(blocks)), dim3(256), 0, st, A);
   return hipGetLastError();
 }
 
@@ -130,7 +130,7 @@ hipError_t launch_l1(int64_t numel, const float* image, const float* target, flo
   if (numel == 0) return hipSuccess;
   int64_t blocks = (numel + 255) / 256;
   if (blocks > 1024) blocks = 1024;  // few blocks: one atomic each for the loss sum
-  hipLaunchKernelGGL(k_l1, dim3(unsigned(blocks)), dim3(256), 0, st, numel, image, target, scale,
+  GS_LAUNCH("k_l1", k_l1, dim3(unsigned(blocks)), dim3(256), 0, st, numel, image, target, scale,
                      dL, loss_sum);
   return hipGetLastError();
 }

@@ -277,24 +277,60 @@ __device__ inline void sh_dir_grad(float x, float y, float z, int deg, const flo
   gy += SH3a * 6.0f * x * y * wk[15];
 }
 
+// One thread per (view, Gaussian) item: sum the item's pair slots (contiguous,
+// tiles_touched of them) into nine planes g2d[c][item], written coalesced.
+__global__ __launch_bounds__(256) void k_pair_sum(const char* __restrict__ proj, size_t stride,
+                                                  size_t tt_off, int n, int64_t M,
+                                                  const uint32_t* __restrict__ grad_off,
+                                                  const float* __restrict__ pair_grad,
+                                                  int64_t cap, float* __restrict__ g2d) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const int64_t v = i / n, g = i - v * n;
+  const uint32_t tt = reinterpret_cast<const uint32_t*>(proj + v * stride + tt_off)[g];
+  float s[kG];
+#pragma unroll
+  for (int c = 0; c < kG; ++c) s[c] = 0.0f;
+  const uint32_t off = grad_off[i];
+  if (tt > 0u && int64_t(off) + tt <= cap) {
+    const float* pg = pair_grad + size_t(off) * kG;
+    for (uint32_t k = 0; k < tt; ++k)
+#pragma unroll
+      for (int c = 0; c < kG; ++c) s[c] += pg[size_t(k) * kG + c];
+  }
+#pragma unroll
+  for (int c = 0; c < kG; ++c) g2d[c * M + i] = s[c];
+}
+
 __global__ __launch_bounds__(128) void k_chain(
     Views V, int n, int sh_degree, const float* __restrict__ means,
     const float* __restrict__ log_scales, const float* __restrict__ quats,
     const float* __restrict__ opacity_logits, const float* __restrict__ sh,
-    const char* __restrict__ proj, const uint32_t* __restrict__ grad_off,
-    const float* __restrict__ pair_grad, int64_t cap, float* __restrict__ d_means,
-    float* __restrict__ d_log_scales, float* __restrict__ d_quats,
+    const char* __restrict__ proj, const float* __restrict__ g2d, int accumulate,
+    float* __restrict__ d_means, float* __restrict__ d_log_scales, float* __restrict__ d_quats,
     float* __restrict__ d_opacity_logits, float* __restrict__ d_sh,
     float* __restrict__ d_mean2d_abs) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   const ProjLayout L(n);
+  const int64_t M = int64_t(V.n_views) * n;
+  const int K = (sh_degree + 1) * (sh_degree + 1);
 
   // does any view have gradient slots for this Gaussian?
   bool any = false;
   for (int v = 0; v < V.n_views; ++v)
     any |= reinterpret_cast<const uint32_t*>(proj + size_t(v) * L.stride + L.tt)[g] > 0u;
-  if (!any) return;
+  if (!any) {
+    if (!accumulate) {
+      for (int k = 0; k < 3; ++k) d_means[3 * g + k] = d_log_scales[3 * g + k] = 0.0f;
+      reinterpret_cast<float4*>(d_quats)[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+      d_opacity_logits[g] = 0.0f;
+      float* dshg = d_sh + size_t(g) * GS_SH_COEFFS * 3;
+      for (int k = 0; k < GS_SH_COEFFS * 3; ++k) dshg[k] = 0.0f;
+      if (d_mean2d_abs) d_mean2d_abs[g] = 0.0f;
+    }
+    return;
+  }
 
   const float mx = means[3 * g + 0], my = means[3 * g + 1], mz = means[3 * g + 2];
   const float s0 = expf(log_scales[3 * g + 0]);
@@ -316,19 +352,19 @@ __global__ __launch_bounds__(128) void k_chain(
   Rq[7] = 2.0f * (qy * qz + qw * qx);
   Rq[8] = 1.0f - 2.0f * (qx * qx + qy * qy);
   const float sc[3] = {s0, s1, s2};
-  float M[9];
+  float M3[9];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) M[3 * i + j] = Rq[3 * i + j] * sc[j];
+    for (int j = 0; j < 3; ++j) M3[3 * i + j] = Rq[3 * i + j] * sc[j];
   float Sg[9];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j)
-      Sg[3 * i + j] = M[3 * i] * M[3 * j] + M[3 * i + 1] * M[3 * j + 1] + M[3 * i + 2] * M[3 * j + 2];
+      Sg[3 * i + j] =
+          M3[3 * i] * M3[3 * j] + M3[3 * i + 1] * M3[3 * j + 1] + M3[3 * i + 2] * M3[3 * j + 2];
   const float o = 1.0f / (1.0f + expf(-opacity_logits[g]));
-  const int K = (sh_degree + 1) * (sh_degree + 1);
   const float* shg = sh + size_t(g) * GS_SH_COEFFS * 3;
 
   float dm[3] = {0, 0, 0}, dS[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -341,13 +377,9 @@ __global__ __launch_bounds__(128) void k_chain(
     const char* base = proj + size_t(v) * L.stride;
     const uint32_t tt = reinterpret_cast<const uint32_t*>(base + L.tt)[g];
     if (tt == 0u) continue;
-    const uint32_t off = grad_off[size_t(v) * n + g];
-    if (int64_t(off) + tt > cap) continue;
-    float gr[kG] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    const float* pg = pair_grad + size_t(off) * kG;
-    for (uint32_t k = 0; k < tt; ++k)
+    float gr[kG];
 #pragma unroll
-      for (int c = 0; c < kG; ++c) gr[c] += pg[size_t(k) * kG + c];
+    for (int c = 0; c < kG; ++c) gr[c] = g2d[c * M + int64_t(v) * n + g];
     const uint32_t flags = reinterpret_cast<const uint32_t*>(base + L.flags)[g];
     const DevView& cv = V.v[v];
 
@@ -454,7 +486,7 @@ __global__ __launch_bounds__(128) void k_chain(
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j)
-      dMm[3 * i + j] = 2.0f * (dS[3 * i] * M[j] + dS[3 * i + 1] * M[3 + j] + dS[3 * i + 2] * M[6 + j]);
+      dMm[3 * i + j] = 2.0f * (dS[3 * i] * M3[j] + dS[3 * i + 1] * M3[3 + j] + dS[3 * i + 2] * M3[6 + j]);
   float dls[3], dR[9];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
@@ -473,25 +505,36 @@ __global__ __launch_bounds__(128) void k_chain(
                    2.0f * qw * dR[3] - 4.0f * qz * dR[4] + 2.0f * qy * dR[5] +
                    2.0f * qx * dR[6] + 2.0f * qy * dR[7];
   const float qd = qw * gw + qx * gx + qy * gy + qz * gz;
-  float4 dq4 = reinterpret_cast<float4*>(d_quats)[g];
-  dq4.x += (gw - qw * qd) * qinv;
-  dq4.y += (gx - qx * qd) * qinv;
-  dq4.z += (gy - qy * qd) * qinv;
-  dq4.w += (gz - qz * qd) * qinv;
-  reinterpret_cast<float4*>(d_quats)[g] = dq4;
-
-  d_means[3 * g + 0] += dm[0];
-  d_means[3 * g + 1] += dm[1];
-  d_means[3 * g + 2] += dm[2];
-  d_log_scales[3 * g + 0] += dls[0];
-  d_log_scales[3 * g + 1] += dls[1];
-  d_log_scales[3 * g + 2] += dls[2];
-  d_opacity_logits[g] += dop * o * (1.0f - o);
+  float4 dq4 = make_float4((gw - qw * qd) * qinv, (gx - qx * qd) * qinv, (gy - qy * qd) * qinv,
+                           (gz - qz * qd) * qinv);
+  const float dlogit = dop * o * (1.0f - o);
   float* dshg = d_sh + size_t(g) * GS_SH_COEFFS * 3;
+  if (accumulate) {
+    const float4 p4 = reinterpret_cast<float4*>(d_quats)[g];
+    dq4.x += p4.x; dq4.y += p4.y; dq4.z += p4.z; dq4.w += p4.w;
 #pragma unroll
-  for (int k = 0; k < GS_SH_COEFFS * 3; ++k)
-    if (k < 3 * K) dshg[k] += dshacc[k];
-  if (d_mean2d_abs) d_mean2d_abs[g] += m2abs;
+    for (int k = 0; k < 3; ++k) {
+      dm[k] += d_means[3 * g + k];
+      dls[k] += d_log_scales[3 * g + k];
+    }
+    d_opacity_logits[g] += dlogit;
+#pragma unroll
+    for (int k = 0; k < GS_SH_COEFFS * 3; ++k)
+      if (k < 3 * K) dshg[k] += dshacc[k];
+    if (d_mean2d_abs) d_mean2d_abs[g] += m2abs;
+  } else {
+    d_opacity_logits[g] = dlogit;
+    // coefficients above the degree receive zero
+#pragma unroll
+    for (int k = 0; k < GS_SH_COEFFS * 3; ++k) dshg[k] = (k < 3 * K) ? dshacc[k] : 0.0f;
+    if (d_mean2d_abs) d_mean2d_abs[g] = m2abs;
+  }
+  reinterpret_cast<float4*>(d_quats)[g] = dq4;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    d_means[3 * g + k] = dm[k];
+    d_log_scales[3 * g + k] = dls[k];
+  }
 }
 
 struct TTSrc {  // tiles touched of item (view, Gaussian), index order
@@ -519,13 +562,14 @@ __global__ __launch_bounds__(256) void k_zero_pairs(float* __restrict__ p,
 }
 
 struct BwdWs {
-  size_t goff, bsum, total, pairs, bytes;
+  size_t goff, bsum, total, g2d, pairs, bytes;
   BwdWs(int64_t M, int64_t cap) {
     size_t o = 0;
     auto take = [&](size_t b) { size_t r = o; o += align256(b); return r; };
     goff = take(4 * M);
     bsum = take(4 * scan_block_sums(M));
     total = take(8);
+    g2d = take(4 * kG * M);
     pairs = take(size_t(cap) * kG * 4);
     bytes = o;
   }
@@ -539,7 +583,7 @@ void launch_bwd_tile(int batch, dim3 grid, const RViews& RV, int n, const char* 
                      hipStream_t st) {
   const dim3 block(64);
 #define GS_BWD_LAUNCH(B)                                                                       \
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(k_blend_bwd<TILE, B>), grid, block, 0, st, RV, n, proj,   \
+  GS_LAUNCH("k_blend_bwd", HIP_KERNEL_NAME(k_blend_bwd<TILE, B>), grid, block, 0, st, RV, n, proj,   \
                      stride, ranges, vals, final_T, last_contrib, dL, goff, pairs, cap, bg[0], \
                      bg[1], bg[2])
   switch (batch) {
@@ -563,7 +607,8 @@ hipError_t launch_render_bwd(const Views& V, int n, const gs_raster_cfg& cfg,
                              const float* final_T, const uint32_t* last_contrib,
                              const float* dL_dimage, float* d_means, float* d_log_scales,
                              float* d_quats, float* d_opacity_logits, float* d_sh,
-                             float* d_mean2d_abs, int64_t cap, void* ws_, hipStream_t st) {
+                             float* d_mean2d_abs, int accumulate, int64_t cap, void* ws_,
+                             hipStream_t st) {
   const int64_t M = int64_t(V.n_views) * n;
   if (M == 0) return hipSuccess;
   const BwdWs B(M, cap);
@@ -575,7 +620,7 @@ hipError_t launch_render_bwd(const Views& V, int n, const gs_raster_cfg& cfg,
   hipError_t e = scan_exclusive(TTSrc{proj, L.stride, L.tt, n}, GoffDst{goff}, Count{nullptr, M},
                                 M, reinterpret_cast<uint32_t*>(ws + B.bsum), total, nullptr, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_zero_pairs, dim3(2048), dim3(256), 0, st, pairs, total, cap);
+  GS_LAUNCH("k_zero_pairs", k_zero_pairs, dim3(2048), dim3(256), 0, st, pairs, total, cap);
   if (V.total_tiles > 0) {
     const RViews RV = make_rviews(V);
     const dim3 grid(unsigned(V.total_tiles));
@@ -594,9 +639,12 @@ hipError_t launch_render_bwd(const Views& V, int n, const gs_raster_cfg& cfg,
         break;
     }
   }
-  hipLaunchKernelGGL(k_chain, dim3(unsigned((n + 127) / 128)), dim3(128), 0, st, V, n, sh_degree,
-                     means, log_scales, quats, opacity_logits, sh, proj, goff, pairs, cap,
-                     d_means, d_log_scales, d_quats, d_opacity_logits, d_sh, d_mean2d_abs);
+  float* g2d = reinterpret_cast<float*>(ws + B.g2d);
+  GS_LAUNCH("k_pair_sum", k_pair_sum, dim3(unsigned((M + 255) / 256)), dim3(256), 0, st, proj,
+            L.stride, L.tt, n, M, goff, pairs, cap, g2d);
+  GS_LAUNCH("k_chain", k_chain, dim3(unsigned((n + 127) / 128)), dim3(128), 0, st, V, n,
+            sh_degree, means, log_scales, quats, opacity_logits, sh, proj, g2d, accumulate,
+            d_means, d_log_scales, d_quats, d_opacity_logits, d_sh, d_mean2d_abs);
   return hipGetLastError();
 }
 

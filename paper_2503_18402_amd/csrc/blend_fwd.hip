@@ -150,15 +150,15 @@ hipError_t launch_tile(int batch, const RViews& RV, const char* proj, size_t str
   const dim3 grid(unsigned(RV.total_tiles)), block(WaveShape<TILE>::kThreads);
   switch (batch) {
     case 128:
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_blend_fwd<TILE, 128>), grid, block, 0, st, RV, proj,
+      GS_LAUNCH("k_blend_fwd", HIP_KERNEL_NAME(k_blend_fwd<TILE, 128>), grid, block, 0, st, RV, proj,
                          stride, ranges, vals, image, final_T, last_contrib, bg[0], bg[1], bg[2]);
       break;
     case 256:
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_blend_fwd<TILE, 256>), grid, block, 0, st, RV, proj,
+      GS_LAUNCH("k_blend_fwd", HIP_KERNEL_NAME(k_blend_fwd<TILE, 256>), grid, block, 0, st, RV, proj,
                          stride, ranges, vals, image, final_T, last_contrib, bg[0], bg[1], bg[2]);
       break;
     default:
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_blend_fwd<TILE, 512>), grid, block, 0, st, RV, proj,
+      GS_LAUNCH("k_blend_fwd", HIP_KERNEL_NAME(k_blend_fwd<TILE, 512>), grid, block, 0, st, RV, proj,
                          stride, ranges, vals, image, final_T, last_contrib, bg[0], bg[1], bg[2]);
       break;
   }

@@ -97,6 +97,28 @@ __device__ inline int box_y(uint32_t b) { return int(b >> 16); }
 // ----------------------------------------------------------- launch helpers
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Opt-in event tracing of kernel launches (abi.cpp): a scope records one event
+// before and one after the launch it encloses, on the launch's stream.
+extern bool g_profile_on;
+void profile_begin(const char* name, hipStream_t st);
+void profile_end(hipStream_t st);
+struct ProfScope {
+  hipStream_t st;
+  bool on;
+  ProfScope(const char* name, hipStream_t s) : st(s), on(g_profile_on) {
+    if (on) profile_begin(name, st);
+  }
+  ~ProfScope() {
+    if (on) profile_end(st);
+  }
+};
+// Launch a kernel inside a tracing scope.
+#define GS_LAUNCH(name, kernel, grid, block, shmem, st, ...)           \
+  do {                                                                 \
+    ::gsk::ProfScope gs_prof_scope_(name, st);                         \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(kernel), grid, block, shmem, st, __VA_ARGS__); \
+  } while (0)
+
 // host-side builders (abi.cpp)
 bool build_views(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg, Views* out);
 
@@ -123,7 +145,8 @@ hipError_t launch_render_bwd(const Views& V, int n, const gs_raster_cfg& cfg,
                              const float* final_T, const uint32_t* last_contrib,
                              const float* dL_dimage, float* d_means, float* d_log_scales,
                              float* d_quats, float* d_opacity_logits, float* d_sh,
-                             float* d_mean2d_abs, int64_t cap, void* ws, hipStream_t st);
+                             float* d_mean2d_abs, int accumulate, int64_t cap, void* ws,
+                             hipStream_t st);
 
 hipError_t launch_adam(const gs_adam_group* groups, int n_groups, int step, float beta1,
                        float beta2, float eps, hipStream_t st);

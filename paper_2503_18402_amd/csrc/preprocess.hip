@@ -194,7 +194,7 @@ hipError_t launch_preprocess(const Views& V, int n, int sh_degree, const float* 
                              hipStream_t st) {
   if (n == 0) return hipSuccess;
   const int nb = (n + 255) / 256;
-  hipLaunchKernelGGL(k_preprocess, dim3(nb), dim3(256), 0, st, V, n, sh_degree, means,
+  GS_LAUNCH("k_preprocess", k_preprocess, dim3(nb), dim3(256), 0, st, V, n, sh_degree, means,
                      log_scales, quats, opacity_logits, sh, proj);
   return hipGetLastError();
 }

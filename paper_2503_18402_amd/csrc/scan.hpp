@@ -138,13 +138,13 @@ hipError_t scan_exclusive(Src src, Dst dst, Count cnt, int64_t max_n, uint32_t* 
                           int64_t* total_out, uint32_t* total_out32, hipStream_t st) {
   const int64_t nb = (max_n + kScanTile - 1) / kScanTile;
   if (nb > 0) {
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan_reduce<Src>), dim3(unsigned(nb)),
+    GS_LAUNCH("k_scan_reduce", HIP_KERNEL_NAME(k_scan_reduce<Src>), dim3(unsigned(nb)),
                        dim3(kScanThreads), 0, st, src, cnt, block_sums);
   }
-  hipLaunchKernelGGL(k_scan_spine, dim3(1), dim3(kScanThreads), 0, st, block_sums, cnt,
+  GS_LAUNCH("k_scan_spine", k_scan_spine, dim3(1), dim3(kScanThreads), 0, st, block_sums, cnt,
                      total_out, total_out32);
   if (nb > 0) {
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_scan_down<Src, Dst>), dim3(unsigned(nb)),
+    GS_LAUNCH("k_scan_down", HIP_KERNEL_NAME(k_scan_down<Src, Dst>), dim3(unsigned(nb)),
                        dim3(kScanThreads), 0, st, src, dst, cnt, block_sums);
   }
   return hipGetLastError();

@@ -154,11 +154,11 @@ hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, 
                       uint32_t* digit_total, hipStream_t st) {
   const int64_t nb = (max_n + kRTile - 1) / kRTile;
   if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_radix_hist, dim3(unsigned(nb)), dim3(kRT), 0, st, kin, cnt, shift, bits,
+  GS_LAUNCH("k_radix_hist", k_radix_hist, dim3(unsigned(nb)), dim3(kRT), 0, st, kin, cnt, shift, bits,
                      hist);
-  hipLaunchKernelGGL(k_radix_rowscan, dim3(1u << bits), dim3(kRT), 0, st, hist, cnt,
+  GS_LAUNCH("k_radix_rowscan", k_radix_rowscan, dim3(1u << bits), dim3(kRT), 0, st, hist, cnt,
                      digit_total);
-  hipLaunchKernelGGL(k_radix_scatter, dim3(unsigned(nb)), dim3(kRT), 0, st, kin, vin, kout, vout,
+  GS_LAUNCH("k_radix_scatter", k_radix_scatter, dim3(unsigned(nb)), dim3(kRT), 0, st, kin, vin, kout, vout,
                      cnt, shift, bits, hist, digit_total);
   return hipGetLastError();
 }
@@ -341,7 +341,7 @@ hipError_t launch_bin_sort(const Views& V, int n, const char* proj, int64_t cap,
   e = scan_exclusive(SortedTTSrc{proj, L.stride, L.tt, n, U(W.ival0)}, OffDst{U(W.offs)},
                      Count{n_vis, 0}, M, U(W.bsum), n_tot, nullptr, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_finalize_count, dim3(1), dim3(64), 0, st, n_tot, cap, n_eff, n_pairs_dev);
+  GS_LAUNCH("k_finalize_count", k_finalize_count, dim3(1), dim3(64), 0, st, n_tot, cap, n_eff, n_pairs_dev);
 
   // 4. expand: pairs in depth order, tiles row-major within each footprint
   TileInfo TI{};
@@ -356,7 +356,7 @@ hipError_t launch_bin_sort(const Views& V, int n, const char* proj, int64_t cap,
   vb[(passes + 1) % 2] = U(W.pval);
   uint32_t* tb[2] = {U(W.ptile0), U(W.ptile1)};
   if (M > 0) {
-    hipLaunchKernelGGL(k_emit, dim3(unsigned((M + 255) / 256)), dim3(256), 0, st, TI, V.tile, n,
+    GS_LAUNCH("k_emit", k_emit, dim3(unsigned((M + 255) / 256)), dim3(256), 0, st, TI, V.tile, n,
                        proj, L.stride, U(W.ival0), U(W.offs), n_vis, n_eff, tb[0], vb[0]);
   }
   // 5. tile digits on the pairs (stable: depth order survives within a tile)
@@ -371,13 +371,13 @@ hipError_t launch_bin_sort(const Views& V, int n, const char* proj, int64_t cap,
   uint32_t* tiles_sorted = tb[passes & 1];
   // 6. ranges
   const int64_t nr = 2 * int64_t(V.total_tiles);
-  hipLaunchKernelGGL(k_fill_u32, dim3(unsigned(nr / 256 + 1 < 4096 ? nr / 256 + 1 : 4096)),
+  GS_LAUNCH("k_fill_u32", k_fill_u32, dim3(unsigned(nr / 256 + 1 < 4096 ? nr / 256 + 1 : 4096)),
                      dim3(256), 0, st, ranges, nr, 0u);
   if (cap > 0) {
-    hipLaunchKernelGGL(k_ranges, dim3(unsigned((cap + 255) / 256)), dim3(256), 0, st,
+    GS_LAUNCH("k_ranges", k_ranges, dim3(unsigned((cap + 255) / 256)), dim3(256), 0, st,
                        tiles_sorted, n_eff, ranges);
     if (keys) {
-      hipLaunchKernelGGL(k_keys, dim3(unsigned((cap + 255) / 256)), dim3(256), 0, st, TI,
+      GS_LAUNCH("k_keys", k_keys, dim3(unsigned((cap + 255) / 256)), dim3(256), 0, st, TI,
                          V.n_views, n, proj, L.stride, tiles_sorted, vals, n_eff, keys);
     }
   }

@@ -38,6 +38,10 @@ class GsRasterCfg(ctypes.Structure):
     _fields_ = [("tile", c_int32), ("lds_batch", c_int32), ("bg", c_float * 3)]
 
 
+class GsKernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", c_int64), ("total_ms", ctypes.c_double)]
+
+
 class GsAdamGroup(ctypes.Structure):
     _fields_ = [("p", c_void_p), ("g", c_void_p), ("m", c_void_p), ("v", c_void_p),
                 ("numel", c_int64), ("lr", c_float)]
@@ -67,9 +71,11 @@ def lib() -> ctypes.CDLL:
             "gs_render_fwd": (i32, [i32, cam_p, cfg_p, i32, vp, vp, vp, vp, vp, vp, vp]),
             "gs_render_bwd_workspace_bytes": (sz, [i32, i32, i64]),
             "gs_render_bwd": (i32, [i32, cam_p, cfg_p, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp,
-                                    vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp, sz, vp]),
+                                    vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, i64, vp, sz, vp]),
             "gs_adam_step": (i32, [POINTER(GsAdamGroup), i32, i32, c_float, c_float, c_float, vp]),
             "gs_l1_loss_grad": (i32, [i64, vp, vp, c_float, vp, vp, vp]),
+            "gs_profile_enable": (None, [i32]),
+            "gs_profile_collect": (i32, [POINTER(GsKernelTime), i32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -175,14 +181,15 @@ def gs_render_bwd_workspace_bytes(n_views: int, n: int, capacity: int) -> int:
 
 def gs_render_bwd(cams_c, cfg, n, means, log_scales, quats, opacity_logits, sh, sh_degree, proj,
                   ranges, vals, final_T, last_contrib, dL_dimage, d_means, d_log_scales, d_quats,
-                  d_opacity_logits, d_sh, d_mean2d_abs, capacity, ws, stream=None):
+                  d_opacity_logits, d_sh, d_mean2d_abs, capacity, ws, stream=None,
+                  accumulate=True):
     _check("gs_render_bwd", lib().gs_render_bwd(
         len(cams_c), cams_c, ctypes.byref(cfg), int(n), _ptr(means), _ptr(log_scales),
         _ptr(quats), _ptr(opacity_logits), _ptr(sh), int(sh_degree), _ptr(proj), _ptr(ranges),
         _ptr(vals), _ptr(final_T), _ptr(last_contrib), _ptr(dL_dimage), _ptr(d_means),
         _ptr(d_log_scales), _ptr(d_quats), _ptr(d_opacity_logits), _ptr(d_sh),
-        _ptr(d_mean2d_abs), int(capacity), _ptr(ws), ws.numel() * ws.element_size(),
-        _stream(stream)))
+        _ptr(d_mean2d_abs), 1 if accumulate else 0, int(capacity), _ptr(ws),
+        ws.numel() * ws.element_size(), _stream(stream)))
 
 
 def gs_adam_step(groups, step: int, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
@@ -200,3 +207,16 @@ def gs_l1_loss_grad(image, target, scale, dL_dimage, loss_sum=None, stream=None)
     _check("gs_l1_loss_grad", lib().gs_l1_loss_grad(
         image.numel(), _ptr(image), _ptr(target), float(scale), _ptr(dL_dimage), _ptr(loss_sum),
         _stream(stream)))
+
+
+def gs_profile_enable(on: bool = True):
+    lib().gs_profile_enable(1 if on else 0)
+
+
+def gs_profile_collect(max_entries: int = 64) -> dict:
+    """{kernel name: (launches, total_ms)} for the launches recorded since the last collect."""
+    arr = (GsKernelTime * max_entries)()
+    n = lib().gs_profile_collect(arr, max_entries)
+    if n < 0:
+        raise GsError("gs_profile_collect", 3)
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(n)}

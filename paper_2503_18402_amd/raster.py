@@ -112,8 +112,10 @@ def zero_grads(params: dict) -> dict:
 
 
 def render_backward(params: dict, frame: Frame, dL_dimage: torch.Tensor, grads: dict | None = None,
-                    mean2d_abs: torch.Tensor | None = None, stream=None) -> dict:
-    """Accumulate the parameter gradients of L given dL/dimage (concatenated layout)."""
+                    mean2d_abs: torch.Tensor | None = None, stream=None,
+                    accumulate: bool = True) -> dict:
+    """Parameter gradients of L given dL/dimage (concatenated layout), added to
+    ``grads`` (``accumulate``) or written over them."""
     if grads is None:
         grads = zero_grads(params)
     n = frame.n
@@ -125,7 +127,7 @@ def render_backward(params: dict, frame: Frame, dL_dimage: torch.Tensor, grads: 
                        frame.sh_degree, frame.proj, frame.ranges, frame.vals, frame.final_T,
                        frame.last_contrib, dL_dimage.contiguous(), grads["means"],
                        grads["log_scales"], grads["quats"], grads["opacity_logits"], grads["sh"],
-                       mean2d_abs, frame.capacity, ws, stream)
+                       mean2d_abs, frame.capacity, ws, stream, accumulate=accumulate)
     return grads
 
 
@@ -230,8 +232,6 @@ class Pipeline:
 
     def backward(self, stream=None):
         p, g = self.params, self.grads
-        for t in g.values():
-            t.zero_()
         self.loss.zero_()
         gsmi.gs_l1_loss_grad(self.image, self.targets, 1.0 / self.image.numel(), self.dL,
                              self.loss, stream)
@@ -239,7 +239,7 @@ class Pipeline:
                            p["quats"], p["opacity_logits"], p["sh"], self.sh_degree, self.proj,
                            self.ranges, self.vals, self.final_T, self.last, self.dL, g["means"],
                            g["log_scales"], g["quats"], g["opacity_logits"], g["sh"], None,
-                           self.capacity, self.bwd_ws, stream)
+                           self.capacity, self.bwd_ws, stream, accumulate=False)
 
     def adam(self, stream=None, step: int | None = None):
         if step is None:

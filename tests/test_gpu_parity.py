@@ -344,3 +344,23 @@ def test_autograd_function_matches_oracle(cfg0):
     for name in ("means", "sh", "quats"):
         U.check_grads(prm[name].grad.cpu().numpy(), B["d_" + name], B["bound"]["d_" + name],
                       mask=mask)
+
+
+def test_overwrite_equals_accumulate_into_zero(cfg0):
+    sc, cam, w = cfg0["sc"], cfg0["cam"], cfg0["w"]
+    params = raster.to_device(sc, "cuda")
+    frame = raster.render(params, [cam])
+    dL = torch.from_numpy(w).cuda().reshape(-1)
+    acc = raster.render_backward(params, frame, dL)
+    junk = {k: torch.full_like(v, 7.0) for k, v in acc.items()}
+    m2 = torch.full((params["means"].shape[0],), 3.0, device="cuda")
+    over = raster.render_backward(params, frame, dL, grads=junk, mean2d_abs=m2, accumulate=False)
+    for k in acc:
+        assert torch.equal(acc[k], over[k]), k
+    m2b = torch.zeros_like(m2)
+    raster.render_backward(params, frame, dL, mean2d_abs=m2b)
+    assert torch.equal(m2, m2b)
+    # accumulating twice doubles
+    twice = raster.render_backward(params, frame, dL, grads={k: v.clone() for k, v in acc.items()})
+    for k in acc:
+        assert torch.allclose(twice[k], 2 * acc[k], rtol=1e-6, atol=0), k
