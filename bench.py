@@ -134,10 +134,12 @@ def main():
     log(f"{ms:.3f} ms/step ({mpix:.1f} Mpix/s), forward blend {fwd_ms:.3f} ms, pairs {n_pairs}")
 
     if args.copy_mib:
+        # a plain streaming kernel of known traffic (reads and writes copy_mib MiB each),
+        # the reference for scaling the profiler's fetch / write byte counters
         a = torch.empty(args.copy_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
         b = torch.empty_like(a)
         for _ in range(3):
-            b.copy_(a)
+            torch.neg(a, out=b)
         torch.cuda.synchronize()
 
     if args.profile_steps:

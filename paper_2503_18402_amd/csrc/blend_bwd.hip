@@ -76,7 +76,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd(
   __shared__ uint32_t s_mask[BATCH];
   __shared__ uint32_t s_pidx[BATCH];
 
-  const int t = blockIdx.x;
+  const int t = xcd_tile(blockIdx.x, RV.total_tiles);
   const int v = view_of_tile(RV, t);
   const int lt = t - RV.tile_base[v];
   const int gw = RV.gw[v], W = RV.W[v], H = RV.H[v];
@@ -156,35 +156,31 @@ __global__ __launch_bounds__(64) void k_blend_bwd(
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         if ((m >> q) & 1u) {
-          if (pos <= last[q]) {
-            float a, G, dx, dy;
-            const float px = px0 + float((q % GX) * 8), py = py0 + float((q / GX) * 8);
-            if (eval_alpha(r0, r1.x, o, px, py, a, G, dx, dy)) {
-              hit = true;
-              const float inv = __builtin_amdgcn_rcpf(1.0f - a);
-              const float Ti = T[q] * inv;
-              const float wgt = a * Ti;
-              const float cg = fmaf(r1.z, g0[q], fmaf(r1.w, g1[q], cb * g2[q]));
-              const float dLda = Ti * cg - SdL[q] * inv;
-              SdL[q] = fmaf(wgt, cg, SdL[q]);
-              T[q] = Ti;
-              acc[6] = fmaf(wgt, g0[q], acc[6]);
-              acc[7] = fmaf(wgt, g1[q], acc[7]);
-              acc[8] = fmaf(wgt, g2[q], acc[8]);
-              const float oG = o * G;
-              if (oG <= kAlphaMax) {
-                acc[5] = fmaf(dLda, G, acc[5]);
-                const float dpow = dLda * oG;
-                const float dpx = dpow * dx, dpy = dpow * dy;
-                acc[2] = fmaf(dpx, dx, acc[2]);
-                acc[3] = fmaf(dpx, dy, acc[3]);
-                acc[4] = fmaf(dpy, dy, acc[4]);
-                // (2A dx + B dy), (B dx + 2C dy): derivative of p2 w.r.t. -mean2D
-                acc[0] = fmaf(dpow, fmaf(A2, dx, r0.w * dy), acc[0]);
-                acc[1] = fmaf(dpow, fmaf(r0.w, dx, C2 * dy), acc[1]);
-              }
-            }
-          }
+          // branch-free: every lane computes, the decisions select the updates
+          const float px = px0 + float((q % GX) * 8), py = py0 + float((q / GX) * 8);
+          const Alpha e = alpha_at(r0, r1.x, o, px, py);
+          const bool ok = e.ok & (pos <= last[q]);
+          const bool grad = ok & (e.raw <= kAlphaMax);  // the 0.99 clamp passes no gradient
+          hit |= ok;
+          const float inv = __builtin_amdgcn_rcpf(1.0f - e.a);
+          const float Ti = T[q] * inv;
+          const float wgt = ok ? e.a * Ti : 0.0f;
+          const float cg = fmaf(r1.z, g0[q], fmaf(r1.w, g1[q], cb * g2[q]));
+          const float dLda = grad ? Ti * cg - SdL[q] * inv : 0.0f;
+          SdL[q] = fmaf(wgt, cg, SdL[q]);
+          T[q] = ok ? Ti : T[q];
+          acc[6] = fmaf(wgt, g0[q], acc[6]);
+          acc[7] = fmaf(wgt, g1[q], acc[7]);
+          acc[8] = fmaf(wgt, g2[q], acc[8]);
+          acc[5] = fmaf(dLda, e.G, acc[5]);
+          const float dpow = dLda * e.raw;
+          const float dpx = dpow * e.dx, dpy = dpow * e.dy;
+          acc[2] = fmaf(dpx, e.dx, acc[2]);
+          acc[3] = fmaf(dpx, e.dy, acc[3]);
+          acc[4] = fmaf(dpy, e.dy, acc[4]);
+          // (2A dx + B dy), (B dx + 2C dy): derivative of p2 w.r.t. -mean2D
+          acc[0] = fmaf(dpow, fmaf(A2, e.dx, r0.w * e.dy), acc[0]);
+          acc[1] = fmaf(dpow, fmaf(r0.w, e.dx, C2 * e.dy), acc[1]);
         }
       }
       if (__ballot(hit) != 0ull) {

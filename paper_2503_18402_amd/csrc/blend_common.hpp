@@ -36,22 +36,39 @@ __device__ __forceinline__ bool box_overlaps(uint32_t lo, uint32_t hi, int x0, i
 }
 
 // alpha of Gaussian (r0 = (mx, my, A, B), C, o) at pixel centre (px, py), all in
-// the tile's frame.  Returns false when the Gaussian is skipped at this pixel.
-__device__ __forceinline__ bool eval_alpha(const float4 r0, const float C, const float o,
-                                           const float px, const float py, float& alpha,
-                                           float& G, float& dx, float& dy) {
-  dx = px - r0.x;
-  dy = py - r0.y;
-  const float t0 = r0.w * dy;
-  const float t1 = fmaf(r0.z, dx, t0);
-  const float t2 = C * dy;
-  const float t3 = t2 * dy;
-  const float p2 = fmaf(dx, t1, t3);
-  if (p2 > 0.0f) return false;
-  G = __builtin_amdgcn_exp2f(p2);
-  const float raw = o * G;
-  alpha = fminf(kAlphaMax, raw);
-  return alpha >= kAlphaMin;
+// the tile's frame, computed without branches.  The Gaussian takes part in the
+// blend at this pixel iff `ok` (quadratic form <= 0 and alpha >= 1/255).
+struct Alpha {
+  float dx, dy, G, raw, a;
+  bool ok;
+};
+__device__ __forceinline__ Alpha alpha_at(const float4 r0, const float C, const float o,
+                                          const float px, const float py) {
+  Alpha r;
+  r.dx = px - r0.x;
+  r.dy = py - r0.y;
+  const float t0 = r0.w * r.dy;
+  const float t1 = fmaf(r0.z, r.dx, t0);
+  const float t2 = C * r.dy;
+  const float t3 = t2 * r.dy;
+  const float p2 = fmaf(r.dx, t1, t3);
+  r.G = __builtin_amdgcn_exp2f(p2);
+  r.raw = o * r.G;
+  r.a = fminf(kAlphaMax, r.raw);
+  r.ok = (p2 <= 0.0f) & (r.a >= kAlphaMin);
+  return r;
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8), and
+// each XCD has its own L2.  Neighbouring tiles share most of their Gaussians, so
+// block b takes tile number  xcd * q + min(xcd, r) + b / 8  (q, r = tiles / 8,
+// tiles % 8): every XCD walks one contiguous run of tiles and re-reads records
+// from its own L2.  A bijection on [0, tiles).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int b, int tiles) {
+  const int q = tiles / kXcds, r = tiles % kXcds;
+  const int xcd = b % kXcds, idx = b / kXcds;
+  return xcd * q + min(xcd, r) + idx;
 }
 
 // global tile id -> view (views are few; the loop runs on the scalar unit)

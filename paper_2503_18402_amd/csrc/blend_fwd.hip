@@ -25,7 +25,7 @@ __global__ __launch_bounds__(WaveShape<TILE>::kThreads) void k_blend_fwd(
   __shared__ uint32_t s_mask[BATCH];
   __shared__ uint16_t s_list[NW][BATCH];
 
-  const int t = blockIdx.x;
+  const int t = xcd_tile(blockIdx.x, RV.total_tiles);
   const int v = view_of_tile(RV, t);
   const int lt = t - RV.tile_base[v];
   const int gw = RV.gw[v], W = RV.W[v], H = RV.H[v];
@@ -101,23 +101,20 @@ __global__ __launch_bounds__(WaveShape<TILE>::kThreads) void k_blend_fwd(
       bool any = false;
 #pragma unroll
       for (int p = 0; p < P; ++p) {
-        if (!done[p]) {
-          float a, G, dx, dy;
-          if (eval_alpha(r0, r1.x, r1.y, pxc[p], pyc[p], a, G, dx, dy)) {
-            const float Tn = T[p] * (1.0f - a);
-            if (Tn < kTMin) {
-              done[p] = true;
-            } else {
-              const float wgt = a * T[p];
-              C0[p] = fmaf(wgt, r1.z, C0[p]);
-              C1[p] = fmaf(wgt, r1.w, C1[p]);
-              C2[p] = fmaf(wgt, cb, C2[p]);
-              T[p] = Tn;
-              last[p] = pos;
-            }
-          }
-          any |= !done[p];
-        }
+        // branch-free: every lane computes, the decisions select the updates
+        const Alpha e = alpha_at(r0, r1.x, r1.y, pxc[p], pyc[p]);
+        const bool ok = e.ok & !done[p];
+        const float Tn = T[p] * (1.0f - e.a);
+        const bool stop = ok & (Tn < kTMin);
+        const bool blend = ok & !stop;
+        const float wgt = blend ? e.a * T[p] : 0.0f;
+        C0[p] = fmaf(wgt, r1.z, C0[p]);
+        C1[p] = fmaf(wgt, r1.w, C1[p]);
+        C2[p] = fmaf(wgt, cb, C2[p]);
+        T[p] = blend ? Tn : T[p];
+        last[p] = blend ? pos : last[p];
+        done[p] = done[p] | stop;
+        any |= !done[p];
       }
       if (__ballot(any) == 0ull) break;
     }
