@@ -77,9 +77,9 @@ typedef struct {
 /* ---------------------------------------------------------------------------
  * gs_preprocess: 3D -> 2D splatting of every Gaussian into every view
  * (Sec. 3: G_i is splatted to G2D_i; colour c_i from SH coefficients).
- *   means [n,3], log_scales [n,3], quats [n,4] (w,x,y,z, need not be unit),
- *   opacity_logits [n], sh [n,16,3] (coefficient-major; only the first
- *   (sh_degree+1)^2 are read), sh_degree in 0..3.
+ *   means [n,3], log_scales [n,3], quats [n,4] (w,x,y,z, need not be unit;
+ *   16-byte aligned), opacity_logits [n], sh [n,16,3] (coefficient-major,
+ *   16-byte aligned; only the first (sh_degree+1)^2 are read), sh_degree 0..3.
  *   cams: host array [n_views]; cfg: host.
  *   proj: output, gs_proj_bytes(n_views, n) bytes, opaque per-view records
  *   (screen mean, conic, opacity, colour, depth, footprint box, tile count,

@@ -164,7 +164,7 @@ gs_status gs_preprocess(int32_t n_views, const gs_camera* cams, const gs_raster_
   if (sh_degree < 0 || sh_degree > 3) return GS_ERR_ARG;
   if (n > 0 && (!means || !log_scales || !quats || !opacity_logits || !sh || !proj))
     return GS_ERR_ARG;
-  if (n > 0 && (!aligned16(quats) || !aligned16(proj))) return GS_ERR_ARG;
+  if (n > 0 && (!aligned16(quats) || !aligned16(sh) || !aligned16(proj))) return GS_ERR_ARG;
   return from_hip(launch_preprocess(V, n, sh_degree, means, log_scales, quats, opacity_logits, sh,
                                     static_cast<char*>(proj), as_stream(stream)));
 }

@@ -12,11 +12,16 @@ struct AdamArgs {
   float* m[GS_MAX_ADAM_GROUPS];
   float* v[GS_MAX_ADAM_GROUPS];
   int64_t numel[GS_MAX_ADAM_GROUPS];
-  int64_t start[GS_MAX_ADAM_GROUPS + 1];  // prefix over groups, in elements
+  int64_t blk_start[GS_MAX_ADAM_GROUPS + 1];  // first block of each group (prefix)
   float lr[GS_MAX_ADAM_GROUPS];
+  int32_t aligned[GS_MAX_ADAM_GROUPS];        // all four arrays 16-byte aligned
   int32_t n_groups;
   float b1, b2, eps, c1, c2;  // c1 = 1/(1-b1^t), c2 = 1/(1-b2^t)
 };
+
+constexpr int kAdamThreads = 256;
+constexpr int kAdamVec = 4;                                    // float4 per thread
+constexpr int kAdamBlock = kAdamThreads * kAdamVec * 4;       // elements per block
 
 __device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, float lr,
                                          const AdamArgs& A) {
@@ -27,49 +32,49 @@ __device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, 
   p -= lr * mh / (sqrtf(vh) + A.eps);
 }
 
-// grid-stride over the concatenated groups; 4 elements per thread-step where aligned
-__global__ __launch_bounds__(256) void k_adam(AdamArgs A) {
-  const int64_t total = A.start[A.n_groups];
-  const int64_t nthreads = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t i4 = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) * 4; i4 < total;
-       i4 += nthreads * 4) {
-    int gi = 0;
-    for (int k = 1; k < A.n_groups; ++k) gi = (A.start[k] <= i4) ? k : gi;
-    const int64_t j = i4 - A.start[gi];
-    const int64_t ne = A.numel[gi];
-    float* P = A.p[gi];
-    const float* G = A.g[gi];
-    float* M = A.m[gi];
-    float* V = A.v[gi];
-    const float lr = A.lr[gi];
-    const bool vec = (j + 4 <= ne) &&
-                     ((reinterpret_cast<uintptr_t>(P + j) | reinterpret_cast<uintptr_t>(G + j) |
-                       reinterpret_cast<uintptr_t>(M + j) | reinterpret_cast<uintptr_t>(V + j)) &
-                      15u) == 0;
-    if (vec) {
-      float4 p4 = *reinterpret_cast<float4*>(P + j);
-      const float4 g4 = *reinterpret_cast<const float4*>(G + j);
-      float4 m4 = *reinterpret_cast<float4*>(M + j);
-      float4 v4 = *reinterpret_cast<float4*>(V + j);
-      adam_one(p4.x, g4.x, m4.x, v4.x, lr, A);
-      adam_one(p4.y, g4.y, m4.y, v4.y, lr, A);
-      adam_one(p4.z, g4.z, m4.z, v4.z, lr, A);
-      adam_one(p4.w, g4.w, m4.w, v4.w, lr, A);
-      *reinterpret_cast<float4*>(P + j) = p4;
-      *reinterpret_cast<float4*>(M + j) = m4;
-      *reinterpret_cast<float4*>(V + j) = v4;
-    } else {
-      // group tail or unaligned pointers: element by element (group starts are padded to
-      // multiples of 4, so the 4 slots of this step belong to group gi; padding is skipped)
-      for (int e = 0; e < 4; ++e) {
-        const int64_t jj = j + e;
-        if (jj >= ne) break;
-        float pp = P[jj], mm = M[jj], vv = V[jj];
-        adam_one(pp, G[jj], mm, vv, lr, A);
-        P[jj] = pp;
-        M[jj] = mm;
-        V[jj] = vv;
-      }
+// One block per 4096-element chunk of one group: every thread issues its four
+// float4 loads of each array before any arithmetic (streaming, HBM-bound).
+__global__ __launch_bounds__(kAdamThreads) void k_adam(AdamArgs A) {
+  const int64_t b = blockIdx.x;
+  int gi = 0;
+  for (int k = 1; k < A.n_groups; ++k) gi = (A.blk_start[k] <= b) ? k : gi;
+  const int64_t base = (b - A.blk_start[gi]) * kAdamBlock;
+  const int64_t ne = A.numel[gi];
+  float* __restrict__ P = A.p[gi];
+  const float* __restrict__ G = A.g[gi];
+  float* __restrict__ M = A.m[gi];
+  float* __restrict__ V = A.v[gi];
+  const float lr = A.lr[gi];
+  if (A.aligned[gi] && base + kAdamBlock <= ne) {
+    float4 p4[kAdamVec], g4[kAdamVec], m4[kAdamVec], v4[kAdamVec];
+#pragma unroll
+    for (int k = 0; k < kAdamVec; ++k) {
+      const int64_t j = base + (int64_t(k) * kAdamThreads + threadIdx.x) * 4;
+      p4[k] = *reinterpret_cast<const float4*>(P + j);
+      g4[k] = *reinterpret_cast<const float4*>(G + j);
+      m4[k] = *reinterpret_cast<const float4*>(M + j);
+      v4[k] = *reinterpret_cast<const float4*>(V + j);
+    }
+#pragma unroll
+    for (int k = 0; k < kAdamVec; ++k) {
+      adam_one(p4[k].x, g4[k].x, m4[k].x, v4[k].x, lr, A);
+      adam_one(p4[k].y, g4[k].y, m4[k].y, v4[k].y, lr, A);
+      adam_one(p4[k].z, g4[k].z, m4[k].z, v4[k].z, lr, A);
+      adam_one(p4[k].w, g4[k].w, m4[k].w, v4[k].w, lr, A);
+      const int64_t j = base + (int64_t(k) * kAdamThreads + threadIdx.x) * 4;
+      *reinterpret_cast<float4*>(P + j) = p4[k];
+      *reinterpret_cast<float4*>(M + j) = m4[k];
+      *reinterpret_cast<float4*>(V + j) = v4[k];
+    }
+  } else {
+    // the group's last chunk, or unaligned arrays: element by element
+    const int64_t lim = (base + kAdamBlock < ne) ? base + kAdamBlock : ne;
+    for (int64_t j = base + threadIdx.x; j < lim; j += kAdamThreads) {
+      float pp = P[j], mm = M[j], vv = V[j];
+      adam_one(pp, G[j], mm, vv, lr, A);
+      P[j] = pp;
+      M[j] = mm;
+      V[j] = vv;
     }
   }
 }
@@ -100,7 +105,8 @@ hipError_t launch_adam(const gs_adam_group* groups, int n_groups, int step, floa
                        float beta2, float eps, hipStream_t st) {
   AdamArgs A{};
   A.n_groups = n_groups;
-  int64_t acc = 0;
+  int64_t blocks = 0;
+  auto al = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
   for (int k = 0; k < n_groups; ++k) {
     A.p[k] = groups[k].p;
     A.g[k] = groups[k].g;
@@ -108,20 +114,18 @@ hipError_t launch_adam(const gs_adam_group* groups, int n_groups, int step, floa
     A.v[k] = groups[k].v;
     A.numel[k] = groups[k].numel;
     A.lr[k] = groups[k].lr;
-    A.start[k] = acc;
-    // groups start on a multiple of 4 elements so each vector step stays in one group
-    acc += (groups[k].numel + 3) & ~int64_t(3);
+    A.aligned[k] = al(A.p[k]) && al(A.g[k]) && al(A.m[k]) && al(A.v[k]);
+    A.blk_start[k] = blocks;
+    blocks += (groups[k].numel + kAdamBlock - 1) / kAdamBlock;
   }
-  A.start[n_groups] = acc;
+  A.blk_start[n_groups] = blocks;
   A.b1 = beta1;
   A.b2 = beta2;
   A.eps = eps;
   A.c1 = float(1.0 / (1.0 - __builtin_pow(double(beta1), step)));
   A.c2 = float(1.0 / (1.0 - __builtin_pow(double(beta2), step)));
-  if (acc == 0) return hipSuccess;
-  int64_t blocks = (acc / 4 + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
-  GS_LAUNCH("k_adam", k_adam, dim3(unsigned(blocks)), dim3(256), 0, st, A);
+  if (blocks == 0) return hipSuccess;
+  GS_LAUNCH("k_adam", k_adam, dim3(unsigned(blocks)), dim3(kAdamThreads), 0, st, A);
   return hipGetLastError();
 }
 

@@ -43,12 +43,34 @@ __device__ inline void sh_basis(float x, float y, float z, int deg, float* Y) {
   Y[15] = -SH3a * x * (xx - 3.0f * yy);
 }
 
-__global__ __launch_bounds__(256) void k_preprocess(
+constexpr int kPreThreads = 128;
+constexpr int kShStride = GS_SH_COEFFS * 3 + 1;  // odd LDS stride: conflict-free rows
+
+__global__ __launch_bounds__(kPreThreads) void k_preprocess(
     Views V, int n, int sh_degree, const float* __restrict__ means,
     const float* __restrict__ log_scales, const float* __restrict__ quats,
     const float* __restrict__ opacity_logits, const float* __restrict__ sh,
     char* __restrict__ proj) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  // the block's SH coefficients (192 B per Gaussian) arrive through LDS with
+  // coalesced 16-byte loads instead of 192-byte strided rows per thread
+  __shared__ float s_sh[kPreThreads * kShStride];
+  const int g0 = blockIdx.x * kPreThreads;
+  const int g = g0 + threadIdx.x;
+  {
+    constexpr int F = GS_SH_COEFFS * 3;
+    const int cnt4 = (min(kPreThreads, n - g0) * F) / 4;
+    const float4* src = reinterpret_cast<const float4*>(sh + size_t(g0) * F);
+    for (int i = threadIdx.x; i < cnt4; i += kPreThreads) {
+      const float4 q = src[i];
+      const int f = 4 * i, row = f / F, k = f - row * F;
+      float* d = s_sh + row * kShStride + k;
+      d[0] = q.x;
+      d[1] = q.y;
+      d[2] = q.z;
+      d[3] = q.w;
+    }
+  }
+  __syncthreads();
   if (g >= n) return;
   const ProjLayout L(n);
 
@@ -83,7 +105,7 @@ __global__ __launch_bounds__(256) void k_preprocess(
 
   const int K = (sh_degree + 1) * (sh_degree + 1);
   float shc[GS_SH_COEFFS * 3];
-  const float* shg = sh + size_t(g) * GS_SH_COEFFS * 3;
+  const float* shg = s_sh + threadIdx.x * kShStride;
 #pragma unroll
   for (int k = 0; k < GS_SH_COEFFS * 3; ++k) shc[k] = (k < 3 * K) ? shg[k] : 0.0f;
 
@@ -193,8 +215,8 @@ hipError_t launch_preprocess(const Views& V, int n, int sh_degree, const float* 
                              const float* opacity_logits, const float* sh, char* proj,
                              hipStream_t st) {
   if (n == 0) return hipSuccess;
-  const int nb = (n + 255) / 256;
-  GS_LAUNCH("k_preprocess", k_preprocess, dim3(nb), dim3(256), 0, st, V, n, sh_degree, means,
+  const int nb = (n + kPreThreads - 1) / kPreThreads;
+  GS_LAUNCH("k_preprocess", k_preprocess, dim3(nb), dim3(kPreThreads), 0, st, V, n, sh_degree, means,
                      log_scales, quats, opacity_logits, sh, proj);
   return hipGetLastError();
 }
