@@ -258,31 +258,72 @@ def level_sweep(torch, raster, scenes, params, tparams_scene, tile, lds):
 
 
 def batched_vs_plain(torch, raster, scenes, params, tscene):
-    """16 views at the four schedule resolutions: one batched step vs 16 plain steps."""
+    """One iteration over the 16 views of the multi-resolution workload (4 each at
+    200x133, 400x266, 800x532, 1600x1064): fwd + bwd of every view and one Adam
+    step.  Batched: all views in one launch per kernel.  Plain: 16 sequential
+    per-view calls accumulating into one gradient buffer, then the same Adam.
+    Both forms use autotuned tile / LDS batch (per mix, per resolution) and are
+    captured as HIP graphs; eager times are reported too."""
+    from paper_2503_18402_amd import autotune
+
     cams = scenes.config3_views()
     tparams = raster.to_device(tscene, params["means"].device)
     tgts = [raster.render(tparams, [c]).image.clone() for c in cams]
     del tparams
     p = {k: v.clone() for k, v in params.items()}
-    batched = raster.Pipeline(p, cams, torch.cat(tgts))
+    cat = torch.cat(tgts)
+    tb = autotune.tune(p, cams, cat, reps=3)
+    batched = raster.Pipeline(p, cams, cat, tile=tb["tile"], lds_batch=tb["lds_batch"])
+    ms_b_eager = time_pipe(torch, batched, 5)
+    batched.capture()
     ms_b = time_pipe(torch, batched, 5)
     del batched
-    plains = [raster.Pipeline(p, [c], t) for c, t in zip(cams, tgts)]
-    for pp in plains:
-        pp.step()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 3
-    e0.record()
-    for _ in range(reps):
-        for pp in plains:
-            pp.step()
-    e1.record()
-    torch.cuda.synchronize()
-    ms_p = e0.elapsed_time(e1) / reps
-    log(f"16 views: batched {ms_b:.3f} ms/it, plain {ms_p:.3f} ms/it")
-    return dict(views=16, batched_it_s=round(1e3 / ms_b, 2), plain_it_s=round(1e3 / ms_p, 2),
-                speedup=round(ms_p / ms_b, 3), pixels=sum(c.width * c.height for c in cams))
+    # plain: per-resolution autotuned pipelines sharing one gradient buffer
+    grads = raster.zero_grads(p)
+    plains, picks = [], {}
+    for c, t in zip(cams, tgts):
+        key = (c.width, c.height)
+        if key not in picks:
+            picks[key] = autotune.tune(p, [c], t, reps=3)
+        pk = picks[key]
+        plains.append(raster.Pipeline(p, [c], t, tile=pk["tile"], lds_batch=pk["lds_batch"],
+                                      grads=grads))
+
+    def plain_iter():
+        for k, pp in enumerate(plains):
+            pp.forward()
+            pp.backward(accumulate=k > 0)
+        plains[0].adam()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_p_eager = timed(plain_iter, 3)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plain_iter()
+    ms_p = timed(g.replay, 3)
+    assert not any(pp.overflowed() for pp in plains)
+    log(f"16 views: batched {ms_b:.3f} ms/it (eager {ms_b_eager:.3f}), plain {ms_p:.3f} ms/it "
+        f"(eager {ms_p_eager:.3f})")
+    return dict(views=16, pixels=sum(c.width * c.height for c in cams),
+                batched_it_s=round(1e3 / ms_b, 2), plain_it_s=round(1e3 / ms_p, 2),
+                speedup=round(ms_p / ms_b, 3),
+                batched_eager_it_s=round(1e3 / ms_b_eager, 2),
+                plain_eager_it_s=round(1e3 / ms_p_eager, 2),
+                batched_cfg=dict(tile=tb["tile"], lds_batch=tb["lds_batch"]),
+                plain_cfg={f"{w}x{h}": dict(tile=v["tile"], lds_batch=v["lds_batch"])
+                           for (w, h), v in picks.items()},
+                note="both forms autotuned and HIP-graph captured; fwd+bwd of all 16 views "
+                     "plus one Adam step per iteration")
 
 
 def cpu_baseline(scene, cam, n_pix):

@@ -179,11 +179,20 @@ typedef struct {
 gs_status gs_adam_step(const gs_adam_group* groups, int32_t n_groups, int32_t step,
                        float beta1, float beta2, float eps, void* stream);
 
+/* gs_adam_step_device: the same update with the 1-based step read from device
+ * memory (*step_dev + 1 is this step) and *step_dev incremented afterwards on
+ * the stream, so one captured HIP graph replays as successive steps.
+ * step_dev: device int32, initialise to 0 before the first step. */
+gs_status gs_adam_step_device(const gs_adam_group* groups, int32_t n_groups, int32_t* step_dev,
+                              float beta1, float beta2, float eps, void* stream);
+
 /* ---------------------------------------------------------------------------
  * gs_l1_loss_grad: L1 photometric loss of the backbones.
  *   dL_dimage[i] = scale * sign(image[i] - target[i])  (sign(0) = 0), numel
  *   elements; if loss_sum (device, [1]) is non-NULL, scale * sum|image-target|
- *   is ADDED to it.  scale = 1/numel gives the mean.
+ *   is ADDED to it (one float atomic per workgroup: the last bits of this
+ *   reported value depend on their order; the gradient does not).  scale =
+ *   1/numel gives the mean.
  * ------------------------------------------------------------------------- */
 gs_status gs_l1_loss_grad(int64_t numel, const float* image, const float* target, float scale,
                           float* dL_dimage, float* loss_sum, void* stream);

@@ -243,7 +243,22 @@ gs_status gs_adam_step(const gs_adam_group* groups, int32_t n_groups, int32_t st
     if (g.numel < 0) return GS_ERR_ARG;
     if (g.numel > 0 && (!g.p || !g.g || !g.m || !g.v)) return GS_ERR_ARG;
   }
-  return from_hip(launch_adam(groups, n_groups, step, beta1, beta2, eps, as_stream(stream)));
+  return from_hip(
+      launch_adam(groups, n_groups, step, beta1, beta2, eps, nullptr, as_stream(stream)));
+}
+
+gs_status gs_adam_step_device(const gs_adam_group* groups, int32_t n_groups, int32_t* step_dev,
+                              float beta1, float beta2, float eps, void* stream) {
+  if (!groups || !step_dev || n_groups < 1 || n_groups > GS_MAX_ADAM_GROUPS) return GS_ERR_ARG;
+  if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps >= 0.0f))
+    return GS_ERR_ARG;
+  for (int k = 0; k < n_groups; ++k) {
+    const gs_adam_group& g = groups[k];
+    if (g.numel < 0) return GS_ERR_ARG;
+    if (g.numel > 0 && (!g.p || !g.g || !g.m || !g.v)) return GS_ERR_ARG;
+  }
+  return from_hip(
+      launch_adam(groups, n_groups, 1, beta1, beta2, eps, step_dev, as_stream(stream)));
 }
 
 gs_status gs_l1_loss_grad(int64_t numel, const float* image, const float* target, float scale,

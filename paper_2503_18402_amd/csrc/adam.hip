@@ -17,14 +17,19 @@ struct AdamArgs {
   int32_t aligned[GS_MAX_ADAM_GROUPS];        // all four arrays 16-byte aligned
   int32_t n_groups;
   float b1, b2, eps, c1, c2;  // c1 = 1/(1-b1^t), c2 = 1/(1-b2^t)
+  const int32_t* step_dev;    // when set: t = *step_dev + 1 and c1, c2 are computed here
 };
 
 constexpr int kAdamThreads = 256;
 constexpr int kAdamVec = 4;                                    // float4 per thread
 constexpr int kAdamBlock = kAdamThreads * kAdamVec * 4;       // elements per block
 
+struct AdamCoef {
+  float b1, b2, eps, c1, c2;
+};
+
 __device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, float lr,
-                                         const AdamArgs& A) {
+                                         const AdamCoef& A) {
   m = fmaf(A.b1, m, (1.0f - A.b1) * g);
   v = fmaf(A.b2, v, (1.0f - A.b2) * g * g);
   const float mh = m * A.c1;
@@ -35,6 +40,18 @@ __device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, 
 // One block per 4096-element chunk of one group: every thread issues its four
 // float4 loads of each array before any arithmetic (streaming, HBM-bound).
 __global__ __launch_bounds__(kAdamThreads) void k_adam(AdamArgs A) {
+  AdamCoef C{A.b1, A.b2, A.eps, A.c1, A.c2};
+  if (A.step_dev) {  // bias corrections of step *step_dev + 1, once per block
+    __shared__ float s_c[2];
+    if (threadIdx.x == 0) {
+      const double t = double(*A.step_dev + 1);
+      s_c[0] = float(1.0 / (1.0 - pow(double(A.b1), t)));
+      s_c[1] = float(1.0 / (1.0 - pow(double(A.b2), t)));
+    }
+    __syncthreads();
+    C.c1 = s_c[0];
+    C.c2 = s_c[1];
+  }
   const int64_t b = blockIdx.x;
   int gi = 0;
   for (int k = 1; k < A.n_groups; ++k) gi = (A.blk_start[k] <= b) ? k : gi;
@@ -57,10 +74,10 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam(AdamArgs A) {
     }
 #pragma unroll
     for (int k = 0; k < kAdamVec; ++k) {
-      adam_one(p4[k].x, g4[k].x, m4[k].x, v4[k].x, lr, A);
-      adam_one(p4[k].y, g4[k].y, m4[k].y, v4[k].y, lr, A);
-      adam_one(p4[k].z, g4[k].z, m4[k].z, v4[k].z, lr, A);
-      adam_one(p4[k].w, g4[k].w, m4[k].w, v4[k].w, lr, A);
+      adam_one(p4[k].x, g4[k].x, m4[k].x, v4[k].x, lr, C);
+      adam_one(p4[k].y, g4[k].y, m4[k].y, v4[k].y, lr, C);
+      adam_one(p4[k].z, g4[k].z, m4[k].z, v4[k].z, lr, C);
+      adam_one(p4[k].w, g4[k].w, m4[k].w, v4[k].w, lr, C);
       const int64_t j = base + (int64_t(k) * kAdamThreads + threadIdx.x) * 4;
       *reinterpret_cast<float4*>(P + j) = p4[k];
       *reinterpret_cast<float4*>(M + j) = m4[k];
@@ -71,12 +88,16 @@ __global__ __launch_bounds__(kAdamThreads) void k_adam(AdamArgs A) {
     const int64_t lim = (base + kAdamBlock < ne) ? base + kAdamBlock : ne;
     for (int64_t j = base + threadIdx.x; j < lim; j += kAdamThreads) {
       float pp = P[j], mm = M[j], vv = V[j];
-      adam_one(pp, G[j], mm, vv, lr, A);
+      adam_one(pp, G[j], mm, vv, lr, C);
       P[j] = pp;
       M[j] = mm;
       V[j] = vv;
     }
   }
+}
+
+__global__ __launch_bounds__(64) void k_step_inc(int32_t* step_dev) {
+  if (threadIdx.x == 0) *step_dev += 1;
 }
 
 __global__ __launch_bounds__(256) void k_l1(int64_t n, const float* __restrict__ img,
@@ -102,8 +123,9 @@ __global__ __launch_bounds__(256) void k_l1(int64_t n, const float* __restrict__
 }  // namespace
 
 hipError_t launch_adam(const gs_adam_group* groups, int n_groups, int step, float beta1,
-                       float beta2, float eps, hipStream_t st) {
+                       float beta2, float eps, int32_t* step_dev, hipStream_t st) {
   AdamArgs A{};
+  A.step_dev = step_dev;
   A.n_groups = n_groups;
   int64_t blocks = 0;
   auto al = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
@@ -124,8 +146,9 @@ hipError_t launch_adam(const gs_adam_group* groups, int n_groups, int step, floa
   A.eps = eps;
   A.c1 = float(1.0 / (1.0 - __builtin_pow(double(beta1), step)));
   A.c2 = float(1.0 / (1.0 - __builtin_pow(double(beta2), step)));
-  if (blocks == 0) return hipSuccess;
-  GS_LAUNCH("k_adam", k_adam, dim3(unsigned(blocks)), dim3(kAdamThreads), 0, st, A);
+  if (blocks > 0)
+    GS_LAUNCH("k_adam", k_adam, dim3(unsigned(blocks)), dim3(kAdamThreads), 0, st, A);
+  if (step_dev) GS_LAUNCH("k_step_inc", k_step_inc, dim3(1), dim3(64), 0, st, step_dev);
   return hipGetLastError();
 }
 

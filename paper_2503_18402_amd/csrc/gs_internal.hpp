@@ -149,7 +149,7 @@ hipError_t launch_render_bwd(const Views& V, int n, const gs_raster_cfg& cfg,
                              hipStream_t st);
 
 hipError_t launch_adam(const gs_adam_group* groups, int n_groups, int step, float beta1,
-                       float beta2, float eps, hipStream_t st);
+                       float beta2, float eps, int32_t* step_dev, hipStream_t st);
 hipError_t launch_l1(int64_t numel, const float* image, const float* target, float scale,
                      float* dL, float* loss_sum, hipStream_t st);
 

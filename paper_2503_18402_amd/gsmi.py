@@ -73,6 +73,8 @@ def lib() -> ctypes.CDLL:
             "gs_render_bwd": (i32, [i32, cam_p, cfg_p, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp,
                                     vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, i64, vp, sz, vp]),
             "gs_adam_step": (i32, [POINTER(GsAdamGroup), i32, i32, c_float, c_float, c_float, vp]),
+            "gs_adam_step_device": (i32, [POINTER(GsAdamGroup), i32, vp, c_float, c_float,
+                                          c_float, vp]),
             "gs_l1_loss_grad": (i32, [i64, vp, vp, c_float, vp, vp, vp]),
             "gs_profile_enable": (None, [i32]),
             "gs_profile_collect": (i32, [POINTER(GsKernelTime), i32]),
@@ -201,6 +203,18 @@ def gs_adam_step(groups, step: int, beta1=0.9, beta2=0.999, eps=1e-15, stream=No
         arr[k].lr = float(lr)
     _check("gs_adam_step", lib().gs_adam_step(arr, len(groups), int(step), float(beta1),
                                               float(beta2), float(eps), _stream(stream)))
+
+
+def gs_adam_step_device(groups, step_dev, beta1=0.9, beta2=0.999, eps=1e-15, stream=None):
+    """Like gs_adam_step, the step count living in the device int32 ``step_dev``."""
+    arr = (GsAdamGroup * len(groups))()
+    for k, (p, g, m, v, lr) in enumerate(groups):
+        arr[k].p, arr[k].g, arr[k].m, arr[k].v = _ptr(p), _ptr(g), _ptr(m), _ptr(v)
+        arr[k].numel = p.numel()
+        arr[k].lr = float(lr)
+    _check("gs_adam_step_device", lib().gs_adam_step_device(
+        arr, len(groups), _ptr(step_dev), float(beta1), float(beta2), float(eps),
+        _stream(stream)))
 
 
 def gs_l1_loss_grad(image, target, scale, dL_dimage, loss_sum=None, stream=None):

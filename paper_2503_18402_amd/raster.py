@@ -180,7 +180,7 @@ class Pipeline:
     def __init__(self, params: dict, cams, targets: torch.Tensor, tile: int = 16,
                  lds_batch: int = 256, bg=(0.0, 0.0, 0.0), sh_degree: int = 3,
                  capacity: int | None = None, lrs: dict | None = None,
-                 betas=(0.9, 0.999), eps: float = 1e-15):
+                 betas=(0.9, 0.999), eps: float = 1e-15, grads: dict | None = None):
         self.params = params
         self.cams = list(cams)
         dev = params["means"].device
@@ -212,13 +212,16 @@ class Pipeline:
         self.last = torch.empty(self.npx, dtype=torch.int32, device=dev)
         self.dL = torch.empty(3 * self.npx, dtype=torch.float32, device=dev)
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
-        self.grads = zero_grads(params)
+        self.grads = zero_grads(params) if grads is None else grads
         self.m = {k: torch.zeros_like(params[k]) for k in PARAM_NAMES}
         self.v = {k: torch.zeros_like(params[k]) for k in PARAM_NAMES}
         self.lrs = lrs or dict(means=1.6e-4, log_scales=5e-3, quats=1e-3, opacity_logits=5e-2,
                                sh=2.5e-3)
         self.betas, self.eps = betas, eps
         self.step_no = 0
+        # the step count lives on the device so a captured graph replays as new steps
+        self.step_dev = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.graph = None
 
     def forward(self, stream=None):
         p = self.params
@@ -230,7 +233,9 @@ class Pipeline:
         gsmi.gs_render_fwd(self.cams_c, self.cfg, self.n, self.proj, self.ranges, self.vals,
                            self.image, self.final_T, self.last, stream)
 
-    def backward(self, stream=None):
+    def backward(self, stream=None, accumulate: bool = False):
+        """L1 loss gradient and gs_render_bwd; gradients are written, or added to
+        ``self.grads`` with ``accumulate`` (several views sharing one buffer)."""
         p, g = self.params, self.grads
         self.loss.zero_()
         gsmi.gs_l1_loss_grad(self.image, self.targets, 1.0 / self.image.numel(), self.dL,
@@ -239,20 +244,43 @@ class Pipeline:
                            p["quats"], p["opacity_logits"], p["sh"], self.sh_degree, self.proj,
                            self.ranges, self.vals, self.final_T, self.last, self.dL, g["means"],
                            g["log_scales"], g["quats"], g["opacity_logits"], g["sh"], None,
-                           self.capacity, self.bwd_ws, stream, accumulate=False)
+                           self.capacity, self.bwd_ws, stream, accumulate=accumulate)
 
     def adam(self, stream=None, step: int | None = None):
-        if step is None:
-            self.step_no += 1
-            step = self.step_no
+        """Adam over all parameter groups; the step count is the device counter
+        unless ``step`` is given explicitly."""
         groups = [(self.params[k], self.grads[k], self.m[k], self.v[k], self.lrs[k])
                   for k in PARAM_NAMES]
-        gsmi.gs_adam_step(groups, step, self.betas[0], self.betas[1], self.eps, stream)
+        if step is None:
+            gsmi.gs_adam_step_device(groups, self.step_dev, self.betas[0], self.betas[1],
+                                     self.eps, stream)
+        else:
+            gsmi.gs_adam_step(groups, step, self.betas[0], self.betas[1], self.eps, stream)
+        self.step_no += 1
 
     def step(self, stream=None, adam_step: int | None = None):
+        if self.graph is not None and stream is None and adam_step is None:
+            self.graph.replay()
+            self.step_no += 1
+            return
         self.forward(stream)
         self.backward(stream)
         self.adam(stream, adam_step)
+
+    def capture(self):
+        """Capture one whole step into a HIP graph; later ``step()`` calls replay it.
+        The capacity must already be large enough (``overflowed()`` checks after)."""
+        self.forward()                   # warm every code path once (no parameter update)
+        self.backward()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.forward()
+            self.backward()
+            self.adam()
+        self.step_no -= 1                # capturing ran nothing
+        self.graph = g
+        return g
 
     def overflowed(self) -> bool:
         return int(self.n_pairs.item()) > self.capacity

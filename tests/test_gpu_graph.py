@@ -1,0 +1,77 @@
+"""HIP-graph replay of a whole training step and the autotuner (GPU).
+
+A captured step replays as successive steps (the Adam step count lives on the
+device): after each of several replays, with eager work and synchronisations
+in between, parameters, image and loss equal those of the same steps run
+eagerly, bit for bit.  The autotuner's pick renders the same image."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import project, render
+from paper_2503_18402_amd import autotune, raster, scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(n=20000, views=None):
+    sc = scenes.make_scene(n, seed=41, mean_range=1.0, ls_mu=-3.5, ls_sigma=0.3)
+    cams = views or [scenes.look_at((0, 0, -3), (0, 0, 0), 128, 96, 120.0)]
+    tgt = torch.cat([torch.from_numpy(scenes.uniform_target(c, seed=42 + k)).reshape(-1)
+                     for k, c in enumerate(cams)]).cuda()
+    return sc, cams, tgt
+
+
+@pytest.mark.parametrize("multi", [False, True])
+def test_graph_replay_equals_eager(multi):
+    views = None
+    if multi:
+        base = scenes.orbit_cameras(4, 3.0, 160, 120, 150.0)
+        views = [scenes.downscale(base[0], 4), scenes.downscale(base[1], 2), base[2], base[3]]
+    sc, cams, tgt = _setup(views=views)
+    pa = raster.Pipeline(raster.to_device(sc), cams, tgt)
+    pb = raster.Pipeline(raster.to_device(sc), cams, tgt, capacity=pa.capacity)
+    pb.capture()
+    for k in range(4):
+        pa.step()
+        pb.step()
+        torch.cuda.synchronize()
+        junk = torch.randn(1000, device="cuda").sum()      # eager work between replays
+        torch.cuda.synchronize()
+        assert not pa.overflowed() and not pb.overflowed()
+        for name in raster.PARAM_NAMES:
+            assert torch.equal(pa.params[name], pb.params[name]), (k, name)
+        assert torch.equal(pa.image, pb.image), k
+        # the reported loss adds one float atomic per block: last bits may differ
+        assert torch.allclose(pa.loss, pb.loss, rtol=1e-6, atol=0), k
+        del junk
+    assert int(pb.step_dev.item()) == 4 and pb.step_no == 4
+
+
+def test_device_step_adam_matches_host_step():
+    sc, cams, tgt = _setup()
+    pa = raster.Pipeline(raster.to_device(sc), cams, tgt)
+    pb = raster.Pipeline(raster.to_device(sc), cams, tgt, capacity=pa.capacity)
+    for k in range(3):
+        pa.step()                       # device counter
+        pb.step(adam_step=k + 1)        # explicit host step
+    torch.cuda.synchronize()
+    for name in raster.PARAM_NAMES:
+        assert torch.allclose(pa.params[name], pb.params[name], rtol=1e-6, atol=1e-7), name
+
+
+def test_autotune_pick_renders_the_same_image():
+    sc, cams, tgt = _setup()
+    params = raster.to_device(sc)
+    res = autotune.tune(params, cams, tgt, reps=2)
+    assert {(r["tile"], r["lds_batch"]) for r in res["table"]} == {
+        (t, b) for t in autotune.TILES for b in autotune.BATCHES}
+    # every candidate renders the oracle's image on the pixels outside the guard band
+    P = project.project(sc, cams[0])
+    F = render.render_fwd(P)
+    ok = ~F["flag"]
+    for tile, batch in ((res["tile"], res["lds_batch"]), (16, 256)):
+        f = raster.render(params, cams, tile=tile, lds_batch=batch)
+        img = f.image.view(3, cams[0].height, cams[0].width).cpu().numpy()
+        assert np.abs(img - F["image"])[:, ok].max() < 1e-5, (tile, batch)
+    assert autotune.tune(params, cams, tgt) is res      # cached
