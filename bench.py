@@ -242,17 +242,24 @@ def time_pipe(torch, pipe, steps):
 
 
 def level_sweep(torch, raster, scenes, params, tparams_scene, tile, lds):
+    """The plain single-view step at each downscale level of the schedule (8/4/2/1),
+    autotuned per level and replayed from a HIP graph."""
+    from paper_2503_18402_amd import autotune
+
     out = {}
     tparams = raster.to_device(tparams_scene, params["means"].device)
     for r in (8, 4, 2, 1):
         _, cam = scenes.config1(level=r, n=1)  # camera only
         tgt = raster.render(tparams, [cam], tile=tile).image.clone()
         p = {k: v.clone() for k, v in params.items()}
-        pipe = raster.Pipeline(p, [cam], tgt, tile=tile, lds_batch=lds)
+        pick = autotune.tune(p, [cam], tgt, reps=3)
+        pipe = raster.Pipeline(p, [cam], tgt, tile=pick["tile"], lds_batch=pick["lds_batch"])
+        pipe.capture()
         ms = time_pipe(torch, pipe, 10)
         out[f"r{r}"] = dict(width=cam.width, height=cam.height, ms_per_step=round(ms, 4),
-                            mpix_per_s=round(cam.width * cam.height / (ms / 1e3) / 1e6, 2))
-        log(f"level r={r}: {ms:.3f} ms/step")
+                            mpix_per_s=round(cam.width * cam.height / (ms / 1e3) / 1e6, 2),
+                            tile=pick["tile"], lds_batch=pick["lds_batch"])
+        log(f"level r={r}: {ms:.3f} ms/step (tile {pick['tile']}, batch {pick['lds_batch']})")
         del pipe, p
     return out
 

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd(
   __shared__ uint32_t s_mask[BATCH];
   __shared__ uint32_t s_pidx[BATCH];
 
-  const int t = xcd_tile(blockIdx.x, RV.total_tiles);
+  const int t = xcd_tile(blockIdx.x, RV);
   const int v = view_of_tile(RV, t);
   const int lt = t - RV.tile_base[v];
   const int gw = RV.gw[v], W = RV.W[v], H = RV.H[v];

@@ -59,16 +59,17 @@ __device__ __forceinline__ Alpha alpha_at(const float4 r0, const float C, const 
   return r;
 }
 
-// Workgroups are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8), and
-// each XCD has its own L2.  Neighbouring tiles share most of their Gaussians, so
-// block b takes tile number  xcd * q + min(xcd, r) + b / 8  (q, r = tiles / 8,
-// tiles % 8): every XCD walks one contiguous run of tiles and re-reads records
-// from its own L2.  A bijection on [0, tiles).
-constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_tile(int b, int tiles) {
-  const int q = tiles / kXcds, r = tiles % kXcds;
-  const int xcd = b % kXcds, idx = b / kXcds;
-  return xcd * q + min(xcd, r) + idx;
+// Workgroups are dealt to the XCDs round-robin (block b runs on XCD b % 8), and each
+// XCD has its own L2.  Neighbouring tiles share most of their Gaussians, so every
+// XCD walks one contiguous eighth of each view's tiles, views in order: block b is
+// the (b / 8)-th tile of XCD b % 8 in that walk.  This keeps L2 locality, balances
+// mixed-resolution batches across XCDs, and starts the views listed first first.
+// A bijection on [0, total tiles).
+__device__ __forceinline__ int xcd_tile(int b, const RViews& RV) {
+  const int x = b % kXcds, idx = b / kXcds;
+  int v = 0;
+  for (int k = 1; k < RV.n_views; ++k) v = (RV.xcd_off[x][k] <= idx) ? k : v;
+  return RV.tile_base[v] + RV.xcd_start[x][v] + (idx - RV.xcd_off[x][v]);
 }
 
 // global tile id -> view (views are few; the loop runs on the scalar unit)

@@ -25,7 +25,7 @@ __global__ __launch_bounds__(WaveShape<TILE>::kThreads) void k_blend_fwd(
   __shared__ uint32_t s_mask[BATCH];
   __shared__ uint16_t s_list[NW][BATCH];
 
-  const int t = xcd_tile(blockIdx.x, RV.total_tiles);
+  const int t = xcd_tile(blockIdx.x, RV);
   const int v = view_of_tile(RV, t);
   const int lt = t - RV.tile_base[v];
   const int gw = RV.gw[v], W = RV.W[v], H = RV.H[v];

@@ -57,9 +57,16 @@ struct Views {
 // so that the exponent of G2D in base 2 is p2 = A dx^2 + B dx dy + C dy^2.
 
 // Compact per-view raster info for the blend kernels.
+constexpr int kXcds = 8;  // MI355X: workgroups are dealt to 8 XCDs round-robin
+
 struct RViews {
   int32_t W[GS_MAX_VIEWS], H[GS_MAX_VIEWS], gw[GS_MAX_VIEWS], tile_base[GS_MAX_VIEWS];
   int64_t pix_base[GS_MAX_VIEWS];
+  // Each XCD takes one contiguous share of every view's tiles (see xcd_tile):
+  // xcd_off[x][v] = tiles XCD x takes from the views before v,
+  // xcd_start[x][v] = first tile (within view v) of XCD x's share.
+  int32_t xcd_off[kXcds][GS_MAX_VIEWS + 1];
+  int32_t xcd_start[kXcds][GS_MAX_VIEWS];
   int32_t n_views;
   int32_t total_tiles;
 };
@@ -75,6 +82,22 @@ inline RViews make_rviews(const Views& V) {
   }
   r.n_views = V.n_views;
   r.total_tiles = V.total_tiles;
+  // shares are tiles / 8 each; the tiles / 8 remainders of successive views are dealt
+  // to the XCDs cyclically, so XCD x ends up with exactly as many tiles as blocks
+  // b < total with b % 8 == x (the round-robin dispatch)
+  int rot = 0;
+  for (int x = 0; x < kXcds; ++x) r.xcd_off[x][0] = 0;
+  for (int k = 0; k < V.n_views; ++k) {
+    const int tiles = V.v[k].gw * V.v[k].gh, q = tiles / kXcds, rem = tiles % kXcds;
+    int start = 0;
+    for (int x = 0; x < kXcds; ++x) {
+      const int share = q + (((x - rot) & (kXcds - 1)) < rem ? 1 : 0);
+      r.xcd_start[x][k] = start;
+      r.xcd_off[x][k + 1] = r.xcd_off[x][k] + share;
+      start += share;
+    }
+    rot = (rot + rem) & (kXcds - 1);
+  }
   return r;
 }
 

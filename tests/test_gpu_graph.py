@@ -42,8 +42,9 @@ def test_graph_replay_equals_eager(multi):
         for name in raster.PARAM_NAMES:
             assert torch.equal(pa.params[name], pb.params[name]), (k, name)
         assert torch.equal(pa.image, pb.image), k
-        # the reported loss adds one float atomic per block: last bits may differ
-        assert torch.allclose(pa.loss, pb.loss, rtol=1e-6, atol=0), k
+        # the reported loss adds one float atomic per block (<= 1024 positive partials in any
+        # order: relative error <= 1024 eps); parameters and image are bit-identical
+        assert torch.allclose(pa.loss, pb.loss, rtol=1e-4, atol=0), k
         del junk
     assert int(pb.step_dev.item()) == 4 and pb.step_no == 4
 
