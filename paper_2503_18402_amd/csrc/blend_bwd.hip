@@ -160,8 +160,10 @@ __global__ __launch_bounds__(64) void k_blend_bwd(
           const float px = px0 + float((q % GX) * 8), py = py0 + float((q / GX) * 8);
           const Alpha e = alpha_at(r0, r1.x, o, px, py);
           const bool ok = e.ok & (pos <= last[q]);
+          // footprint boxes are conservative: often no pixel of the group is reached
+          if (__ballot(ok) == 0ull) continue;
           const bool grad = ok & (e.raw <= kAlphaMax);  // the 0.99 clamp passes no gradient
-          hit |= ok;
+          hit = true;
           const float inv = __builtin_amdgcn_rcpf(1.0f - e.a);
           const float Ti = T[q] * inv;
           const float wgt = ok ? e.a * Ti : 0.0f;
@@ -183,7 +185,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd(
           acc[1] = fmaf(dpow, fmaf(r0.w, e.dx, C2 * e.dy), acc[1]);
         }
       }
-      if (__ballot(hit) != 0ull) {
+      if (hit) {  // wave-uniform
         float qv[3];
         wave_sum9(acc, qv);
         const uint32_t idx = s_pidx[k];

@@ -98,12 +98,12 @@ __global__ __launch_bounds__(WaveShape<TILE>::kThreads) void k_blend_fwd(
       const float4 r1 = s_r1[k];
       const float cb = s_b[k];
       const uint32_t pos = bstart - start + uint32_t(k) + 1u;
-      bool any = false;
 #pragma unroll
       for (int p = 0; p < P; ++p) {
         // branch-free: every lane computes, the decisions select the updates
         const Alpha e = alpha_at(r0, r1.x, r1.y, pxc[p], pyc[p]);
         const bool ok = e.ok & !done[p];
+        if (__ballot(ok) == 0ull) continue;  // no pixel of this lane slot is reached
         const float Tn = T[p] * (1.0f - e.a);
         const bool stop = ok & (Tn < kTMin);
         const bool blend = ok & !stop;
@@ -114,8 +114,10 @@ __global__ __launch_bounds__(WaveShape<TILE>::kThreads) void k_blend_fwd(
         T[p] = blend ? Tn : T[p];
         last[p] = blend ? pos : last[p];
         done[p] = done[p] | stop;
-        any |= !done[p];
       }
+      bool any = false;
+#pragma unroll
+      for (int p = 0; p < P; ++p) any |= !done[p];
       if (__ballot(any) == 0ull) break;
     }
     __syncthreads();
