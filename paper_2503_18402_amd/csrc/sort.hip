@@ -1,250 +1,326 @@
-// Binning: (tile | depth) keys, a stable LSD radix sort on them, tile ranges.
+// Binning: one (tile, Gaussian) pair per tile of every visible footprint,
+// grouped by tile, ordered within a tile by (depth, Gaussian index), plus the
+// per-tile ranges.
 //
-// The 64-bit key is key = (tile_id << 32) | bits(depth_f32) and the sort is an
-// LSD radix sort with 8-bit digits.  An LSD sort handles the least significant
-// digits first, and every pair of one Gaussian carries the same depth bits, so
-// the four depth digits are sorted on the visible Gaussians themselves (about
-// one item per Gaussian) before the pairs are expanded; the expansion keeps
-// that order and the remaining tile digits are then sorted on the pairs.  The
-// result is exactly the stable sort of the full 64-bit keys (ties keep the
-// ascending Gaussian index, because items enter in index order), at a fraction
-// of the traffic of sorting every pair on every digit.
+// That order is the one of the stable ascending sort of
+// key = (tile_id << 32) | bits(depth_f32) over pairs emitted in Gaussian index
+// order.  Because the index breaks every tie, the order is unique, so any
+// correct sort produces it.  Instead of sorting all pairs globally on every key
+// digit, the pairs are bucketed by tile and each tile's (short) list is sorted
+// on chip:
+//   1. count:  one atomic increment per pair on its tile's counter;
+//   2. scan:   one block scans the counters into each tile's first slot and
+//              checks the pair total against the capacity;
+//   3. bucket: every pair claims a slot of its tile through an atomic cursor
+//              that counts down from the tile's end, and stores the 64-bit
+//              sort key (bits(depth_f32) << 32) | Gaussian index there;
+//   4. sort:   one block per tile sorts its keys with a bitonic network in LDS
+//              (lists longer than one LDS chunk also run the network's long
+//              strides through global memory) and writes the values, and the
+//              keys when asked for.
+// The slot order after step 3 depends on atomic timing; after step 4 it does
+// not.  The counters, cursors and first slots live in the caller's ranges
+// array (ranges[2t] = first slot, ranges[2t+1] = counter, then cursor, then
+// end), so the workspace holds only the bucketed keys and three counts.  The
+// cursor returns the slot itself: a pair never reads the line its atomic
+// updates.
 //
-// Each radix pass is reduce-then-scan (histogram, per-digit row scan, stable
-// scatter), with no inter-block waiting.  The stable in-block rank uses
-// wavefront ballots: the lanes holding the same digit are found with one
-// ballot per digit bit, and ranked with a popcount of the lanes below.
+// The pair expansion spreads each wave's pairs evenly over its 64 lanes, so a
+// Gaussian with a footprint of thousands of tiles does not serialise on one lane.
 #include "scan.hpp"
 
 namespace gsk {
 namespace {
-
-constexpr int kRT = 256;          // threads per radix block
-constexpr int kRIPT = 16;         // items per thread
-constexpr int kRTile = kRT * kRIPT;
-constexpr int kRWaveItems = kRTile / 4;
-
-__device__ inline int64_t cnt_blocks(int64_t n) { return (n + kRTile - 1) / kRTile; }
-
-__global__ __launch_bounds__(kRT) void k_radix_hist(const uint32_t* __restrict__ keys, Count cnt,
-                                                    int shift, int bits,
-                                                    uint32_t* __restrict__ hist) {
-  __shared__ uint32_t s_cnt[4][256];
-  const int64_t n = cnt.get();
-  const int64_t nb = cnt_blocks(n);
-  if (int64_t(blockIdx.x) >= nb) return;
-  for (int i = threadIdx.x; i < 4 * 256; i += kRT) (&s_cnt[0][0])[i] = 0;
-  __syncthreads();
-  const uint32_t mask = (1u << bits) - 1u;
-  const int w = threadIdx.x >> 6;
-  const int64_t base = int64_t(blockIdx.x) * kRTile;
-#pragma unroll 4
-  for (int k = 0; k < kRIPT; ++k) {
-    const int64_t i = base + int64_t(k) * kRT + threadIdx.x;
-    if (i < n) atomicAdd(&s_cnt[w][(keys[i] >> shift) & mask], 1u);
-  }
-  __syncthreads();
-  for (int d = threadIdx.x; d <= int(mask); d += kRT)
-    hist[int64_t(d) * nb + blockIdx.x] = s_cnt[0][d] + s_cnt[1][d] + s_cnt[2][d] + s_cnt[3][d];
-}
-
-// one block per digit: exclusive scan of that digit's per-block counts
-__global__ __launch_bounds__(kRT) void k_radix_rowscan(uint32_t* __restrict__ hist, Count cnt,
-                                                       uint32_t* __restrict__ digit_total) {
-  __shared__ uint32_t s_tmp[4];
-  const int64_t nb = cnt_blocks(cnt.get());
-  uint32_t* row = hist + int64_t(blockIdx.x) * nb;
-  uint32_t carry = 0;
-  for (int64_t c = 0; c < nb; c += kRT) {
-    const int64_t i = c + threadIdx.x;
-    const uint32_t x = (i < nb) ? row[i] : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan256(x, tot, s_tmp);
-    if (i < nb) row[i] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
-}
-
-__global__ __launch_bounds__(kRT) void k_radix_scatter(
-    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, Count cnt, int shift, int bits,
-    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ digit_total) {
-  __shared__ uint32_t s_wcnt[4][256];
-  __shared__ uint32_t s_key[kRTile];
-  __shared__ uint32_t s_val[kRTile];
-  __shared__ uint32_t s_boff[256];
-  __shared__ uint32_t s_gbase[256];
-  __shared__ uint32_t s_tmp[4];
-  const int64_t n = cnt.get();
-  const int64_t nb = cnt_blocks(n);
-  const int64_t b = blockIdx.x;
-  if (b >= nb) return;
-  const uint32_t mask = (1u << bits) - 1u;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int i = tid; i < 4 * 256; i += kRT) (&s_wcnt[0][0])[i] = 0;
-  __syncthreads();
-
-  const int64_t base = b * kRTile;
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  uint32_t key[kRIPT], val[kRIPT], dig[kRIPT], rank[kRIPT];
-#pragma unroll
-  for (int r = 0; r < kRIPT; ++r) {
-    const int64_t i = base + int64_t(w) * kRWaveItems + r * 64 + lane;
-    const bool valid = i < n;
-    const uint32_t k = valid ? kin[i] : 0u;
-    const uint32_t v = valid ? vin[i] : 0u;
-    const uint32_t d = (k >> shift) & mask;
-    uint64_t peers = __ballot(valid);
-    for (int bb = 0; bb < bits; ++bb) {
-      const bool bit = (d >> bb) & 1u;
-      const uint64_t m = __ballot(bit);
-      peers &= bit ? m : ~m;
-    }
-    const uint32_t c = s_wcnt[w][d];
-    rank[r] = c + uint32_t(__popcll(peers & lt));
-    // the highest lane of each digit group advances that digit's counter
-    if (valid && (peers >> lane) == 1ull) s_wcnt[w][d] = c + uint32_t(__popcll(peers));
-    key[r] = k;
-    val[r] = v;
-    dig[r] = valid ? d : 0xffffffffu;
-  }
-  __syncthreads();
-  // per digit: prefix over waves, block total, block-local and global offsets
-  {
-    const int d = tid;
-    const uint32_t c0 = s_wcnt[0][d], c1 = s_wcnt[1][d], c2 = s_wcnt[2][d], c3 = s_wcnt[3][d];
-    const uint32_t tot = c0 + c1 + c2 + c3;
-    uint32_t btot;
-    const uint32_t boff = block_excl_scan256(d <= int(mask) ? tot : 0u, btot, s_tmp);
-    const uint32_t dt = (d <= int(mask)) ? digit_total[d] : 0u;
-    uint32_t gtot;
-    const uint32_t gex = block_excl_scan256(dt, gtot, s_tmp);
-    s_wcnt[0][d] = 0;
-    s_wcnt[1][d] = c0;
-    s_wcnt[2][d] = c0 + c1;
-    s_wcnt[3][d] = c0 + c1 + c2;
-    s_boff[d] = boff;
-    if (d <= int(mask)) s_gbase[d] = gex + hist[int64_t(d) * nb + b];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < kRIPT; ++r) {
-    const uint32_t d = dig[r];
-    if (d != 0xffffffffu) {
-      const uint32_t pos = s_boff[d] + s_wcnt[w][d] + rank[r];
-      s_key[pos] = key[r];
-      s_val[pos] = val[r];
-    }
-  }
-  __syncthreads();
-  const int64_t m = (n - base < kRTile) ? (n - base) : kRTile;
-  for (int j = tid; j < m; j += kRT) {
-    const uint32_t k = s_key[j];
-    const uint32_t d = (k >> shift) & mask;
-    const uint32_t out = s_gbase[d] + (uint32_t(j) - s_boff[d]);
-    kout[out] = k;
-    vout[out] = s_val[j];
-  }
-}
-
-// One LSD pass on (key, value) u32 pairs: bits [shift, shift+bits), bits <= 8.
-hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
-                      Count cnt, int64_t max_n, int shift, int bits, uint32_t* hist,
-                      uint32_t* digit_total, hipStream_t st) {
-  const int64_t nb = (max_n + kRTile - 1) / kRTile;
-  if (nb == 0) return hipSuccess;
-  GS_LAUNCH("k_radix_hist", k_radix_hist, dim3(unsigned(nb)), dim3(kRT), 0, st, kin, cnt, shift, bits,
-                     hist);
-  GS_LAUNCH("k_radix_rowscan", k_radix_rowscan, dim3(1u << bits), dim3(kRT), 0, st, hist, cnt,
-                     digit_total);
-  GS_LAUNCH("k_radix_scatter", k_radix_scatter, dim3(unsigned(nb)), dim3(kRT), 0, st, kin, vin, kout, vout,
-                     cnt, shift, bits, hist, digit_total);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------- functors
-struct VisSrc {  // 1 for every (view, Gaussian) item with a non-empty footprint
-  const char* proj;
-  size_t stride, tt_off;
-  int n;
-  __device__ uint32_t operator()(int64_t i) const {
-    const int64_t v = i / n, g = i - v * n;
-    const uint32_t* tt = reinterpret_cast<const uint32_t*>(proj + v * stride + tt_off);
-    return tt[g] > 0u ? 1u : 0u;
-  }
-};
-struct VisDst {  // compact: depth bits as the key, item id as the value
-  const char* proj;
-  size_t stride;
-  int n;
-  uint32_t* key;
-  uint32_t* val;
-  __device__ void operator()(int64_t i, uint32_t pos, uint32_t flag) const {
-    if (!flag) return;
-    const int64_t v = i / n, g = i - v * n;
-    const float4* rec = reinterpret_cast<const float4*>(proj + v * stride);
-    key[pos] = __float_as_uint(rec[3 * g + 2].y);
-    val[pos] = uint32_t(i);
-  }
-};
-struct SortedTTSrc {  // tiles touched of the i-th depth-sorted item
-  const char* proj;
-  size_t stride, tt_off;
-  int n;
-  const uint32_t* items;
-  __device__ uint32_t operator()(int64_t i) const {
-    const uint32_t it = items[i];
-    const uint32_t v = it / uint32_t(n), g = it - v * uint32_t(n);
-    return reinterpret_cast<const uint32_t*>(proj + size_t(v) * stride + tt_off)[g];
-  }
-};
-struct OffDst {
-  uint32_t* off;
-  __device__ void operator()(int64_t i, uint32_t pos, uint32_t) const { off[i] = pos; }
-};
 
 struct TileInfo {  // per view: first global tile and grid width
   int32_t tile_base[GS_MAX_VIEWS];
   int32_t gw[GS_MAX_VIEWS];
 };
 
-__global__ __launch_bounds__(256) void k_finalize_count(const int64_t* __restrict__ total,
-                                                        int64_t cap, int64_t* __restrict__ n_eff,
-                                                        int64_t* __restrict__ n_pairs_user) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    const int64_t t = *total;
-    *n_eff = (t <= cap) ? t : 0;
-    *n_pairs_user = t;
+struct Items {  // the (view, Gaussian) items of a preprocess output
+  TileInfo TI;
+  const char* proj;
+  size_t stride, tt_off;
+  int64_t m;  // n_views * n
+  int n, tile;
+};
+
+constexpr int kXT = 256;  // threads per expansion block
+
+// Calls f(global tile id, sort key) once for every pair of the block's items.
+// Every thread of the block must call it.
+template <class F>
+__device__ inline void for_each_pair(const Items& S, F&& f) {
+  __shared__ uint32_t s_end[kXT];   // inclusive prefix of pair counts within the wave
+  __shared__ uint32_t s_base[kXT];  // global id of the footprint's first tile
+  __shared__ uint32_t s_w[kXT];     // footprint width in tiles
+  __shared__ uint32_t s_gw[kXT];    // tile-grid width of the item's view
+  __shared__ uint64_t s_key[kXT];   // bits(depth) << 32 | Gaussian index
+  const int lane = threadIdx.x & 63, w0 = threadIdx.x & ~63;
+  const int64_t i = int64_t(blockIdx.x) * kXT + threadIdx.x;
+  uint32_t cnt = 0, base = 0, w = 1, gw = 1;
+  uint64_t key = 0;
+  if (i < S.m) {
+    const int64_t v = i / S.n, g = i - v * S.n;
+    const char* pv = S.proj + size_t(v) * S.stride;
+    if (reinterpret_cast<const uint32_t*>(pv + S.tt_off)[g] > 0u) {
+      const float4 r2 = reinterpret_cast<const float4*>(pv)[3 * g + 2];
+      const uint32_t lo = __float_as_uint(r2.z), hi = __float_as_uint(r2.w);
+      const int tx0 = box_x(lo) / S.tile, ty0 = box_y(lo) / S.tile;
+      const int tx1 = box_x(hi) / S.tile, ty1 = box_y(hi) / S.tile;
+      w = uint32_t(tx1 - tx0 + 1);
+      cnt = w * uint32_t(ty1 - ty0 + 1);
+      gw = uint32_t(S.TI.gw[v]);
+      base = uint32_t(S.TI.tile_base[v]) + uint32_t(ty0) * gw + uint32_t(tx0);
+      key = (uint64_t(__float_as_uint(r2.y)) << 32) | uint64_t(g);
+    }
+  }
+  const uint32_t inc = wave_incl_scan(cnt);
+  s_end[threadIdx.x] = inc;
+  s_base[threadIdx.x] = base;
+  s_w[threadIdx.x] = w;
+  s_gw[threadIdx.x] = gw;
+  s_key[threadIdx.x] = key;
+  __syncthreads();
+  const uint32_t total = __shfl(inc, 63, 64);
+  for (uint32_t j = uint32_t(lane); j < total; j += 64) {
+    // the item owning the wave's j-th pair: the first k with s_end[k] > j
+    int k = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1)
+      if (s_end[w0 + k + step - 1] <= j) k += step;
+    const uint32_t local = j - (k > 0 ? s_end[w0 + k - 1] : 0u);
+    const uint32_t wk = s_w[w0 + k];
+    const uint32_t ty = local / wk, tx = local - ty * wk;
+    f(s_base[w0 + k] + ty * s_gw[w0 + k] + tx, s_key[w0 + k]);
   }
 }
 
-// one thread per depth-sorted visible item: write its (tile, Gaussian) pairs
-__global__ __launch_bounds__(256) void k_emit(TileInfo TI, int tile, int n, const char* proj,
-                                              size_t stride, const uint32_t* __restrict__ items,
-                                              const uint32_t* __restrict__ offs,
-                                              const int64_t* __restrict__ n_vis,
-                                              const int64_t* __restrict__ n_eff,
-                                              uint32_t* __restrict__ pair_tile,
-                                              uint32_t* __restrict__ pair_val) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= *n_vis || *n_eff == 0) return;
-  const uint32_t it = items[i];
-  const uint32_t v = it / uint32_t(n), g = it - v * uint32_t(n);
-  const float4 r2 = reinterpret_cast<const float4*>(proj + size_t(v) * stride)[3 * size_t(g) + 2];
-  const uint32_t lo = __float_as_uint(r2.z), hi = __float_as_uint(r2.w);
-  const int tx0 = box_x(lo) / tile, ty0 = box_y(lo) / tile;
-  const int tx1 = box_x(hi) / tile, ty1 = box_y(hi) / tile;
-  const int gw = TI.gw[v];
-  const uint32_t tb = uint32_t(TI.tile_base[v]);
-  uint32_t o = offs[i];
-  for (int ty = ty0; ty <= ty1; ++ty) {
-    const uint32_t row = tb + uint32_t(ty * gw);
-    for (int tx = tx0; tx <= tx1; ++tx) {
-      pair_tile[o] = row + uint32_t(tx);
-      pair_val[o] = g;
-      ++o;
+__global__ __launch_bounds__(kXT) void k_tile_count(Items S, uint32_t* __restrict__ ranges) {
+  for_each_pair(S, [&](uint32_t t, uint64_t) { atomicAdd(&ranges[2 * size_t(t) + 1], 1u); });
+}
+
+__global__ __launch_bounds__(kXT) void k_bucket(Items S, const int64_t* __restrict__ n_eff,
+                                                uint32_t* __restrict__ ranges,
+                                                uint64_t* __restrict__ bucket) {
+  if (*n_eff == 0) return;  // capacity overflow (or no pairs): nothing to place
+  for_each_pair(S, [&](uint32_t t, uint64_t key) {
+    bucket[atomicSub(&ranges[2 * size_t(t) + 1], 1u) - 1u] = key;
+  });
+}
+
+// One block: ranges[2t] = exclusive prefix of the counters ranges[2t+1] and
+// ranges[2t+1] = that prefix plus the count (the cursor start), the pair
+// total, and whether it fits the capacity.  Sums are 64-bit, so an
+// overflowing total is always detected.
+constexpr int kTS = 1024;
+constexpr int kTSItems = 8;
+
+__device__ inline uint64_t wave_incl_scan64(uint64_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
+__global__ __launch_bounds__(kTS) void k_tile_scan(uint32_t* __restrict__ ranges, int n_tiles,
+                                                   int64_t cap, int64_t* __restrict__ n_tot,
+                                                   int64_t* __restrict__ n_eff,
+                                                   int64_t* __restrict__ n_long,
+                                                   int64_t* __restrict__ n_pairs_user) {
+  __shared__ uint64_t s_w[kTS / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint64_t carry = 0;
+  for (int base = 0; base < n_tiles; base += kTS * kTSItems) {
+    const int i0 = base + threadIdx.x * kTSItems;
+    uint32_t c[kTSItems];
+    uint64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kTSItems; ++k) {
+      c[k] = (i0 + k < n_tiles) ? ranges[2 * size_t(i0 + k) + 1] : 0u;
+      s += c[k];
     }
+    const uint64_t inc = wave_incl_scan64(s);
+    if (lane == 63) s_w[wv] = inc;
+    __syncthreads();
+    uint64_t before = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < kTS / 64; ++q) {
+      const uint64_t t = s_w[q];
+      before += (q < wv) ? t : 0u;
+      tot += t;
+    }
+    __syncthreads();
+    uint64_t ex = carry + before + inc - s;
+#pragma unroll
+    for (int k = 0; k < kTSItems; ++k) {
+      if (i0 + k < n_tiles) {
+        ranges[2 * size_t(i0 + k)] = uint32_t(ex);
+        ranges[2 * size_t(i0 + k) + 1] = uint32_t(ex + c[k]);
+      }
+      ex += c[k];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    const int64_t t = int64_t(carry);
+    *n_tot = t;
+    *n_eff = (t <= cap) ? t : 0;
+    *n_pairs_user = t;
+    *n_long = 0;  // set by the small sort when a list is longer than it takes
+  }
+}
+
+// ---- bitonic network without directions: every step puts the smaller key at
+// the lower index.  A merge of block size 2h starts with a mirror step
+// (i, i ^ (2h - 1)) and continues with plain steps (i, i + d), d = h/2 .. 1.
+// Keys at indices >= n act as +infinity: every step with a partner >= n would
+// leave it in place, so they are neither stored nor compared.
+__device__ inline void step_pair(uint32_t c, uint32_t h, bool mirror, uint32_t& i, uint32_t& l) {
+  i = ((c & ~(h - 1)) << 1) | (c & (h - 1));
+  l = mirror ? ((i | (2 * h - 1)) - (c & (h - 1))) : (i + h);
+}
+
+template <int THREADS>
+__device__ inline void net_step(uint64_t* a, uint32_t n, uint32_t half_len, uint32_t h,
+                                bool mirror) {
+  for (uint32_t c = threadIdx.x; c < half_len; c += THREADS) {
+    uint32_t i, l;
+    step_pair(c, h, mirror, i, l);
+    if (l < n) {
+      const uint64_t x = a[i], y = a[l];
+      if (y < x) {
+        a[i] = y;
+        a[l] = x;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// full sort of a[0, n) (n <= len, len a power of two) in LDS
+template <int THREADS>
+__device__ inline void lds_sort(uint64_t* a, uint32_t n, uint32_t len) {
+  for (uint32_t h = 1; h < len; h <<= 1) {
+    net_step<THREADS>(a, n, len / 2, h, true);
+    for (uint32_t d = h >> 1; d > 0; d >>= 1) net_step<THREADS>(a, n, len / 2, d, false);
+  }
+}
+
+__device__ inline uint32_t pow2_ceil(uint32_t x) {
+  return x <= 1u ? 1u : (1u << (32 - __builtin_clz(x - 1u)));
+}
+
+template <int THREADS>
+__device__ inline void write_sorted(const uint64_t* a, uint32_t n, uint32_t start, uint32_t t,
+                                    uint32_t* __restrict__ vals, uint64_t* __restrict__ keys) {
+  for (uint32_t i = threadIdx.x; i < n; i += THREADS) {
+    const uint64_t k = a[i];
+    vals[start + i] = uint32_t(k);
+    if (keys) keys[start + i] = (uint64_t(t) << 32) | (k >> 32);
+  }
+}
+
+// Lists of at most kSmall keys, one 256-thread block per tile.  Also writes
+// every tile's range end (or [0,0) everywhere after a capacity overflow) and
+// flags the presence of longer lists.
+constexpr int kSmall = 2048;
+constexpr int kSmallThreads = 256;
+
+__global__ __launch_bounds__(kSmallThreads) void k_tile_sort_small(
+    int n_tiles, const int64_t* __restrict__ n_tot, const int64_t* __restrict__ n_eff,
+    int64_t* __restrict__ n_long, const uint64_t* __restrict__ bucket,
+    uint32_t* __restrict__ vals, uint64_t* __restrict__ keys, uint32_t* __restrict__ ranges) {
+  __shared__ uint64_t s[kSmall];
+  const uint32_t t = blockIdx.x;
+  if (*n_eff == 0) {
+    if (threadIdx.x == 0) {
+      ranges[2 * size_t(t)] = 0u;
+      ranges[2 * size_t(t) + 1] = 0u;
+    }
+    return;
+  }
+  // each block writes only its own range end (the cursor has counted down to
+  // the first slot); the next tile's first slot stays
+  const uint32_t start = ranges[2 * size_t(t)];
+  const uint32_t end = (t + 1 < uint32_t(n_tiles)) ? ranges[2 * size_t(t) + 2] : uint32_t(*n_tot);
+  if (threadIdx.x == 0) ranges[2 * size_t(t) + 1] = end;
+  const uint32_t n = end - start;
+  if (n > uint32_t(kSmall) && threadIdx.x == 0) *n_long = 1;
+  if (n == 0 || n > uint32_t(kSmall)) return;
+  for (uint32_t i = threadIdx.x; i < n; i += kSmallThreads) s[i] = bucket[start + i];
+  __syncthreads();
+  lds_sort<kSmallThreads>(s, n, pow2_ceil(n));
+  write_sorted<kSmallThreads>(s, n, start, t, vals, keys);
+}
+
+// Longer lists: 1024-thread blocks, each striding over the tiles (a block
+// needs most of a CU's LDS, so one block per tile would serialise on empty
+// tiles), with LDS chunks of kChunk keys.  A list of at most kChunk keys is
+// sorted in LDS.  A longer one is sorted in place in the bucket: each chunk is
+// sorted in LDS, then for every further merge size the strides >= kChunk run on
+// global memory and the shorter ones per chunk in LDS.  (All waves of a block
+// share one CU, whose L1 keeps the block's global writes coherent across the
+// barriers.)
+constexpr int kChunk = 16384;
+constexpr int kBigThreads = 1024;
+constexpr int kBigBlocks = 256;
+
+__device__ inline void sort_long(uint64_t* s, uint64_t* a, uint32_t n) {
+  const uint32_t len = pow2_ceil(n);
+  auto load = [&](uint32_t c0, uint32_t m) {
+    for (uint32_t i = threadIdx.x; i < m; i += kBigThreads) s[i] = a[c0 + i];
+    __syncthreads();
+  };
+  auto store = [&](uint32_t c0, uint32_t m) {
+    for (uint32_t i = threadIdx.x; i < m; i += kBigThreads) a[c0 + i] = s[i];
+    __syncthreads();
+  };
+  // every chunk sorted on its own (chunks are aligned blocks of the network)
+  for (uint32_t c0 = 0; c0 < n; c0 += kChunk) {
+    const uint32_t m = (n - c0 < uint32_t(kChunk)) ? n - c0 : uint32_t(kChunk);
+    load(c0, m);
+    lds_sort<kBigThreads>(s, m, kChunk);
+    store(c0, m);
+  }
+  for (uint32_t h = kChunk; h < len; h <<= 1) {
+    net_step<kBigThreads>(a, n, len / 2, h, true);
+    for (uint32_t d = h >> 1; d >= uint32_t(kChunk); d >>= 1)
+      net_step<kBigThreads>(a, n, len / 2, d, false);
+    for (uint32_t c0 = 0; c0 < n; c0 += kChunk) {
+      const uint32_t m = (n - c0 < uint32_t(kChunk)) ? n - c0 : uint32_t(kChunk);
+      load(c0, m);
+      for (uint32_t d = kChunk / 2; d > 0; d >>= 1)
+        net_step<kBigThreads>(s, m, kChunk / 2, d, false);
+      store(c0, m);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBigThreads) void k_tile_sort_big(
+    int n_tiles, const int64_t* __restrict__ n_eff, const int64_t* __restrict__ n_long,
+    uint64_t* __restrict__ bucket,
+    uint32_t* __restrict__ vals, uint64_t* __restrict__ keys,
+    const uint32_t* __restrict__ ranges) {
+  __shared__ uint64_t s[kChunk];
+  if (*n_eff == 0 || *n_long == 0) return;
+  for (uint32_t t = blockIdx.x; t < uint32_t(n_tiles); t += gridDim.x) {
+    const uint32_t start = ranges[2 * size_t(t)], end = ranges[2 * size_t(t) + 1];
+    const uint32_t n = end - start;
+    if (n <= uint32_t(kSmall)) continue;  // block-uniform
+    if (n <= uint32_t(kChunk)) {
+      for (uint32_t i = threadIdx.x; i < n; i += kBigThreads) s[i] = bucket[start + i];
+      __syncthreads();
+      lds_sort<kBigThreads>(s, n, pow2_ceil(n));
+      write_sorted<kBigThreads>(s, n, start, t, vals, keys);
+    } else {
+      sort_long(s, bucket + start, n);
+      write_sorted<kBigThreads>(bucket + start, n, start, t, vals, keys);
+    }
+    __syncthreads();  // s is reused by the block's next tile
   }
 }
 
@@ -255,132 +331,58 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int6
     p[i] = value;
 }
 
-__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tiles,
-                                                const int64_t* __restrict__ n_eff,
-                                                uint32_t* __restrict__ ranges) {
-  const int64_t n = *n_eff;
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t t = tiles[i];
-  if (i == 0 || tiles[i - 1] != t) ranges[2 * size_t(t)] = uint32_t(i);
-  if (i == n - 1 || tiles[i + 1] != t) ranges[2 * size_t(t) + 1] = uint32_t(i + 1);
-}
-
-__global__ __launch_bounds__(256) void k_keys(TileInfo TI, int n_views, int n, const char* proj,
-                                              size_t stride, const uint32_t* __restrict__ tiles,
-                                              const uint32_t* __restrict__ vals,
-                                              const int64_t* __restrict__ n_eff,
-                                              uint64_t* __restrict__ keys) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= *n_eff) return;
-  const uint32_t t = tiles[i];
-  int v = 0;
-  for (int k = 1; k < n_views; ++k) v = (uint32_t(TI.tile_base[k]) <= t) ? k : v;
-  const float4 r2 =
-      reinterpret_cast<const float4*>(proj + size_t(v) * stride)[3 * size_t(vals[i]) + 2];
-  keys[i] = (uint64_t(t) << 32) | uint64_t(__float_as_uint(r2.y));
-}
-
 struct WsLayout {
-  size_t ikey0, ikey1, ival0, ival1, offs, bsum, hist, dtot, cnt, ptile0, ptile1, pval, total;
-  WsLayout(int64_t M, int64_t cap) {
+  size_t cnt, bucket, total;
+  explicit WsLayout(int64_t cap) {
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
-    const int64_t mx = M > cap ? M : cap;
-    ikey0 = take(4 * M); ikey1 = take(4 * M); ival0 = take(4 * M); ival1 = take(4 * M);
-    offs = take(4 * M);
-    bsum = take(4 * scan_block_sums(mx));
-    hist = take(4 * 256 * size_t((mx + kRTile - 1) / kRTile + 1));
-    dtot = take(4 * 256);
-    cnt = take(8 * 4);
-    ptile0 = take(4 * cap); ptile1 = take(4 * cap); pval = take(4 * cap);
+    cnt = take(8 * 3);
+    bucket = take(8 * size_t(cap));
     total = o;
   }
 };
 
-int ceil_log2(int64_t x) {
-  int b = 0;
-  while ((int64_t(1) << b) < x) ++b;
-  return b;
-}
-
 }  // namespace
 
-size_t bin_sort_ws_bytes(int n_views, int n, int64_t cap) {
-  return WsLayout(int64_t(n_views) * n, cap).total;
-}
+size_t bin_sort_ws_bytes(int, int, int64_t cap) { return WsLayout(cap).total; }
 
 hipError_t launch_bin_sort(const Views& V, int n, const char* proj, int64_t cap, void* ws_,
                            uint64_t* keys, uint32_t* vals, uint32_t* ranges,
                            int64_t* n_pairs_dev, hipStream_t st) {
-  const int64_t M = int64_t(V.n_views) * n;
-  const WsLayout W(M, cap);
+  const WsLayout W(cap);
   char* ws = static_cast<char*>(ws_);
-  auto U = [&](size_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
   int64_t* counts = reinterpret_cast<int64_t*>(ws + W.cnt);
-  int64_t* n_vis = counts + 0;
-  int64_t* n_tot = counts + 1;
-  int64_t* n_eff = counts + 2;
+  int64_t* n_tot = counts + 0;
+  int64_t* n_eff = counts + 1;
+  int64_t* n_long = counts + 2;
+  uint64_t* bucket = reinterpret_cast<uint64_t*>(ws + W.bucket);
   const ProjLayout L(n);
-  hipError_t e;
-
-  // 1. compact the visible items: key = depth bits, value = item id
-  e = scan_exclusive(VisSrc{proj, L.stride, L.tt, n},
-                     VisDst{proj, L.stride, n, U(W.ikey0), U(W.ival0)}, Count{nullptr, M}, M,
-                     U(W.bsum), n_vis, nullptr, st);
-  if (e != hipSuccess) return e;
-  // 2. depth digits: four 8-bit passes on the items (even count: ends in buffer 0)
-  for (int p = 0; p < 4; ++p) {
-    const bool f = (p & 1) == 0;
-    e = radix_pass(U(f ? W.ikey0 : W.ikey1), U(f ? W.ival0 : W.ival1), U(f ? W.ikey1 : W.ikey0),
-                   U(f ? W.ival1 : W.ival0), Count{n_vis, 0}, M, 8 * p, 8, U(W.hist), U(W.dtot),
-                   st);
-    if (e != hipSuccess) return e;
-  }
-  // 3. pair offsets in depth order
-  e = scan_exclusive(SortedTTSrc{proj, L.stride, L.tt, n, U(W.ival0)}, OffDst{U(W.offs)},
-                     Count{n_vis, 0}, M, U(W.bsum), n_tot, nullptr, st);
-  if (e != hipSuccess) return e;
-  GS_LAUNCH("k_finalize_count", k_finalize_count, dim3(1), dim3(64), 0, st, n_tot, cap, n_eff, n_pairs_dev);
-
-  // 4. expand: pairs in depth order, tiles row-major within each footprint
-  TileInfo TI{};
+  Items S{};
   for (int v = 0; v < V.n_views; ++v) {
-    TI.tile_base[v] = V.v[v].tile_base;
-    TI.gw[v] = V.v[v].gw;
+    S.TI.tile_base[v] = V.v[v].tile_base;
+    S.TI.gw[v] = V.v[v].gw;
   }
-  const int tbits = ceil_log2(V.total_tiles);
-  const int passes = (tbits + 7) / 8;
-  uint32_t* vb[2];
-  vb[passes % 2] = vals;
-  vb[(passes + 1) % 2] = U(W.pval);
-  uint32_t* tb[2] = {U(W.ptile0), U(W.ptile1)};
-  if (M > 0) {
-    GS_LAUNCH("k_emit", k_emit, dim3(unsigned((M + 255) / 256)), dim3(256), 0, st, TI, V.tile, n,
-                       proj, L.stride, U(W.ival0), U(W.offs), n_vis, n_eff, tb[0], vb[0]);
-  }
-  // 5. tile digits on the pairs (stable: depth order survives within a tile)
-  int shift = 0;
-  for (int p = 0; p < passes; ++p) {
-    const int bits = (tbits - shift + (passes - p) - 1) / (passes - p);
-    e = radix_pass(tb[p & 1], vb[p & 1], tb[(p + 1) & 1], vb[(p + 1) & 1], Count{n_eff, 0}, cap,
-                   shift, bits, U(W.hist), U(W.dtot), st);
-    if (e != hipSuccess) return e;
-    shift += bits;
-  }
-  uint32_t* tiles_sorted = tb[passes & 1];
-  // 6. ranges
-  const int64_t nr = 2 * int64_t(V.total_tiles);
+  S.proj = proj;
+  S.stride = L.stride;
+  S.tt_off = L.tt;
+  S.m = int64_t(V.n_views) * n;
+  S.n = n;
+  S.tile = V.tile;
+  const int T = V.total_tiles;
+  const int64_t nr = 2 * int64_t(T);
+  const unsigned xb = unsigned((S.m + kXT - 1) / kXT);
+
   GS_LAUNCH("k_fill_u32", k_fill_u32, dim3(unsigned(nr / 256 + 1 < 4096 ? nr / 256 + 1 : 4096)),
-                     dim3(256), 0, st, ranges, nr, 0u);
-  if (cap > 0) {
-    GS_LAUNCH("k_ranges", k_ranges, dim3(unsigned((cap + 255) / 256)), dim3(256), 0, st,
-                       tiles_sorted, n_eff, ranges);
-    if (keys) {
-      GS_LAUNCH("k_keys", k_keys, dim3(unsigned((cap + 255) / 256)), dim3(256), 0, st, TI,
-                         V.n_views, n, proj, L.stride, tiles_sorted, vals, n_eff, keys);
-    }
-  }
+            dim3(256), 0, st, ranges, nr, 0u);
+  if (xb > 0) GS_LAUNCH("k_tile_count", k_tile_count, dim3(xb), dim3(kXT), 0, st, S, ranges);
+  GS_LAUNCH("k_tile_scan", k_tile_scan, dim3(1), dim3(kTS), 0, st, ranges, T, cap, n_tot, n_eff,
+            n_long, n_pairs_dev);
+  if (xb > 0)
+    GS_LAUNCH("k_bucket", k_bucket, dim3(xb), dim3(kXT), 0, st, S, n_eff, ranges, bucket);
+  GS_LAUNCH("k_tile_sort_small", k_tile_sort_small, dim3(unsigned(T)), dim3(kSmallThreads), 0, st,
+            T, n_tot, n_eff, n_long, bucket, vals, keys, ranges);
+  GS_LAUNCH("k_tile_sort_big", k_tile_sort_big, dim3(unsigned(T < kBigBlocks ? T : kBigBlocks)),
+            dim3(kBigThreads), 0, st, T, n_eff, n_long, bucket, vals, keys, ranges);
   return hipGetLastError();
 }
 
