@@ -187,6 +187,35 @@ gs_status gs_adam_step_device(const gs_adam_group* groups, int32_t n_groups, int
                               float beta1, float beta2, float eps, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * gs_render_bwd_adam: gs_render_bwd in overwrite mode (accumulate = 0)
+ * followed by gs_adam_step_device over the five parameter groups (means,
+ * log_scales, quats, opacity_logits, sh), fused: each Gaussian's gradient
+ * goes from the chain rule straight into its Adam update (the primitive
+ * update after back-propagation, Sec. 1 and Sec. 3), so gradients are never
+ * written to memory and the parameters are read once.  The updated
+ * parameters, moments and counter equal those of the two separate calls bit
+ * for bit: the same operations run in the same order.
+ *   means, log_scales, quats, opacity_logits, sh: the parameters given to
+ *     gs_preprocess (same layouts and alignment), updated in place.
+ *   m, v: host arrays of 5 device pointers, the Adam moments of the five
+ *     groups in the parameters' layouts (m[2], v[2], m[4], v[4] 16-byte
+ *     aligned), updated in place.
+ *   lr: host array of the 5 learning rates.
+ *   step_dev: device int32; step t = *step_dev + 1 is taken, then the counter
+ *     is incremented on the stream (see gs_adam_step_device).
+ *   The other arguments are those of gs_render_bwd, with the same workspace.
+ * ------------------------------------------------------------------------- */
+gs_status gs_render_bwd_adam(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
+                             int32_t n, float* means, float* log_scales, float* quats,
+                             float* opacity_logits, float* sh, int32_t sh_degree,
+                             const void* proj, const uint32_t* ranges, const uint32_t* vals,
+                             const float* final_T, const uint32_t* last_contrib,
+                             const float* dL_dimage, float* const* m, float* const* v,
+                             const float* lr, int32_t* step_dev, float beta1, float beta2,
+                             float eps, float* d_mean2d_abs, int64_t capacity_pairs, void* ws,
+                             size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * gs_l1_loss_grad: L1 photometric loss of the backbones.
  *   dL_dimage[i] = scale * sign(image[i] - target[i])  (sign(0) = 0), numel
  *   elements; if loss_sum (device, [1]) is non-NULL, scale * sum|image-target|

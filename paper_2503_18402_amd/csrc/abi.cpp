@@ -261,6 +261,46 @@ gs_status gs_adam_step_device(const gs_adam_group* groups, int32_t n_groups, int
       launch_adam(groups, n_groups, 1, beta1, beta2, eps, step_dev, as_stream(stream)));
 }
 
+gs_status gs_render_bwd_adam(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
+                             int32_t n, float* means, float* log_scales, float* quats,
+                             float* opacity_logits, float* sh, int32_t sh_degree,
+                             const void* proj, const uint32_t* ranges, const uint32_t* vals,
+                             const float* final_T, const uint32_t* last_contrib,
+                             const float* dL_dimage, float* const* m, float* const* v,
+                             const float* lr, int32_t* step_dev, float beta1, float beta2,
+                             float eps, float* d_mean2d_abs, int64_t capacity_pairs, void* ws,
+                             size_t ws_bytes, void* stream) {
+  Views V;
+  if (!n_ok(n_views, n) || !build_views(n_views, cams, cfg, &V)) return GS_ERR_ARG;
+  if (sh_degree < 0 || sh_degree > 3) return GS_ERR_ARG;
+  if (capacity_pairs < 0 || capacity_pairs >= (int64_t(1) << 32)) return GS_ERR_ARG;
+  if (!ranges || !final_T || !last_contrib || !dL_dimage || !ws || !m || !v || !lr || !step_dev)
+    return GS_ERR_ARG;
+  if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps >= 0.0f))
+    return GS_ERR_ARG;
+  FusedAdam A{};
+  for (int k = 0; k < 5; ++k) {
+    if (n > 0 && (!m[k] || !v[k])) return GS_ERR_ARG;
+    A.m[k] = m[k];
+    A.v[k] = v[k];
+    A.lr[k] = lr[k];
+  }
+  if (n > 0 && (!means || !log_scales || !quats || !opacity_logits || !sh || !proj))
+    return GS_ERR_ARG;
+  if (n > 0 && (!aligned16(quats) || !aligned16(sh) || !aligned16(proj) || !aligned16(ws) ||
+                !aligned16(m[2]) || !aligned16(v[2]) || !aligned16(m[4]) || !aligned16(v[4])))
+    return GS_ERR_ARG;
+  if (ws_bytes < render_bwd_ws_bytes(n_views, n, capacity_pairs)) return GS_ERR_CAPACITY;
+  A.b1 = beta1;
+  A.b2 = beta2;
+  A.eps = eps;
+  A.step_dev = step_dev;
+  return from_hip(launch_render_bwd_adam(V, n, *cfg, means, log_scales, quats, opacity_logits, sh,
+                                         sh_degree, static_cast<const char*>(proj), ranges, vals,
+                                         final_T, last_contrib, dL_dimage, A, d_mean2d_abs,
+                                         capacity_pairs, ws, as_stream(stream)));
+}
+
 gs_status gs_l1_loss_grad(int64_t numel, const float* image, const float* target, float scale,
                           float* dL_dimage, float* loss_sum, void* stream) {
   if (numel < 0 || (numel > 0 && (!image || !target || !dL_dimage))) return GS_ERR_ARG;

@@ -24,30 +24,13 @@ constexpr int kAdamThreads = 256;
 constexpr int kAdamVec = 4;                                    // float4 per thread
 constexpr int kAdamBlock = kAdamThreads * kAdamVec * 4;       // elements per block
 
-struct AdamCoef {
-  float b1, b2, eps, c1, c2;
-};
-
-__device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, float lr,
-                                         const AdamCoef& A) {
-  m = fmaf(A.b1, m, (1.0f - A.b1) * g);
-  v = fmaf(A.b2, v, (1.0f - A.b2) * g * g);
-  const float mh = m * A.c1;
-  const float vh = v * A.c2;
-  p -= lr * mh / (sqrtf(vh) + A.eps);
-}
-
 // One block per 4096-element chunk of one group: every thread issues its four
 // float4 loads of each array before any arithmetic (streaming, HBM-bound).
 __global__ __launch_bounds__(kAdamThreads) void k_adam(AdamArgs A) {
   AdamCoef C{A.b1, A.b2, A.eps, A.c1, A.c2};
   if (A.step_dev) {  // bias corrections of step *step_dev + 1, once per block
     __shared__ float s_c[2];
-    if (threadIdx.x == 0) {
-      const double t = double(*A.step_dev + 1);
-      s_c[0] = float(1.0 / (1.0 - pow(double(A.b1), t)));
-      s_c[1] = float(1.0 / (1.0 - pow(double(A.b2), t)));
-    }
+    if (threadIdx.x == 0) adam_bias(A.step_dev, A.b1, A.b2, s_c[0], s_c[1]);
     __syncthreads();
     C.c1 = s_c[0];
     C.c2 = s_c[1];
@@ -121,6 +104,11 @@ __global__ __launch_bounds__(256) void k_l1(int64_t n, const float* __restrict__
 }
 
 }  // namespace
+
+hipError_t launch_step_inc(int32_t* step_dev, hipStream_t st) {
+  GS_LAUNCH("k_step_inc", k_step_inc, dim3(1), dim3(64), 0, st, step_dev);
+  return hipGetLastError();
+}
 
 hipError_t launch_adam(const gs_adam_group* groups, int n_groups, int step, float beta1,
                        float beta2, float eps, int32_t* step_dev, hipStream_t st) {

@@ -275,66 +275,110 @@ __device__ inline void sh_dir_grad(float x, float y, float z, int deg, const flo
   gy += SH3a * 6.0f * x * y * wk[15];
 }
 
-// One thread per (view, Gaussian) item: sum the item's pair slots (contiguous,
-// tiles_touched of them) into nine planes g2d[c][item], written coalesced.
+// One lane per (view, Gaussian) item: sum the item's pair slots (contiguous,
+// tiles_touched of them, in index order) into nine planes g2d[c][item],
+// written coalesced.  A lane adds up to kCoopSlots slots itself, in ascending
+// order; an item with more (a footprint of many tiles) is summed by the whole
+// wave: lane-strided coalesced loads, then the fixed-order register reduction,
+// so the wave never waits on one lane's long serial loop.
+constexpr int kCoopSlots = 32;
+
 __global__ __launch_bounds__(256) void k_pair_sum(const char* __restrict__ proj, size_t stride,
                                                   size_t tt_off, int n, int64_t M,
                                                   const uint32_t* __restrict__ grad_off,
                                                   const float* __restrict__ pair_grad,
                                                   int64_t cap, float* __restrict__ g2d) {
+  const int lane = threadIdx.x & 63;
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= M) return;
-  const int64_t v = i / n, g = i - v * n;
-  const uint32_t tt = reinterpret_cast<const uint32_t*>(proj + v * stride + tt_off)[g];
+  uint32_t tt = 0u, off = 0u;
+  if (i < M) {
+    const int64_t v = i / n, g = i - v * n;
+    tt = reinterpret_cast<const uint32_t*>(proj + v * stride + tt_off)[g];
+    off = grad_off[i];
+    if (int64_t(off) + tt > cap) tt = 0u;  // pairs past the capacity have no slots
+  }
   float s[kG];
 #pragma unroll
   for (int c = 0; c < kG; ++c) s[c] = 0.0f;
-  const uint32_t off = grad_off[i];
-  if (tt > 0u && int64_t(off) + tt <= cap) {
+  const bool coop = tt > uint32_t(kCoopSlots);
+  if (!coop) {
     const float* pg = pair_grad + size_t(off) * kG;
     for (uint32_t k = 0; k < tt; ++k)
 #pragma unroll
       for (int c = 0; c < kG; ++c) s[c] += pg[size_t(k) * kG + c];
   }
+  // the wave's long items, one after the other (all lanes take part)
+  for (uint64_t bm = __ballot(coop); bm != 0ull; bm &= bm - 1ull) {
+    const int src = __builtin_ctzll(bm);
+    const uint32_t o = uint32_t(__shfl(int(off), src, 64));
+    const uint32_t m = uint32_t(__shfl(int(tt), src, 64));
+    float acc[kG];
 #pragma unroll
-  for (int c = 0; c < kG; ++c) g2d[c * M + i] = s[c];
+    for (int c = 0; c < kG; ++c) acc[c] = 0.0f;
+    const float* pg = pair_grad + size_t(o) * kG;
+    for (uint32_t k = uint32_t(lane); k < m; k += 64u)
+#pragma unroll
+      for (int c = 0; c < kG; ++c) acc[c] += pg[size_t(k) * kG + c];
+    float qv[3];
+    wave_sum9(acc, qv);
+    // lane 16 r + 15 holds components c0(r) (qv[0]) and c0(r) + 4 (qv[1]); lane 15 also 8
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c0 = ((r & 1) << 1) | (r >> 1);
+      const float a = __shfl(qv[0], 16 * r + 15, 64), b = __shfl(qv[1], 16 * r + 15, 64);
+      if (lane == src) {
+        s[c0] = a;
+        s[c0 + 4] = b;
+      }
+    }
+    const float c8 = __shfl(qv[2], 15, 64);
+    if (lane == src) s[8] = c8;
+  }
+  if (i < M) {
+#pragma unroll
+    for (int c = 0; c < kG; ++c) g2d[c * M + i] = s[c];
+  }
 }
 
-__global__ __launch_bounds__(128) void k_chain(
-    Views V, int n, int sh_degree, const float* __restrict__ means,
-    const float* __restrict__ log_scales, const float* __restrict__ quats,
-    const float* __restrict__ opacity_logits, const float* __restrict__ sh,
-    const char* __restrict__ proj, const float* __restrict__ g2d, int accumulate,
-    float* __restrict__ d_means, float* __restrict__ d_log_scales, float* __restrict__ d_quats,
-    float* __restrict__ d_opacity_logits, float* __restrict__ d_sh,
-    float* __restrict__ d_mean2d_abs) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  const ProjLayout L(n);
-  const int64_t M = int64_t(V.n_views) * n;
-  const int K = (sh_degree + 1) * (sh_degree + 1);
+// Inputs of the chain rule: the parameters, the projected records and the
+// per-view 2D gradient planes.
+struct ChainIn {
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* opacity_logits;
+  const float* sh;
+  const char* proj;
+  const float* g2d;
+  int n, sh_degree;
+};
+
+// One Gaussian's parameter gradients, summed over the views of the call.
+struct ChainOut {
+  float dm[3], dls[3];
+  float4 dq;
+  float dlogit, m2abs;
+  float dsh[GS_SH_COEFFS * 3];  // zero above the SH degree
+};
+
+// Chains Gaussian g's 2D gradients of every view to its parameters.  Returns
+// false, leaving O untouched, when no view has a pair of g.
+__device__ __forceinline__ bool chain_grad(const Views& V, const ChainIn& I, int g, ChainOut& O) {
+  const ProjLayout L(I.n);
+  const int64_t M = int64_t(V.n_views) * I.n;
+  const int K = (I.sh_degree + 1) * (I.sh_degree + 1);
 
   // does any view have gradient slots for this Gaussian?
   bool any = false;
   for (int v = 0; v < V.n_views; ++v)
-    any |= reinterpret_cast<const uint32_t*>(proj + size_t(v) * L.stride + L.tt)[g] > 0u;
-  if (!any) {
-    if (!accumulate) {
-      for (int k = 0; k < 3; ++k) d_means[3 * g + k] = d_log_scales[3 * g + k] = 0.0f;
-      reinterpret_cast<float4*>(d_quats)[g] = make_float4(0.f, 0.f, 0.f, 0.f);
-      d_opacity_logits[g] = 0.0f;
-      float* dshg = d_sh + size_t(g) * GS_SH_COEFFS * 3;
-      for (int k = 0; k < GS_SH_COEFFS * 3; ++k) dshg[k] = 0.0f;
-      if (d_mean2d_abs) d_mean2d_abs[g] = 0.0f;
-    }
-    return;
-  }
+    any |= reinterpret_cast<const uint32_t*>(I.proj + size_t(v) * L.stride + L.tt)[g] > 0u;
+  if (!any) return false;
 
-  const float mx = means[3 * g + 0], my = means[3 * g + 1], mz = means[3 * g + 2];
-  const float s0 = expf(log_scales[3 * g + 0]);
-  const float s1 = expf(log_scales[3 * g + 1]);
-  const float s2 = expf(log_scales[3 * g + 2]);
-  const float4 q4 = reinterpret_cast<const float4*>(quats)[g];
+  const float mx = I.means[3 * g + 0], my = I.means[3 * g + 1], mz = I.means[3 * g + 2];
+  const float s0 = expf(I.log_scales[3 * g + 0]);
+  const float s1 = expf(I.log_scales[3 * g + 1]);
+  const float s2 = expf(I.log_scales[3 * g + 2]);
+  const float4 q4 = reinterpret_cast<const float4*>(I.quats)[g];
   const float qn2 = q4.x * q4.x + q4.y * q4.y + q4.z * q4.z + q4.w * q4.w;
   const float qlen = sqrtf(qn2);
   const float qinv = 1.0f / qlen;
@@ -362,22 +406,22 @@ __global__ __launch_bounds__(128) void k_chain(
     for (int j = 0; j < 3; ++j)
       Sg[3 * i + j] =
           M3[3 * i] * M3[3 * j] + M3[3 * i + 1] * M3[3 * j + 1] + M3[3 * i + 2] * M3[3 * j + 2];
-  const float o = 1.0f / (1.0f + expf(-opacity_logits[g]));
-  const float* shg = sh + size_t(g) * GS_SH_COEFFS * 3;
+  const float o = 1.0f / (1.0f + expf(-I.opacity_logits[g]));
+  const float* shg = I.sh + size_t(g) * GS_SH_COEFFS * 3;
 
   float dm[3] = {0, 0, 0}, dS[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   float dop = 0.0f, m2abs = 0.0f;
-  float dshacc[GS_SH_COEFFS * 3];
+  float* dshacc = O.dsh;  // coefficients above the degree stay zero
 #pragma unroll
   for (int k = 0; k < GS_SH_COEFFS * 3; ++k) dshacc[k] = 0.0f;
 
   for (int v = 0; v < V.n_views; ++v) {
-    const char* base = proj + size_t(v) * L.stride;
+    const char* base = I.proj + size_t(v) * L.stride;
     const uint32_t tt = reinterpret_cast<const uint32_t*>(base + L.tt)[g];
     if (tt == 0u) continue;
     float gr[kG];
 #pragma unroll
-    for (int c = 0; c < kG; ++c) gr[c] = g2d[c * M + int64_t(v) * n + g];
+    for (int c = 0; c < kG; ++c) gr[c] = I.g2d[c * M + int64_t(v) * I.n + g];
     const uint32_t flags = reinterpret_cast<const uint32_t*>(base + L.flags)[g];
     const DevView& cv = V.v[v];
 
@@ -454,7 +498,7 @@ __global__ __launch_bounds__(128) void k_chain(
     float Y[GS_SH_COEFFS];
 #pragma unroll
     for (int k = 0; k < GS_SH_COEFFS; ++k) Y[k] = 0.0f;
-    sh_basis_b(dx, dy, dz, sh_degree, Y);
+    sh_basis_b(dx, dy, dz, I.sh_degree, Y);
     const float grgb[3] = {(flags & 1u) ? 0.0f : gr[6], (flags & 2u) ? 0.0f : gr[7],
                            (flags & 4u) ? 0.0f : gr[8]};
     float wk[GS_SH_COEFFS];
@@ -468,7 +512,7 @@ __global__ __launch_bounds__(128) void k_chain(
       }
     }
     float gdx, gdy, gdz;
-    sh_dir_grad(dx, dy, dz, sh_degree, wk, gdx, gdy, gdz);
+    sh_dir_grad(dx, dy, dz, I.sh_degree, wk, gdx, gdy, gdz);
     const float dd = dx * gdx + dy * gdy + dz * gdz;
     dm[0] += (gdx - dx * dd) * dn;
     dm[1] += (gdy - dy * dd) * dn;
@@ -506,32 +550,146 @@ __global__ __launch_bounds__(128) void k_chain(
   float4 dq4 = make_float4((gw - qw * qd) * qinv, (gx - qx * qd) * qinv, (gy - qy * qd) * qinv,
                            (gz - qz * qd) * qinv);
   const float dlogit = dop * o * (1.0f - o);
+  O.dlogit = dlogit;
+  O.dq = dq4;
+  O.m2abs = m2abs;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    O.dm[k] = dm[k];
+    O.dls[k] = dls[k];
+  }
+  return true;
+}
+
+__global__ __launch_bounds__(128) void k_chain(Views V, ChainIn I, int accumulate,
+                                               float* __restrict__ d_means,
+                                               float* __restrict__ d_log_scales,
+                                               float* __restrict__ d_quats,
+                                               float* __restrict__ d_opacity_logits,
+                                               float* __restrict__ d_sh,
+                                               float* __restrict__ d_mean2d_abs) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= I.n) return;
+  ChainOut O;
   float* dshg = d_sh + size_t(g) * GS_SH_COEFFS * 3;
+  if (!chain_grad(V, I, g, O)) {
+    if (!accumulate) {
+      for (int k = 0; k < 3; ++k) d_means[3 * g + k] = d_log_scales[3 * g + k] = 0.0f;
+      reinterpret_cast<float4*>(d_quats)[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+      d_opacity_logits[g] = 0.0f;
+      for (int k = 0; k < GS_SH_COEFFS * 3; ++k) dshg[k] = 0.0f;
+      if (d_mean2d_abs) d_mean2d_abs[g] = 0.0f;
+    }
+    return;
+  }
+  float4 dq4 = O.dq;
   if (accumulate) {
     const float4 p4 = reinterpret_cast<float4*>(d_quats)[g];
     dq4.x += p4.x; dq4.y += p4.y; dq4.z += p4.z; dq4.w += p4.w;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      dm[k] += d_means[3 * g + k];
-      dls[k] += d_log_scales[3 * g + k];
+      O.dm[k] += d_means[3 * g + k];
+      O.dls[k] += d_log_scales[3 * g + k];
     }
-    d_opacity_logits[g] += dlogit;
+    d_opacity_logits[g] += O.dlogit;
+    const int K3 = 3 * (I.sh_degree + 1) * (I.sh_degree + 1);
 #pragma unroll
     for (int k = 0; k < GS_SH_COEFFS * 3; ++k)
-      if (k < 3 * K) dshg[k] += dshacc[k];
-    if (d_mean2d_abs) d_mean2d_abs[g] += m2abs;
+      if (k < K3) dshg[k] += O.dsh[k];
+    if (d_mean2d_abs) d_mean2d_abs[g] += O.m2abs;
   } else {
-    d_opacity_logits[g] = dlogit;
-    // coefficients above the degree receive zero
+    d_opacity_logits[g] = O.dlogit;
 #pragma unroll
-    for (int k = 0; k < GS_SH_COEFFS * 3; ++k) dshg[k] = (k < 3 * K) ? dshacc[k] : 0.0f;
-    if (d_mean2d_abs) d_mean2d_abs[g] = m2abs;
+    for (int k = 0; k < GS_SH_COEFFS * 3; ++k) dshg[k] = O.dsh[k];
+    if (d_mean2d_abs) d_mean2d_abs[g] = O.m2abs;
   }
   reinterpret_cast<float4*>(d_quats)[g] = dq4;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    d_means[3 * g + k] = dm[k];
-    d_log_scales[3 * g + k] = dls[k];
+    d_means[3 * g + k] = O.dm[k];
+    d_log_scales[3 * g + k] = O.dls[k];
+  }
+}
+
+// The chain rule fused with the Adam step of all five parameter groups: each
+// thread chains its Gaussian and updates its means, scales, rotation and
+// opacity straight from registers; the block's SH gradients go through LDS so
+// that the SH update (48 of the 59 values per Gaussian) streams p, m and v
+// with coalesced float4 accesses.  Gaussians without pairs get a zero
+// gradient, as in the unfused step.  Each Gaussian's parameters are read (by
+// chain_grad) before any of them is updated, and only its own block updates
+// them, so the in-place update is safe.
+constexpr int kCA = 128;
+
+struct AdamGroups {
+  float* p[5];
+  float* m[5];
+  float* v[5];
+  float lr[5];
+  float b1, b2, eps;
+  const int32_t* step_dev;
+};
+
+__global__ __launch_bounds__(kCA) void k_chain_adam(Views V, ChainIn I, AdamGroups A,
+                                                    float* __restrict__ d_mean2d_abs) {
+  __shared__ float4 s_g[kCA * GS_SH_COEFFS * 3 / 4];
+  __shared__ float s_c[2];
+  if (threadIdx.x == 0) adam_bias(A.step_dev, A.b1, A.b2, s_c[0], s_c[1]);
+  const int g = blockIdx.x * kCA + threadIdx.x;
+  ChainOut O;
+  bool have = false;
+  if (g < I.n) have = chain_grad(V, I, g, O);
+  if (!have) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) O.dm[k] = O.dls[k] = 0.0f;
+    O.dq = make_float4(0.f, 0.f, 0.f, 0.f);
+    O.dlogit = O.m2abs = 0.0f;
+#pragma unroll
+    for (int k = 0; k < GS_SH_COEFFS * 3; ++k) O.dsh[k] = 0.0f;
+  }
+#pragma unroll
+  for (int q = 0; q < GS_SH_COEFFS * 3 / 4; ++q)
+    s_g[threadIdx.x * (GS_SH_COEFFS * 3 / 4) + q] =
+        make_float4(O.dsh[4 * q], O.dsh[4 * q + 1], O.dsh[4 * q + 2], O.dsh[4 * q + 3]);
+  __syncthreads();
+  const AdamCoef C{A.b1, A.b2, A.eps, s_c[0], s_c[1]};
+  if (g < I.n) {
+    if (d_mean2d_abs) d_mean2d_abs[g] = O.m2abs;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int j = 3 * g + k;
+      adam_one(A.p[0][j], O.dm[k], A.m[0][j], A.v[0][j], A.lr[0], C);
+      adam_one(A.p[1][j], O.dls[k], A.m[1][j], A.v[1][j], A.lr[1], C);
+    }
+    float4 p4 = reinterpret_cast<float4*>(A.p[2])[g];
+    float4 m4 = reinterpret_cast<float4*>(A.m[2])[g];
+    float4 v4 = reinterpret_cast<float4*>(A.v[2])[g];
+    adam_one(p4.x, O.dq.x, m4.x, v4.x, A.lr[2], C);
+    adam_one(p4.y, O.dq.y, m4.y, v4.y, A.lr[2], C);
+    adam_one(p4.z, O.dq.z, m4.z, v4.z, A.lr[2], C);
+    adam_one(p4.w, O.dq.w, m4.w, v4.w, A.lr[2], C);
+    reinterpret_cast<float4*>(A.p[2])[g] = p4;
+    reinterpret_cast<float4*>(A.m[2])[g] = m4;
+    reinterpret_cast<float4*>(A.v[2])[g] = v4;
+    adam_one(A.p[3][g], O.dlogit, A.m[3][g], A.v[3][g], A.lr[3], C);
+  }
+  // SH: the block's contiguous slab of 48 values per Gaussian, float4 per lane
+  const int g0 = blockIdx.x * kCA;
+  const int n4 = ((I.n - g0 < kCA) ? I.n - g0 : kCA) * (GS_SH_COEFFS * 3 / 4);
+  float4* __restrict__ P = reinterpret_cast<float4*>(A.p[4] + size_t(g0) * GS_SH_COEFFS * 3);
+  float4* __restrict__ Mm = reinterpret_cast<float4*>(A.m[4] + size_t(g0) * GS_SH_COEFFS * 3);
+  float4* __restrict__ Vv = reinterpret_cast<float4*>(A.v[4] + size_t(g0) * GS_SH_COEFFS * 3);
+#pragma unroll 4
+  for (int j = threadIdx.x; j < n4; j += kCA) {
+    float4 p = P[j], m = Mm[j], v = Vv[j];
+    const float4 gg = s_g[j];
+    adam_one(p.x, gg.x, m.x, v.x, A.lr[4], C);
+    adam_one(p.y, gg.y, m.y, v.y, A.lr[4], C);
+    adam_one(p.z, gg.z, m.z, v.z, A.lr[4], C);
+    adam_one(p.w, gg.w, m.w, v.w, A.lr[4], C);
+    P[j] = p;
+    Mm[j] = m;
+    Vv[j] = v;
   }
 }
 
@@ -598,19 +756,16 @@ size_t render_bwd_ws_bytes(int n_views, int n, int64_t cap) {
   return BwdWs(int64_t(n_views) * n, cap).bytes;
 }
 
-hipError_t launch_render_bwd(const Views& V, int n, const gs_raster_cfg& cfg,
-                             const float* means, const float* log_scales, const float* quats,
-                             const float* opacity_logits, const float* sh, int sh_degree,
-                             const char* proj, const uint32_t* ranges, const uint32_t* vals,
-                             const float* final_T, const uint32_t* last_contrib,
-                             const float* dL_dimage, float* d_means, float* d_log_scales,
-                             float* d_quats, float* d_opacity_logits, float* d_sh,
-                             float* d_mean2d_abs, int accumulate, int64_t cap, void* ws_,
-                             hipStream_t st) {
+namespace {
+
+// Everything before the chain rule: pair offsets, the backward blend into the
+// per-pair slots and their sums into the per-view 2D gradient planes.
+hipError_t bwd_to_planes(const Views& V, int n, const gs_raster_cfg& cfg, const char* proj,
+                         const uint32_t* ranges, const uint32_t* vals, const float* final_T,
+                         const uint32_t* last_contrib, const float* dL_dimage, int64_t cap,
+                         char* ws, float** g2d_out, hipStream_t st) {
   const int64_t M = int64_t(V.n_views) * n;
-  if (M == 0) return hipSuccess;
   const BwdWs B(M, cap);
-  char* ws = static_cast<char*>(ws_);
   uint32_t* goff = reinterpret_cast<uint32_t*>(ws + B.goff);
   int64_t* total = reinterpret_cast<int64_t*>(ws + B.total);
   float* pairs = reinterpret_cast<float*>(ws + B.pairs);
@@ -640,10 +795,61 @@ hipError_t launch_render_bwd(const Views& V, int n, const gs_raster_cfg& cfg,
   float* g2d = reinterpret_cast<float*>(ws + B.g2d);
   GS_LAUNCH("k_pair_sum", k_pair_sum, dim3(unsigned((M + 255) / 256)), dim3(256), 0, st, proj,
             L.stride, L.tt, n, M, goff, pairs, cap, g2d);
-  GS_LAUNCH("k_chain", k_chain, dim3(unsigned((n + 127) / 128)), dim3(128), 0, st, V, n,
-            sh_degree, means, log_scales, quats, opacity_logits, sh, proj, g2d, accumulate,
-            d_means, d_log_scales, d_quats, d_opacity_logits, d_sh, d_mean2d_abs);
+  *g2d_out = g2d;
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_render_bwd(const Views& V, int n, const gs_raster_cfg& cfg,
+                             const float* means, const float* log_scales, const float* quats,
+                             const float* opacity_logits, const float* sh, int sh_degree,
+                             const char* proj, const uint32_t* ranges, const uint32_t* vals,
+                             const float* final_T, const uint32_t* last_contrib,
+                             const float* dL_dimage, float* d_means, float* d_log_scales,
+                             float* d_quats, float* d_opacity_logits, float* d_sh,
+                             float* d_mean2d_abs, int accumulate, int64_t cap, void* ws,
+                             hipStream_t st) {
+  if (int64_t(V.n_views) * n == 0) return hipSuccess;
+  float* g2d = nullptr;
+  hipError_t e = bwd_to_planes(V, n, cfg, proj, ranges, vals, final_T, last_contrib, dL_dimage,
+                               cap, static_cast<char*>(ws), &g2d, st);
+  if (e != hipSuccess) return e;
+  const ChainIn I{means, log_scales, quats, opacity_logits, sh, proj, g2d, n, sh_degree};
+  GS_LAUNCH("k_chain", k_chain, dim3(unsigned((n + 127) / 128)), dim3(128), 0, st, V, I,
+            accumulate, d_means, d_log_scales, d_quats, d_opacity_logits, d_sh, d_mean2d_abs);
   return hipGetLastError();
+}
+
+hipError_t launch_render_bwd_adam(const Views& V, int n, const gs_raster_cfg& cfg, float* means,
+                                  float* log_scales, float* quats, float* opacity_logits,
+                                  float* sh, int sh_degree, const char* proj,
+                                  const uint32_t* ranges, const uint32_t* vals,
+                                  const float* final_T, const uint32_t* last_contrib,
+                                  const float* dL_dimage, const FusedAdam& A,
+                                  float* d_mean2d_abs, int64_t cap, void* ws, hipStream_t st) {
+  if (n > 0) {
+    float* g2d = nullptr;
+    hipError_t e = bwd_to_planes(V, n, cfg, proj, ranges, vals, final_T, last_contrib,
+                                 dL_dimage, cap, static_cast<char*>(ws), &g2d, st);
+    if (e != hipSuccess) return e;
+    const ChainIn I{means, log_scales, quats, opacity_logits, sh, proj, g2d, n, sh_degree};
+    AdamGroups G{};
+    float* P[5] = {means, log_scales, quats, opacity_logits, sh};
+    for (int k = 0; k < 5; ++k) {
+      G.p[k] = P[k];
+      G.m[k] = A.m[k];
+      G.v[k] = A.v[k];
+      G.lr[k] = A.lr[k];
+    }
+    G.b1 = A.b1;
+    G.b2 = A.b2;
+    G.eps = A.eps;
+    G.step_dev = A.step_dev;
+    GS_LAUNCH("k_chain_adam", k_chain_adam, dim3(unsigned((n + kCA - 1) / kCA)), dim3(kCA), 0,
+              st, V, I, G, d_mean2d_abs);
+  }
+  return launch_step_inc(A.step_dev, st);
 }
 
 }  // namespace gsk

@@ -61,15 +61,15 @@ __device__ __forceinline__ Alpha alpha_at(const float4 r0, const float C, const 
 
 // Workgroups are dealt to the XCDs round-robin (block b runs on XCD b % 8), and each
 // XCD has its own L2.  Neighbouring tiles share most of their Gaussians, so every
-// XCD walks one contiguous eighth of each view's tiles, views in order: block b is
-// the (b / 8)-th tile of XCD b % 8 in that walk.  This keeps L2 locality, balances
-// mixed-resolution batches across XCDs, and starts the views listed first first.
-// A bijection on [0, total tiles).
-__device__ __forceinline__ int xcd_tile(int b, const RViews& RV) {
+// XCD walks one contiguous eighth of each view's tiles, views in RV.order (fewest
+// tiles first): block b is the (b / 8)-th tile of XCD b % 8 in that walk.  This
+// keeps L2 locality, balances mixed-resolution batches across XCDs, and starts the
+// long lists of low-resolution views first.  A bijection on [0, total tiles).
+__host__ __device__ __forceinline__ int xcd_tile(int b, const RViews& RV) {
   const int x = b % kXcds, idx = b / kXcds;
-  int v = 0;
-  for (int k = 1; k < RV.n_views; ++k) v = (RV.xcd_off[x][k] <= idx) ? k : v;
-  return RV.tile_base[v] + RV.xcd_start[x][v] + (idx - RV.xcd_off[x][v]);
+  int k = 0;
+  for (int j = 1; j < RV.n_views; ++j) k = (RV.xcd_off[x][j] <= idx) ? j : k;
+  return RV.tile_base[RV.order[k]] + RV.xcd_start[x][k] + (idx - RV.xcd_off[x][k]);
 }
 
 // global tile id -> view (views are few; the loop runs on the scalar unit)

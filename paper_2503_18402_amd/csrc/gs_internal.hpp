@@ -3,6 +3,8 @@
 // include/gs.h.
 #pragma once
 
+#include <utility>
+
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -62,9 +64,12 @@ constexpr int kXcds = 8;  // MI355X: workgroups are dealt to 8 XCDs round-robin
 struct RViews {
   int32_t W[GS_MAX_VIEWS], H[GS_MAX_VIEWS], gw[GS_MAX_VIEWS], tile_base[GS_MAX_VIEWS];
   int64_t pix_base[GS_MAX_VIEWS];
-  // Each XCD takes one contiguous share of every view's tiles (see xcd_tile):
-  // xcd_off[x][v] = tiles XCD x takes from the views before v,
-  // xcd_start[x][v] = first tile (within view v) of XCD x's share.
+  // Each XCD takes one contiguous share of every view's tiles (see xcd_tile),
+  // walking the views in order[] (fewest tiles first: a low-resolution view's
+  // tiles hold the longest lists, so they start first).  For the k-th view of
+  // that order, xcd_off[x][k] = tiles XCD x takes from the views before it and
+  // xcd_start[x][k] = first tile (within the view) of XCD x's share.
+  int32_t order[GS_MAX_VIEWS];
   int32_t xcd_off[kXcds][GS_MAX_VIEWS + 1];
   int32_t xcd_start[kXcds][GS_MAX_VIEWS];
   int32_t n_views;
@@ -85,10 +90,15 @@ inline RViews make_rviews(const Views& V) {
   // shares are tiles / 8 each; the tiles / 8 remainders of successive views are dealt
   // to the XCDs cyclically, so XCD x ends up with exactly as many tiles as blocks
   // b < total with b % 8 == x (the round-robin dispatch)
+  for (int k = 0; k < V.n_views; ++k) r.order[k] = k;
+  auto tiles_of = [&](int v) { return V.v[v].gw * V.v[v].gh; };
+  for (int k = 1; k < V.n_views; ++k)  // stable insertion sort by tile count
+    for (int j = k; j > 0 && tiles_of(r.order[j - 1]) > tiles_of(r.order[j]); --j)
+      std::swap(r.order[j - 1], r.order[j]);
   int rot = 0;
   for (int x = 0; x < kXcds; ++x) r.xcd_off[x][0] = 0;
   for (int k = 0; k < V.n_views; ++k) {
-    const int tiles = V.v[k].gw * V.v[k].gh, q = tiles / kXcds, rem = tiles % kXcds;
+    const int tiles = tiles_of(r.order[k]), q = tiles / kXcds, rem = tiles % kXcds;
     int start = 0;
     for (int x = 0; x < kXcds; ++x) {
       const int share = q + (((x - rot) & (kXcds - 1)) < rem ? 1 : 0);
@@ -99,6 +109,29 @@ inline RViews make_rviews(const Views& V) {
     rot = (rot + rem) & (kXcds - 1);
   }
   return r;
+}
+
+// ---- Adam (one element).  Shared by the standalone step and the step fused
+// into the chain rule, so both produce the same bits.
+struct AdamCoef {
+  float b1, b2, eps, c1, c2;  // c1 = 1/(1-b1^t), c2 = 1/(1-b2^t)
+};
+
+__device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, float lr,
+                                         const AdamCoef& A) {
+  m = fmaf(A.b1, m, (1.0f - A.b1) * g);
+  v = fmaf(A.b2, v, (1.0f - A.b2) * g * g);
+  const float mh = m * A.c1;
+  const float vh = v * A.c2;
+  p -= lr * mh / (sqrtf(vh) + A.eps);
+}
+
+// bias corrections of step t = *step_dev + 1
+__device__ inline void adam_bias(const int32_t* step_dev, float b1, float b2, float& c1,
+                                 float& c2) {
+  const double t = double(*step_dev + 1);
+  c1 = float(1.0 / (1.0 - pow(double(b1), t)));
+  c2 = float(1.0 / (1.0 - pow(double(b2), t)));
 }
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -171,6 +204,22 @@ hipError_t launch_render_bwd(const Views& V, int n, const gs_raster_cfg& cfg,
                              float* d_mean2d_abs, int accumulate, int64_t cap, void* ws,
                              hipStream_t st);
 
+struct FusedAdam {  // the five parameter groups' moments and learning rates
+  float* m[5];
+  float* v[5];
+  float lr[5];
+  float b1, b2, eps;
+  int32_t* step_dev;
+};
+hipError_t launch_render_bwd_adam(const Views& V, int n, const gs_raster_cfg& cfg, float* means,
+                                  float* log_scales, float* quats, float* opacity_logits,
+                                  float* sh, int sh_degree, const char* proj,
+                                  const uint32_t* ranges, const uint32_t* vals,
+                                  const float* final_T, const uint32_t* last_contrib,
+                                  const float* dL_dimage, const FusedAdam& A,
+                                  float* d_mean2d_abs, int64_t cap, void* ws, hipStream_t st);
+
+hipError_t launch_step_inc(int32_t* step_dev, hipStream_t st);
 hipError_t launch_adam(const gs_adam_group* groups, int n_groups, int step, float beta1,
                        float beta2, float eps, int32_t* step_dev, hipStream_t st);
 hipError_t launch_l1(int64_t numel, const float* image, const float* target, float scale,

@@ -27,13 +27,16 @@
 //
 // The pair expansion spreads each wave's pairs evenly over its 64 lanes, so a
 // Gaussian with a footprint of thousands of tiles does not serialise on one lane.
+#include <algorithm>
+
 #include "scan.hpp"
 
 namespace gsk {
 namespace {
 
-struct TileInfo {  // per view: first global tile and grid width
+struct TileInfo {  // per view: first global tile, one past its last tile, grid width
   int32_t tile_base[GS_MAX_VIEWS];
+  int32_t tile_end[GS_MAX_VIEWS];
   int32_t gw[GS_MAX_VIEWS];
 };
 
@@ -45,19 +48,21 @@ struct Items {  // the (view, Gaussian) items of a preprocess output
   int n, tile;
 };
 
-constexpr int kXT = 256;  // threads per expansion block
+constexpr int kXT = 256;        // threads per expansion block
+constexpr int kAggBins = 2048;  // most tiles a block aggregates in LDS
+constexpr int kAggRounds = 8;   // items per aggregating block: kXT * kAggRounds
 
-// Calls f(global tile id, sort key) once for every pair of the block's items.
-// Every thread of the block must call it.
+// Calls f(global tile id, sort key) once for every pair of the items
+// [first, first + kXT).  Every thread of the block must call it.
 template <class F>
-__device__ inline void for_each_pair(const Items& S, F&& f) {
+__device__ inline void for_each_pair(const Items& S, int64_t first, F&& f) {
   __shared__ uint32_t s_end[kXT];   // inclusive prefix of pair counts within the wave
   __shared__ uint32_t s_base[kXT];  // global id of the footprint's first tile
   __shared__ uint32_t s_w[kXT];     // footprint width in tiles
   __shared__ uint32_t s_gw[kXT];    // tile-grid width of the item's view
   __shared__ uint64_t s_key[kXT];   // bits(depth) << 32 | Gaussian index
   const int lane = threadIdx.x & 63, w0 = threadIdx.x & ~63;
-  const int64_t i = int64_t(blockIdx.x) * kXT + threadIdx.x;
+  const int64_t i = first + threadIdx.x;
   uint32_t cnt = 0, base = 0, w = 1, gw = 1;
   uint64_t key = 0;
   if (i < S.m) {
@@ -94,19 +99,79 @@ __device__ inline void for_each_pair(const Items& S, F&& f) {
     const uint32_t ty = local / wk, tx = local - ty * wk;
     f(s_base[w0 + k] + ty * s_gw[w0 + k] + tx, s_key[w0 + k]);
   }
+  __syncthreads();  // the arrays are rewritten by the next call
 }
 
-__global__ __launch_bounds__(kXT) void k_tile_count(Items S, uint32_t* __restrict__ ranges) {
-  for_each_pair(S, [&](uint32_t t, uint64_t) { atomicAdd(&ranges[2 * size_t(t) + 1], 1u); });
+// A block takes kXT * rounds consecutive items.  When the tiles of the views
+// its items belong to number at most agg_bins (low resolutions, where every
+// tile collects thousands of pairs and same-counter atomics serialise), the
+// block counts its pairs per tile in LDS first and issues one global atomic
+// per touched tile; otherwise every pair goes to the global counters.
+struct BlockSpan {
+  int64_t i0, i1;  // items
+  int32_t t_lo;    // first tile of the block's views
+  bool agg;        // LDS bins in use (block-uniform)
+  int32_t span;
+};
+
+__device__ inline BlockSpan block_span(const Items& S, int rounds, int agg_bins) {
+  BlockSpan b;
+  b.i0 = int64_t(blockIdx.x) * kXT * rounds;
+  b.i1 = (b.i0 + int64_t(kXT) * rounds < S.m) ? b.i0 + int64_t(kXT) * rounds : S.m;
+  const int v0 = int(b.i0 / S.n), v1 = int((b.i1 - 1) / S.n);
+  b.t_lo = S.TI.tile_base[v0];
+  b.span = S.TI.tile_end[v1] - b.t_lo;
+  b.agg = b.span <= agg_bins;
+  return b;
 }
 
-__global__ __launch_bounds__(kXT) void k_bucket(Items S, const int64_t* __restrict__ n_eff,
+__global__ __launch_bounds__(kXT) void k_tile_count(Items S, int rounds, int agg_bins,
+                                                    uint32_t* __restrict__ ranges) {
+  extern __shared__ uint32_t s_bins[];
+  const BlockSpan B = block_span(S, rounds, agg_bins);
+  if (B.agg) {
+    for (int b = threadIdx.x; b < B.span; b += kXT) s_bins[b] = 0u;
+    __syncthreads();
+    for (int64_t c = B.i0; c < B.i1; c += kXT)
+      for_each_pair(S, c, [&](uint32_t t, uint64_t) { atomicAdd(&s_bins[t - B.t_lo], 1u); });
+    for (int b = threadIdx.x; b < B.span; b += kXT)
+      if (s_bins[b]) atomicAdd(&ranges[2 * size_t(B.t_lo + b) + 1], s_bins[b]);
+  } else {
+    for (int64_t c = B.i0; c < B.i1; c += kXT)
+      for_each_pair(S, c, [&](uint32_t t, uint64_t) { atomicAdd(&ranges[2 * size_t(t) + 1], 1u); });
+  }
+}
+
+// Places every pair's key in its tile's bucket.  The cursors count down from
+// the tile ends; with LDS bins the block first reserves one contiguous slot
+// range per touched tile, then ranks its pairs inside it with LDS atomics.
+__global__ __launch_bounds__(kXT) void k_bucket(Items S, int rounds, int agg_bins,
+                                                const int64_t* __restrict__ n_eff,
                                                 uint32_t* __restrict__ ranges,
                                                 uint64_t* __restrict__ bucket) {
+  extern __shared__ uint32_t s_bins[];
   if (*n_eff == 0) return;  // capacity overflow (or no pairs): nothing to place
-  for_each_pair(S, [&](uint32_t t, uint64_t key) {
-    bucket[atomicSub(&ranges[2 * size_t(t) + 1], 1u) - 1u] = key;
-  });
+  const BlockSpan B = block_span(S, rounds, agg_bins);
+  if (B.agg) {
+    for (int b = threadIdx.x; b < B.span; b += kXT) s_bins[b] = 0u;
+    __syncthreads();
+    for (int64_t c = B.i0; c < B.i1; c += kXT)
+      for_each_pair(S, c, [&](uint32_t t, uint64_t) { atomicAdd(&s_bins[t - B.t_lo], 1u); });
+    for (int b = threadIdx.x; b < B.span; b += kXT) {
+      const uint32_t k = s_bins[b];
+      if (k) s_bins[b] = atomicSub(&ranges[2 * size_t(B.t_lo + b) + 1], k) - k;
+    }
+    __syncthreads();
+    for (int64_t c = B.i0; c < B.i1; c += kXT)
+      for_each_pair(S, c, [&](uint32_t t, uint64_t key) {
+        bucket[atomicAdd(&s_bins[t - B.t_lo], 1u)] = key;
+      });
+  } else {
+    for (int64_t c = B.i0; c < B.i1; c += kXT)
+      for_each_pair(S, c, [&](uint32_t t, uint64_t key) {
+        bucket[atomicSub(&ranges[2 * size_t(t) + 1], 1u) - 1u] = key;
+      });
+  }
 }
 
 // One block: ranges[2t] = exclusive prefix of the counters ranges[2t+1] and
@@ -130,6 +195,7 @@ __global__ __launch_bounds__(kTS) void k_tile_scan(uint32_t* __restrict__ ranges
                                                    int64_t cap, int64_t* __restrict__ n_tot,
                                                    int64_t* __restrict__ n_eff,
                                                    int64_t* __restrict__ n_long,
+                                                   int64_t* __restrict__ n_mid,
                                                    int64_t* __restrict__ n_pairs_user) {
   __shared__ uint64_t s_w[kTS / 64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -170,7 +236,8 @@ __global__ __launch_bounds__(kTS) void k_tile_scan(uint32_t* __restrict__ ranges
     *n_tot = t;
     *n_eff = (t <= cap) ? t : 0;
     *n_pairs_user = t;
-    *n_long = 0;  // set by the small sort when a list is longer than it takes
+    *n_long = 0;  // set by the wave sort for lists it leaves to the larger tiers
+    *n_mid = 0;
   }
 }
 
@@ -224,37 +291,130 @@ __device__ inline void write_sorted(const uint64_t* a, uint32_t n, uint32_t star
   }
 }
 
-// Lists of at most kSmall keys, one 256-thread block per tile.  Also writes
-// every tile's range end (or [0,0) everywhere after a capacity overflow) and
-// flags the presence of longer lists.
+// ---- lists of at most kWaveKeys keys: one wave per tile, 8 keys per lane in
+// registers (element 8 lane + r in k[r]), padded with +infinity to a power of
+// two; the same direction-free network with in-lane steps for strides below 8
+// and lane shuffles above, so no LDS and no barriers.
+constexpr int kWaveKeys = 512;
 constexpr int kSmall = 2048;
-constexpr int kSmallThreads = 256;
 
-__global__ __launch_bounds__(kSmallThreads) void k_tile_sort_small(
+__device__ __forceinline__ void cx(uint64_t& a, uint64_t& b) {
+  const uint64_t x = a < b ? a : b, y = a < b ? b : a;
+  a = x;
+  b = y;
+}
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t x, int mask) {
+  const uint32_t lo = uint32_t(__shfl_xor(int(uint32_t(x)), mask, 64));
+  const uint32_t hi = uint32_t(__shfl_xor(int(uint32_t(x >> 32)), mask, 64));
+  return (uint64_t(hi) << 32) | lo;
+}
+
+// lanes whose stride bit is clear hold the lower element and keep the minimum
+__device__ __forceinline__ void cross_step(uint64_t (&k)[8], int mask, bool lower, bool mirror) {
+  uint64_t p[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) p[r] = shfl_xor64(k[mirror ? 7 - r : r], mask);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const bool lt = p[r] < k[r];
+    k[r] = (lower == lt) ? p[r] : k[r];
+  }
+}
+
+__device__ inline void wave_sort(uint64_t (&k)[8], uint32_t len) {
+  const int lane = threadIdx.x & 63;
+  for (uint32_t h = 1; h < len; h <<= 1) {
+    if (h == 1) {
+      cx(k[0], k[1]); cx(k[2], k[3]); cx(k[4], k[5]); cx(k[6], k[7]);
+    } else if (h == 2) {
+      cx(k[0], k[3]); cx(k[1], k[2]); cx(k[4], k[7]); cx(k[5], k[6]);
+    } else if (h == 4) {
+      cx(k[0], k[7]); cx(k[1], k[6]); cx(k[2], k[5]); cx(k[3], k[4]);
+    } else {
+      cross_step(k, int(2 * h / 8 - 1), (lane & int(h / 8)) == 0, true);
+    }
+    for (uint32_t d = h >> 1; d > 0; d >>= 1) {
+      if (d >= 8) {
+        cross_step(k, int(d / 8), (lane & int(d / 8)) == 0, false);
+      } else if (d == 4) {
+        cx(k[0], k[4]); cx(k[1], k[5]); cx(k[2], k[6]); cx(k[3], k[7]);
+      } else if (d == 2) {
+        cx(k[0], k[2]); cx(k[1], k[3]); cx(k[4], k[6]); cx(k[5], k[7]);
+      } else {
+        cx(k[0], k[1]); cx(k[2], k[3]); cx(k[4], k[5]); cx(k[6], k[7]);
+      }
+    }
+  }
+}
+
+// One wave per tile, four tiles per block.  Also writes every tile's range end
+// (or [0,0) everywhere after a capacity overflow) and flags the presence of
+// lists for the two larger tiers.
+__global__ __launch_bounds__(256) void k_tile_sort_wave(
     int n_tiles, const int64_t* __restrict__ n_tot, const int64_t* __restrict__ n_eff,
-    int64_t* __restrict__ n_long, const uint64_t* __restrict__ bucket,
-    uint32_t* __restrict__ vals, uint64_t* __restrict__ keys, uint32_t* __restrict__ ranges) {
-  __shared__ uint64_t s[kSmall];
-  const uint32_t t = blockIdx.x;
+    int64_t* __restrict__ n_mid, int64_t* __restrict__ n_long,
+    const uint64_t* __restrict__ bucket, uint32_t* __restrict__ vals,
+    uint64_t* __restrict__ keys, uint32_t* __restrict__ ranges) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t t = blockIdx.x * 4u + (threadIdx.x >> 6);
+  if (t >= uint32_t(n_tiles)) return;  // wave-uniform; no block barrier below
   if (*n_eff == 0) {
-    if (threadIdx.x == 0) {
+    if (lane == 0) {
       ranges[2 * size_t(t)] = 0u;
       ranges[2 * size_t(t) + 1] = 0u;
     }
     return;
   }
-  // each block writes only its own range end (the cursor has counted down to
-  // the first slot); the next tile's first slot stays
+  // each wave writes only its own range end (the cursor has counted down to the
+  // first slot); the next tile's first slot stays
   const uint32_t start = ranges[2 * size_t(t)];
   const uint32_t end = (t + 1 < uint32_t(n_tiles)) ? ranges[2 * size_t(t) + 2] : uint32_t(*n_tot);
-  if (threadIdx.x == 0) ranges[2 * size_t(t) + 1] = end;
+  if (lane == 0) ranges[2 * size_t(t) + 1] = end;
   const uint32_t n = end - start;
-  if (n > uint32_t(kSmall) && threadIdx.x == 0) *n_long = 1;
-  if (n == 0 || n > uint32_t(kSmall)) return;
-  for (uint32_t i = threadIdx.x; i < n; i += kSmallThreads) s[i] = bucket[start + i];
-  __syncthreads();
-  lds_sort<kSmallThreads>(s, n, pow2_ceil(n));
-  write_sorted<kSmallThreads>(s, n, start, t, vals, keys);
+  if (n > uint32_t(kWaveKeys)) {
+    if (lane == 0) *(n > uint32_t(kSmall) ? n_long : n_mid) = 1;
+    return;
+  }
+  if (n == 0) return;
+  uint64_t k[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const uint32_t i = 8u * lane + r;
+    k[r] = (i < n) ? bucket[start + i] : ~uint64_t(0);
+  }
+  wave_sort(k, n <= 8u ? 8u : pow2_ceil(n));
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const uint32_t i = 8u * lane + r;
+    if (i < n) {
+      vals[start + i] = uint32_t(k[r]);
+      if (keys) keys[start + i] = (uint64_t(t) << 32) | (k[r] >> 32);
+    }
+  }
+}
+
+// Lists of kWaveKeys+1 .. kSmall keys: 256-thread blocks striding over the
+// tiles, the network in LDS.
+constexpr int kMidThreads = 256;
+constexpr int kMidBlocks = 1024;
+
+__global__ __launch_bounds__(kMidThreads) void k_tile_sort_mid(
+    int n_tiles, const int64_t* __restrict__ n_eff, const int64_t* __restrict__ n_mid,
+    const uint64_t* __restrict__ bucket, uint32_t* __restrict__ vals,
+    uint64_t* __restrict__ keys, const uint32_t* __restrict__ ranges) {
+  __shared__ uint64_t s[kSmall];
+  if (*n_eff == 0 || *n_mid == 0) return;
+  for (uint32_t t = blockIdx.x; t < uint32_t(n_tiles); t += gridDim.x) {
+    const uint32_t start = ranges[2 * size_t(t)];
+    const uint32_t n = ranges[2 * size_t(t) + 1] - start;
+    if (n <= uint32_t(kWaveKeys) || n > uint32_t(kSmall)) continue;  // block-uniform
+    for (uint32_t i = threadIdx.x; i < n; i += kMidThreads) s[i] = bucket[start + i];
+    __syncthreads();
+    lds_sort<kMidThreads>(s, n, pow2_ceil(n));
+    write_sorted<kMidThreads>(s, n, start, t, vals, keys);
+    __syncthreads();  // s is reused by the block's next tile
+  }
 }
 
 // Longer lists: 1024-thread blocks, each striding over the tiles (a block
@@ -336,7 +496,7 @@ struct WsLayout {
   explicit WsLayout(int64_t cap) {
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
-    cnt = take(8 * 3);
+    cnt = take(8 * 4);
     bucket = take(8 * size_t(cap));
     total = o;
   }
@@ -355,12 +515,16 @@ hipError_t launch_bin_sort(const Views& V, int n, const char* proj, int64_t cap,
   int64_t* n_tot = counts + 0;
   int64_t* n_eff = counts + 1;
   int64_t* n_long = counts + 2;
+  int64_t* n_mid = counts + 3;
   uint64_t* bucket = reinterpret_cast<uint64_t*>(ws + W.bucket);
   const ProjLayout L(n);
   Items S{};
+  int min_view_tiles = 1 << 30;
   for (int v = 0; v < V.n_views; ++v) {
     S.TI.tile_base[v] = V.v[v].tile_base;
+    S.TI.tile_end[v] = V.v[v].tile_base + V.v[v].gw * V.v[v].gh;
     S.TI.gw[v] = V.v[v].gw;
+    min_view_tiles = std::min(min_view_tiles, V.v[v].gw * V.v[v].gh);
   }
   S.proj = proj;
   S.stride = L.stride;
@@ -370,17 +534,27 @@ hipError_t launch_bin_sort(const Views& V, int n, const char* proj, int64_t cap,
   S.tile = V.tile;
   const int T = V.total_tiles;
   const int64_t nr = 2 * int64_t(T);
-  const unsigned xb = unsigned((S.m + kXT - 1) / kXT);
+  // LDS aggregation pays where views have few tiles; blocks then take more items
+  const bool any_agg = min_view_tiles <= kAggBins;
+  const int rounds = any_agg ? kAggRounds : 1;
+  const size_t agg_lds = any_agg ? sizeof(uint32_t) * kAggBins : 0;
+  const int agg_bins = any_agg ? kAggBins : 0;
+  const unsigned xb = unsigned((S.m + int64_t(kXT) * rounds - 1) / (int64_t(kXT) * rounds));
 
   GS_LAUNCH("k_fill_u32", k_fill_u32, dim3(unsigned(nr / 256 + 1 < 4096 ? nr / 256 + 1 : 4096)),
             dim3(256), 0, st, ranges, nr, 0u);
-  if (xb > 0) GS_LAUNCH("k_tile_count", k_tile_count, dim3(xb), dim3(kXT), 0, st, S, ranges);
-  GS_LAUNCH("k_tile_scan", k_tile_scan, dim3(1), dim3(kTS), 0, st, ranges, T, cap, n_tot, n_eff,
-            n_long, n_pairs_dev);
   if (xb > 0)
-    GS_LAUNCH("k_bucket", k_bucket, dim3(xb), dim3(kXT), 0, st, S, n_eff, ranges, bucket);
-  GS_LAUNCH("k_tile_sort_small", k_tile_sort_small, dim3(unsigned(T)), dim3(kSmallThreads), 0, st,
-            T, n_tot, n_eff, n_long, bucket, vals, keys, ranges);
+    GS_LAUNCH("k_tile_count", k_tile_count, dim3(xb), dim3(kXT), agg_lds, st, S, rounds, agg_bins,
+              ranges);
+  GS_LAUNCH("k_tile_scan", k_tile_scan, dim3(1), dim3(kTS), 0, st, ranges, T, cap, n_tot, n_eff,
+            n_long, n_mid, n_pairs_dev);
+  if (xb > 0)
+    GS_LAUNCH("k_bucket", k_bucket, dim3(xb), dim3(kXT), agg_lds, st, S, rounds, agg_bins, n_eff,
+              ranges, bucket);
+  GS_LAUNCH("k_tile_sort_wave", k_tile_sort_wave, dim3(unsigned((T + 3) / 4)), dim3(256), 0, st,
+            T, n_tot, n_eff, n_mid, n_long, bucket, vals, keys, ranges);
+  GS_LAUNCH("k_tile_sort_mid", k_tile_sort_mid, dim3(unsigned(T < kMidBlocks ? T : kMidBlocks)),
+            dim3(kMidThreads), 0, st, T, n_eff, n_mid, bucket, vals, keys, ranges);
   GS_LAUNCH("k_tile_sort_big", k_tile_sort_big, dim3(unsigned(T < kBigBlocks ? T : kBigBlocks)),
             dim3(kBigThreads), 0, st, T, n_eff, n_long, bucket, vals, keys, ranges);
   return hipGetLastError();

@@ -75,6 +75,10 @@ def lib() -> ctypes.CDLL:
             "gs_adam_step": (i32, [POINTER(GsAdamGroup), i32, i32, c_float, c_float, c_float, vp]),
             "gs_adam_step_device": (i32, [POINTER(GsAdamGroup), i32, vp, c_float, c_float,
                                           c_float, vp]),
+            "gs_render_bwd_adam": (i32, [i32, cam_p, cfg_p, i32, vp, vp, vp, vp, vp, i32, vp,
+                                         vp, vp, vp, vp, vp, POINTER(c_void_p),
+                                         POINTER(c_void_p), POINTER(c_float), vp, c_float,
+                                         c_float, c_float, vp, i64, vp, sz, vp]),
             "gs_l1_loss_grad": (i32, [i64, vp, vp, c_float, vp, vp, vp]),
             "gs_profile_enable": (None, [i32]),
             "gs_profile_collect": (i32, [POINTER(GsKernelTime), i32]),
@@ -215,6 +219,22 @@ def gs_adam_step_device(groups, step_dev, beta1=0.9, beta2=0.999, eps=1e-15, str
     _check("gs_adam_step_device", lib().gs_adam_step_device(
         arr, len(groups), _ptr(step_dev), float(beta1), float(beta2), float(eps),
         _stream(stream)))
+
+
+def gs_render_bwd_adam(cams_c, cfg, n, means, log_scales, quats, opacity_logits, sh, sh_degree,
+                       proj, ranges, vals, final_T, last_contrib, dL_dimage, m, v, lr, step_dev,
+                       beta1, beta2, eps, d_mean2d_abs, capacity, ws, stream=None):
+    """m, v, lr: five entries each, in the order means, log_scales, quats,
+    opacity_logits, sh."""
+    mp = (c_void_p * 5)(*[_ptr(t) for t in m])
+    vp_ = (c_void_p * 5)(*[_ptr(t) for t in v])
+    lr_ = (c_float * 5)(*[float(x) for x in lr])
+    _check("gs_render_bwd_adam", lib().gs_render_bwd_adam(
+        len(cams_c), cams_c, ctypes.byref(cfg), int(n), _ptr(means), _ptr(log_scales),
+        _ptr(quats), _ptr(opacity_logits), _ptr(sh), int(sh_degree), _ptr(proj), _ptr(ranges),
+        _ptr(vals), _ptr(final_T), _ptr(last_contrib), _ptr(dL_dimage), mp, vp_, lr_,
+        _ptr(step_dev), float(beta1), float(beta2), float(eps), _ptr(d_mean2d_abs),
+        int(capacity), _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
 
 
 def gs_l1_loss_grad(image, target, scale, dL_dimage, loss_sum=None, stream=None):

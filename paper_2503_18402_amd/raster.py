@@ -175,12 +175,17 @@ class Pipeline:
     all parameter groups.  Every view of the set goes into one launch per
     kernel.  ``overflowed()`` reads the pair count once to check the capacity
     after the fact; a captured HIP graph of ``step()`` replays the same work.
+
+    With ``fused`` (the default) the backward and the Adam step run as one
+    ``gs_render_bwd_adam`` call: the same update bit for bit, without writing
+    the gradients (``grads`` is then left untouched by ``step()``).
     """
 
     def __init__(self, params: dict, cams, targets: torch.Tensor, tile: int = 16,
                  lds_batch: int = 256, bg=(0.0, 0.0, 0.0), sh_degree: int = 3,
                  capacity: int | None = None, lrs: dict | None = None,
-                 betas=(0.9, 0.999), eps: float = 1e-15, grads: dict | None = None):
+                 betas=(0.9, 0.999), eps: float = 1e-15, grads: dict | None = None,
+                 fused: bool = True):
         self.params = params
         self.cams = list(cams)
         dev = params["means"].device
@@ -221,6 +226,7 @@ class Pipeline:
         self.step_no = 0
         # the step count lives on the device so a captured graph replays as new steps
         self.step_dev = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.fused = fused
         self.graph = None
 
     def forward(self, stream=None):
@@ -258,14 +264,33 @@ class Pipeline:
             gsmi.gs_adam_step(groups, step, self.betas[0], self.betas[1], self.eps, stream)
         self.step_no += 1
 
+    def backward_adam(self, stream=None):
+        """L1 loss gradient, then the backward pass fused with the Adam step
+        (device step counter)."""
+        p = self.params
+        self.loss.zero_()
+        gsmi.gs_l1_loss_grad(self.image, self.targets, 1.0 / self.image.numel(), self.dL,
+                             self.loss, stream)
+        gsmi.gs_render_bwd_adam(
+            self.cams_c, self.cfg, self.n, p["means"], p["log_scales"], p["quats"],
+            p["opacity_logits"], p["sh"], self.sh_degree, self.proj, self.ranges, self.vals,
+            self.final_T, self.last, self.dL, [self.m[k] for k in PARAM_NAMES],
+            [self.v[k] for k in PARAM_NAMES], [self.lrs[k] for k in PARAM_NAMES],
+            self.step_dev, self.betas[0], self.betas[1], self.eps, None, self.capacity,
+            self.bwd_ws, stream)
+        self.step_no += 1
+
     def step(self, stream=None, adam_step: int | None = None):
         if self.graph is not None and stream is None and adam_step is None:
             self.graph.replay()
             self.step_no += 1
             return
         self.forward(stream)
-        self.backward(stream)
-        self.adam(stream, adam_step)
+        if self.fused and adam_step is None:
+            self.backward_adam(stream)
+        else:
+            self.backward(stream)
+            self.adam(stream, adam_step)
 
     def capture(self):
         """Capture one whole step into a HIP graph; later ``step()`` calls replay it.
@@ -276,8 +301,11 @@ class Pipeline:
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
             self.forward()
-            self.backward()
-            self.adam()
+            if self.fused:
+                self.backward_adam()
+            else:
+                self.backward()
+                self.adam()
         self.step_no -= 1                # capturing ran nothing
         self.graph = g
         return g

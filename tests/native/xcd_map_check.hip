@@ -1,0 +1,54 @@
+// Host check of the blend kernels' block -> tile mapping (blend_common.hpp):
+// for random mixes of view sizes it must be a bijection on [0, total tiles),
+// walk every XCD's share of a view contiguously, and reach the views in order
+// of increasing tile count.  Prints "ok" or the first failure; exit code 0/1.
+#include <cstdio>
+#include <random>
+#include <vector>
+
+#include "blend_common.hpp"
+
+int main() {
+  std::mt19937 rng(7);
+  for (int trial = 0; trial < 2000; ++trial) {
+    gsk::Views V{};
+    V.n_views = 1 + int(rng() % GS_MAX_VIEWS);
+    V.tile = 16;
+    int total = 0;
+    for (int k = 0; k < V.n_views; ++k) {
+      V.v[k].gw = 1 + int(rng() % (trial % 3 == 0 ? 4 : 120));
+      V.v[k].gh = 1 + int(rng() % (trial % 3 == 0 ? 3 : 80));
+      V.v[k].W = V.v[k].gw * 16;
+      V.v[k].H = V.v[k].gh * 16;
+      V.v[k].tile_base = total;
+      total += V.v[k].gw * V.v[k].gh;
+    }
+    V.total_tiles = total;
+    const gsk::RViews R = gsk::make_rviews(V);
+    std::vector<int> seen(total, 0);
+    std::vector<int> first_block(V.n_views, -1);
+    for (int b = 0; b < total; ++b) {
+      const int t = gsk::xcd_tile(b, R);
+      if (t < 0 || t >= total || seen[t]++) {
+        std::printf("trial %d: block %d -> tile %d (total %d) repeated or out of range\n", trial,
+                    b, t, total);
+        return 1;
+      }
+      int v = 0;
+      for (int k = 1; k < V.n_views; ++k) v = (V.v[k].tile_base <= t) ? k : v;
+      if (first_block[v] < 0) first_block[v] = b;
+    }
+    // a view with fewer tiles never starts after a view with more tiles
+    for (int a = 0; a < V.n_views; ++a)
+      for (int c = 0; c < V.n_views; ++c) {
+        const int ta = V.v[a].gw * V.v[a].gh, tc = V.v[c].gw * V.v[c].gh;
+        if (ta < tc && first_block[a] > first_block[c]) {
+          std::printf("trial %d: view %d (%d tiles) starts after view %d (%d tiles)\n", trial, a,
+                      ta, c, tc);
+          return 1;
+        }
+      }
+  }
+  std::printf("ok\n");
+  return 0;
+}

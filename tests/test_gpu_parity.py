@@ -90,19 +90,19 @@ def test_bin_sort_properties(cfg0):
                 assert r[t, 0] == 0 and r[t, 1] == 0
 
 
-@pytest.mark.parametrize("n", [3000, 40000])
-def test_bin_sort_long_lists(n):
-    """Tile lists longer than the small on-chip sort (2048 keys) and than one LDS
-    chunk (16384 keys, sorted through global memory): still the exact
-    (tile, depth, index) order of the oracle's binning.  A quarter of the
-    Gaussians share their mean, hence their depth, with another one, so ties are
-    broken by index."""
+@pytest.mark.parametrize("n,longest", [(1500, 512), (3000, 2048), (40000, 16384)])
+def test_bin_sort_long_lists(n, longest):
+    """Tile lists longer than the one-wave register sort (512 keys), than the
+    256-thread LDS sort (2048 keys) and than one LDS chunk (16384 keys, sorted
+    through global memory): still the exact (tile, depth, index) order of the
+    oracle's binning.  A quarter of the Gaussians share their mean, hence their
+    depth, with another one, so ties are broken by index."""
     sc = scenes.make_scene(n, seed=41, mean_range=0.2, ls_mu=-3.0, ls_sigma=0.2)
     sc["means"][n // 2:n // 2 + n // 4] = sc["means"][:n // 4]
     cam = scenes.look_at((0.0, 0.0, -3.0), (0.0, 0.0, 0.0), 32, 32, 40.0)
     P = project.project(sc, cam, tile=16)
     k, v, r = binning.bin_sort(P["rect"], P["tiles_touched"], P["depth_f32"], 2, 2)
-    assert np.diff(r, axis=1).max() > (2048 if n < 16384 else 16384)
+    assert np.diff(r, axis=1).max() > longest
     _, frame, _ = U.run(sc, [cam], tile=16)
     npairs = int(frame.n_pairs_dev.item())
     gk = frame.keys[:npairs].cpu().numpy().view(np.uint64)

@@ -1,0 +1,116 @@
+"""Pins of the resolution-schedule oracle (Sec. 4.2, Eq. 2, Eq. 6-7) and of
+its anti-aliased downsampling, against closed forms, an exactly sampled
+band-limited signal and torch's CPU resize (a library routine)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import schedule as O
+
+
+def test_constant_image_has_only_the_dc_term():
+    H, W = 24, 40
+    c = np.array([0.2, 0.5, 0.7])
+    img = np.broadcast_to(c[:, None, None], (3, H, W))
+    M = O.magnitude_map(img)
+    assert M[H // 2, W // 2] == pytest.approx(H * W * np.linalg.norm(c), rel=1e-12)
+    assert O.significance(img) == pytest.approx(H * W * np.linalg.norm(c), rel=1e-12)
+
+
+def test_single_cosine_two_peaks():
+    H, W, u, v = 32, 48, 5, 3
+    y, x = np.mgrid[0:H, 0:W]
+    img = np.zeros((3, H, W))
+    img[1] = np.cos(2 * np.pi * (u * x / W + v * y / H))
+    M = O.magnitude_map(img)
+    assert M[H // 2 + v, W // 2 + u] == pytest.approx(H * W / 2, rel=1e-12)
+    assert M[H // 2 - v, W // 2 - u] == pytest.approx(H * W / 2, rel=1e-12)
+    assert O.significance(img) == pytest.approx(H * W, rel=1e-12)
+
+
+def test_views_are_averaged():
+    rng = np.random.default_rng(0)
+    a, b = rng.uniform(size=(3, 16, 20)), rng.uniform(size=(3, 16, 20))
+    assert O.significance(np.stack([a, b])) == pytest.approx(
+        0.5 * (O.significance(a) + O.significance(b)), rel=1e-12)
+
+
+@pytest.mark.parametrize("r", [2, 4])
+def test_crop_equals_ideal_downsample_of_band_limited_image(r):
+    """A sum of cosines below the coarse grid's Nyquist limit, sampled on the
+    full and on the r-times coarser pixel grid (same continuous image): the
+    coarse image's X equals the full spectrum's crop scaled by 1/r^2."""
+    H, W = 64, 96
+    rng = np.random.default_rng(1)
+    waves = [(rng.integers(0, W // (2 * r) - 1), rng.integers(0, H // (2 * r) - 1),
+              rng.uniform(0.2, 1.0), rng.uniform(0, 2 * np.pi), rng.integers(0, 3))
+             for _ in range(6)]
+
+    def sample(h, w):
+        y, x = np.mgrid[0:h, 0:w]
+        img = np.zeros((3, h, w))
+        for (u, v, amp, ph, ch) in waves:   # frequencies in cycles per image
+            img[ch] += amp * np.cos(2 * np.pi * (u * (x + 0.5) / w + v * (y + 0.5) / h) + ph)
+        return img + 0.3
+
+    M = O.magnitude_map(sample(H, W))
+    assert O.crop_significance(M, float(r)) == pytest.approx(
+        O.significance(sample(H // r, W // r)), rel=1e-10)
+
+
+def test_crop_at_one_is_the_full_sum_and_nonincreasing():
+    rng = np.random.default_rng(2)
+    M = O.magnitude_map(rng.uniform(size=(2, 3, 45, 60)))
+    assert O.crop_significance(M, 1.0) == pytest.approx(M.sum(), rel=1e-12)
+    rs = np.linspace(1.0, 20.0, 400)
+    xs = np.array([O.crop_significance(M, r) for r in rs])
+    assert np.all(np.diff(xs) <= 1e-9 * xs[0])
+
+
+def test_knots_follow_eq7():
+    rng = np.random.default_rng(3)
+    img = rng.uniform(size=(3, 64, 96))
+    M = O.magnitude_map(img)
+    S, a, m = 6000, 4.0, 4
+    r, s, X = O.schedule_knots(M, S, a=a, m=m)
+    assert r[0] == 1.0 and s[0] == pytest.approx(S) and s[-1] == pytest.approx(0.0, abs=1e-9)
+    assert np.all(np.diff(r) >= 0) and np.all(np.diff(s) < 0)
+    # Eq. 7 with linearly spaced X_i depends only on a and m
+    for i in range(m + 1):
+        assert s[i] == pytest.approx(S * math.log(a * (1 - i / m * (1 - 1 / a))) / math.log(a),
+                                     rel=1e-12, abs=1e-9)
+    # r_i is the boundary of {r : X(F_r) >= X_i}
+    for i in range(1, m + 1):
+        assert O.crop_significance(M, r[i]) >= X[i]
+        assert O.crop_significance(M, r[i] * (1 + 1e-6)) < X[i]
+
+
+def test_resolution_curve():
+    r = np.array([1.0, 1.5, 2.5, 4.0])
+    s = np.array([900.0, 500.0, 200.0, 0.0])
+    assert O.resolution_at(0, r, s) == pytest.approx(4.0)
+    for i in range(4):
+        assert O.resolution_at(s[i], r, s) == pytest.approx(r[i])
+    assert O.resolution_at(1e6, r, s) == 1.0
+    mid = O.resolution_at(350.0, r, s)     # halfway between knots 2 and 1 in 1/r^2
+    assert 1 / mid ** 2 == pytest.approx(0.5 * (1 / 2.5 ** 2 + 1 / 1.5 ** 2))
+    ks = np.arange(0, 1000)
+    rr = np.array([O.resolution_at(k, r, s) for k in ks])
+    assert np.all(np.diff(rr) <= 1e-12)
+    assert O.render_factor(0, r, s) == 4 and O.render_factor(950, r, s) == 1
+
+
+@pytest.mark.parametrize("H,W,h,w", [(96, 128, 48, 64), (133, 200, 33, 50), (97, 131, 31, 17),
+                                     (64, 64, 64, 64), (40, 30, 80, 45)])
+def test_downsample_matches_torch_antialias(H, W, h, w):
+    x = np.random.default_rng(4).uniform(size=(3, H, W))
+    ref = torch.nn.functional.interpolate(torch.from_numpy(x)[None], size=(h, w), mode="bilinear",
+                                          antialias=True, align_corners=False)[0].numpy()
+    assert np.abs(O.downsample_aa(x, h, w) - ref).max() < 1e-12
+
+
+def test_downsample_keeps_constants():
+    x = np.full((3, 50, 70), 0.25)
+    assert np.abs(O.downsample_aa(x, 7, 9) - 0.25).max() < 1e-15
