@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--cpu-pixels", type=int, default=16)
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 4M-Gaussian, 16-view workload")
     ap.add_argument("--no-extras", action="store_true", help="skip levels and batched form")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run warmup + this many steps (for rocprofv3), no extras")
@@ -182,6 +184,8 @@ def main():
         extras["levels"] = level_sweep(torch, raster, scenes, params, tparams_scene=tscene,
                                        tile=args.tile, lds=args.lds_batch)
         extras["batched"] = batched_vs_plain(torch, raster, scenes, params, tscene)
+        if not args.no_large:
+            extras["large"] = large_scene(torch, raster, scenes, dev)
 
     cpu = None if args.no_cpu else cpu_baseline(scene, cam, args.cpu_pixels)
 
@@ -271,12 +275,30 @@ def batched_vs_plain(torch, raster, scenes, params, tscene):
     per-view calls accumulating into one gradient buffer, then the same Adam.
     Both forms use autotuned tile / LDS batch (per mix, per resolution) and are
     captured as HIP graphs; eager times are reported too."""
-    from paper_2503_18402_amd import autotune
-
     cams = scenes.config3_views()
     tparams = raster.to_device(tscene, params["means"].device)
     tgts = [raster.render(tparams, [c]).image.clone() for c in cams]
     del tparams
+    return compare_forms(torch, raster, params, cams, tgts, "16 views (config 3)")
+
+
+def large_scene(torch, raster, scenes, dev):
+    """The large workload: 4M Gaussians, 8 views at 1920x1080 and 8 at 960x540,
+    gradients of all 16 views accumulated into one Adam step over 236M floats;
+    seeded uniform random targets."""
+    scene, cams = scenes.config4()
+    params = raster.to_device(scene, dev)
+    del scene
+    gen = torch.Generator(device=dev).manual_seed(2)
+    tgts = [torch.rand(3 * c.width * c.height, generator=gen, device=dev) for c in cams]
+    out = compare_forms(torch, raster, params, cams, tgts, "16 views, 4M Gaussians (config 4)")
+    out["n_gaussians"] = int(params["means"].shape[0])
+    return out
+
+
+def compare_forms(torch, raster, params, cams, tgts, label):
+    from paper_2503_18402_amd import autotune
+
     p = {k: v.clone() for k, v in params.items()}
     cat = torch.cat(tgts)
     tb = autotune.tune(p, cams, cat, reps=3)
@@ -284,6 +306,7 @@ def batched_vs_plain(torch, raster, scenes, params, tscene):
     ms_b_eager = time_pipe(torch, batched, 5)
     batched.capture()
     ms_b = time_pipe(torch, batched, 5)
+    pairs_b = int(batched.n_pairs.item())
     del batched
     # plain: per-resolution autotuned pipelines sharing one gradient buffer
     grads = raster.zero_grads(p)
@@ -319,9 +342,10 @@ def batched_vs_plain(torch, raster, scenes, params, tscene):
         plain_iter()
     ms_p = timed(g.replay, 3)
     assert not any(pp.overflowed() for pp in plains)
-    log(f"16 views: batched {ms_b:.3f} ms/it (eager {ms_b_eager:.3f}), plain {ms_p:.3f} ms/it "
+    del plains, g
+    log(f"{label}: batched {ms_b:.3f} ms/it (eager {ms_b_eager:.3f}), plain {ms_p:.3f} ms/it "
         f"(eager {ms_p_eager:.3f})")
-    return dict(views=16, pixels=sum(c.width * c.height for c in cams),
+    return dict(views=len(cams), pixels=sum(c.width * c.height for c in cams), pairs=pairs_b,
                 batched_it_s=round(1e3 / ms_b, 2), plain_it_s=round(1e3 / ms_p, 2),
                 speedup=round(ms_p / ms_b, 3),
                 batched_eager_it_s=round(1e3 / ms_b_eager, 2),

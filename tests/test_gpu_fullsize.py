@@ -132,3 +132,24 @@ def test_gradcheck_smooth_subcase():
     B = render.render_bwd(sc, P, w, with_bound=True)
     for k, name in zip(inp, raster.PARAM_NAMES):
         U.check_grads(k.grad.cpu().numpy(), B["d_" + name], B["bound"]["d_" + name], max_frac=0.0)
+
+
+def test_large_scene_batched_sampled_pixels():
+    """The 4M-Gaussian workload: all 16 views (8 at 1920x1080, 8 at 960x540) in
+    one batched launch, in the bench's launch configuration; sampled pixels of
+    one view of each resolution (plus the ragged edges) against the oracle."""
+    sc, cams = scenes.config4()
+    params = raster.to_device(sc, "cuda")
+    fb = raster.render(params, cams, tile=TILE, lds_batch=BATCH)
+    imgs = fb.images()
+    torch.cuda.synchronize()
+    del params
+    for k in (0, 12):
+        cam = cams[k]
+        P = project.project(sc, cam, tile=TILE)
+        pix = _sample_pixels(cam, 8, seed=30 + k)
+        F = render.render_fwd(P, pixels=pix, chunk=4)
+        img = imgs[k].reshape(3, -1).cpu().numpy()[:, pix]
+        ok = ~F["flag"]
+        assert ok.sum() >= len(pix) - 2
+        assert np.abs(img - F["image"])[:, ok].max() < 1e-5, k
