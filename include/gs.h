@@ -216,6 +216,47 @@ gs_status gs_render_bwd_adam(int32_t n_views, const gs_camera* cams, const gs_ra
                              size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * The frequency-guided resolution schedule (Sec. 4.2, Eq. 2; supplementary
+ * Eq. 6-7) and the anti-aliased ground-truth downsampling (supplementary,
+ * "Ground Truth Downsampling").
+ *
+ * gs_frequency_map: mag[H][W] (device, FP64, natural DFT order: index (ky, kx)
+ *   holds frequency (ky, kx) modulo (H, W)) = (1/n) sum over the n views of
+ *   ||F^n(ky, kx)||_2, F^n the unnormalised 2D DFT of view n and the norm
+ *   taken over the 3 colour channels (Eq. 2 before the sum over (ky, kx)).
+ *   images: device [n][3][H][W] FP32, planar.  1 <= H, W <= 4096, n >= 1.
+ *   Computed in FP64; deterministic.  ws: gs_frequency_map_workspace_bytes.
+ * ------------------------------------------------------------------------- */
+size_t gs_frequency_map_workspace_bytes(int32_t H, int32_t W);
+gs_status gs_frequency_map(int32_t n_images, int32_t H, int32_t W, const float* images,
+                           double* mag, void* ws, size_t ws_bytes, void* stream);
+
+/* gs_resolution_schedule (host code, host arrays): the knots of the
+ * resolution schedule for S iterations from a frequency map copied to the
+ * host.  X(F_r) = (1/r^2) * (sum of mag over |f_y| <= H/(2r), |f_x| <= W/(2r)),
+ * the spectrum of the ideal downsample by r.  r_m is the largest r in
+ * [1, r_max] with X(F_r) >= X(F)/a (r_max <= 0: min(H, W)); the values
+ * X_i = X(F) - (i/m)(X(F) - X(F)/a), i = 1..m-1, are solved for r_i the same
+ * way (bisection), and Eq. 7 gives s_i = S ln(X_i / X_m) / ln(X(F) / X_m).
+ *   r_knots, s_knots: m + 1 entries each, knot 0 = (r 1, s S), knot m =
+ *   (r_m, s 0).  m >= 1, a > 1, S > 0. */
+gs_status gs_resolution_schedule(const double* mag_host, int32_t H, int32_t W, double S, double a,
+                                 int32_t m, double r_max, double* r_knots, double* s_knots);
+
+/* gs_schedule_resolution: r at iteration k for the knots above, 1/r^2 linear
+ * in k between consecutive knots, 1 from s_0 = S on, r_m before s_m = 0.
+ * The render uses the integer factor floor(r). */
+double gs_schedule_resolution(double k, int32_t m, const double* r_knots, const double* s_knots);
+
+/* gs_downsample_aa: [n_planes][H][W] -> [n_planes][h][w] (device, FP32)
+ * anti-aliased linear resampling: output sample i is centred at input
+ * coordinate (i + 0.5) * H / h (pixel centres at +0.5) and weighs the inputs
+ * with a triangle of half-width max(1, H / h) input pixels, normalised to sum
+ * 1; likewise along W.  1 <= h, H, w, W <= 16384. */
+gs_status gs_downsample_aa(int32_t n_planes, int32_t H, int32_t W, int32_t h, int32_t w,
+                           const float* src, float* dst, void* stream);
+
+/* ---------------------------------------------------------------------------
  * gs_l1_loss_grad: L1 photometric loss of the backbones.
  *   dL_dimage[i] = scale * sign(image[i] - target[i])  (sign(0) = 0), numel
  *   elements; if loss_sum (device, [1]) is non-NULL, scale * sum|image-target|

@@ -129,6 +129,7 @@ def aa_weights(n_in: int, n_out: int) -> np.ndarray:
 
 
 def downsample_aa(img, h: int, w: int) -> np.ndarray:
-    """[C, H, W] -> [C, h, w] anti-aliased resize (rows, then columns)."""
+    """[C, H, W] -> [C, h, w] anti-aliased resize: Wy @ I_c @ Wx^T per channel."""
     x = np.asarray(img, dtype=np.float64)
-    return np.einsum("ij,cjk,lk->cil", aa_weights(x.shape[1], h), x, aa_weights(x.shape[2], w))
+    Wy, Wx = aa_weights(x.shape[1], h), aa_weights(x.shape[2], w)
+    return np.stack([Wy @ x[c] @ Wx.T for c in range(x.shape[0])])

@@ -301,6 +301,52 @@ gs_status gs_render_bwd_adam(int32_t n_views, const gs_camera* cams, const gs_ra
                                          capacity_pairs, ws, as_stream(stream)));
 }
 
+size_t gs_frequency_map_workspace_bytes(int32_t H, int32_t W) {
+  if (H < 1 || W < 1 || H > kDftMax || W > kDftMax) return 0;
+  return frequency_map_ws_bytes(H, W);
+}
+
+gs_status gs_frequency_map(int32_t n_images, int32_t H, int32_t W, const float* images,
+                           double* mag, void* ws, size_t ws_bytes, void* stream) {
+  if (n_images < 1 || H < 1 || W < 1 || H > kDftMax || W > kDftMax) return GS_ERR_ARG;
+  if (!images || !mag || !ws) return GS_ERR_ARG;
+  if (ws_bytes < frequency_map_ws_bytes(H, W)) return GS_ERR_CAPACITY;
+  if (!aligned16(ws)) return GS_ERR_ARG;
+  return from_hip(launch_frequency_map(n_images, H, W, images, mag, ws, as_stream(stream)));
+}
+
+gs_status gs_resolution_schedule(const double* mag_host, int32_t H, int32_t W, double S, double a,
+                                 int32_t m, double r_max, double* r_knots, double* s_knots) {
+  if (!mag_host || !r_knots || !s_knots || H < 1 || W < 1 || m < 1 || !(a > 1.0) || !(S > 0.0))
+    return GS_ERR_ARG;
+  if (r_max <= 0.0) r_max = double(H < W ? H : W);
+  if (r_max < 1.0) return GS_ERR_ARG;
+  resolution_schedule(mag_host, H, W, S, a, m, r_max, r_knots, s_knots, nullptr);
+  return GS_OK;
+}
+
+double gs_schedule_resolution(double k, int32_t m, const double* r_knots, const double* s_knots) {
+  if (!r_knots || !s_knots || m < 1) return 1.0;
+  if (k >= s_knots[0]) return 1.0;
+  for (int i = 1; i <= m; ++i) {
+    if (k >= s_knots[i]) {
+      const double t = (k - s_knots[i]) / (s_knots[i - 1] - s_knots[i]);
+      const double a = 1.0 / (r_knots[i] * r_knots[i]), b = 1.0 / (r_knots[i - 1] * r_knots[i - 1]);
+      return 1.0 / std::sqrt(a + t * (b - a));
+    }
+  }
+  return r_knots[m];
+}
+
+gs_status gs_downsample_aa(int32_t n_planes, int32_t H, int32_t W, int32_t h, int32_t w,
+                           const float* src, float* dst, void* stream) {
+  if (n_planes < 0 || H < 1 || W < 1 || h < 1 || w < 1 || H > 16384 || W > 16384 || h > 16384 ||
+      w > 16384)
+    return GS_ERR_ARG;
+  if (n_planes > 0 && (!src || !dst)) return GS_ERR_ARG;
+  return from_hip(launch_downsample(n_planes, H, W, h, w, src, dst, as_stream(stream)));
+}
+
 gs_status gs_l1_loss_grad(int64_t numel, const float* image, const float* target, float scale,
                           float* dL_dimage, float* loss_sum, void* stream) {
   if (numel < 0 || (numel > 0 && (!image || !target || !dL_dimage))) return GS_ERR_ARG;

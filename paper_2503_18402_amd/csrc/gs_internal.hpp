@@ -220,6 +220,16 @@ hipError_t launch_render_bwd_adam(const Views& V, int n, const gs_raster_cfg& cf
                                   float* d_mean2d_abs, int64_t cap, void* ws, hipStream_t st);
 
 hipError_t launch_step_inc(int32_t* step_dev, hipStream_t st);
+
+// resolution schedule (schedule.hip)
+constexpr int kDftMax = 4096;  // largest image side for the frequency map
+size_t frequency_map_ws_bytes(int H, int W);
+hipError_t launch_frequency_map(int n_images, int H, int W, const float* images, double* mag,
+                                void* ws, hipStream_t st);
+hipError_t launch_downsample(int n_planes, int H, int W, int h, int w, const float* src, float* dst,
+                             hipStream_t st);
+void resolution_schedule(const double* mag, int H, int W, double S, double a, int m, double r_max,
+                         double* r_knots, double* s_knots, double* x_knots);
 hipError_t launch_adam(const gs_adam_group* groups, int n_groups, int step, float beta1,
                        float beta2, float eps, int32_t* step_dev, hipStream_t st);
 hipError_t launch_l1(int64_t numel, const float* image, const float* target, float scale,

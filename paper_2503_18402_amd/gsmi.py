@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, c_float, c_int32, c_int64, c_size_t, c_uint32, c_uint64, c_void_p
+from ctypes import POINTER, c_double, c_float, c_int32, c_int64, c_size_t, c_uint32, c_uint64, c_void_p
 
 import torch
 
@@ -79,6 +79,13 @@ def lib() -> ctypes.CDLL:
                                          vp, vp, vp, vp, vp, POINTER(c_void_p),
                                          POINTER(c_void_p), POINTER(c_float), vp, c_float,
                                          c_float, c_float, vp, i64, vp, sz, vp]),
+            "gs_frequency_map_workspace_bytes": (sz, [i32, i32]),
+            "gs_frequency_map": (i32, [i32, i32, i32, vp, vp, vp, sz, vp]),
+            "gs_resolution_schedule": (i32, [POINTER(c_double), i32, i32, c_double, c_double, i32,
+                                             c_double, POINTER(c_double), POINTER(c_double)]),
+            "gs_schedule_resolution": (c_double, [c_double, i32, POINTER(c_double),
+                                                  POINTER(c_double)]),
+            "gs_downsample_aa": (i32, [i32, i32, i32, i32, i32, vp, vp, vp]),
             "gs_l1_loss_grad": (i32, [i64, vp, vp, c_float, vp, vp, vp]),
             "gs_profile_enable": (None, [i32]),
             "gs_profile_collect": (i32, [POINTER(GsKernelTime), i32]),
@@ -235,6 +242,43 @@ def gs_render_bwd_adam(cams_c, cfg, n, means, log_scales, quats, opacity_logits,
         _ptr(vals), _ptr(final_T), _ptr(last_contrib), _ptr(dL_dimage), mp, vp_, lr_,
         _ptr(step_dev), float(beta1), float(beta2), float(eps), _ptr(d_mean2d_abs),
         int(capacity), _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def gs_frequency_map_workspace_bytes(H: int, W: int) -> int:
+    return int(lib().gs_frequency_map_workspace_bytes(int(H), int(W)))
+
+
+def gs_frequency_map(images, H, W, mag, ws, stream=None):
+    """images: device float32 [n,3,H,W] (contiguous); mag: device float64 [H,W]."""
+    n = images.numel() // (3 * H * W)
+    _check("gs_frequency_map", lib().gs_frequency_map(
+        int(n), int(H), int(W), _ptr(images), _ptr(mag), _ptr(ws), ws.numel() * ws.element_size(),
+        _stream(stream)))
+
+
+def gs_resolution_schedule(mag_host, S, a=4.0, m=4, r_max=0.0):
+    """mag_host: numpy float64 [H,W] frequency map; returns (r_knots, s_knots)."""
+    import numpy as np
+    mag = np.ascontiguousarray(mag_host, dtype=np.float64)
+    H, W = mag.shape
+    r = (c_double * (m + 1))()
+    s = (c_double * (m + 1))()
+    _check("gs_resolution_schedule", lib().gs_resolution_schedule(
+        mag.ctypes.data_as(POINTER(c_double)), int(H), int(W), float(S), float(a), int(m),
+        float(r_max), r, s))
+    return np.array(r[:]), np.array(s[:])
+
+
+def gs_schedule_resolution(k, r_knots, s_knots) -> float:
+    m = len(r_knots) - 1
+    r = (c_double * (m + 1))(*[float(x) for x in r_knots])
+    s = (c_double * (m + 1))(*[float(x) for x in s_knots])
+    return float(lib().gs_schedule_resolution(float(k), int(m), r, s))
+
+
+def gs_downsample_aa(src, n_planes, H, W, h, w, dst, stream=None):
+    _check("gs_downsample_aa", lib().gs_downsample_aa(
+        int(n_planes), int(H), int(W), int(h), int(w), _ptr(src), _ptr(dst), _stream(stream)))
 
 
 def gs_l1_loss_grad(image, target, scale, dL_dimage, loss_sum=None, stream=None):
