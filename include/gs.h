@@ -200,7 +200,10 @@ gs_status gs_adam_step_device(const gs_adam_group* groups, int32_t n_groups, int
  *   m, v: host arrays of 5 device pointers, the Adam moments of the five
  *     groups in the parameters' layouts (m[2], v[2], m[4], v[4] 16-byte
  *     aligned), updated in place.
- *   lr: host array of the 5 learning rates.
+ *   lr: host array of 6 learning rates: the five groups, except that lr[4]
+ *     applies to the SH degree-0 coefficients (values 0..2 of a Gaussian's
+ *     48) and lr[5] to the higher degrees.  lr[5] = lr[4] gives the update of
+ *     gs_adam_step_device with one SH group.
  *   step_dev: device int32; step t = *step_dev + 1 is taken, then the counter
  *     is incremented on the stream (see gs_adam_step_device).
  *   The other arguments are those of gs_render_bwd, with the same workspace.
@@ -233,15 +236,19 @@ gs_status gs_frequency_map(int32_t n_images, int32_t H, int32_t W, const float* 
 
 /* gs_resolution_schedule (host code, host arrays): the knots of the
  * resolution schedule for S iterations from a frequency map copied to the
- * host.  X(F_r) = (1/r^2) * (sum of mag over |f_y| <= H/(2r), |f_x| <= W/(2r)),
- * the spectrum of the ideal downsample by r.  r_m is the largest r in
+ * host.  X(F_r) = c(r) * (sum of mag over |f_y| <= H/(2r), |f_x| <= W/(2r)),
+ * the spectrum of the ideal downsample by r, with c(r) = 1/r^2 (Eq. 2 with
+ * unnormalised DFTs, per_pixel = 0) or c = 1/(H W) (each view's DFT
+ * normalised by its pixel count, per_pixel = 1).  For natural-image spectra
+ * (amplitude ~ 1/f) the first gives r_m near a^(1/3), the second near a.  r_m is the largest r in
  * [1, r_max] with X(F_r) >= X(F)/a (r_max <= 0: min(H, W)); the values
  * X_i = X(F) - (i/m)(X(F) - X(F)/a), i = 1..m-1, are solved for r_i the same
  * way (bisection), and Eq. 7 gives s_i = S ln(X_i / X_m) / ln(X(F) / X_m).
  *   r_knots, s_knots: m + 1 entries each, knot 0 = (r 1, s S), knot m =
  *   (r_m, s 0).  m >= 1, a > 1, S > 0. */
 gs_status gs_resolution_schedule(const double* mag_host, int32_t H, int32_t W, double S, double a,
-                                 int32_t m, double r_max, double* r_knots, double* s_knots);
+                                 int32_t m, double r_max, int32_t per_pixel, double* r_knots,
+                                 double* s_knots);
 
 /* gs_schedule_resolution: r at iteration k for the knots above, 1/r^2 linear
  * in k between consecutive knots, 1 from s_0 = S on, r_m before s_m = 0.

@@ -12,8 +12,14 @@ Readings (the paper leaves these open):
 * The spectrum of a view downsampled by r (anti-aliased, Sec. 4.1) is the
   central (H/r) x (W/r) crop of the full spectrum scaled by 1/r^2: the ideal
   low-pass downsample.  So X(F_r) is a crop sum of the full-resolution mean
-  magnitude map M, scaled by 1/r^2; the crop keeps the frequencies with
-  |k_y| <= H/(2r) and |k_x| <= W/(2r).  X(F_r) is non-increasing in r.
+  magnitude map M; the crop keeps the frequencies with |k_y| <= H/(2r) and
+  |k_x| <= W/(2r).  Two normalisations: "sum" takes Eq. 2 literally with the
+  unnormalised DFT, X(F_r) = (1/r^2) sum_crop M; "mean" normalises each
+  view's DFT by its own pixel count (h w), X(F_r) = sum_crop M / (H W).  Under
+  "sum", a 1/f amplitude spectrum gives X(F_r) ~ r^-3, so X(F_{r_m}) = X(F)/a
+  puts r_m near a^(1/3) (1.6 for a = 4) and floor(r) never leaves 1; under
+  "mean", X(F_r) ~ 1/r and r_m is near a.  X(F_r) is non-increasing in r
+  either way.
 * r_m is the largest r with X(F_r) >= X(F)/a, and likewise r_i for the knot
   values X_i: "solve" means the boundary of the superlevel set, found by
   bisection on [1, r_max].
@@ -47,26 +53,29 @@ def significance(images) -> float:
     return float(magnitude_map(images).sum())
 
 
-def crop_significance(M: np.ndarray, r: float) -> float:
-    """X(F_r) under the crop reading: (1/r^2) times the sum of M over the
-    frequencies with |k_y| <= H/(2r) and |k_x| <= W/(2r)."""
+def crop_significance(M: np.ndarray, r: float, norm: str = "sum") -> float:
+    """X(F_r) under the crop reading: the sum of M over the frequencies with
+    |k_y| <= H/(2r) and |k_x| <= W/(2r), times 1/r^2 ("sum") or 1/(H W)
+    ("mean")."""
     H, W = M.shape
     ky = np.arange(H) - H // 2
     kx = np.arange(W) - W // 2
     sel_y = np.abs(ky) <= H / (2.0 * r)
     sel_x = np.abs(kx) <= W / (2.0 * r)
-    return float(M[np.ix_(sel_y, sel_x)].sum()) / (r * r)
+    total = float(M[np.ix_(sel_y, sel_x)].sum())
+    return total / (r * r) if norm == "sum" else total / (H * W)
 
 
-def solve_r(M: np.ndarray, target: float, r_max: float, iters: int = 60) -> float:
+def solve_r(M: np.ndarray, target: float, r_max: float, iters: int = 60,
+            norm: str = "sum") -> float:
     """Largest r in [1, r_max] with X(F_r) >= target (bisection; X is
     non-increasing in r).  r_max when even X(F_{r_max}) >= target."""
-    if crop_significance(M, r_max) >= target:
+    if crop_significance(M, r_max, norm) >= target:
         return float(r_max)
     lo, hi = 1.0, float(r_max)
     for _ in range(iters):
         mid = 0.5 * (lo + hi)
-        if crop_significance(M, mid) >= target:
+        if crop_significance(M, mid, norm) >= target:
             lo = mid
         else:
             hi = mid
@@ -74,7 +83,8 @@ def solve_r(M: np.ndarray, target: float, r_max: float, iters: int = 60) -> floa
 
 
 # ------------------------------------------------------------ Eq. 6 and 7
-def schedule_knots(M: np.ndarray, S: int, a: float = 4.0, m: int = 4, r_max: float | None = None):
+def schedule_knots(M: np.ndarray, S: int, a: float = 4.0, m: int = 4, r_max: float | None = None,
+                   norm: str = "sum"):
     """Knots (r_i, s_{r_i}) for i = 0..m, with r_0 = 1 at s = S and r_m at s = 0.
 
     X_F = X(F); r_m solves X(F_{r_m}) = X_F / a; the values X_1..X_{m-1} are
@@ -83,10 +93,10 @@ def schedule_knots(M: np.ndarray, S: int, a: float = 4.0, m: int = 4, r_max: flo
     H, W = M.shape
     if r_max is None:
         r_max = float(min(H, W))
-    XF = crop_significance(M, 1.0)
+    XF = crop_significance(M, 1.0, norm)
     Xm = XF / a
     X = [XF - (XF - Xm) * i / m for i in range(m + 1)]
-    r = [1.0] + [solve_r(M, X[i], r_max) for i in range(1, m + 1)]
+    r = [1.0] + [solve_r(M, X[i], r_max, norm=norm) for i in range(1, m + 1)]
     s = [S * np.log(X[i] / Xm) / np.log(XF / Xm) for i in range(m + 1)]
     return np.array(r), np.array(s), np.array(X)
 

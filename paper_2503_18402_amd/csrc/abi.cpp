@@ -283,8 +283,8 @@ gs_status gs_render_bwd_adam(int32_t n_views, const gs_camera* cams, const gs_ra
     if (n > 0 && (!m[k] || !v[k])) return GS_ERR_ARG;
     A.m[k] = m[k];
     A.v[k] = v[k];
-    A.lr[k] = lr[k];
   }
+  for (int k = 0; k < 6; ++k) A.lr[k] = lr[k];
   if (n > 0 && (!means || !log_scales || !quats || !opacity_logits || !sh || !proj))
     return GS_ERR_ARG;
   if (n > 0 && (!aligned16(quats) || !aligned16(sh) || !aligned16(proj) || !aligned16(ws) ||
@@ -316,12 +316,13 @@ gs_status gs_frequency_map(int32_t n_images, int32_t H, int32_t W, const float* 
 }
 
 gs_status gs_resolution_schedule(const double* mag_host, int32_t H, int32_t W, double S, double a,
-                                 int32_t m, double r_max, double* r_knots, double* s_knots) {
+                                 int32_t m, double r_max, int32_t per_pixel, double* r_knots,
+                                 double* s_knots) {
   if (!mag_host || !r_knots || !s_knots || H < 1 || W < 1 || m < 1 || !(a > 1.0) || !(S > 0.0))
     return GS_ERR_ARG;
   if (r_max <= 0.0) r_max = double(H < W ? H : W);
   if (r_max < 1.0) return GS_ERR_ARG;
-  resolution_schedule(mag_host, H, W, S, a, m, r_max, r_knots, s_knots, nullptr);
+  resolution_schedule(mag_host, H, W, S, a, m, r_max, per_pixel, r_knots, s_knots, nullptr);
   return GS_OK;
 }
 

@@ -625,7 +625,7 @@ struct AdamGroups {
   float* p[5];
   float* m[5];
   float* v[5];
-  float lr[5];
+  float lr[6];  // the five groups; lr[4] for the SH degree-0 terms, lr[5] for the rest
   float b1, b2, eps;
   const int32_t* step_dev;
 };
@@ -683,10 +683,12 @@ __global__ __launch_bounds__(kCA) void k_chain_adam(Views V, ChainIn I, AdamGrou
   for (int j = threadIdx.x; j < n4; j += kCA) {
     float4 p = P[j], m = Mm[j], v = Vv[j];
     const float4 gg = s_g[j];
-    adam_one(p.x, gg.x, m.x, v.x, A.lr[4], C);
-    adam_one(p.y, gg.y, m.y, v.y, A.lr[4], C);
-    adam_one(p.z, gg.z, m.z, v.z, A.lr[4], C);
-    adam_one(p.w, gg.w, m.w, v.w, A.lr[4], C);
+    // values 0..2 of a Gaussian's 48 are its degree-0 coefficients
+    const int e = (4 * j) % (GS_SH_COEFFS * 3);
+    adam_one(p.x, gg.x, m.x, v.x, e + 0 < 3 ? A.lr[4] : A.lr[5], C);
+    adam_one(p.y, gg.y, m.y, v.y, e + 1 < 3 ? A.lr[4] : A.lr[5], C);
+    adam_one(p.z, gg.z, m.z, v.z, e + 2 < 3 ? A.lr[4] : A.lr[5], C);
+    adam_one(p.w, gg.w, m.w, v.w, A.lr[5], C);
     P[j] = p;
     Mm[j] = m;
     Vv[j] = v;
@@ -840,8 +842,8 @@ hipError_t launch_render_bwd_adam(const Views& V, int n, const gs_raster_cfg& cf
       G.p[k] = P[k];
       G.m[k] = A.m[k];
       G.v[k] = A.v[k];
-      G.lr[k] = A.lr[k];
     }
+    for (int k = 0; k < 6; ++k) G.lr[k] = A.lr[k];
     G.b1 = A.b1;
     G.b2 = A.b2;
     G.eps = A.eps;

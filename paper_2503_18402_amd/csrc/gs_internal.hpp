@@ -207,7 +207,7 @@ hipError_t launch_render_bwd(const Views& V, int n, const gs_raster_cfg& cfg,
 struct FusedAdam {  // the five parameter groups' moments and learning rates
   float* m[5];
   float* v[5];
-  float lr[5];
+  float lr[6];  // lr[4]: SH degree-0 coefficients, lr[5]: the higher degrees
   float b1, b2, eps;
   int32_t* step_dev;
 };
@@ -229,7 +229,7 @@ hipError_t launch_frequency_map(int n_images, int H, int W, const float* images,
 hipError_t launch_downsample(int n_planes, int H, int W, int h, int w, const float* src, float* dst,
                              hipStream_t st);
 void resolution_schedule(const double* mag, int H, int W, double S, double a, int m, double r_max,
-                         double* r_knots, double* s_knots, double* x_knots);
+                         int per_pixel, double* r_knots, double* s_knots, double* x_knots);
 hipError_t launch_adam(const gs_adam_group* groups, int n_groups, int step, float beta1,
                        float beta2, float eps, int32_t* step_dev, hipStream_t st);
 hipError_t launch_l1(int64_t numel, const float* image, const float* target, float scale,

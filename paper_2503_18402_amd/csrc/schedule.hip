@@ -12,8 +12,9 @@
 // kDftMax (both passes keep their twiddles and one line of data in LDS).
 //
 // Schedule: from the map, X(F_r) is the sum of M over the centred crop
-// |k_y| <= H/(2r), |k_x| <= W/(2r), scaled by 1/r^2 (the spectrum of the ideal
-// downsample by r); r_m solves X(F_r) = X(F)/a, the knots X_1..X_{m-1} are
+// |k_y| <= H/(2r), |k_x| <= W/(2r) (the spectrum of the ideal downsample by r),
+// scaled by 1/r^2 (Eq. 2 with unnormalised DFTs) or by 1/(H W) (each view's
+// DFT normalised by its pixel count); r_m solves X(F_r) = X(F)/a, the knots X_1..X_{m-1} are
 // spaced linearly between X(F) and X(F_{r_m}) and solved for r_i by
 // bisection, and Eq. 7 places them at s_{r_i} = S ln(X_i/X_m) / ln(X_F/X_m).
 // This part is host code over a summed-area table of the map.
@@ -213,14 +214,15 @@ struct CropTable {
       }
     }
   }
-  // (1/r^2) sum of the map over |f_y| <= H/(2r), |f_x| <= W/(2r)
+  // sum of the map over |f_y| <= H/(2r), |f_x| <= W/(2r), times 1/r^2 or 1/(H W)
+  bool per_pixel = false;
   double significance(double r) const {
     const int by = int(std::floor(double(H) / (2.0 * r))), bx = int(std::floor(double(W) / (2.0 * r)));
     const int y0 = std::max(0, H / 2 - by), y1 = std::min(H - 1, H / 2 + by);
     const int x0 = std::max(0, W / 2 - bx), x1 = std::min(W - 1, W / 2 + bx);
     const double s = sat[size_t(y1 + 1) * (W + 1) + (x1 + 1)] - sat[size_t(y0) * (W + 1) + (x1 + 1)] -
                      sat[size_t(y1 + 1) * (W + 1) + x0] + sat[size_t(y0) * (W + 1) + x0];
-    return s / (r * r);
+    return per_pixel ? s / (double(H) * double(W)) : s / (r * r);
   }
   // largest r in [1, r_max] with significance(r) >= target (bisection)
   double solve(double target, double r_max) const {
@@ -238,8 +240,9 @@ struct CropTable {
 };
 
 void resolution_schedule(const double* mag, int H, int W, double S, double a, int m, double r_max,
-                         double* r_knots, double* s_knots, double* x_knots) {
-  const CropTable T(mag, H, W);
+                         int per_pixel, double* r_knots, double* s_knots, double* x_knots) {
+  CropTable T(mag, H, W);
+  T.per_pixel = per_pixel != 0;
   const double XF = T.significance(1.0), Xm = XF / a;
   for (int i = 0; i <= m; ++i) {
     const double Xi = XF - (XF - Xm) * double(i) / double(m);

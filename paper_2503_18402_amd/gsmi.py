@@ -82,7 +82,7 @@ def lib() -> ctypes.CDLL:
             "gs_frequency_map_workspace_bytes": (sz, [i32, i32]),
             "gs_frequency_map": (i32, [i32, i32, i32, vp, vp, vp, sz, vp]),
             "gs_resolution_schedule": (i32, [POINTER(c_double), i32, i32, c_double, c_double, i32,
-                                             c_double, POINTER(c_double), POINTER(c_double)]),
+                                             c_double, i32, POINTER(c_double), POINTER(c_double)]),
             "gs_schedule_resolution": (c_double, [c_double, i32, POINTER(c_double),
                                                   POINTER(c_double)]),
             "gs_downsample_aa": (i32, [i32, i32, i32, i32, i32, vp, vp, vp]),
@@ -231,11 +231,15 @@ def gs_adam_step_device(groups, step_dev, beta1=0.9, beta2=0.999, eps=1e-15, str
 def gs_render_bwd_adam(cams_c, cfg, n, means, log_scales, quats, opacity_logits, sh, sh_degree,
                        proj, ranges, vals, final_T, last_contrib, dL_dimage, m, v, lr, step_dev,
                        beta1, beta2, eps, d_mean2d_abs, capacity, ws, stream=None):
-    """m, v, lr: five entries each, in the order means, log_scales, quats,
-    opacity_logits, sh."""
+    """m, v: five entries each, in the order means, log_scales, quats,
+    opacity_logits, sh; lr: those five learning rates (the SH one for every
+    coefficient) or six (the last for the SH coefficients above degree 0)."""
+    lr = list(lr)
+    if len(lr) == 5:
+        lr.append(lr[4])
     mp = (c_void_p * 5)(*[_ptr(t) for t in m])
     vp_ = (c_void_p * 5)(*[_ptr(t) for t in v])
-    lr_ = (c_float * 5)(*[float(x) for x in lr])
+    lr_ = (c_float * 6)(*[float(x) for x in lr])
     _check("gs_render_bwd_adam", lib().gs_render_bwd_adam(
         len(cams_c), cams_c, ctypes.byref(cfg), int(n), _ptr(means), _ptr(log_scales),
         _ptr(quats), _ptr(opacity_logits), _ptr(sh), int(sh_degree), _ptr(proj), _ptr(ranges),
@@ -256,8 +260,11 @@ def gs_frequency_map(images, H, W, mag, ws, stream=None):
         _stream(stream)))
 
 
-def gs_resolution_schedule(mag_host, S, a=4.0, m=4, r_max=0.0):
-    """mag_host: numpy float64 [H,W] frequency map; returns (r_knots, s_knots)."""
+def gs_resolution_schedule(mag_host, S, a=4.0, m=4, r_max=0.0, norm="sum"):
+    """mag_host: numpy float64 [H,W] frequency map; norm "sum" (X(F_r) scaled by
+    1/r^2) or "mean" (by 1/(H W)); returns (r_knots, s_knots)."""
+    if norm not in ("sum", "mean"):
+        raise ValueError(norm)
     import numpy as np
     mag = np.ascontiguousarray(mag_host, dtype=np.float64)
     H, W = mag.shape
@@ -265,7 +272,7 @@ def gs_resolution_schedule(mag_host, S, a=4.0, m=4, r_max=0.0):
     s = (c_double * (m + 1))()
     _check("gs_resolution_schedule", lib().gs_resolution_schedule(
         mag.ctypes.data_as(POINTER(c_double)), int(H), int(W), float(S), float(a), int(m),
-        float(r_max), r, s))
+        float(r_max), 1 if norm == "mean" else 0, r, s))
     return np.array(r[:]), np.array(s[:])
 
 

@@ -185,7 +185,7 @@ class Pipeline:
                  lds_batch: int = 256, bg=(0.0, 0.0, 0.0), sh_degree: int = 3,
                  capacity: int | None = None, lrs: dict | None = None,
                  betas=(0.9, 0.999), eps: float = 1e-15, grads: dict | None = None,
-                 fused: bool = True):
+                 fused: bool = True, share: "Pipeline | None" = None):
         self.params = params
         self.cams = list(cams)
         dev = params["means"].device
@@ -217,15 +217,19 @@ class Pipeline:
         self.last = torch.empty(self.npx, dtype=torch.int32, device=dev)
         self.dL = torch.empty(3 * self.npx, dtype=torch.float32, device=dev)
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
-        self.grads = zero_grads(params) if grads is None else grads
-        self.m = {k: torch.zeros_like(params[k]) for k in PARAM_NAMES}
-        self.v = {k: torch.zeros_like(params[k]) for k in PARAM_NAMES}
+        if share is not None:  # one optimiser state for several pipelines (e.g. per level)
+            self.grads, self.m, self.v = share.grads, share.m, share.v
+        else:
+            self.grads = zero_grads(params) if grads is None else grads
+            self.m = {k: torch.zeros_like(params[k]) for k in PARAM_NAMES}
+            self.v = {k: torch.zeros_like(params[k]) for k in PARAM_NAMES}
         self.lrs = lrs or dict(means=1.6e-4, log_scales=5e-3, quats=1e-3, opacity_logits=5e-2,
                                sh=2.5e-3)
         self.betas, self.eps = betas, eps
         self.step_no = 0
         # the step count lives on the device so a captured graph replays as new steps
-        self.step_dev = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.step_dev = (share.step_dev if share is not None
+                         else torch.zeros(1, dtype=torch.int32, device=dev))
         self.fused = fused
         self.graph = None
 
@@ -255,6 +259,8 @@ class Pipeline:
     def adam(self, stream=None, step: int | None = None):
         """Adam over all parameter groups; the step count is the device counter
         unless ``step`` is given explicitly."""
+        if self.lrs.get("sh_rest", self.lrs["sh"]) != self.lrs["sh"]:
+            raise ValueError("a separate SH learning rate above degree 0 needs the fused step")
         groups = [(self.params[k], self.grads[k], self.m[k], self.v[k], self.lrs[k])
                   for k in PARAM_NAMES]
         if step is None:
@@ -275,7 +281,8 @@ class Pipeline:
             self.cams_c, self.cfg, self.n, p["means"], p["log_scales"], p["quats"],
             p["opacity_logits"], p["sh"], self.sh_degree, self.proj, self.ranges, self.vals,
             self.final_T, self.last, self.dL, [self.m[k] for k in PARAM_NAMES],
-            [self.v[k] for k in PARAM_NAMES], [self.lrs[k] for k in PARAM_NAMES],
+            [self.v[k] for k in PARAM_NAMES],
+            [self.lrs[k] for k in PARAM_NAMES] + [self.lrs.get("sh_rest", self.lrs["sh"])],
             self.step_dev, self.betas[0], self.betas[1], self.eps, None, self.capacity,
             self.bwd_ws, stream)
         self.step_no += 1
@@ -291,6 +298,17 @@ class Pipeline:
         else:
             self.backward(stream)
             self.adam(stream, adam_step)
+
+    def set_view(self, cam, target: torch.Tensor):
+        """Point a one-view pipeline at another view of the same resolution."""
+        if len(self.cams) != 1 or (int(cam.width), int(cam.height)) != (
+                int(self.cams[0].width), int(self.cams[0].height)):
+            raise ValueError("set_view needs a one-view pipeline and a view of its resolution")
+        if self.graph is not None:
+            raise ValueError("a captured graph replays its own view")
+        self.cams = [cam]
+        self.cams_c = gsmi.make_cameras(self.cams)
+        self.targets = target.reshape(-1)
 
     def capture(self):
         """Capture one whole step into a HIP graph; later ``step()`` calls replay it.

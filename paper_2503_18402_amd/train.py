@@ -1,0 +1,165 @@
+"""Optimisation loop under the frequency-guided resolution schedule (Sec. 4.2;
+supplementary Eq. 6-7, "Ground Truth Downsampling", "Learning Rate").
+
+One iteration renders one training view at the scheduled resolution, takes
+the L1 loss against the view's ground truth downsampled to that resolution,
+and runs the backward pass fused with Adam.  The schedule comes from the
+views' frequency map (``gs_frequency_map``, Eq. 2) and the knots of Eq. 7
+(``gs_resolution_schedule``); iteration k renders at the integer factor
+floor(r(k)); X(F_r) is normalised per pixel by default (see
+``gs_resolution_schedule``: with the literal sum of unnormalised DFT magnitudes
+natural-image spectra give r_m near a^(1/3), so floor(r) would stay 1).  The
+position learning rate is held at its initial value while
+floor(r) > 1 and decays exponentially to its final value from the first
+full-resolution iteration on.  With ``schedule=False`` every iteration renders
+at full resolution and the position rate decays from the start: the
+backbone's loop, for comparison.
+
+Everything here marshals buffers and calls the C ABI; the arithmetic runs in
+the library's kernels.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import gsmi, raster
+
+
+@dataclass
+class View:
+    """A pinhole camera (the fields the rasterizer reads)."""
+    R: np.ndarray
+    t: np.ndarray
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    width: int
+    height: int
+    near: float = 0.2
+
+
+def downscale_view(cam, f: int) -> View:
+    """The view at integer factor f: floor(W/f) x floor(H/f), focal lengths
+    divided by f, principal point at the new image centre."""
+    W, H = int(cam.width) // f, int(cam.height) // f
+    return View(np.asarray(cam.R, np.float64), np.asarray(cam.t, np.float64), cam.fx / f,
+                cam.fy / f, W / 2.0, H / 2.0, W, H, float(getattr(cam, "near", 0.2)))
+
+
+class ResolutionSchedule:
+    """r(k) of Eq. 7 for the ground-truth views ``gt`` (device [N,3,H,W])."""
+
+    def __init__(self, gt: torch.Tensor, iters: int, a: float = 4.0, m: int = 4,
+                 r_max: float = 0.0, norm: str = "mean"):
+        n, _, H, W = gt.shape
+        mag = torch.empty(H, W, dtype=torch.float64, device=gt.device)
+        ws = torch.empty(gsmi.gs_frequency_map_workspace_bytes(H, W), dtype=torch.uint8,
+                         device=gt.device)
+        gsmi.gs_frequency_map(gt.contiguous(), H, W, mag, ws)
+        self.mag = mag.cpu().numpy()
+        self.iters = iters
+        self.r_knots, self.s_knots = gsmi.gs_resolution_schedule(self.mag, iters, a=a, m=m,
+                                                                 r_max=r_max, norm=norm)
+
+    def r(self, k: float) -> float:
+        return gsmi.gs_schedule_resolution(k, self.r_knots, self.s_knots)
+
+    def factor(self, k: int) -> int:
+        return max(1, int(math.floor(self.r(k))))
+
+
+def downsample(gt: torch.Tensor, h: int, w: int) -> torch.Tensor:
+    """Anti-aliased resize of device images [N,3,H,W] to [N,3,h,w]."""
+    n, c, H, W = gt.shape
+    out = torch.empty(n, c, h, w, dtype=torch.float32, device=gt.device)
+    gsmi.gs_downsample_aa(gt.contiguous(), n * c, H, W, h, w, out)
+    return out
+
+
+def psnr(params: dict, cams, gt: torch.Tensor, sh_degree: int = 3, tile: int = 16) -> float:
+    """Mean PSNR over the views at full resolution (images in [0, 1])."""
+    vals = []
+    for k, c in enumerate(cams):
+        img = raster.render(params, [c], tile=tile, sh_degree=sh_degree).image
+        mse = torch.mean((img.view_as(gt[k]) - gt[k]) ** 2).item()
+        vals.append(-10.0 * math.log10(max(mse, 1e-12)))
+    return float(np.mean(vals))
+
+
+DEFAULT_LRS = dict(means=1.6e-4, log_scales=5e-3, quats=1e-3, opacity_logits=5e-2, sh=2.5e-3,
+                   sh_rest=2.5e-3 / 20.0)
+
+
+class Trainer:
+    """``iters`` optimisation steps of ``params`` (device tensors, updated in
+    place) against ground-truth views ``gt`` (device [N,3,H,W]) seen from
+    ``cams``.  ``means_lr`` = (initial, final) position learning rates."""
+
+    def __init__(self, params: dict, cams, gt: torch.Tensor, iters: int, schedule: bool = True,
+                 a: float = 4.0, m: int = 4, lrs: dict | None = None,
+                 means_lr=(1.6e-4, 1.6e-6), sh_degree: int = 3, seed: int = 0,
+                 capacity_margin: float = 1.5, norm: str = "mean"):
+        self.params, self.cams, self.gt, self.iters = params, list(cams), gt, iters
+        self.lrs = dict(DEFAULT_LRS if lrs is None else lrs)
+        self.means_lr = means_lr
+        self.sched = ResolutionSchedule(gt, iters, a=a, m=m, norm=norm) if schedule else None
+        self.factors = np.array([self.sched.factor(k) if schedule else 1 for k in range(iters)])
+        # first iteration at full resolution: the position rate decays from there
+        full = np.nonzero(self.factors == 1)[0]
+        self.k_full = int(full[0]) if full.size else iters
+        self.rng = np.random.default_rng(seed)
+        self.levels = {}
+        first = None
+        for f in sorted(set(self.factors.tolist()), reverse=True):
+            views = [downscale_view(c, f) for c in self.cams]
+            h, w = views[0].height, views[0].width
+            gt_f = gt if f == 1 else downsample(gt, h, w)
+            tile = 8 if f >= 4 else 16
+            cap = 0
+            for v in views:
+                probe = raster.render(params, [v], tile=tile, sh_degree=sh_degree)
+                cap = max(cap, int(probe.n_pairs_dev.item()))
+                del probe
+            pipe = raster.Pipeline(params, [views[0]], gt_f[0].reshape(-1), tile=tile,
+                                   lds_batch=128, sh_degree=sh_degree,
+                                   capacity=int(cap * capacity_margin) + 4096, lrs=self.lrs,
+                                   share=first)
+            first = first or pipe
+            self.levels[f] = (views, gt_f, pipe)
+
+    def means_lr_at(self, k: int) -> float:
+        lo, hi = self.means_lr
+        if k < self.k_full:
+            return lo
+        t = (k - self.k_full) / max(1, self.iters - self.k_full)
+        return math.exp((1.0 - t) * math.log(lo) + t * math.log(hi))
+
+    def run(self) -> dict:
+        """Run all iterations; returns the wall time and the iterations per factor."""
+        order = []
+        n = len(self.cams)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(self.iters):
+            if not order:
+                order = list(self.rng.permutation(n))
+            v = order.pop()
+            views, gt_f, pipe = self.levels[int(self.factors[k])]
+            pipe.set_view(views[v], gt_f[v])
+            pipe.lrs["means"] = self.means_lr_at(k)
+            pipe.step()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        for _, _, pipe in self.levels.values():
+            if pipe.overflowed():
+                raise RuntimeError("pair capacity overflowed during training")
+        return dict(seconds=wall, s_per_iter=wall / max(1, self.iters),
+                    iters_per_factor={int(f): int((self.factors == f).sum())
+                                      for f in sorted(set(self.factors.tolist()))},
+                    k_full=self.k_full)

@@ -85,3 +85,22 @@ def test_fused_with_no_gaussians_only_counts_the_step():
                             px, [e] * 5, [e] * 5, [1e-3] * 5, step, 0.9, 0.999, 1e-15, None, 0, ws)
     torch.cuda.synchronize()
     assert int(step.item()) == 1
+
+
+def test_separate_sh_rest_rate():
+    """lr[5] for the SH coefficients above degree 0: one step from the same
+    state sees the same gradient, and Adam is elementwise, so the fused step
+    with (lr_dc, lr_rest) equals, coefficient by coefficient, the separate step
+    run once with lr_dc and once with lr_rest."""
+    sc, cams, tgt = _setup(3000, False)
+    runs = {}
+    for name, lr_sh, lr_rest, fused in (("dc", 3e-3, 3e-3, False), ("rest", 2e-4, 2e-4, False),
+                                        ("both", 3e-3, 2e-4, True)):
+        p = raster.Pipeline(raster.to_device(sc), cams, tgt, fused=fused,
+                            lrs=dict(means=1e-4, log_scales=5e-3, quats=1e-3,
+                                     opacity_logits=5e-2, sh=lr_sh, sh_rest=lr_rest))
+        p.step()
+        torch.cuda.synchronize()
+        runs[name] = p.params["sh"].clone()
+    assert torch.equal(runs["both"][:, 0], runs["dc"][:, 0])
+    assert torch.equal(runs["both"][:, 1:], runs["rest"][:, 1:])

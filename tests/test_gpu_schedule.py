@@ -46,7 +46,8 @@ def test_downsample_matches_oracle(H, W, h, w):
     assert np.abs(got - ref).max() < 2e-6
 
 
-def test_knots_from_rendered_views():
+@pytest.mark.parametrize("norm", ["sum", "mean"])
+def test_knots_from_rendered_views(norm):
     """Render views of a scene, build the map on the device, solve the knots on
     the host, and compare with the oracle's knots from its own map."""
     sc = scenes.make_scene(20000, seed=61, mean_range=1.0, ls_mu=-3.5, ls_sigma=0.6)
@@ -56,7 +57,8 @@ def test_knots_from_rendered_views():
     torch.cuda.synchronize()
     imgs_np = imgs.cpu().numpy()
     got = _freq_map(imgs_np)
-    r_c, s_c = gsmi.gs_resolution_schedule(got, 6000, a=4.0, m=4)
-    r_o, s_o, _ = O.schedule_knots(O.magnitude_map(imgs_np.astype(np.float64)), 6000, a=4.0, m=4)
+    r_c, s_c = gsmi.gs_resolution_schedule(got, 6000, a=4.0, m=4, norm=norm)
+    r_o, s_o, _ = O.schedule_knots(O.magnitude_map(imgs_np.astype(np.float64)), 6000, a=4.0, m=4,
+                                   norm=norm)
     assert np.allclose(r_c, r_o, rtol=1e-9) and np.allclose(s_c, s_o, rtol=1e-12, atol=1e-9)
-    assert r_c[-1] > 1.5
+    assert r_c[-1] > 1.2

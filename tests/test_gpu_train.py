@@ -1,0 +1,62 @@
+"""The optimisation loop under the resolution schedule (Sec. 4.2; supplementary
+Eq. 6-7): the per-iteration render factors equal the oracle's floor(r(k)) for
+the oracle's knots of the same ground-truth views, training lowers the loss,
+and the unscheduled loop renders every iteration at full resolution.  The
+ground truth is seeded procedural imagery (no device output feeds the oracle)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import schedule as O
+from paper_2503_18402_amd import raster, scenes, train
+
+pytestmark = pytest.mark.gpu
+
+
+def _gt(cams, seed=71):
+    """Smooth random colour fields plus fine texture, [N,3,H,W] in [0,1]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for c in cams:
+        H, W = c.height, c.width
+        y, x = np.mgrid[0:H, 0:W] / max(H, W)
+        img = np.full((3, H, W), 0.5)
+        for _ in range(12):
+            u, v = rng.uniform(-12, 12, size=2)
+            img += rng.uniform(-0.08, 0.08, size=(3, 1, 1)) * np.cos(
+                2 * np.pi * (u * x + v * y) + rng.uniform(0, 2 * np.pi))
+        img += rng.uniform(-0.05, 0.05, size=img.shape)
+        out.append(np.clip(img, 0, 1))
+    return np.stack(out).astype(np.float32)
+
+
+def test_schedule_factors_match_oracle_and_training_improves():
+    cams = scenes.fibonacci_cameras(8, 3.0, 160, 120, 150.0)
+    gt_np = _gt(cams)
+    gt = torch.from_numpy(gt_np).cuda()
+    sc = scenes.make_scene(6000, seed=72, mean_range=1.0, ls_mu=-3.0, ls_sigma=0.4)
+    params = raster.to_device(sc, "cuda")
+    iters = 240
+    tr = train.Trainer(params, cams, gt, iters, schedule=True, a=4.0, m=4, norm="mean")
+    r_o, s_o, _ = O.schedule_knots(O.magnitude_map(gt_np.astype(np.float64)), iters, a=4.0, m=4,
+                                   norm="mean")
+    assert np.allclose(tr.sched.r_knots, r_o, rtol=1e-9)
+    ref = np.array([O.render_factor(k, r_o, s_o) for k in range(iters)])
+    near = np.array([abs(O.resolution_at(k, r_o, s_o) - round(O.resolution_at(k, r_o, s_o)))
+                     < 1e-9 for k in range(iters)])
+    assert np.array_equal(tr.factors[~near], ref[~near])
+    assert tr.factors[0] > 1 and tr.factors[-1] == 1
+    before = train.psnr(params, cams, gt)
+    out = tr.run()
+    after = train.psnr(params, cams, gt)
+    assert after > before + 0.5, (before, after)
+    assert sum(out["iters_per_factor"].values()) == iters
+
+
+def test_unscheduled_loop_renders_full_resolution():
+    cams = scenes.fibonacci_cameras(4, 3.0, 96, 64, 90.0)
+    gt = torch.from_numpy(_gt(cams, seed=73)).cuda()
+    params = raster.to_device(scenes.make_scene(2000, seed=74), "cuda")
+    tr = train.Trainer(params, cams, gt, 30, schedule=False)
+    assert set(tr.factors.tolist()) == {1} and tr.k_full == 0
+    tr.run()

@@ -38,10 +38,12 @@ def test_views_are_averaged():
 
 
 @pytest.mark.parametrize("r", [2, 4])
-def test_crop_equals_ideal_downsample_of_band_limited_image(r):
+@pytest.mark.parametrize("norm", ["sum", "mean"])
+def test_crop_equals_ideal_downsample_of_band_limited_image(r, norm):
     """A sum of cosines below the coarse grid's Nyquist limit, sampled on the
     full and on the r-times coarser pixel grid (same continuous image): the
-    coarse image's X equals the full spectrum's crop scaled by 1/r^2."""
+    coarse image's X equals the full spectrum's crop scaled by 1/r^2 (or, with
+    each DFT normalised by its pixel count, by 1/(H W))."""
     H, W = 64, 96
     rng = np.random.default_rng(1)
     waves = [(rng.integers(0, W // (2 * r) - 1), rng.integers(0, H // (2 * r) - 1),
@@ -56,8 +58,10 @@ def test_crop_equals_ideal_downsample_of_band_limited_image(r):
         return img + 0.3
 
     M = O.magnitude_map(sample(H, W))
-    assert O.crop_significance(M, float(r)) == pytest.approx(
-        O.significance(sample(H // r, W // r)), rel=1e-10)
+    coarse = O.significance(sample(H // r, W // r))
+    if norm == "mean":   # each view's DFT normalised by its own pixel count
+        coarse /= (H // r) * (W // r)
+    assert O.crop_significance(M, float(r), norm) == pytest.approx(coarse, rel=1e-10)
 
 
 def test_crop_at_one_is_the_full_sum_and_nonincreasing():
@@ -69,12 +73,13 @@ def test_crop_at_one_is_the_full_sum_and_nonincreasing():
     assert np.all(np.diff(xs) <= 1e-9 * xs[0])
 
 
-def test_knots_follow_eq7():
+@pytest.mark.parametrize("norm", ["sum", "mean"])
+def test_knots_follow_eq7(norm):
     rng = np.random.default_rng(3)
     img = rng.uniform(size=(3, 64, 96))
     M = O.magnitude_map(img)
     S, a, m = 6000, 4.0, 4
-    r, s, X = O.schedule_knots(M, S, a=a, m=m)
+    r, s, X = O.schedule_knots(M, S, a=a, m=m, norm=norm)
     assert r[0] == 1.0 and s[0] == pytest.approx(S) and s[-1] == pytest.approx(0.0, abs=1e-9)
     assert np.all(np.diff(r) >= 0) and np.all(np.diff(s) < 0)
     # Eq. 7 with linearly spaced X_i depends only on a and m
@@ -83,8 +88,8 @@ def test_knots_follow_eq7():
                                      rel=1e-12, abs=1e-9)
     # r_i is the boundary of {r : X(F_r) >= X_i}
     for i in range(1, m + 1):
-        assert O.crop_significance(M, r[i]) >= X[i]
-        assert O.crop_significance(M, r[i] * (1 + 1e-6)) < X[i]
+        assert O.crop_significance(M, r[i], norm) >= X[i]
+        assert O.crop_significance(M, r[i] * (1 + 1e-6), norm) < X[i]
 
 
 def test_resolution_curve():
@@ -114,3 +119,17 @@ def test_downsample_matches_torch_antialias(H, W, h, w):
 def test_downsample_keeps_constants():
     x = np.full((3, 50, 70), 0.25)
     assert np.abs(O.downsample_aa(x, 7, 9) - 0.25).max() < 1e-15
+
+
+def test_one_over_f_spectrum_places_r_m():
+    """Amplitude 1/|f| (natural-image statistics), no DC: X(F_r) ~ r^-3 under
+    "sum" and ~ r^-1 under "mean", so r_m is near a^(1/3) and a."""
+    H = W = 512
+    ky = np.arange(H) - H // 2
+    kx = np.arange(W) - W // 2
+    f = np.hypot(*np.meshgrid(ky, kx, indexing="ij"))
+    M = np.where(f > 0, 1.0 / np.maximum(f, 1e-12), 0.0)
+    r_sum = O.schedule_knots(M, 100, a=4.0, m=1, norm="sum")[0][1]
+    r_mean = O.schedule_knots(M, 100, a=4.0, m=1, norm="mean")[0][1]
+    assert r_sum == pytest.approx(4.0 ** (1 / 3), rel=0.05)
+    assert r_mean == pytest.approx(4.0, rel=0.05)

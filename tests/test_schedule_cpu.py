@@ -16,15 +16,16 @@ def L():
     return gsmi.lib()
 
 
+@pytest.mark.parametrize("norm", ["sum", "mean"])
 @pytest.mark.parametrize("shape,m,a", [((2, 3, 64, 96), 4, 4.0), ((1, 3, 133, 200), 6, 4.0),
                                        ((3, 3, 45, 61), 3, 2.5)])
-def test_knots_match_oracle(L, shape, m, a):
+def test_knots_match_oracle(L, shape, m, a, norm):
     rng = np.random.default_rng(sum(shape))
     imgs = rng.uniform(size=shape)
     imgs += np.linspace(0, 1, shape[-1])[None, None, None, :]   # some low-frequency content
     Mc = O.magnitude_map(imgs)                                   # centred
-    r_o, s_o, _ = O.schedule_knots(Mc, 6000, a=a, m=m)
-    r_c, s_c = gsmi.gs_resolution_schedule(np.fft.ifftshift(Mc), 6000, a=a, m=m)
+    r_o, s_o, _ = O.schedule_knots(Mc, 6000, a=a, m=m, norm=norm)
+    r_c, s_c = gsmi.gs_resolution_schedule(np.fft.ifftshift(Mc), 6000, a=a, m=m, norm=norm)
     assert np.allclose(r_c, r_o, rtol=1e-12, atol=0)
     assert np.allclose(s_c, s_o, rtol=1e-12, atol=1e-9)
     for k in np.linspace(0, 6500, 57):
