@@ -62,146 +62,341 @@ __device__ __forceinline__ void wave_sum9(const float* v, float* q) {
   q[2] = row_sum16(swap16_add(r8, r8));       // rows: v8, v8, 0, 0
 }
 
+// ---- one wave's walk over a tile's list, shared by the short- and the
+// long-list kernels.  The wave's 64 lanes own the tile's pixels (lane l: pixel
+// (l % 8, l / 8) of every 8x8 group); per pixel it carries T, dL/dC and the
+// colour behind the current entry dotted with dL/dC.
+template <int TILE>
+struct BwdPix {
+  static constexpr int Q = TileShape<TILE>::kGroups;
+  float T[Q], g0[Q], g1[Q], g2[Q], SdL[Q];
+  uint32_t last[Q];
+  uint32_t glast[Q];  // per group: the largest last contributor (wave-uniform)
+  uint32_t mylast;    // over the tile (wave-uniform)
+};
+
+// load final_T, last_contrib and dL/dC of the tile's pixels; SdL starts at
+// T_final * (bg . dL/dC)
+template <int TILE>
+__device__ __forceinline__ void bwd_load_pixels(BwdPix<TILE>& P, const RViews& RV, int v, int tx,
+                                                int ty, int lane, const float* __restrict__ final_T,
+                                                const uint32_t* __restrict__ last_contrib,
+                                                const float* __restrict__ dL_dimage, float bg0,
+                                                float bg1, float bg2) {
+  constexpr int GX = TileShape<TILE>::kGroupsX, Q = TileShape<TILE>::kGroups;
+  const int lx = lane & 7, ly = lane >> 3;
+  const int W = RV.W[v], H = RV.H[v];
+  const int64_t pb = RV.pix_base[v];
+  const int64_t plane = int64_t(W) * H;
+  P.mylast = 0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int x = tx * TILE + (q % GX) * 8 + lx, y = ty * TILE + (q / GX) * 8 + ly;
+    // pixels past the image edge load pixel 0 and are neutralised by selects
+    // (conditional stores into the arrays would keep them in scratch memory)
+    const bool in = (x < W) & (y < H);
+    const int64_t o = in ? int64_t(y) * W + x : 0;
+    const float ft = final_T[pb + o];
+    const uint32_t lc = last_contrib[pb + o];
+    const float d0 = dL_dimage[3 * pb + o], d1 = dL_dimage[3 * pb + plane + o],
+                d2 = dL_dimage[3 * pb + 2 * plane + o];
+    P.T[q] = in ? ft : 1.0f;
+    P.last[q] = in ? lc : 0u;
+    P.g0[q] = in ? d0 : 0.0f;
+    P.g1[q] = in ? d1 : 0.0f;
+    P.g2[q] = in ? d2 : 0.0f;
+    P.SdL[q] = P.T[q] * fmaf(bg0, P.g0[q], fmaf(bg1, P.g1[q], bg2 * P.g2[q]));
+    uint32_t mx = P.last[q];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) mx = max(mx, uint32_t(__shfl_xor(int(mx), d, 64)));
+    P.glast[q] = __builtin_amdgcn_readfirstlane(mx);
+    P.mylast = max(P.mylast, P.glast[q]);
+  }
+}
+
+// one wave's LDS staging of list entries: record in the tile frame, box mask,
+// and the entry's per-pair gradient slot
+struct BwdStage {
+  float4* r0;
+  float4* r1;
+  float* b;
+  uint32_t* mask;
+  uint32_t* pidx;
+};
+
+template <int TILE>
+__device__ __forceinline__ void bwd_stage(const BwdStage& S, uint32_t bstart, int nb, int lane,
+                                          const uint32_t* __restrict__ vals, const float4* rec,
+                                          const uint32_t* goff, int tx, int ty) {
+  for (int k = lane; k < nb; k += 64) {
+    const uint32_t g = vals[bstart + k];
+    const float4 r0 = rec[3 * size_t(g)];
+    const float4 r1 = rec[3 * size_t(g) + 1];
+    const float4 r2 = rec[3 * size_t(g) + 2];
+    const uint32_t lo = __float_as_uint(r2.z), hi = __float_as_uint(r2.w);
+    S.r0[k] = to_tile_frame<TILE>(r0, lo, tx, ty);
+    S.r1[k] = r1;
+    S.b[k] = r2.x;
+    S.mask[k] = group_mask<TILE>(lo, hi, tx, ty);
+    const int tx0 = box_x(lo) / TILE, ty0 = box_y(lo) / TILE, tx1 = box_x(hi) / TILE;
+    S.pidx[k] = goff[g] + uint32_t((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
+  }
+}
+
+// The backward step of staged entry k at list position pos (1-based) for every
+// pixel of the wave: recover T_i, accumulate the nine 2D gradients, reduce
+// them over the wave and write the pair's slot.
+template <int TILE>
+__device__ __forceinline__ void bwd_step(BwdPix<TILE>& P, const BwdStage& S, int k, uint32_t pos,
+                                         int lane, float px0, float py0,
+                                         float* __restrict__ pair_grad, int64_t cap) {
+  constexpr int GX = TileShape<TILE>::kGroupsX, Q = TileShape<TILE>::kGroups;
+  uint32_t m = __builtin_amdgcn_readfirstlane(S.mask[k]);
+#pragma unroll
+  for (int q = 0; q < Q; ++q)
+    if (pos > P.glast[q]) m &= ~(1u << q);
+  if (m == 0u) return;
+  const float4 r0 = S.r0[k];
+  const float4 r1 = S.r1[k];
+  const float cb = S.b[k];
+  const float o = r1.y;
+  const float A2 = 2.0f * r0.z, C2 = 2.0f * r1.x;
+  float acc[kG];
+#pragma unroll
+  for (int c = 0; c < kG; ++c) acc[c] = 0.0f;
+  bool hit = false;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    if ((m >> q) & 1u) {
+      // branch-free: every lane computes, the decisions select the updates
+      const float px = px0 + float((q % GX) * 8), py = py0 + float((q / GX) * 8);
+      const Alpha e = alpha_at(r0, r1.x, o, px, py);
+      const bool ok = e.ok & (pos <= P.last[q]);
+      // footprint boxes are conservative: often no pixel of the group is reached
+      if (__ballot(ok) == 0ull) continue;
+      const bool grad = ok & (e.raw <= kAlphaMax);  // the 0.99 clamp passes no gradient
+      hit = true;
+      const float inv = __builtin_amdgcn_rcpf(1.0f - e.a);
+      const float Ti = P.T[q] * inv;
+      const float wgt = ok ? e.a * Ti : 0.0f;
+      const float cg = fmaf(r1.z, P.g0[q], fmaf(r1.w, P.g1[q], cb * P.g2[q]));
+      const float dLda = grad ? Ti * cg - P.SdL[q] * inv : 0.0f;
+      P.SdL[q] = fmaf(wgt, cg, P.SdL[q]);
+      P.T[q] = ok ? Ti : P.T[q];
+      acc[6] = fmaf(wgt, P.g0[q], acc[6]);
+      acc[7] = fmaf(wgt, P.g1[q], acc[7]);
+      acc[8] = fmaf(wgt, P.g2[q], acc[8]);
+      acc[5] = fmaf(dLda, e.G, acc[5]);
+      const float dpow = dLda * e.raw;
+      const float dpx = dpow * e.dx, dpy = dpow * e.dy;
+      acc[2] = fmaf(dpx, e.dx, acc[2]);
+      acc[3] = fmaf(dpx, e.dy, acc[3]);
+      acc[4] = fmaf(dpy, e.dy, acc[4]);
+      // (2A dx + B dy), (B dx + 2C dy): derivative of p2 w.r.t. -mean2D
+      acc[0] = fmaf(dpow, fmaf(A2, e.dx, r0.w * e.dy), acc[0]);
+      acc[1] = fmaf(dpow, fmaf(r0.w, e.dx, C2 * e.dy), acc[1]);
+    }
+  }
+  if (hit) {  // wave-uniform
+    float qv[3];
+    wave_sum9(acc, qv);
+    const uint32_t idx = S.pidx[k];
+    if ((lane & 15) == 15 && int64_t(idx) < cap) {
+      // natural-unit conic and mean gradients from the base-2 accumulators
+      // scales of components (0..3) and (4..7): -ln2, -ln2, -1/2, -1 and -1/2, 1, 1, 1
+      const int row = lane >> 4;
+      const int c0 = ((row & 1) << 1) | (row >> 1);  // 0, 2, 1, 3
+      const float s0 = c0 < 2 ? -kLn2 : (c0 == 2 ? -0.5f : -1.0f);
+      const float s1 = c0 == 0 ? -0.5f : 1.0f;
+      float* dst = pair_grad + size_t(idx) * kG;
+      dst[c0] = s0 * qv[0];
+      dst[c0 + 4] = s1 * qv[1];
+      if (row == 0) dst[8] = qv[2];
+    }
+  }
+}
+
+
+
+// One 64-lane wave per tile walks the list back to front in LDS-staged batches.
+// With `skip_long`, tiles whose list is longer than their view's threshold are
+// left to k_blend_bwd_long.
 template <int TILE, int BATCH>
 __global__ __launch_bounds__(64) void k_blend_bwd(
     RViews RV, int n, const char* __restrict__ proj, size_t stride,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const float* __restrict__ final_T, const uint32_t* __restrict__ last_contrib,
     const float* __restrict__ dL_dimage, const uint32_t* __restrict__ grad_off,
-    float* __restrict__ pair_grad, int64_t cap, float bg0, float bg1, float bg2) {
-  constexpr int GX = TileShape<TILE>::kGroupsX, Q = TileShape<TILE>::kGroups;
+    float* __restrict__ pair_grad, int64_t cap, float bg0, float bg1, float bg2, int skip_long) {
   __shared__ float4 s_r0[BATCH];
   __shared__ float4 s_r1[BATCH];
   __shared__ float s_b[BATCH];
   __shared__ uint32_t s_mask[BATCH];
   __shared__ uint32_t s_pidx[BATCH];
+  const BwdStage S{s_r0, s_r1, s_b, s_mask, s_pidx};
 
   const int t = xcd_tile(blockIdx.x, RV);
+  const uint32_t start = ranges[2 * t], end = ranges[2 * t + 1];
   const int v = view_of_tile(RV, t);
+  if (skip_long && end - start > long_list_threshold<TILE>(RV, v)) return;
   const int lt = t - RV.tile_base[v];
-  const int gw = RV.gw[v], W = RV.W[v], H = RV.H[v];
+  const int gw = RV.gw[v];
   const int tx = lt % gw, ty = lt / gw;
   const int lane = threadIdx.x;
-  const int lx = lane & 7, ly = lane >> 3;
-  const int64_t pb = RV.pix_base[v];
-  const int64_t plane = int64_t(W) * H;
-
-  float T[Q], g0[Q], g1[Q], g2[Q], SdL[Q];
-  uint32_t last[Q];
-  uint32_t glast[Q];  // per group: the largest last contributor (wave-uniform)
-  uint32_t mylast = 0;
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int x = tx * TILE + (q % GX) * 8 + lx, y = ty * TILE + (q / GX) * 8 + ly;
-    if (x < W && y < H) {
-      const int64_t o = int64_t(y) * W + x;
-      T[q] = final_T[pb + o];
-      last[q] = last_contrib[pb + o];
-      g0[q] = dL_dimage[3 * pb + o];
-      g1[q] = dL_dimage[3 * pb + plane + o];
-      g2[q] = dL_dimage[3 * pb + 2 * plane + o];
-    } else {
-      T[q] = 1.0f;
-      last[q] = 0;
-      g0[q] = g1[q] = g2[q] = 0.0f;
-    }
-    // colour behind the current Gaussian, dotted with dL/dC: starts at T_final * bg
-    SdL[q] = T[q] * fmaf(bg0, g0[q], fmaf(bg1, g1[q], bg2 * g2[q]));
-    uint32_t mx = last[q];
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) mx = max(mx, uint32_t(__shfl_xor(int(mx), d, 64)));
-    glast[q] = __builtin_amdgcn_readfirstlane(mx);
-    mylast = max(mylast, glast[q]);
-  }
-  const uint32_t start = ranges[2 * t];
-  const uint32_t stop = min(start + mylast, ranges[2 * t + 1]);
+  BwdPix<TILE> P;
+  bwd_load_pixels<TILE>(P, RV, v, tx, ty, lane, final_T, last_contrib, dL_dimage, bg0, bg1, bg2);
+  const uint32_t stop = min(start + P.mylast, end);
   const float4* rec = reinterpret_cast<const float4*>(proj + size_t(v) * stride);
   const uint32_t* goff = grad_off + size_t(v) * n;
-  const float px0 = float(lx) + 0.5f, py0 = float(ly) + 0.5f;
+  const float px0 = float(lane & 7) + 0.5f, py0 = float(lane >> 3) + 0.5f;
 
   for (uint32_t bend = stop; bend > start;) {
     const uint32_t bstart = (bend - start > uint32_t(BATCH)) ? bend - BATCH : start;
     const int nb = int(bend - bstart);
     __syncthreads();  // the previous batch is consumed
-    for (int k = lane; k < nb; k += 64) {
-      const uint32_t g = vals[bstart + k];
-      const float4 r0 = rec[3 * size_t(g)];
-      const float4 r1 = rec[3 * size_t(g) + 1];
-      const float4 r2 = rec[3 * size_t(g) + 2];
-      const uint32_t lo = __float_as_uint(r2.z), hi = __float_as_uint(r2.w);
-      s_r0[k] = to_tile_frame<TILE>(r0, lo, tx, ty);
-      s_r1[k] = r1;
-      s_b[k] = r2.x;
-      s_mask[k] = group_mask<TILE>(lo, hi, tx, ty);
-      const int tx0 = box_x(lo) / TILE, ty0 = box_y(lo) / TILE, tx1 = box_x(hi) / TILE;
-      s_pidx[k] = goff[g] + uint32_t((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
+    bwd_stage<TILE>(S, bstart, nb, lane, vals, rec, goff, tx, ty);
+    __syncthreads();
+    for (int k = nb - 1; k >= 0; --k)
+      bwd_step<TILE>(P, S, k, bstart - start + uint32_t(k) + 1u, lane, px0, py0, pair_grad, cap);
+    bend = bstart;
+  }
+}
+
+// ---- long lists (low resolutions: few tiles, thousands of entries each): one
+// block of kLongWaves waves per tile, the list cut into nch <= kMaxChunks
+// chunks dealt to the waves.  Which entries a pixel blends is fixed by the
+// forward's last_contrib and the alpha test alone, so the chunks are
+// independent:
+//   A. each chunk's transmittance product and colour (front to back, T = 1 at
+//      its start) per pixel;
+//   B. per pixel, the transmittance after each chunk (prefix of the products)
+//      and the colour behind it dotted with dL/dC (suffix of the chunk
+//      colours, weighted by their incoming T, plus T_final (bg . dL/dC));
+//   C. each chunk's backward walk from that state, as in k_blend_bwd.
+// The T recovery by division therefore runs over at most one chunk.
+constexpr int kLongWaves = 8;
+constexpr int kMaxChunks = 16;
+constexpr uint32_t kMinChunk = 64;
+constexpr int kLongBatch = 64;
+constexpr int kLongBlocks = 1024;
+
+template <int TILE>
+__global__ __launch_bounds__(64 * kLongWaves) void k_blend_bwd_long(
+    RViews RV, int n, const char* __restrict__ proj, size_t stride,
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
+    const float* __restrict__ final_T, const uint32_t* __restrict__ last_contrib,
+    const float* __restrict__ dL_dimage, const uint32_t* __restrict__ grad_off,
+    float* __restrict__ pair_grad, int64_t cap, float bg0, float bg1, float bg2) {
+  constexpr int GX = TileShape<TILE>::kGroupsX, Q = TileShape<TILE>::kGroups;
+  __shared__ float4 s_r0[kLongWaves][kLongBatch];
+  __shared__ float4 s_r1[kLongWaves][kLongBatch];
+  __shared__ float s_b[kLongWaves][kLongBatch];
+  __shared__ uint32_t s_mask[kLongWaves][kLongBatch];
+  __shared__ uint32_t s_pidx[kLongWaves][kLongBatch];
+  // per chunk and pixel: (product, colour) after pass A, (T after, SdL after) after B
+  __shared__ float4 s_ch[kMaxChunks][Q][64];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const BwdStage S{s_r0[wv], s_r1[wv], s_b[wv], s_mask[wv], s_pidx[wv]};
+  const float px0 = float(lane & 7) + 0.5f, py0 = float(lane >> 3) + 0.5f;
+
+  for (int t = blockIdx.x; t < RV.total_tiles; t += gridDim.x) {
+    const uint32_t start = ranges[2 * t], end = ranges[2 * t + 1];
+    const int v = view_of_tile(RV, t);
+    if (end - start <= long_list_threshold<TILE>(RV, v)) continue;  // block-uniform
+    const int lt = t - RV.tile_base[v];
+    const int gw = RV.gw[v];
+    const int tx = lt % gw, ty = lt / gw;
+    BwdPix<TILE> P;
+    bwd_load_pixels<TILE>(P, RV, v, tx, ty, lane, final_T, last_contrib, dL_dimage, bg0, bg1,
+                          bg2);
+    const uint32_t len = min(P.mylast, end - start);  // entries anyone blends
+    const uint32_t want = (len + kMinChunk - 1) / kMinChunk;
+    const int nch = int(want < uint32_t(kMaxChunks) ? want : uint32_t(kMaxChunks));
+    const uint32_t ch = nch > 0 ? (len + uint32_t(nch) - 1) / uint32_t(nch) : 0u;
+    const float4* rec = reinterpret_cast<const float4*>(proj + size_t(v) * stride);
+    const uint32_t* goff = grad_off + size_t(v) * n;
+
+    // A. per chunk: product of (1 - alpha) and colour over the blended entries
+    for (int c = wv; c < nch; c += kLongWaves) {
+      const uint32_t c0 = uint32_t(c) * ch, c1 = min(c0 + ch, len);
+      float Pr[Q], C0[Q], C1[Q], C2[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) Pr[q] = 1.0f, C0[q] = C1[q] = C2[q] = 0.0f;
+      for (uint32_t b0 = c0; b0 < c1; b0 += kLongBatch) {
+        const int nb = int(min(c1 - b0, uint32_t(kLongBatch)));
+        bwd_stage<TILE>(S, start + b0, nb, lane, vals, rec, goff, tx, ty);
+        __builtin_amdgcn_wave_barrier();
+        for (int k = 0; k < nb; ++k) {
+          const uint32_t pos = b0 + uint32_t(k) + 1u;
+          const uint32_t m = __builtin_amdgcn_readfirstlane(S.mask[k]);
+          const float4 r0 = S.r0[k], r1 = S.r1[k];
+          const float cb = S.b[k];
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            if (((m >> q) & 1u) == 0u || pos > P.glast[q]) continue;  // wave-uniform
+            const float px = px0 + float((q % GX) * 8), py = py0 + float((q / GX) * 8);
+            const Alpha e = alpha_at(r0, r1.x, r1.y, px, py);
+            const bool ok = e.ok & (pos <= P.last[q]);
+            const float w = ok ? e.a * Pr[q] : 0.0f;
+            C0[q] = fmaf(w, r1.z, C0[q]);
+            C1[q] = fmaf(w, r1.w, C1[q]);
+            C2[q] = fmaf(w, cb, C2[q]);
+            Pr[q] = ok ? Pr[q] * (1.0f - e.a) : Pr[q];
+          }
+        }
+        __builtin_amdgcn_wave_barrier();  // the staging is rewritten next
+      }
+#pragma unroll
+      for (int q = 0; q < Q; ++q) s_ch[c][q][lane] = make_float4(Pr[q], C0[q], C1[q], C2[q]);
     }
     __syncthreads();
-    for (int k = nb - 1; k >= 0; --k) {
-      const uint32_t pos = bstart - start + uint32_t(k) + 1u;
-      uint32_t m = __builtin_amdgcn_readfirstlane(s_mask[k]);
-#pragma unroll
-      for (int q = 0; q < Q; ++q)
-        if (pos > glast[q]) m &= ~(1u << q);
-      if (m == 0u) continue;
-      const float4 r0 = s_r0[k];
-      const float4 r1 = s_r1[k];
-      const float cb = s_b[k];
-      const float o = r1.y;
-      const float A2 = 2.0f * r0.z, C2 = 2.0f * r1.x;
-      float acc[kG];
-#pragma unroll
-      for (int c = 0; c < kG; ++c) acc[c] = 0.0f;
-      bool hit = false;
+    // B. wave q handles pixel group q: T after each chunk and the colour behind it
+    if (wv < Q) {
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        if ((m >> q) & 1u) {
-          // branch-free: every lane computes, the decisions select the updates
-          const float px = px0 + float((q % GX) * 8), py = py0 + float((q / GX) * 8);
-          const Alpha e = alpha_at(r0, r1.x, o, px, py);
-          const bool ok = e.ok & (pos <= last[q]);
-          // footprint boxes are conservative: often no pixel of the group is reached
-          if (__ballot(ok) == 0ull) continue;
-          const bool grad = ok & (e.raw <= kAlphaMax);  // the 0.99 clamp passes no gradient
-          hit = true;
-          const float inv = __builtin_amdgcn_rcpf(1.0f - e.a);
-          const float Ti = T[q] * inv;
-          const float wgt = ok ? e.a * Ti : 0.0f;
-          const float cg = fmaf(r1.z, g0[q], fmaf(r1.w, g1[q], cb * g2[q]));
-          const float dLda = grad ? Ti * cg - SdL[q] * inv : 0.0f;
-          SdL[q] = fmaf(wgt, cg, SdL[q]);
-          T[q] = ok ? Ti : T[q];
-          acc[6] = fmaf(wgt, g0[q], acc[6]);
-          acc[7] = fmaf(wgt, g1[q], acc[7]);
-          acc[8] = fmaf(wgt, g2[q], acc[8]);
-          acc[5] = fmaf(dLda, e.G, acc[5]);
-          const float dpow = dLda * e.raw;
-          const float dpx = dpow * e.dx, dpy = dpow * e.dy;
-          acc[2] = fmaf(dpx, e.dx, acc[2]);
-          acc[3] = fmaf(dpx, e.dy, acc[3]);
-          acc[4] = fmaf(dpy, e.dy, acc[4]);
-          // (2A dx + B dy), (B dx + 2C dy): derivative of p2 w.r.t. -mean2D
-          acc[0] = fmaf(dpow, fmaf(A2, e.dx, r0.w * e.dy), acc[0]);
-          acc[1] = fmaf(dpow, fmaf(r0.w, e.dx, C2 * e.dy), acc[1]);
+        if (q != wv) continue;
+        // prefix: the transmittance entering each chunk replaces its product
+        float T = 1.0f;
+        for (int c = 0; c < nch; ++c) {
+          const float pr = s_ch[c][q][lane].x;
+          s_ch[c][q][lane].x = T;
+          T *= pr;
         }
-      }
-      if (hit) {  // wave-uniform
-        float qv[3];
-        wave_sum9(acc, qv);
-        const uint32_t idx = s_pidx[k];
-        if ((lane & 15) == 15 && int64_t(idx) < cap) {
-          // natural-unit conic and mean gradients from the base-2 accumulators
-          const int row = lane >> 4;
-          const int c0 = ((row & 1) << 1) | (row >> 1);  // 0, 2, 1, 3
-          constexpr float kScale[kG] = {-kLn2, -kLn2, -0.5f, -1.0f, -0.5f, 1.0f, 1.0f, 1.0f, 1.0f};
-          float* dst = pair_grad + size_t(idx) * kG;
-          dst[c0] = kScale[c0] * qv[0];
-          dst[c0 + 4] = kScale[c0 + 4] * qv[1];
-          if (row == 0) dst[8] = qv[2];
+        // suffix: P.SdL holds T_final (bg . dL/dC); the forward's T_final is the
+        // transmittance after the last chunk
+        float behind = P.SdL[q];
+        float Tafter = P.T[q];
+        for (int c = nch - 1; c >= 0; --c) {
+          const float4 pc = s_ch[c][q][lane];  // (T entering, colour)
+          s_ch[c][q][lane] = make_float4(Tafter, behind, 0.0f, 0.0f);
+          const float cg = fmaf(pc.y, P.g0[q], fmaf(pc.z, P.g1[q], pc.w * P.g2[q]));
+          behind = fmaf(pc.x, cg, behind);
+          Tafter = pc.x;
         }
       }
     }
-    bend = bstart;
+    __syncthreads();
+    // C. backward walk of each chunk from its end state
+    for (int c = wv; c < nch; c += kLongWaves) {
+      const uint32_t c0 = uint32_t(c) * ch, c1 = min(c0 + ch, len);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const float4 st = s_ch[c][q][lane];
+        P.T[q] = st.x;
+        P.SdL[q] = st.y;
+      }
+      for (uint32_t bend = c1; bend > c0;) {
+        const uint32_t bstart = (bend - c0 > uint32_t(kLongBatch)) ? bend - kLongBatch : c0;
+        const int nb = int(bend - bstart);
+        bwd_stage<TILE>(S, start + bstart, nb, lane, vals, rec, goff, tx, ty);
+        __builtin_amdgcn_wave_barrier();
+        for (int k = nb - 1; k >= 0; --k)
+          bwd_step<TILE>(P, S, k, bstart + uint32_t(k) + 1u, lane, px0, py0, pair_grad, cap);
+        __builtin_amdgcn_wave_barrier();
+        bend = bstart;
+      }
+    }
+    __syncthreads();  // s_ch is rewritten for the block's next tile
   }
 }
 
@@ -740,16 +935,24 @@ void launch_bwd_tile(int batch, dim3 grid, const RViews& RV, int n, const char* 
                      const uint32_t* goff, float* pairs, int64_t cap, const float* bg,
                      hipStream_t st) {
   const dim3 block(64);
+  // tiles of 8 and 16 pixels hand long lists to the list-parallel kernel
+  constexpr int kSplit = TILE <= 16 ? 1 : 0;
 #define GS_BWD_LAUNCH(B)                                                                       \
   GS_LAUNCH("k_blend_bwd", HIP_KERNEL_NAME(k_blend_bwd<TILE, B>), grid, block, 0, st, RV, n, proj,   \
                      stride, ranges, vals, final_T, last_contrib, dL, goff, pairs, cap, bg[0], \
-                     bg[1], bg[2])
+                     bg[1], bg[2], kSplit)
   switch (batch) {
     case 128: GS_BWD_LAUNCH(128); break;
     case 256: GS_BWD_LAUNCH(256); break;
     default: GS_BWD_LAUNCH(512); break;
   }
 #undef GS_BWD_LAUNCH
+  if (kSplit) {
+    const unsigned nb = unsigned(RV.total_tiles < kLongBlocks ? RV.total_tiles : kLongBlocks);
+    GS_LAUNCH("k_blend_bwd_long", HIP_KERNEL_NAME(k_blend_bwd_long<TILE <= 16 ? TILE : 16>),
+              dim3(nb), dim3(64 * kLongWaves), 0, st, RV, n, proj, stride, ranges, vals, final_T,
+              last_contrib, dL, goff, pairs, cap, bg[0], bg[1], bg[2]);
+  }
 }
 
 }  // namespace

@@ -72,6 +72,21 @@ __host__ __device__ __forceinline__ int xcd_tile(int b, const RViews& RV) {
   return RV.tile_base[RV.order[k]] + RV.xcd_start[x][k] + (idx - RV.xcd_off[x][k]);
 }
 
+// Lists longer than this go to the list-parallel kernels (tiles of 8 and 16
+// pixels; the forward and the backward use the same rule, so both take the same
+// path for a tile).  A wave walking a list alone on its SIMD costs about 0.4 us
+// per entry, so views with few tiles (nothing else to run meanwhile) split
+// much shorter lists.
+constexpr uint32_t kLongList = 512;
+constexpr uint32_t kLongListFewTiles = 96;
+constexpr int kFewTiles = 2048;
+
+template <int TILE>
+__device__ __forceinline__ uint32_t long_list_threshold(const RViews& RV, int v) {
+  const int tiles = RV.gw[v] * ((RV.H[v] + TILE - 1) / TILE);
+  return tiles < kFewTiles ? kLongListFewTiles : kLongList;
+}
+
 // global tile id -> view (views are few; the loop runs on the scalar unit)
 __device__ __forceinline__ int view_of_tile(const RViews& RV, int t) {
   int v = 0;

@@ -16,7 +16,7 @@ template <int TILE, int BATCH>
 __global__ __launch_bounds__(WaveShape<TILE>::kThreads) void k_blend_fwd(
     RViews RV, const char* __restrict__ proj, size_t stride, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ vals, float* __restrict__ image, float* __restrict__ final_T,
-    uint32_t* __restrict__ last_contrib, float bg0, float bg1, float bg2) {
+    uint32_t* __restrict__ last_contrib, float bg0, float bg1, float bg2, int skip_long) {
   using S = WaveShape<TILE>;
   constexpr int NT = S::kThreads, NW = S::kWaves, R = S::kRegion, SUB = S::kSub, P = S::kPix;
   __shared__ float4 s_r0[BATCH];
@@ -27,6 +27,7 @@ __global__ __launch_bounds__(WaveShape<TILE>::kThreads) void k_blend_fwd(
 
   const int t = xcd_tile(blockIdx.x, RV);
   const int v = view_of_tile(RV, t);
+  if (skip_long && ranges[2 * t + 1] - ranges[2 * t] > long_list_threshold<TILE>(RV, v)) return;
   const int lt = t - RV.tile_base[v];
   const int gw = RV.gw[v], W = RV.W[v], H = RV.H[v];
   const int tx = lt % gw, ty = lt / gw;
@@ -142,23 +143,251 @@ __global__ __launch_bounds__(WaveShape<TILE>::kThreads) void k_blend_fwd(
     }
 }
 
+// ---- long lists (low resolutions: few tiles, thousands of entries each): one
+// block of kFWaves waves per tile, the list cut into nch <= kFMaxChunks chunks
+// dealt to the waves; lane l owns pixel (l % 8, l / 8) of every 8x8 group.
+// Transmittance only decreases along the list, so a pixel stops inside chunk
+// k exactly when T entering k times the product of (1 - alpha) over k's
+// entries falls below 1e-4:
+//   A. per chunk and pixel, with no stopping: the product, the colour (T = 1
+//      at the chunk start) and the last entry with alpha >= 1/255;
+//   B. per pixel: the first chunk whose product takes T below 1e-4, and T and
+//      colour entering it (or, if none, the final T, colour and last entry);
+//   C. from that chunk on, the sequential front-to-back walk of the short
+//      kernel until the pixel stops.
+constexpr int kFWaves = 8;
+constexpr int kFMaxChunks = 16;
+constexpr uint32_t kFMinChunk = 64;
+constexpr int kFBatch = 64;
+constexpr int kFLongBlocks = 1024;
+
+template <int TILE>
+__device__ __forceinline__ void fwd_stage(float4* r0s, float4* r1s, float* bs, uint32_t* ms,
+                                          uint32_t bstart, int nb, int lane,
+                                          const uint32_t* __restrict__ vals, const float4* rec,
+                                          int tx, int ty) {
+  for (int k = lane; k < nb; k += 64) {
+    const uint32_t g = vals[bstart + k];
+    const float4 r0 = rec[3 * size_t(g)];
+    const float4 r1 = rec[3 * size_t(g) + 1];
+    const float4 r2 = rec[3 * size_t(g) + 2];
+    const uint32_t lo = __float_as_uint(r2.z), hi = __float_as_uint(r2.w);
+    r0s[k] = to_tile_frame<TILE>(r0, lo, tx, ty);
+    r1s[k] = r1;
+    bs[k] = r2.x;
+    ms[k] = group_mask<TILE>(lo, hi, tx, ty);
+  }
+}
+
+template <int TILE>
+__global__ __launch_bounds__(64 * kFWaves) void k_blend_fwd_long(
+    RViews RV, const char* __restrict__ proj, size_t stride, const uint32_t* __restrict__ ranges,
+    const uint32_t* __restrict__ vals, float* __restrict__ image, float* __restrict__ final_T,
+    uint32_t* __restrict__ last_contrib, float bg0, float bg1, float bg2) {
+  constexpr int GX = TileShape<TILE>::kGroupsX, Q = TileShape<TILE>::kGroups;
+  __shared__ float4 s_r0[kFWaves][kFBatch];
+  __shared__ float4 s_r1[kFWaves][kFBatch];
+  __shared__ float s_b[kFWaves][kFBatch];
+  __shared__ uint32_t s_mask[kFWaves][kFBatch];
+  __shared__ float4 s_ch[kFMaxChunks][Q][64];    // A: (product, colour)
+  __shared__ uint32_t s_lp[kFMaxChunks][Q][64];  // A: last entry with alpha >= 1/255
+  __shared__ float4 s_st[Q][64];                 // B/C: (T, colour) of the pixel
+  __shared__ uint32_t s_stop[Q][64];             // B: stop chunk + 1, 0 if none
+  __shared__ uint32_t s_last[Q][64];             // B/C: last blended entry
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lx = lane & 7, ly = lane >> 3;
+  const float px0 = float(lx) + 0.5f, py0 = float(ly) + 0.5f;
+  float4* r0s = s_r0[wv];
+  float4* r1s = s_r1[wv];
+  float* bs = s_b[wv];
+  uint32_t* ms = s_mask[wv];
+
+  for (int t = blockIdx.x; t < RV.total_tiles; t += gridDim.x) {
+    const uint32_t start = ranges[2 * t], end = ranges[2 * t + 1];
+    const int v = view_of_tile(RV, t);
+    if (end - start <= long_list_threshold<TILE>(RV, v)) continue;  // block-uniform
+    const int lt = t - RV.tile_base[v];
+    const int gw = RV.gw[v], W = RV.W[v], H = RV.H[v];
+    const int tx = lt % gw, ty = lt / gw;
+    const uint32_t len = end - start;
+    const uint32_t want = (len + kFMinChunk - 1) / kFMinChunk;
+    const int nch = int(want < uint32_t(kFMaxChunks) ? want : uint32_t(kFMaxChunks));
+    const uint32_t ch = (len + uint32_t(nch) - 1) / uint32_t(nch);
+    const float4* rec = reinterpret_cast<const float4*>(proj + size_t(v) * stride);
+
+    // A. per chunk, no stopping
+    for (int c = wv; c < nch; c += kFWaves) {
+      const uint32_t c0 = uint32_t(c) * ch, c1 = min(c0 + ch, len);
+      float Pr[Q], C0[Q], C1[Q], C2[Q];
+      uint32_t lp[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) Pr[q] = 1.0f, C0[q] = C1[q] = C2[q] = 0.0f, lp[q] = 0u;
+      for (uint32_t b0 = c0; b0 < c1; b0 += kFBatch) {
+        const int nb = int(min(c1 - b0, uint32_t(kFBatch)));
+        fwd_stage<TILE>(r0s, r1s, bs, ms, start + b0, nb, lane, vals, rec, tx, ty);
+        __builtin_amdgcn_wave_barrier();
+        for (int k = 0; k < nb; ++k) {
+          const uint32_t m = __builtin_amdgcn_readfirstlane(ms[k]);
+          const float4 r0 = r0s[k], r1 = r1s[k];
+          const float cb = bs[k];
+          const uint32_t pos = b0 + uint32_t(k) + 1u;
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            if (((m >> q) & 1u) == 0u) continue;  // wave-uniform: the box misses the group
+            const Alpha e = alpha_at(r0, r1.x, r1.y, px0 + float((q % GX) * 8),
+                                     py0 + float((q / GX) * 8));
+            const float w = e.ok ? e.a * Pr[q] : 0.0f;
+            C0[q] = fmaf(w, r1.z, C0[q]);
+            C1[q] = fmaf(w, r1.w, C1[q]);
+            C2[q] = fmaf(w, cb, C2[q]);
+            Pr[q] = e.ok ? Pr[q] * (1.0f - e.a) : Pr[q];
+            lp[q] = e.ok ? pos : lp[q];
+          }
+        }
+        __builtin_amdgcn_wave_barrier();  // the staging is rewritten next
+      }
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        s_ch[c][q][lane] = make_float4(Pr[q], C0[q], C1[q], C2[q]);
+        s_lp[c][q][lane] = lp[q];
+      }
+    }
+    __syncthreads();
+    // B. wave q handles pixel group q
+    if (wv < Q) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        if (q != wv) continue;
+        float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+        uint32_t last = 0u, stop = 0u;
+        for (int c = 0; c < nch; ++c) {
+          const float4 pc = s_ch[c][q][lane];
+          if (T * pc.x < kTMin) {
+            stop = uint32_t(c) + 1u;
+            break;
+          }
+          C0 = fmaf(T, pc.y, C0);
+          C1 = fmaf(T, pc.z, C1);
+          C2 = fmaf(T, pc.w, C2);
+          T *= pc.x;
+          const uint32_t l = s_lp[c][q][lane];
+          last = l ? l : last;
+        }
+        s_st[q][lane] = make_float4(T, C0, C1, C2);
+        s_stop[q][lane] = stop;
+        s_last[q][lane] = last;
+      }
+    }
+    __syncthreads();
+    // C. sequential walk from each pixel's stop chunk until it stops
+    for (int c = wv; c < nch; c += kFWaves) {
+      float T[Q], C0[Q], C1[Q], C2[Q];
+      uint32_t last[Q];
+      bool done[Q], mine[Q];
+      bool any = false;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        mine[q] = s_stop[q][lane] == uint32_t(c) + 1u;
+        const float4 st = s_st[q][lane];
+        T[q] = st.x, C0[q] = st.y, C1[q] = st.z, C2[q] = st.w;
+        last[q] = s_last[q][lane];
+        done[q] = !mine[q];
+        any |= mine[q];
+      }
+      if (__ballot(any) == 0ull) continue;
+      for (uint32_t b0 = uint32_t(c) * ch; b0 < len; b0 += kFBatch) {
+        bool alive = false;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) alive |= !done[q];
+        if (__ballot(alive) == 0ull) break;
+        const int nb = int(min(len - b0, uint32_t(kFBatch)));
+        fwd_stage<TILE>(r0s, r1s, bs, ms, start + b0, nb, lane, vals, rec, tx, ty);
+        __builtin_amdgcn_wave_barrier();
+        for (int k = 0; k < nb; ++k) {
+          const uint32_t m = __builtin_amdgcn_readfirstlane(ms[k]);
+          const float4 r0 = r0s[k], r1 = r1s[k];
+          const float cb = bs[k];
+          const uint32_t pos = b0 + uint32_t(k) + 1u;
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            if (((m >> q) & 1u) == 0u) continue;
+            const Alpha e = alpha_at(r0, r1.x, r1.y, px0 + float((q % GX) * 8),
+                                     py0 + float((q / GX) * 8));
+            const bool ok = e.ok & !done[q];
+            const float Tn = T[q] * (1.0f - e.a);
+            const bool stop = ok & (Tn < kTMin);
+            const bool blend = ok & !stop;
+            const float wgt = blend ? e.a * T[q] : 0.0f;
+            C0[q] = fmaf(wgt, r1.z, C0[q]);
+            C1[q] = fmaf(wgt, r1.w, C1[q]);
+            C2[q] = fmaf(wgt, cb, C2[q]);
+            T[q] = blend ? Tn : T[q];
+            last[q] = blend ? pos : last[q];
+            done[q] = done[q] | stop;
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        if (mine[q]) {
+          s_st[q][lane] = make_float4(T[q], C0[q], C1[q], C2[q]);
+          s_last[q][lane] = last[q];
+        }
+      }
+    }
+    __syncthreads();
+    // outputs: wave q writes pixel group q
+    if (wv < Q) {
+      const int64_t pb = RV.pix_base[v];
+      const int64_t plane = int64_t(W) * H;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        if (q != wv) continue;
+        const int x = tx * TILE + (q % GX) * 8 + lx, y = ty * TILE + (q / GX) * 8 + ly;
+        if (x < W && y < H) {
+          const float4 st = s_st[q][lane];
+          const int64_t o = int64_t(y) * W + x;
+          image[3 * pb + o] = fmaf(st.x, bg0, st.y);
+          image[3 * pb + plane + o] = fmaf(st.x, bg1, st.z);
+          image[3 * pb + 2 * plane + o] = fmaf(st.x, bg2, st.w);
+          final_T[pb + o] = st.x;
+          last_contrib[pb + o] = s_last[q][lane];
+        }
+      }
+    }
+    __syncthreads();  // the block's next tile rewrites the LDS
+  }
+}
+
 template <int TILE>
 hipError_t launch_tile(int batch, const RViews& RV, const char* proj, size_t stride,
                        const uint32_t* ranges, const uint32_t* vals, float* image,
                        float* final_T, uint32_t* last_contrib, const float* bg, hipStream_t st) {
   const dim3 grid(unsigned(RV.total_tiles)), block(WaveShape<TILE>::kThreads);
+  // tiles of 8 and 16 pixels hand long lists to the list-parallel kernel
+  constexpr int skip_long = TILE <= 16 ? 1 : 0;
+  if (skip_long) {
+    const unsigned nb = unsigned(RV.total_tiles < kFLongBlocks ? RV.total_tiles : kFLongBlocks);
+    GS_LAUNCH("k_blend_fwd_long", HIP_KERNEL_NAME(k_blend_fwd_long<TILE <= 16 ? TILE : 16>),
+              dim3(nb), dim3(64 * kFWaves), 0, st, RV, proj, stride, ranges, vals, image, final_T,
+              last_contrib, bg[0], bg[1], bg[2]);
+  }
   switch (batch) {
     case 128:
       GS_LAUNCH("k_blend_fwd", HIP_KERNEL_NAME(k_blend_fwd<TILE, 128>), grid, block, 0, st, RV, proj,
-                         stride, ranges, vals, image, final_T, last_contrib, bg[0], bg[1], bg[2]);
+                         stride, ranges, vals, image, final_T, last_contrib, bg[0], bg[1], bg[2],
+                         skip_long);
       break;
     case 256:
       GS_LAUNCH("k_blend_fwd", HIP_KERNEL_NAME(k_blend_fwd<TILE, 256>), grid, block, 0, st, RV, proj,
-                         stride, ranges, vals, image, final_T, last_contrib, bg[0], bg[1], bg[2]);
+                         stride, ranges, vals, image, final_T, last_contrib, bg[0], bg[1], bg[2],
+                         skip_long);
       break;
     default:
       GS_LAUNCH("k_blend_fwd", HIP_KERNEL_NAME(k_blend_fwd<TILE, 512>), grid, block, 0, st, RV, proj,
-                         stride, ranges, vals, image, final_T, last_contrib, bg[0], bg[1], bg[2]);
+                         stride, ranges, vals, image, final_T, last_contrib, bg[0], bg[1], bg[2],
+                         skip_long);
       break;
   }
   return hipGetLastError();

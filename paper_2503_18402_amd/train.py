@@ -120,7 +120,7 @@ class Trainer:
             views = [downscale_view(c, f) for c in self.cams]
             h, w = views[0].height, views[0].width
             gt_f = gt if f == 1 else downsample(gt, h, w)
-            tile = 8 if f >= 4 else 16
+            tile = 8 if f >= 2 else 16  # few tiles at low resolution: split them finer
             cap = 0
             for v in views:
                 probe = raster.render(params, [v], tile=tile, sh_degree=sh_degree)

@@ -114,6 +114,33 @@ def test_bin_sort_long_lists(n, longest):
         assert np.array_equal(gv[~P["flag_rect"][gv]], v[~P["flag_rect"][v]])
 
 
+@pytest.mark.parametrize("n,tile", [(1500, 16), (3000, 8)])
+def test_backward_long_lists(n, tile):
+    """Tile lists of 700-1400 entries with low opacities, so pixels blend deep
+    into them: the backward runs list-parallel (chunks walked by separate
+    waves from the chunk-boundary transmittance and colour behind).  Every
+    gradient against the FP64 oracle at the conditioned tolerance."""
+    sc = scenes.make_scene(n, seed=43, mean_range=0.2, ls_mu=-3.0, ls_sigma=0.2)
+    sc["opacity_logits"][:] = np.random.default_rng(44).uniform(-4.6, -3.5, n)
+    cam = scenes.look_at((0.0, 0.0, -3.0), (0.0, 0.0, 0.0), 32, 32, 40.0)
+    w = np.random.default_rng(45).uniform(-1, 1, size=(3, 32, 32)).astype(np.float32)
+    _, frame, g = U.run(sc, [cam], tile=tile, upstream=[w])
+    assert np.diff(frame.ranges.cpu().numpy().reshape(-1, 2), axis=1).max() > 512
+    P = project.project(sc, cam, tile=tile)
+    F = render.render_fwd(P)
+    B = render.render_bwd(sc, P, w, with_bound=True)
+    skip = P["flag_rgb"].any(1)
+    if F["flag"].any():
+        order = render._order(P)
+        ys, xs = np.nonzero(F["flag"].reshape(32, 32))
+        Bk = render._pixel_block(P, order, ys * 32 + xs, cam.width)
+        skip[order[(Bk["alpha"] >= 0.9 / 255.0).any(axis=0)]] = True
+    img = frame.image.view(3, 32, 32).cpu().numpy()
+    assert np.abs(img - F["image"])[:, ~F["flag"].reshape(32, 32)].max() < IMG_TOL
+    for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        U.check_grads(g[name], B["d_" + name], B["bound"]["d_" + name], mask=~skip)
+
+
 def test_bin_sort_end_to_end_matches_oracle(cfg0):
     sc, cam, P = cfg0["sc"], cfg0["cam"], cfg0["P"]
     _, frame, _ = U.run(sc, [cam], tile=16)
