@@ -264,6 +264,53 @@ gs_status gs_downsample_aa(int32_t n_planes, int32_t H, int32_t W, int32_t h, in
                            const float* src, float* dst, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * The resolution-guided primitive schedule (Sec. 4.3, Eq. 4-5; supplementary
+ * "Densification of DashGaussian").
+ *
+ * gs_primitive_target: Eq. 4, P_i = P_init + (P_fin - P_init) / r^(2 - i/S).
+ * gs_primitive_budget: Eq. 5, max(P_fin, gamma P_fin + eta P_add).
+ * (host arithmetic)
+ *
+ * A densification step is four calls; the caller reads two device counts in
+ * between and allocates the outputs:
+ *   gs_densify_stats (every iteration): accum[g] += d_mean2d_abs[g] and
+ *     count[g] += the number of views where g has a footprint (from proj),
+ *     for Gaussians seen in at least one view.  accum, count: device [n].
+ *   gs_densify_classify: score = accum / count (0 if count = 0, float32);
+ *     prune where sigmoid(opacity_logit) < min_opacity; candidate where not
+ *     pruned, count > 0 and score >= grad_thr.  counts_dev (device int64[2])
+ *     receives (pruned, candidates).
+ *   gs_densify_plan: selects the min(k, candidates) candidates of highest
+ *     score (ties: lowest index; k <= 0 selects none), marks a selected one
+ *     for a split when its largest exp(log_scale) exceeds max_scale (else a
+ *     clone) and plans the output; *n_new_dev receives the new count.
+ *   gs_densify_apply: writes the new parameter and moment arrays (n_new rows
+ *     each; 5 groups in the order means, log_scales, quats, opacity_logits,
+ *     sh).  In index order a pruned Gaussian writes nothing, a kept one itself
+ *     (moments copied), a cloned one itself then an identical copy (moments
+ *     zero), a split one two children at mu + R(q) diag(exp(log_scale)) z_j,
+ *     log_scale - ln 1.6, other parameters copied, moments zero.
+ *     z: device [n][2][3] standard normal samples.  Outputs must not alias
+ *     inputs.
+ *   ws: gs_densify_workspace_bytes(n), kept between the calls of one step.
+ * ------------------------------------------------------------------------- */
+double gs_primitive_target(double i, double S, double r, double p_init, double p_fin);
+double gs_primitive_budget(double p_fin_prev, double p_add, double gamma, double eta);
+size_t gs_densify_workspace_bytes(int32_t n);
+gs_status gs_densify_stats(int32_t n_views, int32_t n, const void* proj,
+                           const float* d_mean2d_abs, float* accum, float* count, void* stream);
+gs_status gs_densify_classify(int32_t n, const float* accum, const float* count,
+                              const float* opacity_logits, float grad_thr, float min_opacity,
+                              void* ws, size_t ws_bytes, int64_t* counts_dev, void* stream);
+gs_status gs_densify_plan(int32_t n, int64_t k, int64_t n_candidates, const float* log_scales,
+                          float max_scale, void* ws, size_t ws_bytes, int64_t* n_new_dev,
+                          void* stream);
+gs_status gs_densify_apply(int32_t n, const float* const* params, const float* const* m,
+                           const float* const* v, const float* z, const void* ws,
+                           size_t ws_bytes, float* const* params_out, float* const* m_out,
+                           float* const* v_out, void* stream);
+
+/* ---------------------------------------------------------------------------
  * gs_l1_loss_grad: L1 photometric loss of the backbones.
  *   dL_dimage[i] = scale * sign(image[i] - target[i])  (sign(0) = 0), numel
  *   elements; if loss_sum (device, [1]) is non-NULL, scale * sum|image-target|

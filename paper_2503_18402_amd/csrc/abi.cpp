@@ -348,6 +348,62 @@ gs_status gs_downsample_aa(int32_t n_planes, int32_t H, int32_t W, int32_t h, in
   return from_hip(launch_downsample(n_planes, H, W, h, w, src, dst, as_stream(stream)));
 }
 
+double gs_primitive_target(double i, double S, double r, double p_init, double p_fin) {
+  return p_init + (p_fin - p_init) / std::pow(r, 2.0 - i / S);
+}
+
+double gs_primitive_budget(double p_fin_prev, double p_add, double gamma, double eta) {
+  const double x = gamma * p_fin_prev + eta * p_add;
+  return x > p_fin_prev ? x : p_fin_prev;
+}
+
+size_t gs_densify_workspace_bytes(int32_t n) { return n < 0 ? 0 : densify_ws_bytes(n); }
+
+gs_status gs_densify_stats(int32_t n_views, int32_t n, const void* proj,
+                           const float* d_mean2d_abs, float* accum, float* count, void* stream) {
+  if (!n_ok(n_views, n)) return GS_ERR_ARG;
+  if (n > 0 && (!proj || !d_mean2d_abs || !accum || !count || !aligned16(proj))) return GS_ERR_ARG;
+  return from_hip(launch_densify_stats(n_views, n, static_cast<const char*>(proj), d_mean2d_abs,
+                                       accum, count, as_stream(stream)));
+}
+
+gs_status gs_densify_classify(int32_t n, const float* accum, const float* count,
+                              const float* opacity_logits, float grad_thr, float min_opacity,
+                              void* ws, size_t ws_bytes, int64_t* counts_dev, void* stream) {
+  if (n < 0 || !ws || !counts_dev || (n > 0 && (!accum || !count || !opacity_logits)))
+    return GS_ERR_ARG;
+  if (ws_bytes < densify_ws_bytes(n)) return GS_ERR_CAPACITY;
+  if (!aligned16(ws)) return GS_ERR_ARG;
+  return from_hip(launch_densify_classify(n, accum, count, opacity_logits, grad_thr, min_opacity,
+                                          ws, counts_dev, as_stream(stream)));
+}
+
+gs_status gs_densify_plan(int32_t n, int64_t k, int64_t n_candidates, const float* log_scales,
+                          float max_scale, void* ws, size_t ws_bytes, int64_t* n_new_dev,
+                          void* stream) {
+  if (n < 0 || n_candidates < 0 || n_candidates > n || !ws || !n_new_dev ||
+      (n > 0 && !log_scales))
+    return GS_ERR_ARG;
+  if (ws_bytes < densify_ws_bytes(n)) return GS_ERR_CAPACITY;
+  if (!aligned16(ws)) return GS_ERR_ARG;
+  return from_hip(launch_densify_plan(n, k, n_candidates, log_scales, max_scale, ws, n_new_dev,
+                                      as_stream(stream)));
+}
+
+gs_status gs_densify_apply(int32_t n, const float* const* params, const float* const* m,
+                           const float* const* v, const float* z, const void* ws,
+                           size_t ws_bytes, float* const* params_out, float* const* m_out,
+                           float* const* v_out, void* stream) {
+  if (n < 0 || !params || !m || !v || !params_out || !m_out || !v_out || !ws) return GS_ERR_ARG;
+  if (n > 0 && !z) return GS_ERR_ARG;
+  for (int t = 0; t < 5; ++t)
+    if (n > 0 && (!params[t] || !m[t] || !v[t] || !params_out[t] || !m_out[t] || !v_out[t]))
+      return GS_ERR_ARG;
+  if (ws_bytes < densify_ws_bytes(n)) return GS_ERR_CAPACITY;
+  return from_hip(launch_densify_apply(n, params, m, v, z, ws, params_out, m_out, v_out,
+                                       as_stream(stream)));
+}
+
 gs_status gs_l1_loss_grad(int64_t numel, const float* image, const float* target, float scale,
                           float* dL_dimage, float* loss_sum, void* stream) {
   if (numel < 0 || (numel > 0 && (!image || !target || !dL_dimage))) return GS_ERR_ARG;

@@ -221,6 +221,20 @@ hipError_t launch_render_bwd_adam(const Views& V, int n, const gs_raster_cfg& cf
 
 hipError_t launch_step_inc(int32_t* step_dev, hipStream_t st);
 
+// densification (densify.hip)
+size_t densify_ws_bytes(int n);
+hipError_t launch_densify_stats(int n_views, int n, const char* proj, const float* mean2d_abs,
+                                float* accum, float* count, hipStream_t st);
+hipError_t launch_densify_classify(int n, const float* accum, const float* count,
+                                   const float* opacity_logits, float thr, float min_opacity,
+                                   void* ws, int64_t* counts_out, hipStream_t st);
+hipError_t launch_densify_plan(int n, int64_t k, int64_t n_cand, const float* log_scales,
+                               float max_scale, void* ws, int64_t* n_new, hipStream_t st);
+hipError_t launch_densify_apply(int n, const float* const* p, const float* const* m,
+                                const float* const* v, const float* z, const void* ws,
+                                float* const* po, float* const* mo, float* const* vo,
+                                hipStream_t st);
+
 // resolution schedule (schedule.hip)
 constexpr int kDftMax = 4096;  // largest image side for the frequency map
 size_t frequency_map_ws_bytes(int H, int W);

@@ -86,6 +86,16 @@ def lib() -> ctypes.CDLL:
             "gs_schedule_resolution": (c_double, [c_double, i32, POINTER(c_double),
                                                   POINTER(c_double)]),
             "gs_downsample_aa": (i32, [i32, i32, i32, i32, i32, vp, vp, vp]),
+            "gs_primitive_target": (c_double, [c_double, c_double, c_double, c_double,
+                                               c_double]),
+            "gs_primitive_budget": (c_double, [c_double, c_double, c_double, c_double]),
+            "gs_densify_workspace_bytes": (sz, [i32]),
+            "gs_densify_stats": (i32, [i32, i32, vp, vp, vp, vp, vp]),
+            "gs_densify_classify": (i32, [i32, vp, vp, vp, c_float, c_float, vp, sz, vp, vp]),
+            "gs_densify_plan": (i32, [i32, i64, i64, vp, c_float, vp, sz, vp, vp]),
+            "gs_densify_apply": (i32, [i32, POINTER(c_void_p), POINTER(c_void_p),
+                                       POINTER(c_void_p), vp, vp, sz, POINTER(c_void_p),
+                                       POINTER(c_void_p), POINTER(c_void_p), vp]),
             "gs_l1_loss_grad": (i32, [i64, vp, vp, c_float, vp, vp, vp]),
             "gs_profile_enable": (None, [i32]),
             "gs_profile_collect": (i32, [POINTER(GsKernelTime), i32]),
@@ -286,6 +296,49 @@ def gs_schedule_resolution(k, r_knots, s_knots) -> float:
 def gs_downsample_aa(src, n_planes, H, W, h, w, dst, stream=None):
     _check("gs_downsample_aa", lib().gs_downsample_aa(
         int(n_planes), int(H), int(W), int(h), int(w), _ptr(src), _ptr(dst), _stream(stream)))
+
+
+def gs_primitive_target(i, S, r, p_init, p_fin) -> float:
+    return float(lib().gs_primitive_target(float(i), float(S), float(r), float(p_init),
+                                           float(p_fin)))
+
+
+def gs_primitive_budget(p_fin_prev, p_add, gamma=0.98, eta=1.0) -> float:
+    return float(lib().gs_primitive_budget(float(p_fin_prev), float(p_add), float(gamma),
+                                           float(eta)))
+
+
+def gs_densify_workspace_bytes(n: int) -> int:
+    return int(lib().gs_densify_workspace_bytes(int(n)))
+
+
+def gs_densify_stats(n_views, n, proj, d_mean2d_abs, accum, count, stream=None):
+    _check("gs_densify_stats", lib().gs_densify_stats(
+        int(n_views), int(n), _ptr(proj), _ptr(d_mean2d_abs), _ptr(accum), _ptr(count),
+        _stream(stream)))
+
+
+def gs_densify_classify(n, accum, count, opacity_logits, grad_thr, min_opacity, ws, counts_dev,
+                        stream=None):
+    _check("gs_densify_classify", lib().gs_densify_classify(
+        int(n), _ptr(accum), _ptr(count), _ptr(opacity_logits), float(grad_thr),
+        float(min_opacity), _ptr(ws), ws.numel() * ws.element_size(), _ptr(counts_dev),
+        _stream(stream)))
+
+
+def gs_densify_plan(n, k, n_candidates, log_scales, max_scale, ws, n_new_dev, stream=None):
+    _check("gs_densify_plan", lib().gs_densify_plan(
+        int(n), int(k), int(n_candidates), _ptr(log_scales), float(max_scale), _ptr(ws),
+        ws.numel() * ws.element_size(), _ptr(n_new_dev), _stream(stream)))
+
+
+def gs_densify_apply(n, params, m, v, z, ws, params_out, m_out, v_out, stream=None):
+    """params, m, v, params_out, m_out, v_out: five tensors each (means,
+    log_scales, quats, opacity_logits, sh)."""
+    arr = lambda ts: (c_void_p * 5)(*[_ptr(t) for t in ts])
+    _check("gs_densify_apply", lib().gs_densify_apply(
+        int(n), arr(params), arr(m), arr(v), _ptr(z), _ptr(ws), ws.numel() * ws.element_size(),
+        arr(params_out), arr(m_out), arr(v_out), _stream(stream)))
 
 
 def gs_l1_loss_grad(image, target, scale, dL_dimage, loss_sum=None, stream=None):
