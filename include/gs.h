@@ -273,7 +273,7 @@ gs_status gs_downsample_aa(int32_t n_planes, int32_t H, int32_t W, int32_t h, in
  *
  * A densification step is four calls; the caller reads two device counts in
  * between and allocates the outputs:
- *   gs_densify_stats (every iteration): accum[g] += d_mean2d_abs[g] and
+ *   gs_densify_stats (every iteration): accum[g] += scale * d_mean2d_abs[g] and
  *     count[g] += the number of views where g has a footprint (from proj),
  *     for Gaussians seen in at least one view.  accum, count: device [n].
  *   gs_densify_classify: score = accum / count (0 if count = 0, float32);
@@ -298,7 +298,8 @@ double gs_primitive_target(double i, double S, double r, double p_init, double p
 double gs_primitive_budget(double p_fin_prev, double p_add, double gamma, double eta);
 size_t gs_densify_workspace_bytes(int32_t n);
 gs_status gs_densify_stats(int32_t n_views, int32_t n, const void* proj,
-                           const float* d_mean2d_abs, float* accum, float* count, void* stream);
+                           const float* d_mean2d_abs, float scale, float* accum, float* count,
+                           void* stream);
 gs_status gs_densify_classify(int32_t n, const float* accum, const float* count,
                               const float* opacity_logits, float grad_thr, float min_opacity,
                               void* ws, size_t ws_bytes, int64_t* counts_dev, void* stream);

@@ -360,11 +360,12 @@ double gs_primitive_budget(double p_fin_prev, double p_add, double gamma, double
 size_t gs_densify_workspace_bytes(int32_t n) { return n < 0 ? 0 : densify_ws_bytes(n); }
 
 gs_status gs_densify_stats(int32_t n_views, int32_t n, const void* proj,
-                           const float* d_mean2d_abs, float* accum, float* count, void* stream) {
+                           const float* d_mean2d_abs, float scale, float* accum, float* count,
+                           void* stream) {
   if (!n_ok(n_views, n)) return GS_ERR_ARG;
   if (n > 0 && (!proj || !d_mean2d_abs || !accum || !count || !aligned16(proj))) return GS_ERR_ARG;
   return from_hip(launch_densify_stats(n_views, n, static_cast<const char*>(proj), d_mean2d_abs,
-                                       accum, count, as_stream(stream)));
+                                       scale, accum, count, as_stream(stream)));
 }
 
 gs_status gs_densify_classify(int32_t n, const float* accum, const float* count,

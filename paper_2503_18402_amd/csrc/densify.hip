@@ -26,7 +26,7 @@ constexpr uint32_t kPrune = 1u, kCand = 2u, kSel = 4u, kSplit = 8u;
 __global__ __launch_bounds__(256) void k_densify_stats(int n, int n_views, const char* __restrict__ proj,
                                                        size_t stride, size_t tt_off,
                                                        const float* __restrict__ mean2d_abs,
-                                                       float* __restrict__ accum,
+                                                       float scale, float* __restrict__ accum,
                                                        float* __restrict__ count) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
@@ -34,7 +34,7 @@ __global__ __launch_bounds__(256) void k_densify_stats(int n, int n_views, const
   for (int v = 0; v < n_views; ++v)
     seen += reinterpret_cast<const uint32_t*>(proj + size_t(v) * stride + tt_off)[g] > 0u ? 1 : 0;
   if (seen) {
-    accum[g] += mean2d_abs[g];
+    accum[g] += scale * mean2d_abs[g];
     count[g] += float(seen);
   }
 }
@@ -249,11 +249,11 @@ struct DWs {
 size_t densify_ws_bytes(int n) { return DWs(n).bytes; }
 
 hipError_t launch_densify_stats(int n_views, int n, const char* proj, const float* mean2d_abs,
-                                float* accum, float* count, hipStream_t st) {
+                                float scale, float* accum, float* count, hipStream_t st) {
   if (n == 0) return hipSuccess;
   const ProjLayout L(n);
   GS_LAUNCH("k_densify_stats", k_densify_stats, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st,
-            n, n_views, proj, L.stride, L.tt, mean2d_abs, accum, count);
+            n, n_views, proj, L.stride, L.tt, mean2d_abs, scale, accum, count);
   return hipGetLastError();
 }
 

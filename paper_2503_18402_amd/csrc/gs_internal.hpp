@@ -224,7 +224,7 @@ hipError_t launch_step_inc(int32_t* step_dev, hipStream_t st);
 // densification (densify.hip)
 size_t densify_ws_bytes(int n);
 hipError_t launch_densify_stats(int n_views, int n, const char* proj, const float* mean2d_abs,
-                                float* accum, float* count, hipStream_t st);
+                                float scale, float* accum, float* count, hipStream_t st);
 hipError_t launch_densify_classify(int n, const float* accum, const float* count,
                                    const float* opacity_logits, float thr, float min_opacity,
                                    void* ws, int64_t* counts_out, hipStream_t st);

@@ -90,7 +90,7 @@ def lib() -> ctypes.CDLL:
                                                c_double]),
             "gs_primitive_budget": (c_double, [c_double, c_double, c_double, c_double]),
             "gs_densify_workspace_bytes": (sz, [i32]),
-            "gs_densify_stats": (i32, [i32, i32, vp, vp, vp, vp, vp]),
+            "gs_densify_stats": (i32, [i32, i32, vp, vp, c_float, vp, vp, vp]),
             "gs_densify_classify": (i32, [i32, vp, vp, vp, c_float, c_float, vp, sz, vp, vp]),
             "gs_densify_plan": (i32, [i32, i64, i64, vp, c_float, vp, sz, vp, vp]),
             "gs_densify_apply": (i32, [i32, POINTER(c_void_p), POINTER(c_void_p),
@@ -312,10 +312,10 @@ def gs_densify_workspace_bytes(n: int) -> int:
     return int(lib().gs_densify_workspace_bytes(int(n)))
 
 
-def gs_densify_stats(n_views, n, proj, d_mean2d_abs, accum, count, stream=None):
+def gs_densify_stats(n_views, n, proj, d_mean2d_abs, accum, count, scale=1.0, stream=None):
     _check("gs_densify_stats", lib().gs_densify_stats(
-        int(n_views), int(n), _ptr(proj), _ptr(d_mean2d_abs), _ptr(accum), _ptr(count),
-        _stream(stream)))
+        int(n_views), int(n), _ptr(proj), _ptr(d_mean2d_abs), float(scale), _ptr(accum),
+        _ptr(count), _stream(stream)))
 
 
 def gs_densify_classify(n, accum, count, opacity_logits, grad_thr, min_opacity, ws, counts_dev,

@@ -185,7 +185,8 @@ class Pipeline:
                  lds_batch: int = 256, bg=(0.0, 0.0, 0.0), sh_degree: int = 3,
                  capacity: int | None = None, lrs: dict | None = None,
                  betas=(0.9, 0.999), eps: float = 1e-15, grads: dict | None = None,
-                 fused: bool = True, share: "Pipeline | None" = None):
+                 fused: bool = True, share: "Pipeline | None" = None,
+                 state: tuple | None = None, mean2d_abs: torch.Tensor | None = None):
         self.params = params
         self.cams = list(cams)
         dev = params["means"].device
@@ -219,6 +220,9 @@ class Pipeline:
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
         if share is not None:  # one optimiser state for several pipelines (e.g. per level)
             self.grads, self.m, self.v = share.grads, share.m, share.v
+        elif state is not None:  # (m, v, step_dev) carried over, e.g. across densification
+            self.grads = zero_grads(params) if grads is None else grads
+            self.m, self.v = state[0], state[1]
         else:
             self.grads = zero_grads(params) if grads is None else grads
             self.m = {k: torch.zeros_like(params[k]) for k in PARAM_NAMES}
@@ -228,8 +232,11 @@ class Pipeline:
         self.betas, self.eps = betas, eps
         self.step_no = 0
         # the step count lives on the device so a captured graph replays as new steps
-        self.step_dev = (share.step_dev if share is not None
-                         else torch.zeros(1, dtype=torch.int32, device=dev))
+        self.step_dev = (share.step_dev if share is not None else
+                         state[2] if state is not None else
+                         torch.zeros(1, dtype=torch.int32, device=dev))
+        # |d mean2D| per Gaussian from the fused backward (densification statistics)
+        self.mean2d_abs = mean2d_abs
         self.fused = fused
         self.graph = None
 
@@ -283,8 +290,8 @@ class Pipeline:
             self.final_T, self.last, self.dL, [self.m[k] for k in PARAM_NAMES],
             [self.v[k] for k in PARAM_NAMES],
             [self.lrs[k] for k in PARAM_NAMES] + [self.lrs.get("sh_rest", self.lrs["sh"])],
-            self.step_dev, self.betas[0], self.betas[1], self.eps, None, self.capacity,
-            self.bwd_ws, stream)
+            self.step_dev, self.betas[0], self.betas[1], self.eps, self.mean2d_abs,
+            self.capacity, self.bwd_ws, stream)
         self.step_no += 1
 
     def step(self, stream=None, adam_step: int | None = None):

@@ -96,42 +96,101 @@ DEFAULT_LRS = dict(means=1.6e-4, log_scales=5e-3, quats=1e-3, opacity_logits=5e-
                    sh_rest=2.5e-3 / 20.0)
 
 
+@dataclass
+class DensifyConfig:
+    """Densification every ``every`` iterations in [start, stop).  ``schedule``:
+    densify the top k = P_i - N' candidates with P_i from Eq. 4 (else every
+    candidate: the backbone); ``momentum``: grow the budget P_fin by Eq. 5
+    from ``p_fin`` (default 5 P_init), else keep ``p_fin`` fixed.  grad_thr
+    applies to the 2D-mean gradient in normalised device coordinates (the
+    pixel gradient times half the rendered width), so it does not depend on
+    the resolution; max_scale = percent_dense * scene extent."""
+    every: int = 100
+    start: int = 100
+    stop: int | None = None
+    grad_thr: float = 2e-4
+    min_opacity: float = 0.005
+    percent_dense: float = 0.01
+    extent: float = 1.0
+    schedule: bool = True
+    momentum: bool = True
+    p_fin: float | None = None
+    gamma: float = 0.98
+    eta: float = 1.0
+    seed: int = 0
+
+
 class Trainer:
-    """``iters`` optimisation steps of ``params`` (device tensors, updated in
-    place) against ground-truth views ``gt`` (device [N,3,H,W]) seen from
-    ``cams``.  ``means_lr`` = (initial, final) position learning rates."""
+    """``iters`` optimisation steps of ``params`` (device tensors, replaced in
+    the dict as densification grows them) against ground-truth views ``gt``
+    (device [N,3,H,W]) seen from ``cams``.  ``means_lr`` = (initial, final)
+    position learning rates."""
 
     def __init__(self, params: dict, cams, gt: torch.Tensor, iters: int, schedule: bool = True,
                  a: float = 4.0, m: int = 4, lrs: dict | None = None,
                  means_lr=(1.6e-4, 1.6e-6), sh_degree: int = 3, seed: int = 0,
-                 capacity_margin: float = 1.5, norm: str = "mean"):
+                 capacity_margin: float = 2.0, norm: str = "mean",
+                 densify: DensifyConfig | None = None):
         self.params, self.cams, self.gt, self.iters = params, list(cams), gt, iters
+        self.sh_degree = sh_degree
         self.lrs = dict(DEFAULT_LRS if lrs is None else lrs)
         self.means_lr = means_lr
+        self.capacity_margin = capacity_margin
         self.sched = ResolutionSchedule(gt, iters, a=a, m=m, norm=norm) if schedule else None
         self.factors = np.array([self.sched.factor(k) if schedule else 1 for k in range(iters)])
         # first iteration at full resolution: the position rate decays from there
         full = np.nonzero(self.factors == 1)[0]
         self.k_full = int(full[0]) if full.size else iters
         self.rng = np.random.default_rng(seed)
-        self.levels = {}
-        first = None
+        self.dcfg = densify
+        dev = params["means"].device
+        self.p_init = float(params["means"].shape[0])
+        if densify is not None:
+            self.p_fin = float(densify.p_fin) if densify.p_fin is not None else 5.0 * self.p_init
+            self.zgen = torch.Generator(device=dev).manual_seed(densify.seed)
+        self.log = []
+        self.step_dev = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.m = {k: torch.zeros_like(params[k]) for k in raster.PARAM_NAMES}
+        self.v = {k: torch.zeros_like(params[k]) for k in raster.PARAM_NAMES}
+        self.gt_levels = {}
         for f in sorted(set(self.factors.tolist()), reverse=True):
             views = [downscale_view(c, f) for c in self.cams]
             h, w = views[0].height, views[0].width
-            gt_f = gt if f == 1 else downsample(gt, h, w)
+            self.gt_levels[f] = (views, gt if f == 1 else downsample(gt, h, w))
+        self._build_levels(0)
+
+    def _build_levels(self, k0: int):
+        """Pipelines for the levels still ahead of iteration k0, sized for the
+        current Gaussians, sharing the optimiser state."""
+        n = self.params["means"].shape[0]
+        dev = self.params["means"].device
+        self.mean2d = torch.zeros(n, device=dev)
+        self.accum = torch.zeros(n, device=dev)
+        self.count = torch.zeros(n, device=dev)
+        self.levels = {}
+        first = None
+        probe_views = np.linspace(0, len(self.cams) - 1, min(4, len(self.cams))).astype(int)
+        for f in sorted(set(self.factors[k0:].tolist()), reverse=True):
+            views, gt_f = self.gt_levels[f]
             tile = 8 if f >= 2 else 16  # few tiles at low resolution: split them finer
             cap = 0
-            for v in views:
-                probe = raster.render(params, [v], tile=tile, sh_degree=sh_degree)
+            for vi in probe_views:
+                probe = raster.render(self.params, [views[vi]], tile=tile, sh_degree=self.sh_degree)
                 cap = max(cap, int(probe.n_pairs_dev.item()))
                 del probe
-            pipe = raster.Pipeline(params, [views[0]], gt_f[0].reshape(-1), tile=tile,
-                                   lds_batch=128, sh_degree=sh_degree,
-                                   capacity=int(cap * capacity_margin) + 4096, lrs=self.lrs,
-                                   share=first)
+            pipe = raster.Pipeline(self.params, [views[0]], gt_f[0].reshape(-1), tile=tile,
+                                   lds_batch=128, sh_degree=self.sh_degree,
+                                   capacity=int(cap * self.capacity_margin) + 4096, lrs=self.lrs,
+                                   share=first, state=(self.m, self.v, self.step_dev),
+                                   mean2d_abs=self.mean2d)
+            pipe.pairs_max = torch.zeros(1, dtype=torch.int64, device=dev)
             first = first or pipe
             self.levels[f] = (views, gt_f, pipe)
+
+    def _check_capacity(self):
+        for _, _, pipe in self.levels.values():
+            if int(pipe.pairs_max.item()) > pipe.capacity:
+                raise RuntimeError("pair capacity overflowed during training")
 
     def means_lr_at(self, k: int) -> float:
         lo, hi = self.means_lr
@@ -140,26 +199,62 @@ class Trainer:
         t = (k - self.k_full) / max(1, self.iters - self.k_full)
         return math.exp((1.0 - t) * math.log(lo) + t * math.log(hi))
 
+    def _densify(self, k: int):
+        from .densify import densify_step
+        c = self.dcfg
+        r = self.sched.r(k) if self.sched is not None else 1.0
+
+        def k_of(kept, cand):
+            if not c.schedule:
+                return cand
+            if c.momentum:
+                self.p_fin = gsmi.gs_primitive_budget(self.p_fin, cand, c.gamma, c.eta)
+            target = gsmi.gs_primitive_target(k, self.iters, r, self.p_init, self.p_fin)
+            return int(round(target)) - kept
+
+        self._check_capacity()
+        n = self.params["means"].shape[0]
+        z = torch.randn(n, 2, 3, generator=self.zgen, device=self.accum.device)
+        newp, newm, newv, info = densify_step(self.params, self.m, self.v, self.accum, self.count,
+                                              z, c.grad_thr, c.min_opacity,
+                                              c.percent_dense * c.extent, k_of)
+        for name in raster.PARAM_NAMES:
+            self.params[name] = newp[name]
+            self.m[name] = newm[name]
+            self.v[name] = newv[name]
+        info.update(iteration=k, r=r, p_fin=getattr(self, "p_fin", None))
+        self.log.append(info)
+        self._build_levels(k)
+
     def run(self) -> dict:
-        """Run all iterations; returns the wall time and the iterations per factor."""
+        """Run all iterations; returns the wall time, the iterations per factor
+        and the primitive count."""
         order = []
-        n = len(self.cams)
+        n_views = len(self.cams)
+        c = self.dcfg
+        stop = (c.stop if c.stop is not None else self.iters // 2) if c else 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(self.iters):
+            if c is not None and c.start <= k < stop and k > 0 and (k - c.start) % c.every == 0:
+                self._densify(k)
             if not order:
-                order = list(self.rng.permutation(n))
+                order = list(self.rng.permutation(n_views))
             v = order.pop()
-            views, gt_f, pipe = self.levels[int(self.factors[k])]
+            f = int(self.factors[k])
+            views, gt_f, pipe = self.levels[f]
             pipe.set_view(views[v], gt_f[v])
             pipe.lrs["means"] = self.means_lr_at(k)
             pipe.step()
+            torch.maximum(pipe.pairs_max, pipe.n_pairs, out=pipe.pairs_max)
+            if c is not None and k < stop:
+                gsmi.gs_densify_stats(1, pipe.n, pipe.proj, self.mean2d, self.accum, self.count,
+                                      scale=0.5 * views[v].width)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        for _, _, pipe in self.levels.values():
-            if pipe.overflowed():
-                raise RuntimeError("pair capacity overflowed during training")
+        self._check_capacity()
         return dict(seconds=wall, s_per_iter=wall / max(1, self.iters),
                     iters_per_factor={int(f): int((self.factors == f).sum())
                                       for f in sorted(set(self.factors.tolist()))},
-                    k_full=self.k_full)
+                    k_full=self.k_full, n_gaussians=int(self.params["means"].shape[0]),
+                    densify_steps=len(self.log))

@@ -60,3 +60,36 @@ def test_unscheduled_loop_renders_full_resolution():
     tr = train.Trainer(params, cams, gt, 30, schedule=False)
     assert set(tr.factors.tolist()) == {1} and tr.k_full == 0
     tr.run()
+
+
+@pytest.mark.parametrize("scheduled", [True, False])
+def test_densifying_loop_follows_eq4_eq5(scheduled):
+    """DashGaussian mode: every densification step takes
+    k = clamp(round(P_i) - N', 0, candidates) with P_fin from Eq. 5 (momentum,
+    starting at 5 P_init) and P_i from Eq. 4 at the step's r; the backbone mode
+    (full resolution, no schedule) densifies every candidate."""
+    from oracle import densify as OD
+    cams = scenes.fibonacci_cameras(8, 3.0, 160, 120, 150.0)
+    gt = torch.from_numpy(_gt(cams, seed=75)).cuda()
+    params = raster.to_device(scenes.make_scene(3000, seed=76, mean_range=1.0, ls_mu=-3.0,
+                                                ls_sigma=0.4), "cuda")
+    dcfg = train.DensifyConfig(every=40, start=40, stop=200, grad_thr=2e-4, min_opacity=0.005,
+                               percent_dense=0.01, extent=3.3, schedule=scheduled)
+    tr = train.Trainer(params, cams, gt, 300, schedule=scheduled, densify=dcfg)
+    out = tr.run()
+    assert len(tr.log) == 4 and out["n_gaussians"] == tr.log[-1]["n_new"]
+    p_fin = 5.0 * 3000
+    n_prev = 3000
+    for e in tr.log:
+        assert e["n"] == n_prev
+        kept = e["n"] - e["n_pruned"]
+        if scheduled:
+            p_fin = OD.budget_update(p_fin, e["n_candidates"])
+            target = OD.primitive_target(e["iteration"], 300, e["r"], 3000.0, p_fin)
+            want = int(max(0, min(int(round(target)) - kept, e["n_candidates"])))
+            assert e["p_fin"] == pytest.approx(p_fin)
+        else:
+            want = e["n_candidates"]
+        assert e["k"] == want and e["n_new"] == kept + want
+        n_prev = e["n_new"]
+    assert out["n_gaussians"] > 3000
