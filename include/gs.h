@@ -219,6 +219,29 @@ gs_status gs_render_bwd_adam(int32_t n_views, const gs_camera* cams, const gs_ra
                              size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * gs_render_bwd_sparse_adam: gs_render_bwd_adam with the sparse (lazy) Adam of
+ * the Taming backbone the paper equips (its headline configuration; the
+ * per-iteration primitive update, Sec. 1): a Gaussian that has no pair in any
+ * of the n_views views -- culled, behind the camera or off every image --
+ * keeps its parameters and both moments unchanged; every other Gaussian takes
+ * exactly the update of gs_render_bwd_adam, bias-corrected with the global
+ * step t = *step_dev + 1, even where its gradient is zero.  The counter
+ * advances once per call.  d_mean2d_abs, when given, is written for every
+ * Gaussian (0 for the untouched ones).  Arguments, layouts, alignment and
+ * errors are those of gs_render_bwd_adam.
+ * ------------------------------------------------------------------------- */
+gs_status gs_render_bwd_sparse_adam(int32_t n_views, const gs_camera* cams,
+                                    const gs_raster_cfg* cfg, int32_t n, float* means,
+                                    float* log_scales, float* quats, float* opacity_logits,
+                                    float* sh, int32_t sh_degree, const void* proj,
+                                    const uint32_t* ranges, const uint32_t* vals,
+                                    const float* final_T, const uint32_t* last_contrib,
+                                    const float* dL_dimage, float* const* m, float* const* v,
+                                    const float* lr, int32_t* step_dev, float beta1, float beta2,
+                                    float eps, float* d_mean2d_abs, int64_t capacity_pairs,
+                                    void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * The frequency-guided resolution schedule (Sec. 4.2, Eq. 2; supplementary
  * Eq. 6-7) and the anti-aliased ground-truth downsampling (supplementary,
  * "Ground Truth Downsampling").

@@ -22,3 +22,17 @@ def adam_step(p, g, m, v, step: int, lr: float, beta1: float = 0.9, beta2: float
     vhat = v / (1.0 - beta2 ** step)
     p -= lr * mhat / (np.sqrt(vhat) + eps)
     return p, m, v
+
+
+def sparse_adam_step(p, g, m, v, rows, step: int, lr: float, beta1: float = 0.9,
+                     beta2: float = 0.999, eps: float = 1e-15):
+    """Sparse (lazy) Adam, the optimiser of the Taming backbone: the rows
+    (first axis) where ``rows`` is true take the Adam update above with the
+    global step t; the other rows keep p, m and v unchanged."""
+    rows = np.asarray(rows, bool)
+    p1, m1, v1 = adam_step(p, g, m, v, step, lr, beta1, beta2, eps)
+    keep = ~rows
+    p1[keep] = np.asarray(p, np.float64)[keep]
+    m1[keep] = np.asarray(m, np.float64)[keep]
+    v1[keep] = np.asarray(v, np.float64)[keep]
+    return p1, m1, v1

@@ -261,15 +261,15 @@ gs_status gs_adam_step_device(const gs_adam_group* groups, int32_t n_groups, int
       launch_adam(groups, n_groups, 1, beta1, beta2, eps, step_dev, as_stream(stream)));
 }
 
-gs_status gs_render_bwd_adam(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
-                             int32_t n, float* means, float* log_scales, float* quats,
-                             float* opacity_logits, float* sh, int32_t sh_degree,
-                             const void* proj, const uint32_t* ranges, const uint32_t* vals,
-                             const float* final_T, const uint32_t* last_contrib,
-                             const float* dL_dimage, float* const* m, float* const* v,
-                             const float* lr, int32_t* step_dev, float beta1, float beta2,
-                             float eps, float* d_mean2d_abs, int64_t capacity_pairs, void* ws,
-                             size_t ws_bytes, void* stream) {
+namespace {
+gs_status render_bwd_adam(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
+                          int32_t n, float* means, float* log_scales, float* quats,
+                          float* opacity_logits, float* sh, int32_t sh_degree, const void* proj,
+                          const uint32_t* ranges, const uint32_t* vals, const float* final_T,
+                          const uint32_t* last_contrib, const float* dL_dimage, float* const* m,
+                          float* const* v, const float* lr, int32_t* step_dev, float beta1,
+                          float beta2, float eps, float* d_mean2d_abs, int64_t capacity_pairs,
+                          void* ws, size_t ws_bytes, void* stream, int sparse) {
   Views V;
   if (!n_ok(n_views, n) || !build_views(n_views, cams, cfg, &V)) return GS_ERR_ARG;
   if (sh_degree < 0 || sh_degree > 3) return GS_ERR_ARG;
@@ -295,10 +295,43 @@ gs_status gs_render_bwd_adam(int32_t n_views, const gs_camera* cams, const gs_ra
   A.b2 = beta2;
   A.eps = eps;
   A.step_dev = step_dev;
+  A.sparse = sparse;
   return from_hip(launch_render_bwd_adam(V, n, *cfg, means, log_scales, quats, opacity_logits, sh,
                                          sh_degree, static_cast<const char*>(proj), ranges, vals,
                                          final_T, last_contrib, dL_dimage, A, d_mean2d_abs,
                                          capacity_pairs, ws, as_stream(stream)));
+}
+}  // namespace
+
+gs_status gs_render_bwd_adam(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
+                             int32_t n, float* means, float* log_scales, float* quats,
+                             float* opacity_logits, float* sh, int32_t sh_degree,
+                             const void* proj, const uint32_t* ranges, const uint32_t* vals,
+                             const float* final_T, const uint32_t* last_contrib,
+                             const float* dL_dimage, float* const* m, float* const* v,
+                             const float* lr, int32_t* step_dev, float beta1, float beta2,
+                             float eps, float* d_mean2d_abs, int64_t capacity_pairs, void* ws,
+                             size_t ws_bytes, void* stream) {
+  return render_bwd_adam(n_views, cams, cfg, n, means, log_scales, quats, opacity_logits, sh,
+                         sh_degree, proj, ranges, vals, final_T, last_contrib, dL_dimage, m, v, lr,
+                         step_dev, beta1, beta2, eps, d_mean2d_abs, capacity_pairs, ws, ws_bytes,
+                         stream, 0);
+}
+
+gs_status gs_render_bwd_sparse_adam(int32_t n_views, const gs_camera* cams,
+                                    const gs_raster_cfg* cfg, int32_t n, float* means,
+                                    float* log_scales, float* quats, float* opacity_logits,
+                                    float* sh, int32_t sh_degree, const void* proj,
+                                    const uint32_t* ranges, const uint32_t* vals,
+                                    const float* final_T, const uint32_t* last_contrib,
+                                    const float* dL_dimage, float* const* m, float* const* v,
+                                    const float* lr, int32_t* step_dev, float beta1, float beta2,
+                                    float eps, float* d_mean2d_abs, int64_t capacity_pairs,
+                                    void* ws, size_t ws_bytes, void* stream) {
+  return render_bwd_adam(n_views, cams, cfg, n, means, log_scales, quats, opacity_logits, sh,
+                         sh_degree, proj, ranges, vals, final_T, last_contrib, dL_dimage, m, v, lr,
+                         step_dev, beta1, beta2, eps, d_mean2d_abs, capacity_pairs, ws, ws_bytes,
+                         stream, 1);
 }
 
 size_t gs_frequency_map_workspace_bytes(int32_t H, int32_t W) {

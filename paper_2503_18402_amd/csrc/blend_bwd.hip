@@ -823,17 +823,21 @@ struct AdamGroups {
   float lr[6];  // the five groups; lr[4] for the SH degree-0 terms, lr[5] for the rest
   float b1, b2, eps;
   const int32_t* step_dev;
+  int sparse;  // 1: Gaussians with no pair in any view keep p, m and v unchanged
 };
 
 __global__ __launch_bounds__(kCA) void k_chain_adam(Views V, ChainIn I, AdamGroups A,
                                                     float* __restrict__ d_mean2d_abs) {
   __shared__ float4 s_g[kCA * GS_SH_COEFFS * 3 / 4];
   __shared__ float s_c[2];
+  __shared__ int s_upd[kCA];
   if (threadIdx.x == 0) adam_bias(A.step_dev, A.b1, A.b2, s_c[0], s_c[1]);
   const int g = blockIdx.x * kCA + threadIdx.x;
   ChainOut O;
   bool have = false;
   if (g < I.n) have = chain_grad(V, I, g, O);
+  const bool upd = have || !A.sparse;
+  s_upd[threadIdx.x] = upd ? 1 : 0;
   if (!have) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) O.dm[k] = O.dls[k] = 0.0f;
@@ -848,8 +852,8 @@ __global__ __launch_bounds__(kCA) void k_chain_adam(Views V, ChainIn I, AdamGrou
         make_float4(O.dsh[4 * q], O.dsh[4 * q + 1], O.dsh[4 * q + 2], O.dsh[4 * q + 3]);
   __syncthreads();
   const AdamCoef C{A.b1, A.b2, A.eps, s_c[0], s_c[1]};
-  if (g < I.n) {
-    if (d_mean2d_abs) d_mean2d_abs[g] = O.m2abs;
+  if (g < I.n && d_mean2d_abs) d_mean2d_abs[g] = O.m2abs;
+  if (g < I.n && upd) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const int j = 3 * g + k;
@@ -876,6 +880,7 @@ __global__ __launch_bounds__(kCA) void k_chain_adam(Views V, ChainIn I, AdamGrou
   float4* __restrict__ Vv = reinterpret_cast<float4*>(A.v[4] + size_t(g0) * GS_SH_COEFFS * 3);
 #pragma unroll 4
   for (int j = threadIdx.x; j < n4; j += kCA) {
+    if (!s_upd[j / (GS_SH_COEFFS * 3 / 4)]) continue;
     float4 p = P[j], m = Mm[j], v = Vv[j];
     const float4 gg = s_g[j];
     // values 0..2 of a Gaussian's 48 are its degree-0 coefficients
@@ -1051,6 +1056,7 @@ hipError_t launch_render_bwd_adam(const Views& V, int n, const gs_raster_cfg& cf
     G.b2 = A.b2;
     G.eps = A.eps;
     G.step_dev = A.step_dev;
+    G.sparse = A.sparse;
     GS_LAUNCH("k_chain_adam", k_chain_adam, dim3(unsigned((n + kCA - 1) / kCA)), dim3(kCA), 0,
               st, V, I, G, d_mean2d_abs);
   }

@@ -210,6 +210,7 @@ struct FusedAdam {  // the five parameter groups' moments and learning rates
   float lr[6];  // lr[4]: SH degree-0 coefficients, lr[5]: the higher degrees
   float b1, b2, eps;
   int32_t* step_dev;
+  int sparse;  // 1: leave Gaussians with no pair in any view untouched (sparse Adam)
 };
 hipError_t launch_render_bwd_adam(const Views& V, int n, const gs_raster_cfg& cfg, float* means,
                                   float* log_scales, float* quats, float* opacity_logits,

@@ -79,6 +79,10 @@ def lib() -> ctypes.CDLL:
                                          vp, vp, vp, vp, vp, POINTER(c_void_p),
                                          POINTER(c_void_p), POINTER(c_float), vp, c_float,
                                          c_float, c_float, vp, i64, vp, sz, vp]),
+            "gs_render_bwd_sparse_adam": (i32, [i32, cam_p, cfg_p, i32, vp, vp, vp, vp, vp, i32,
+                                                vp, vp, vp, vp, vp, vp, POINTER(c_void_p),
+                                                POINTER(c_void_p), POINTER(c_float), vp, c_float,
+                                                c_float, c_float, vp, i64, vp, sz, vp]),
             "gs_frequency_map_workspace_bytes": (sz, [i32, i32]),
             "gs_frequency_map": (i32, [i32, i32, i32, vp, vp, vp, sz, vp]),
             "gs_resolution_schedule": (i32, [POINTER(c_double), i32, i32, c_double, c_double, i32,
@@ -240,22 +244,32 @@ def gs_adam_step_device(groups, step_dev, beta1=0.9, beta2=0.999, eps=1e-15, str
 
 def gs_render_bwd_adam(cams_c, cfg, n, means, log_scales, quats, opacity_logits, sh, sh_degree,
                        proj, ranges, vals, final_T, last_contrib, dL_dimage, m, v, lr, step_dev,
-                       beta1, beta2, eps, d_mean2d_abs, capacity, ws, stream=None):
+                       beta1, beta2, eps, d_mean2d_abs, capacity, ws, stream=None, sparse=False):
     """m, v: five entries each, in the order means, log_scales, quats,
     opacity_logits, sh; lr: those five learning rates (the SH one for every
-    coefficient) or six (the last for the SH coefficients above degree 0)."""
+    coefficient) or six (the last for the SH coefficients above degree 0).
+    sparse: call gs_render_bwd_sparse_adam instead (Gaussians with no pair in
+    any view left untouched)."""
+    name = "gs_render_bwd_sparse_adam" if sparse else "gs_render_bwd_adam"
     lr = list(lr)
     if len(lr) == 5:
         lr.append(lr[4])
     mp = (c_void_p * 5)(*[_ptr(t) for t in m])
     vp_ = (c_void_p * 5)(*[_ptr(t) for t in v])
     lr_ = (c_float * 6)(*[float(x) for x in lr])
-    _check("gs_render_bwd_adam", lib().gs_render_bwd_adam(
+    _check(name, getattr(lib(), name)(
         len(cams_c), cams_c, ctypes.byref(cfg), int(n), _ptr(means), _ptr(log_scales),
         _ptr(quats), _ptr(opacity_logits), _ptr(sh), int(sh_degree), _ptr(proj), _ptr(ranges),
         _ptr(vals), _ptr(final_T), _ptr(last_contrib), _ptr(dL_dimage), mp, vp_, lr_,
         _ptr(step_dev), float(beta1), float(beta2), float(eps), _ptr(d_mean2d_abs),
         int(capacity), _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def gs_render_bwd_sparse_adam(*args, **kw):
+    """gs_render_bwd_adam's arguments; Gaussians with no pair in any view keep
+    their parameters and moments."""
+    kw["sparse"] = True
+    gs_render_bwd_adam(*args, **kw)
 
 
 def gs_frequency_map_workspace_bytes(H: int, W: int) -> int:

@@ -178,7 +178,9 @@ class Pipeline:
 
     With ``fused`` (the default) the backward and the Adam step run as one
     ``gs_render_bwd_adam`` call: the same update bit for bit, without writing
-    the gradients (``grads`` is then left untouched by ``step()``).
+    the gradients (``grads`` is then left untouched by ``step()``).  With
+    ``sparse_adam`` the fused call is ``gs_render_bwd_sparse_adam``: Gaussians
+    no view of the set touches keep their parameters and moments.
     """
 
     def __init__(self, params: dict, cams, targets: torch.Tensor, tile: int = 16,
@@ -186,7 +188,10 @@ class Pipeline:
                  capacity: int | None = None, lrs: dict | None = None,
                  betas=(0.9, 0.999), eps: float = 1e-15, grads: dict | None = None,
                  fused: bool = True, share: "Pipeline | None" = None,
-                 state: tuple | None = None, mean2d_abs: torch.Tensor | None = None):
+                 state: tuple | None = None, mean2d_abs: torch.Tensor | None = None,
+                 sparse_adam: bool = False):
+        if sparse_adam and not fused:
+            raise ValueError("sparse Adam runs fused with the backward pass")
         self.params = params
         self.cams = list(cams)
         dev = params["means"].device
@@ -238,6 +243,7 @@ class Pipeline:
         # |d mean2D| per Gaussian from the fused backward (densification statistics)
         self.mean2d_abs = mean2d_abs
         self.fused = fused
+        self.sparse_adam = sparse_adam
         self.graph = None
 
     def forward(self, stream=None):
@@ -291,7 +297,7 @@ class Pipeline:
             [self.v[k] for k in PARAM_NAMES],
             [self.lrs[k] for k in PARAM_NAMES] + [self.lrs.get("sh_rest", self.lrs["sh"])],
             self.step_dev, self.betas[0], self.betas[1], self.eps, self.mean2d_abs,
-            self.capacity, self.bwd_ws, stream)
+            self.capacity, self.bwd_ws, stream, sparse=self.sparse_adam)
         self.step_no += 1
 
     def step(self, stream=None, adam_step: int | None = None):
@@ -302,6 +308,8 @@ class Pipeline:
         self.forward(stream)
         if self.fused and adam_step is None:
             self.backward_adam(stream)
+        elif self.sparse_adam:
+            raise ValueError("sparse Adam takes its step count from the device counter")
         else:
             self.backward(stream)
             self.adam(stream, adam_step)

@@ -124,19 +124,24 @@ class Trainer:
     """``iters`` optimisation steps of ``params`` (device tensors, replaced in
     the dict as densification grows them) against ground-truth views ``gt``
     (device [N,3,H,W]) seen from ``cams``.  ``means_lr`` = (initial, final)
-    position learning rates."""
+    position learning rates; ``r_max`` caps the schedule's downsampling factor
+    (0: the smaller image side); ``sparse_adam``: Gaussians the iteration's
+    view does not touch keep their parameters and moments."""
 
     def __init__(self, params: dict, cams, gt: torch.Tensor, iters: int, schedule: bool = True,
                  a: float = 4.0, m: int = 4, lrs: dict | None = None,
                  means_lr=(1.6e-4, 1.6e-6), sh_degree: int = 3, seed: int = 0,
                  capacity_margin: float = 2.0, norm: str = "mean",
-                 densify: DensifyConfig | None = None):
+                 densify: DensifyConfig | None = None, r_max: float = 0.0,
+                 sparse_adam: bool = False):
         self.params, self.cams, self.gt, self.iters = params, list(cams), gt, iters
         self.sh_degree = sh_degree
         self.lrs = dict(DEFAULT_LRS if lrs is None else lrs)
         self.means_lr = means_lr
         self.capacity_margin = capacity_margin
-        self.sched = ResolutionSchedule(gt, iters, a=a, m=m, norm=norm) if schedule else None
+        self.sparse_adam = sparse_adam
+        self.sched = (ResolutionSchedule(gt, iters, a=a, m=m, r_max=r_max, norm=norm)
+                      if schedule else None)
         self.factors = np.array([self.sched.factor(k) if schedule else 1 for k in range(iters)])
         # first iteration at full resolution: the position rate decays from there
         full = np.nonzero(self.factors == 1)[0]
@@ -182,7 +187,7 @@ class Trainer:
                                    lds_batch=128, sh_degree=self.sh_degree,
                                    capacity=int(cap * self.capacity_margin) + 4096, lrs=self.lrs,
                                    share=first, state=(self.m, self.v, self.step_dev),
-                                   mean2d_abs=self.mean2d)
+                                   mean2d_abs=self.mean2d, sparse_adam=self.sparse_adam)
             pipe.pairs_max = torch.zeros(1, dtype=torch.int64, device=dev)
             first = first or pipe
             self.levels[f] = (views, gt_f, pipe)
@@ -227,17 +232,23 @@ class Trainer:
         self._build_levels(k)
 
     def run(self) -> dict:
-        """Run all iterations; returns the wall time, the iterations per factor
-        and the primitive count."""
+        """Run all iterations; returns the wall time (and the part of it spent
+        in densification steps, pipeline rebuilds included), the iterations
+        per factor and the primitive count."""
         order = []
         n_views = len(self.cams)
         c = self.dcfg
         stop = (c.stop if c.stop is not None else self.iters // 2) if c else 0
+        t_densify = 0.0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(self.iters):
             if c is not None and c.start <= k < stop and k > 0 and (k - c.start) % c.every == 0:
+                torch.cuda.synchronize()
+                td = time.perf_counter()
                 self._densify(k)
+                torch.cuda.synchronize()
+                t_densify += time.perf_counter() - td
             if not order:
                 order = list(self.rng.permutation(n_views))
             v = order.pop()
@@ -257,4 +268,4 @@ class Trainer:
                     iters_per_factor={int(f): int((self.factors == f).sum())
                                       for f in sorted(set(self.factors.tolist()))},
                     k_full=self.k_full, n_gaussians=int(self.params["means"].shape[0]),
-                    densify_steps=len(self.log))
+                    densify_steps=len(self.log), densify_seconds=t_densify)

@@ -96,20 +96,20 @@ def test_argument_errors(L):
     assert L.gs_l1_loss_grad(-1, 16, 16, 1.0, 16, None, None) == 1
     # fused backward + Adam: null moment table, a null moment, bad beta, misaligned SH moments
     ptrs = (ctypes.c_void_p * 5)(*([256] * 5))
-    lrs = (ctypes.c_float * 5)(*([1e-3] * 5))
+    lrs = (ctypes.c_float * 6)(*([1e-3] * 6))
     ws_need = gsmi.gs_render_bwd_workspace_bytes(1, 10, 100)
-
-    def fused(m, v, b1=0.9, ws_bytes=ws_need):
-        return L.gs_render_bwd_adam(1, cams, ctypes.byref(good), 10, 256, 256, 256, 256, 256, 3,
-                                    256, 256, 256, 256, 256, 256, m, v, lrs, 256, b1, 0.999,
-                                    1e-15, None, 100, 256, ws_bytes, None)
-    assert fused(None, ptrs) == 1
-    nul = (ctypes.c_void_p * 5)(256, 256, 256, None, 256)
-    assert fused(nul, ptrs) == 1
-    assert fused(ptrs, ptrs, b1=1.0) == 1
-    mis = (ctypes.c_void_p * 5)(256, 256, 256, 256, 260)
-    assert fused(ptrs, mis) == 1
-    assert fused(ptrs, ptrs, ws_bytes=ws_need - 1) == 2
+    for entry in (L.gs_render_bwd_adam, L.gs_render_bwd_sparse_adam):
+        def fused(m, v, b1=0.9, ws_bytes=ws_need):
+            return entry(1, cams, ctypes.byref(good), 10, 256, 256, 256, 256, 256, 3,
+                         256, 256, 256, 256, 256, 256, m, v, lrs, 256, b1, 0.999,
+                         1e-15, None, 100, 256, ws_bytes, None)
+        assert fused(None, ptrs) == 1
+        nul = (ctypes.c_void_p * 5)(256, 256, 256, None, 256)
+        assert fused(nul, ptrs) == 1
+        assert fused(ptrs, ptrs, b1=1.0) == 1
+        mis = (ctypes.c_void_p * 5)(256, 256, 256, 256, 260)
+        assert fused(ptrs, mis) == 1
+        assert fused(ptrs, ptrs, ws_bytes=ws_need - 1) == 2
 
 
 def test_header_mentions_every_entry_point_in_binding():

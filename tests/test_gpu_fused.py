@@ -104,3 +104,61 @@ def test_separate_sh_rest_rate():
         runs[name] = p.params["sh"].clone()
     assert torch.equal(runs["both"][:, 0], runs["dc"][:, 0])
     assert torch.equal(runs["both"][:, 1:], runs["rest"][:, 1:])
+
+
+@pytest.mark.parametrize("multi", [False, True])
+def test_sparse_step_updates_exactly_the_touched_gaussians(multi):
+    """gs_render_bwd_sparse_adam over two steps with different view sets (the
+    step counter shared): the Gaussians it updates are those the FP64 oracle
+    projects onto at least one tile of the step's views (rows within a float32
+    guard band of that decision aside); they equal the dense fused step taken
+    from the same state bit for bit, and every other row keeps p, m and v.
+    Geometry and opacity rates are zero so the footprints, hence the oracle's
+    sets, stay those of the initial scene; the moments start nonzero so a
+    dense step would change every row."""
+    import numpy as np
+    from oracle import project
+
+    sc, cams, tgt = _setup(6001, multi)
+    sc["means"][:64] = (0.0, 50.0, 0.0)      # above every view
+    if multi:
+        sets = [cams[:2], cams[2:]]
+    else:
+        sets = [cams, [scenes.look_at((0, 0, 3), (0, 0, 0), 128, 96, 120.0)]]
+    rng = np.random.default_rng(54)
+    params = raster.to_device(sc)
+    m = {k: torch.from_numpy(rng.normal(0, 1e-3, size=params[k].shape).astype(np.float32)).cuda()
+         for k in raster.PARAM_NAMES}
+    v = {k: torch.from_numpy(rng.uniform(1e-7, 1e-6, size=params[k].shape).astype(np.float32))
+         .cuda() for k in raster.PARAM_NAMES}
+    step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    lrs = dict(means=0.0, log_scales=0.0, quats=0.0, opacity_logits=0.0, sh=2e-3, sh_rest=1e-4)
+    for k, views in enumerate(sets):
+        tv = torch.cat([torch.from_numpy(scenes.uniform_target(c, seed=60 + k + j)).reshape(-1)
+                        for j, c in enumerate(views)]).cuda()
+        Ps = [project.project(sc, c, tile=16) for c in views]
+        touched = np.any([P["tiles_touched"] > 0 for P in Ps], axis=0)
+        ambiguous = np.any([P["flag_rect"] for P in Ps], axis=0)
+        before = ({n: t.clone() for n, t in params.items()}, {n: t.clone() for n, t in m.items()},
+                  {n: t.clone() for n, t in v.items()}, step.clone())
+        dp, dm, dv, ds = ({n: t.clone() for n, t in x.items()} if isinstance(x, dict) else
+                          x.clone() for x in before)
+        sp = raster.Pipeline(params, views, tv, lrs=lrs, state=(m, v, step), sparse_adam=True)
+        dn = raster.Pipeline(dp, views, tv, lrs=lrs, state=(dm, dv, ds), capacity=sp.capacity)
+        sp.step()
+        dn.step()
+        torch.cuda.synchronize()
+        assert not sp.overflowed()
+        upd = torch.zeros(params["means"].shape[0], dtype=torch.bool, device="cuda")
+        for name in raster.PARAM_NAMES:
+            upd |= (m[name] != before[1][name]).reshape(upd.shape[0], -1).any(1)
+        upd_h = upd.cpu().numpy()
+        assert np.array_equal(upd_h[~ambiguous], touched[~ambiguous])
+        assert (~upd_h).sum() >= 64
+        for name in raster.PARAM_NAMES:
+            sel = upd.view(-1, *([1] * (params[name].dim() - 1)))
+            for got, dense, old in ((params[name], dp[name], before[0][name]),
+                                    (m[name], dm[name], before[1][name]),
+                                    (v[name], dv[name], before[2][name])):
+                assert torch.equal(got, torch.where(sel, dense, old)), (k, name)
+        assert int(step.item()) == int(ds.item()) == k + 1
