@@ -60,6 +60,8 @@ def parse():
                     help="only run warmup + this many steps (for rocprofv3), no extras")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--training-only", action="store_true",
+                    help="run only the training comparison (for rocprofv3) and print its JSON")
     return ap.parse_args()
 
 
@@ -90,6 +92,9 @@ def main():
     gsmi.lib()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.training_only:
+        print(json.dumps(scheduled_training(torch, raster, scenes, dev, args.train_iters)))
+        return
 
     # ---------------------------------------------------------------- inputs
     log("generating the 1M-Gaussian scene and target")
@@ -281,7 +286,7 @@ def time_pipe(torch, pipe, steps):
 def level_sweep(torch, raster, scenes, params, tparams_scene, tile, lds):
     """The plain single-view step at each downscale level of the schedule (8/4/2/1),
     autotuned per level and replayed from a HIP graph."""
-    from paper_2503_18402_amd import autotune
+    from paper_2503_18402_amd import autotune, gsmi
 
     out = {}
     tparams = raster.to_device(tparams_scene, params["means"].device)
@@ -293,9 +298,20 @@ def level_sweep(torch, raster, scenes, params, tparams_scene, tile, lds):
         pipe = raster.Pipeline(p, [cam], tgt, tile=pick["tile"], lds_batch=pick["lds_batch"])
         pipe.capture()
         ms = time_pipe(torch, pipe, 10)
+        # per-kernel durations over a few eager steps (event-bracketed launches)
+        graph, pipe.graph = pipe.graph, None
+        gsmi.gs_profile_enable(True)
+        for _ in range(5):
+            pipe.step()
+        torch.cuda.synchronize()
+        kt = gsmi.gs_profile_collect()
+        gsmi.gs_profile_enable(False)
+        pipe.graph = graph
+        top = sorted(kt.items(), key=lambda kv: -kv[1][1])[:8]
         out[f"r{r}"] = dict(width=cam.width, height=cam.height, ms_per_step=round(ms, 4),
                             mpix_per_s=round(cam.width * cam.height / (ms / 1e3) / 1e6, 2),
-                            tile=pick["tile"], lds_batch=pick["lds_batch"])
+                            tile=pick["tile"], lds_batch=pick["lds_batch"],
+                            kernel_ms=({k: round(v[1] / 5, 4) for k, v in top}))
         log(f"level r={r}: {ms:.3f} ms/step (tile {pick['tile']}, batch {pick['lds_batch']})")
         del pipe, p
     return out
