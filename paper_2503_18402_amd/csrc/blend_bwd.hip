@@ -940,19 +940,19 @@ void launch_bwd_tile(int batch, dim3 grid, const RViews& RV, int n, const char* 
                      const uint32_t* goff, float* pairs, int64_t cap, const float* bg,
                      hipStream_t st) {
   const dim3 block(64);
-  // tiles of 8 and 16 pixels hand long lists to the list-parallel kernel
-  constexpr int kSplit = TILE <= 16 ? 1 : 0;
+  // launches with few tiles hand long lists to the list-parallel kernel
+  const int split = split_long_lists(RV, TILE) ? 1 : 0;
 #define GS_BWD_LAUNCH(B)                                                                       \
   GS_LAUNCH("k_blend_bwd", HIP_KERNEL_NAME(k_blend_bwd<TILE, B>), grid, block, 0, st, RV, n, proj,   \
                      stride, ranges, vals, final_T, last_contrib, dL, goff, pairs, cap, bg[0], \
-                     bg[1], bg[2], kSplit)
+                     bg[1], bg[2], split)
   switch (batch) {
     case 128: GS_BWD_LAUNCH(128); break;
     case 256: GS_BWD_LAUNCH(256); break;
     default: GS_BWD_LAUNCH(512); break;
   }
 #undef GS_BWD_LAUNCH
-  if (kSplit) {
+  if (split) {
     const unsigned nb = unsigned(RV.total_tiles < kLongBlocks ? RV.total_tiles : kLongBlocks);
     GS_LAUNCH("k_blend_bwd_long", HIP_KERNEL_NAME(k_blend_bwd_long<TILE <= 16 ? TILE : 16>),
               dim3(nb), dim3(64 * kLongWaves), 0, st, RV, n, proj, stride, ranges, vals, final_T,

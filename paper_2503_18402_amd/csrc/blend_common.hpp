@@ -72,19 +72,26 @@ __host__ __device__ __forceinline__ int xcd_tile(int b, const RViews& RV) {
   return RV.tile_base[RV.order[k]] + RV.xcd_start[x][k] + (idx - RV.xcd_off[x][k]);
 }
 
-// Lists longer than this go to the list-parallel kernels (tiles of 8 and 16
-// pixels; the forward and the backward use the same rule, so both take the same
-// path for a tile).  A wave walking a list alone on its SIMD costs about 0.4 us
-// per entry, so views with few tiles (nothing else to run meanwhile) split
-// much shorter lists.
-constexpr uint32_t kLongList = 512;
-constexpr uint32_t kLongListFewTiles = 96;
+// List-parallel blending, for launches with few tiles: when the whole launch
+// has fewer than kFewTiles tiles (a low-resolution view on its own), lists
+// longer than kLongList go to the list-parallel kernels (tiles of 8 and 16
+// pixels; the forward and the backward use the same rule, so both take the
+// same path for a tile).  A wave walking a list alone on its SIMD costs about
+// 0.4 us per entry, and with few tiles nothing else runs meanwhile.  A launch
+// with more tiles (a full-resolution view, or a batch of views) fills the chip
+// with tiles alone; its longest lists start first (views are walked fewest
+// tiles first), and splitting them only adds the list-parallel passes' extra
+// work, so such launches skip the long-list kernels altogether.
+constexpr uint32_t kLongList = 96;
 constexpr int kFewTiles = 2048;
 
+__host__ __device__ inline bool split_long_lists(const RViews& RV, int tile) {
+  return tile <= 16 && RV.total_tiles < kFewTiles;
+}
+
 template <int TILE>
-__device__ __forceinline__ uint32_t long_list_threshold(const RViews& RV, int v) {
-  const int tiles = RV.gw[v] * ((RV.H[v] + TILE - 1) / TILE);
-  return tiles < kFewTiles ? kLongListFewTiles : kLongList;
+__device__ __forceinline__ uint32_t long_list_threshold(const RViews&, int) {
+  return kLongList;
 }
 
 // global tile id -> view (views are few; the loop runs on the scalar unit)

@@ -365,8 +365,8 @@ hipError_t launch_tile(int batch, const RViews& RV, const char* proj, size_t str
                        const uint32_t* ranges, const uint32_t* vals, float* image,
                        float* final_T, uint32_t* last_contrib, const float* bg, hipStream_t st) {
   const dim3 grid(unsigned(RV.total_tiles)), block(WaveShape<TILE>::kThreads);
-  // tiles of 8 and 16 pixels hand long lists to the list-parallel kernel
-  constexpr int skip_long = TILE <= 16 ? 1 : 0;
+  // launches with few tiles hand long lists to the list-parallel kernel
+  const int skip_long = split_long_lists(RV, TILE) ? 1 : 0;
   if (skip_long) {
     const unsigned nb = unsigned(RV.total_tiles < kFLongBlocks ? RV.total_tiles : kFLongBlocks);
     GS_LAUNCH("k_blend_fwd_long", HIP_KERNEL_NAME(k_blend_fwd_long<TILE <= 16 ? TILE : 16>),

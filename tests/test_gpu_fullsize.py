@@ -6,8 +6,12 @@ LDS batch 128), on outputs the FP64 oracle can compute one by one:
   ragged last tile row and column);
 * every parameter gradient for an upstream that is non-zero only at sampled
   pixels, so the oracle's per-pixel brute force covers all contributions;
-* the batched 16-view form against the plain per-view form (bit-identical
-  images) and against the oracle at sampled pixels of its largest view.
+* the batched 16-view form against the plain per-view form and against the
+  oracle at sampled pixels of its largest view.  A plain launch of a
+  low-resolution view (fewer than 2048 tiles) splits its long lists across
+  waves, while the batch (tens of thousands of tiles) walks every list in one
+  wave: those views agree within twice the oracle's image tolerance (each side
+  is within it), the full-resolution views, on the same path, bit for bit.
 """
 import numpy as np
 import pytest
@@ -98,7 +102,11 @@ def test_batched_config3_equals_plain_and_oracle(scene1m):
     imgs = fb.images()
     for k in (0, 5, 10, 15):
         fp = raster.render(params, [cams[k]], tile=TILE, lds_batch=BATCH)
-        assert torch.equal(imgs[k].reshape(-1), fp.image), k
+        tiles = -(-cams[k].width // TILE) * -(-cams[k].height // TILE)
+        if tiles >= 2048:
+            assert torch.equal(imgs[k].reshape(-1), fp.image), k
+        else:
+            assert (imgs[k].reshape(-1) - fp.image).abs().max().item() < 2e-5, k
     cam = cams[15]
     P = project.project(scene1m, cam, tile=TILE)
     pix = _sample_pixels(cam, 16, seed=21)
