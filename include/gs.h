@@ -316,6 +316,7 @@ gs_status gs_downsample_aa(int32_t n_planes, int32_t H, int32_t W, int32_t h, in
  *     z: device [n][2][3] standard normal samples.  Outputs must not alias
  *     inputs.
  *   ws: gs_densify_workspace_bytes(n), kept between the calls of one step.
+ *   0 <= n < 2^30 (GS_ERR_ARG otherwise; the workspace size is then 0).
  * ------------------------------------------------------------------------- */
 double gs_primitive_target(double i, double S, double r, double p_init, double p_fin);
 double gs_primitive_budget(double p_fin_prev, double p_add, double gamma, double eta);

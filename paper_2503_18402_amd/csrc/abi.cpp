@@ -390,7 +390,9 @@ double gs_primitive_budget(double p_fin_prev, double p_add, double gamma, double
   return x > p_fin_prev ? x : p_fin_prev;
 }
 
-size_t gs_densify_workspace_bytes(int32_t n) { return n < 0 ? 0 : densify_ws_bytes(n); }
+size_t gs_densify_workspace_bytes(int32_t n) {
+  return n < 0 || n >= kDensifyMaxN ? 0 : densify_ws_bytes(n);
+}
 
 gs_status gs_densify_stats(int32_t n_views, int32_t n, const void* proj,
                            const float* d_mean2d_abs, float scale, float* accum, float* count,
@@ -404,7 +406,8 @@ gs_status gs_densify_stats(int32_t n_views, int32_t n, const void* proj,
 gs_status gs_densify_classify(int32_t n, const float* accum, const float* count,
                               const float* opacity_logits, float grad_thr, float min_opacity,
                               void* ws, size_t ws_bytes, int64_t* counts_dev, void* stream) {
-  if (n < 0 || !ws || !counts_dev || (n > 0 && (!accum || !count || !opacity_logits)))
+  if (n < 0 || n >= kDensifyMaxN || !ws || !counts_dev ||
+      (n > 0 && (!accum || !count || !opacity_logits)))
     return GS_ERR_ARG;
   if (ws_bytes < densify_ws_bytes(n)) return GS_ERR_CAPACITY;
   if (!aligned16(ws)) return GS_ERR_ARG;
@@ -415,7 +418,7 @@ gs_status gs_densify_classify(int32_t n, const float* accum, const float* count,
 gs_status gs_densify_plan(int32_t n, int64_t k, int64_t n_candidates, const float* log_scales,
                           float max_scale, void* ws, size_t ws_bytes, int64_t* n_new_dev,
                           void* stream) {
-  if (n < 0 || n_candidates < 0 || n_candidates > n || !ws || !n_new_dev ||
+  if (n < 0 || n >= kDensifyMaxN || n_candidates < 0 || n_candidates > n || !ws || !n_new_dev ||
       (n > 0 && !log_scales))
     return GS_ERR_ARG;
   if (ws_bytes < densify_ws_bytes(n)) return GS_ERR_CAPACITY;
@@ -428,7 +431,9 @@ gs_status gs_densify_apply(int32_t n, const float* const* params, const float* c
                            const float* const* v, const float* z, const void* ws,
                            size_t ws_bytes, float* const* params_out, float* const* m_out,
                            float* const* v_out, void* stream) {
-  if (n < 0 || !params || !m || !v || !params_out || !m_out || !v_out || !ws) return GS_ERR_ARG;
+  if (n < 0 || n >= kDensifyMaxN || !params || !m || !v || !params_out || !m_out || !v_out ||
+      !ws)
+    return GS_ERR_ARG;
   if (n > 0 && !z) return GS_ERR_ARG;
   for (int t = 0; t < 5; ++t)
     if (n > 0 && (!params[t] || !m[t] || !v[t] || !params_out[t] || !m_out[t] || !v_out[t]))

@@ -162,63 +162,87 @@ struct DensifyIO {
   float* vo[5];
 };
 
-constexpr int kWidth[5] = {3, 3, 4, 1, 48};  // floats per Gaussian of each group
-
-__device__ __forceinline__ void copy_row(const float* src, float* dst, int w) {
-  for (int k = 0; k < w; ++k) dst[k] = src[k];
-}
-__device__ __forceinline__ void zero_row(float* dst, int w) {
-  for (int k = 0; k < w; ++k) dst[k] = 0.0f;
-}
-
-__global__ __launch_bounds__(256) void k_densify_apply(int n, DensifyIO io,
-                                                       const float* __restrict__ z,
-                                                       const uint32_t* __restrict__ flags,
-                                                       const uint32_t* __restrict__ off) {
+// Output row o -> (source Gaussian g, kind), packed as g << 2 | kind:
+// kind 0 the Gaussian itself (moments copied), 1 a clone's copy (fresh
+// moments), 2 + j split child j (fresh moments).
+__global__ __launch_bounds__(256) void k_densify_src(int n, const uint32_t* __restrict__ flags,
+                                                     const uint32_t* __restrict__ off,
+                                                     uint32_t* __restrict__ src) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   const uint32_t f = flags[g];
   if (f & kPrune) return;
-  const size_t o = off[g];
+  const uint32_t o = off[g], base = uint32_t(g) << 2;
   if (f & kSplit) {
-    const float* q = io.p[2] + 4 * size_t(g);
-    const float qinv = 1.0f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    const float qw = q[0] * qinv, qx = q[1] * qinv, qy = q[2] * qinv, qz = q[3] * qinv;
-    const float R[9] = {1.0f - 2.0f * (qy * qy + qz * qz), 2.0f * (qx * qy - qw * qz),
-                        2.0f * (qx * qz + qw * qy),        2.0f * (qx * qy + qw * qz),
-                        1.0f - 2.0f * (qx * qx + qz * qz), 2.0f * (qy * qz - qw * qx),
-                        2.0f * (qx * qz - qw * qy),        2.0f * (qy * qz + qw * qx),
-                        1.0f - 2.0f * (qx * qx + qy * qy)};
-    const float* ls = io.p[1] + 3 * size_t(g);
-    const float s[3] = {expf(ls[0]), expf(ls[1]), expf(ls[2])};
-    const float shrink = logf(1.6f);
-    for (int j = 0; j < 2; ++j) {
-      const size_t c = o + j;
-      const float* zz = z + 6 * size_t(g) + 3 * j;
-      const float d[3] = {s[0] * zz[0], s[1] * zz[1], s[2] * zz[2]};
-      for (int a = 0; a < 3; ++a)
-        io.po[0][3 * c + a] =
-            io.p[0][3 * size_t(g) + a] + (R[3 * a] * d[0] + R[3 * a + 1] * d[1] + R[3 * a + 2] * d[2]);
-      for (int a = 0; a < 3; ++a) io.po[1][3 * c + a] = ls[a] - shrink;
-      for (int t = 2; t < 5; ++t) copy_row(io.p[t] + kWidth[t] * size_t(g), io.po[t] + kWidth[t] * c, kWidth[t]);
-      for (int t = 0; t < 5; ++t) {
-        zero_row(io.mo[t] + kWidth[t] * c, kWidth[t]);
-        zero_row(io.vo[t] + kWidth[t] * c, kWidth[t]);
+    src[o] = base | 2u;
+    src[o + 1] = base | 3u;
+  } else {
+    src[o] = base;
+    if (f & kSel) src[o + 1] = base | 1u;
+  }
+}
+
+// One group of the new arrays, one thread per output element (consecutive
+// threads write consecutive floats of p, m and v).
+template <int G, int W>
+__device__ __forceinline__ void apply_group(const DensifyIO& io, const float* __restrict__ z,
+                                            const uint32_t* __restrict__ src, uint32_t total) {
+  const int64_t E = int64_t(total) * W;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < E; e += stride) {
+    const int64_t o = e / W;
+    const int k = int(e - o * W);
+    const uint32_t sk = src[o];
+    const size_t g = sk >> 2;
+    const uint32_t kind = sk & 3u;
+    const size_t i = g * W + k;
+    float pv;
+    if (G == 0 && kind >= 2u) {  // child mean: mu + R(q) diag(s) z_j, row k of R
+      const float* q = io.p[2] + 4 * g;
+      const float qinv = 1.0f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+      const float qw = q[0] * qinv, qx = q[1] * qinv, qy = q[2] * qinv, qz = q[3] * qinv;
+      float r0, r1, r2;
+      if (k == 0) {
+        r0 = 1.0f - 2.0f * (qy * qy + qz * qz);
+        r1 = 2.0f * (qx * qy - qw * qz);
+        r2 = 2.0f * (qx * qz + qw * qy);
+      } else if (k == 1) {
+        r0 = 2.0f * (qx * qy + qw * qz);
+        r1 = 1.0f - 2.0f * (qx * qx + qz * qz);
+        r2 = 2.0f * (qy * qz - qw * qx);
+      } else {
+        r0 = 2.0f * (qx * qz - qw * qy);
+        r1 = 2.0f * (qy * qz + qw * qx);
+        r2 = 1.0f - 2.0f * (qx * qx + qy * qy);
       }
+      const float* ls = io.p[1] + 3 * g;
+      const float* zz = z + 6 * g + 3 * (kind - 2u);
+      const float d0 = expf(ls[0]) * zz[0], d1 = expf(ls[1]) * zz[1], d2 = expf(ls[2]) * zz[2];
+      pv = io.p[0][i] + (r0 * d0 + r1 * d1 + r2 * d2);
+    } else if (G == 1 && kind >= 2u) {
+      pv = io.p[1][i] - logf(1.6f);
+    } else {
+      pv = io.p[G][i];
     }
-    return;
+    io.po[G][e] = pv;
+    io.mo[G][e] = kind == 0u ? io.m[G][i] : 0.0f;
+    io.vo[G][e] = kind == 0u ? io.v[G][i] : 0.0f;
   }
-  for (int t = 0; t < 5; ++t) {
-    copy_row(io.p[t] + kWidth[t] * size_t(g), io.po[t] + kWidth[t] * o, kWidth[t]);
-    copy_row(io.m[t] + kWidth[t] * size_t(g), io.mo[t] + kWidth[t] * o, kWidth[t]);
-    copy_row(io.v[t] + kWidth[t] * size_t(g), io.vo[t] + kWidth[t] * o, kWidth[t]);
-  }
-  if (f & kSel) {  // clone: an identical copy with fresh moments
-    for (int t = 0; t < 5; ++t) {
-      copy_row(io.p[t] + kWidth[t] * size_t(g), io.po[t] + kWidth[t] * (o + 1), kWidth[t]);
-      zero_row(io.mo[t] + kWidth[t] * (o + 1), kWidth[t]);
-      zero_row(io.vo[t] + kWidth[t] * (o + 1), kWidth[t]);
-    }
+}
+
+// blockIdx.y selects the group; the row count is the plan's scan total
+__global__ __launch_bounds__(256) void k_densify_apply(int n, DensifyIO io,
+                                                       const float* __restrict__ z,
+                                                       const uint32_t* __restrict__ src,
+                                                       const uint32_t* __restrict__ off,
+                                                       const uint32_t* __restrict__ outn) {
+  const uint32_t total = off[n - 1] + outn[n - 1];
+  switch (blockIdx.y) {
+    case 0: apply_group<0, 3>(io, z, src, total); break;
+    case 1: apply_group<1, 3>(io, z, src, total); break;
+    case 2: apply_group<2, 4>(io, z, src, total); break;
+    case 3: apply_group<3, 1>(io, z, src, total); break;
+    default: apply_group<4, 48>(io, z, src, total); break;
   }
 }
 
@@ -227,7 +251,7 @@ __global__ __launch_bounds__(64) void k_zero_u64(unsigned long long* p, int k) {
 }
 
 struct DWs {
-  size_t keys, flags, rank, outn, off, bsum, hist, st, cnt, bytes;
+  size_t keys, flags, rank, outn, off, src, bsum, hist, st, cnt, bytes;
   explicit DWs(int64_t n) {
     size_t o = 0;
     auto take = [&](size_t b) { size_t r = o; o += align256(b); return r; };
@@ -236,6 +260,7 @@ struct DWs {
     rank = take(4 * size_t(n));
     outn = take(4 * size_t(n));
     off = take(4 * size_t(n));
+    src = take(8 * size_t(n));  // up to two output rows per Gaussian
     bsum = take(4 * scan_block_sums(n));
     hist = take(4 * 256);
     st = take(sizeof(SelState));
@@ -300,8 +325,12 @@ hipError_t launch_densify_plan(int n, int64_t k, int64_t n_cand, const float* lo
     GS_LAUNCH("k_densify_mark", k_densify_mark, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st,
               n, mode, keys, rank, sst, log_scales, max_scale, flags, outn);
   }
-  return scan_exclusive(OutnSrc{outn}, OffDst{off}, Count{nullptr, n}, n,
-                        reinterpret_cast<uint32_t*>(ws + W.bsum), n_new, nullptr, st);
+  hipError_t e = scan_exclusive(OutnSrc{outn}, OffDst{off}, Count{nullptr, n}, n,
+                                reinterpret_cast<uint32_t*>(ws + W.bsum), n_new, nullptr, st);
+  if (e != hipSuccess || n == 0) return e;
+  GS_LAUNCH("k_densify_src", k_densify_src, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, n,
+            flags, off, reinterpret_cast<uint32_t*>(ws + W.src));
+  return hipGetLastError();
 }
 
 hipError_t launch_densify_apply(int n, const float* const* p, const float* const* m,
@@ -320,9 +349,13 @@ hipError_t launch_densify_apply(int n, const float* const* p, const float* const
     io.mo[t] = mo[t];
     io.vo[t] = vo[t];
   }
-  GS_LAUNCH("k_densify_apply", k_densify_apply, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st,
-            n, io, z, reinterpret_cast<const uint32_t*>(ws + W.flags),
-            reinterpret_cast<const uint32_t*>(ws + W.off));
+  const uint32_t* off = reinterpret_cast<const uint32_t*>(ws + W.off);
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(ws + W.src);
+  // enough blocks for the largest group (48 floats per row, up to 2n rows); the
+  // smaller groups' extra blocks find no element and exit
+  const unsigned gx = unsigned(std::min<int64_t>((int64_t(n) * 96 + 255) / 256, 8192));
+  GS_LAUNCH("k_densify_apply", k_densify_apply, dim3(gx, 5), dim3(256), 0, st, n, io, z, src, off,
+            reinterpret_cast<const uint32_t*>(ws + W.outn));
   return hipGetLastError();
 }
 

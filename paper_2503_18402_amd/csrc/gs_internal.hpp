@@ -222,7 +222,9 @@ hipError_t launch_render_bwd_adam(const Views& V, int n, const gs_raster_cfg& cf
 
 hipError_t launch_step_inc(int32_t* step_dev, hipStream_t st);
 
-// densification (densify.hip)
+// densification (densify.hip); output rows are indexed in 32 bits with the
+// source index packed beside two kind bits, so n < 2^30
+constexpr int32_t kDensifyMaxN = 1 << 30;
 size_t densify_ws_bytes(int n);
 hipError_t launch_densify_stats(int n_views, int n, const char* proj, const float* mean2d_abs,
                                 float scale, float* accum, float* count, hipStream_t st);
