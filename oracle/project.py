@@ -25,6 +25,19 @@ paper is silent):
   product and sum rounded to float32 in that order (no fused multiply-add);
   its IEEE bits, which order like the values for z > 0, are the sort key.
 
+Mip-Splatting's filters (the second backbone family the paper equips, Sec. 5
+and the supplementary), both optional:
+
+* 3D smoothing filter: a per-Gaussian variance f (world units squared, from
+  ``filter3d_variance``) is added to Sigma, Sigma_f = Sigma + f I, and the
+  opacity is scaled by sqrt(det Sigma / det Sigma_f) = prod_i s_i /
+  sqrt(s_i^2 + f), so the filtered Gaussian keeps its 3D integral;
+* 2D mip filter: Sigma' = J W Sigma_f W^T J^T + 0.1 I replaces the 0.3
+  dilation, and the opacity is scaled by sqrt(det(Sigma'-0.1 I) / det Sigma'),
+  so the splat keeps its 2D integral;
+* the blending opacity o' = sigmoid(logit) times both factors replaces o in
+  the cull, the footprint and Eq. 1.
+
 Guard bands flag the decisions that float32 and float64 may legitimately take
 differently, so tests can exclude exactly those cases.
 """
@@ -37,6 +50,8 @@ from . import sh as _sh
 F64 = np.float64
 NEAR_DEFAULT = 0.2
 DILATION = 0.3
+MIP_2D_VARIANCE = 0.1   # the 2D mip filter: a one-pixel box approximated by a Gaussian
+FILTER_3D_SCALE = 0.2   # Mip-Splatting's 3D filter variance in units of (pixel footprint)^2
 ALPHA_MIN = 1.0 / 255.0
 EXT_REL = 1.0e-3
 EXT_ABS = 1.0e-2
@@ -81,8 +96,11 @@ def _near_edge(v: np.ndarray, fn, guard: np.ndarray) -> np.ndarray:
     return fn(v - guard) != fn(v + guard)
 
 
-def project(scene: dict, cam, tile: int = 16, sh_degree: int = 3) -> dict:
+def project(scene: dict, cam, tile: int = 16, sh_degree: int = 3, mip2d: bool = False,
+            filter3d=None) -> dict:
     """Project every Gaussian of ``scene`` into ``cam``; all outputs FP64 unless noted.
+    ``mip2d``: the 2D mip filter instead of the 0.3 dilation; ``filter3d``:
+    per-Gaussian 3D filter variances [N] (None: no 3D filter).
 
     Returns a dict with
       xc [N,3], depth_f32 [N] (float32), mean2d [N,2], cov2d [N,3] (S00,S01,S11),
@@ -91,7 +109,9 @@ def project(scene: dict, cam, tile: int = 16, sh_degree: int = 3) -> dict:
       Tm [N,2,3], live [N] (passes z/det/opacity culls: the blend candidates),
       rect [N,4] int64 (tx0, ty0, tx1, ty1 inclusive), tiles_touched [N] int64,
       px_box [N,4] int64 (pixel box, inclusive, clamped), flag_rect, flag_rgb [N,3],
-      flag_opacity.
+      flag_opacity; opacity is the blending opacity o', opacity_raw the sigmoid,
+      coef3 / coef2 the 3D / 2D filter factors (1 when off), C2raw [N,3] the
+      projected covariance before the 2D low-pass, Sigma the filtered Sigma_f.
     """
     means = np.asarray(scene["means"], F64)
     ls = np.asarray(scene["log_scales"], F64)
@@ -116,6 +136,12 @@ def project(scene: dict, cam, tile: int = 16, sh_degree: int = 3) -> dict:
     Rq = quat_to_rot(qn)
     M = Rq * s[:, None, :]
     Sigma = M @ np.transpose(M, (0, 2, 1))
+    f3 = np.zeros(n) if filter3d is None else np.asarray(filter3d, F64)
+    if filter3d is not None:
+        Sigma = Sigma + f3[:, None, None] * np.eye(3)
+        coef3 = np.prod(s, axis=1) / np.sqrt(np.prod(s * s + f3[:, None], axis=1))
+    else:
+        coef3 = np.ones(n)
 
     J = np.zeros((n, 2, 3), F64)
     J[:, 0, 0] = fx / zs
@@ -124,12 +150,18 @@ def project(scene: dict, cam, tile: int = 16, sh_degree: int = 3) -> dict:
     J[:, 1, 2] = -fy * y / (zs * zs)
     Tm = J @ Rc
     C2 = Tm @ Sigma @ np.transpose(Tm, (0, 2, 1))
-    c00 = C2[:, 0, 0] + DILATION
+    low = MIP_2D_VARIANCE if mip2d else DILATION
+    c00 = C2[:, 0, 0] + low
     c01 = C2[:, 0, 1]
-    c11 = C2[:, 1, 1] + DILATION
+    c11 = C2[:, 1, 1] + low
     det = c00 * c11 - c01 * c01
     good_det = det > 0
     dets = np.where(good_det, det, 1.0)
+    if mip2d:
+        det_raw = C2[:, 0, 0] * C2[:, 1, 1] - C2[:, 0, 1] * C2[:, 0, 1]
+        coef2 = np.sqrt(np.maximum(det_raw, 0.0) / dets)
+    else:
+        coef2 = np.ones(n)
     conic = np.stack([c11 / dets, -c01 / dets, c00 / dets], axis=1)
     mean2d = np.stack([fx * x / zs + cx, fy * y / zs + cy], axis=1)
 
@@ -142,7 +174,12 @@ def project(scene: dict, cam, tile: int = 16, sh_degree: int = 3) -> dict:
     rgb_raw = np.einsum("nk,nkc->nc", Y, shc[:, :K, :]) + 0.5
     rgb = np.maximum(rgb_raw, 0.0)
 
-    opacity = 1.0 / (1.0 + np.exp(-logit))
+    opacity_raw = 1.0 / (1.0 + np.exp(-logit))
+    opacity = opacity_raw
+    if filter3d is not None:
+        opacity = opacity * coef3
+    if mip2d:
+        opacity = opacity * coef2
     opaque = opacity >= ALPHA_MIN
     live = front & good_det & opaque
 
@@ -188,10 +225,49 @@ def project(scene: dict, cam, tile: int = 16, sh_degree: int = 3) -> dict:
     flag_opacity = np.abs(opacity - ALPHA_MIN) < OPACITY_GUARD_REL * ALPHA_MIN
 
     return dict(xc=xc, depth_f32=z32, mean2d=mean2d, cov2d=np.stack([c00, c01, c11], 1),
-                conic=conic, opacity=opacity, rgb_raw=rgb_raw, rgb=rgb, dirs=dirs, dist=dist,
+                conic=conic, opacity=opacity, opacity_raw=opacity_raw, coef3=coef3, coef2=coef2,
+                C2raw=np.stack([C2[:, 0, 0], C2[:, 0, 1], C2[:, 1, 1]], 1), f3=f3,
+                mip2d=bool(mip2d), has_filter3d=filter3d is not None,
+                rgb_raw=rgb_raw, rgb=rgb, dirs=dirs, dist=dist,
                 Y=Y, Rq=Rq, scales=s, qn=qn, qnorm=np.linalg.norm(q, axis=1), Sigma=Sigma,
                 J=J, Tm=Tm, Rc=Rc, campos=campos, live=live, rect=rect,
                 tiles_touched=tiles_touched.astype(np.int64),
                 px_box=np.stack([px0, py0, px1, py1], 1), flag_rect=flag_rect,
                 flag_rgb=flag_rgb, flag_opacity=flag_opacity, sh_degree=sh_degree,
                 width=W, height=H, tile=tile, fx=fx, fy=fy)
+
+
+def filter3d_variance(means, cams, scale: float = FILTER_3D_SCALE):
+    """Mip-Splatting's 3D smoothing filter: per Gaussian, the variance
+    scale / nu^2 with nu the highest sampling rate fx / z over the cameras
+    whose image rectangle [0, W] x [0, H] contains the projected centre in
+    front of the near plane.  A Gaussian that no camera sees takes the largest
+    variance among the seen ones (0 when none is seen).
+
+    Also returns flag [N]: the centre sits within a float32 guard band of an
+    image edge or the near plane in some camera, where a float32 evaluation
+    may see it differently."""
+    m = np.asarray(means, F64)
+    n = m.shape[0]
+    nu = np.zeros(n)
+    flag = np.zeros(n, bool)
+    for cam in cams:
+        R, t = np.asarray(cam.R, F64), np.asarray(cam.t, F64)
+        xc = m @ R.T + t
+        z = xc[:, 2]
+        near = float(getattr(cam, "near", NEAR_DEFAULT))
+        zs = np.where(z > 0, z, 1.0)
+        u = float(cam.fx) * xc[:, 0] / zs + float(cam.cx)
+        v = float(cam.fy) * xc[:, 1] / zs + float(cam.cy)
+        W, H = float(cam.width), float(cam.height)
+        seen = (z > near) & (u >= 0) & (u <= W) & (v >= 0) & (v <= H)
+        nu = np.where(seen, np.maximum(nu, float(cam.fx) / zs), nu)
+        g = 1e-4 * (np.abs(u) + np.abs(v) + W + H)
+        flag |= (z > 0) & ((np.abs(z - near) < 1e-5 * np.abs(z) + 1e-6) |
+                           (np.minimum(np.abs(u), np.abs(u - W)) < g) |
+                           (np.minimum(np.abs(v), np.abs(v - H)) < g))
+    seen = nu > 0
+    var = np.where(seen, scale / np.where(seen, nu, 1.0) ** 2, 0.0)
+    if seen.any():
+        var[~seen] = var[seen].max()
+    return var, flag

@@ -19,6 +19,12 @@ T_final bg), dC/dc_i = alpha_i T_i and dC/dalpha_i = T_i c_i - S_i/(1-alpha_i);
 the 0.99 clamp has zero derivative where it is active.  Then through
 alpha = o G and G = exp(power) to (mean2d, conic, opacity, rgb) and, in
 ``chain_to_3d``, through the projection of ``project.py`` to the parameters.
+With Mip-Splatting's filters the blending opacity is sigmoid(logit) c3 c2, so
+its gradient also reaches the log-scales through the 3D factor c3 and the
+projected covariance through the 2D factor c2.
+
+Test infrastructure only: imported by tests/ (and bench.py's CPU baseline),
+never by the product path.
 """
 from __future__ import annotations
 
@@ -220,6 +226,30 @@ def _dR_dq(qn: np.ndarray) -> np.ndarray:
     return D
 
 
+def _dcoef2(P: dict, absolute: bool = False) -> np.ndarray:
+    """Symmetric 2x2 gradient of the 2D mip filter's factor c2 = sqrt(D1/D2)
+    w.r.t. the projected covariance (a, b; b, c) before the low-pass h:
+    d/da = c2/2 (c/D1 - (c+h)/D2), d/dc likewise, d/db = c2 b (1/D2 - 1/D1),
+    split half and half over the two off-diagonal entries.  ``absolute``: the
+    same with every term taken in magnitude (for the error scale)."""
+    h = _proj.MIP_2D_VARIANCE
+    a, b, c = P["C2raw"][:, 0], P["C2raw"][:, 1], P["C2raw"][:, 2]
+    live = P["live"]
+    D1 = np.where(live, a * c - b * b, 1.0)
+    D2 = np.where(live, (a + h) * (c + h) - b * b, 1.0)
+    c2 = P["coef2"]
+    if absolute:
+        A = np.abs
+        da = 0.5 * c2 * (A(c) / D1 + A(c + h) / D2)
+        dc = 0.5 * c2 * (A(a) / D1 + A(a + h) / D2)
+        db = c2 * A(b) * (1.0 / D2 + 1.0 / D1)
+    else:
+        da = 0.5 * c2 * (c / D1 - (c + h) / D2)
+        dc = 0.5 * c2 * (a / D1 - (a + h) / D2)
+        db = c2 * b * (1.0 / D2 - 1.0 / D1)
+    return np.stack([np.stack([da, 0.5 * db], -1), np.stack([0.5 * db, dc], -1)], -2)
+
+
 def chain_to_3d(scene: dict, P: dict, g2: dict) -> dict:
     """Chain the 2D gradients of ``render_bwd_2d`` back to the parameters.
 
@@ -237,6 +267,12 @@ def chain_to_3d(scene: dict, P: dict, g2: dict) -> dict:
     Q = np.stack([np.stack([a, b], -1), np.stack([b, c], -1)], -2)
     GQ = np.stack([np.stack([ga, 0.5 * gb], -1), np.stack([0.5 * gb, gc], -1)], -2)
     GS2 = -Q @ GQ @ Q                                       # [N,2,2] symmetric
+    go = g2["d_opacity"]                                    # w.r.t. the blending opacity
+    o_raw, c3, c2 = P["opacity_raw"], P["coef3"], P["coef2"]
+    if P["mip2d"]:
+        # c2 = sqrt(D1 / D2), D1 = det(C2raw), D2 = det(C2raw + h I): its gradient
+        # w.r.t. the symmetric C2raw (= w.r.t. Sigma', which differs by a constant)
+        GS2 = GS2 + (go * o_raw * c3)[:, None, None] * _dcoef2(P)
     Tm, Sigma, Rc = P["Tm"], P["Sigma"], P["Rc"]
     GSigma = np.transpose(Tm, (0, 2, 1)) @ GS2 @ Tm         # [N,3,3]
     GTm = 2.0 * GS2 @ Tm @ Sigma                            # [N,2,3]
@@ -254,12 +290,15 @@ def chain_to_3d(scene: dict, P: dict, g2: dict) -> dict:
     GM = 2.0 * GSigma @ M
     gs = np.einsum("nik,nik->nk", GM, Rq)
     d_ls = gs * s
+    if P["has_filter3d"]:
+        # c3 = prod_i s_i / sqrt(s_i^2 + f): d c3 / d log s_i = c3 f / (s_i^2 + f)
+        f3 = P["f3"][:, None]
+        d_ls = d_ls + (go * o_raw * c2 * c3)[:, None] * f3 / (s * s + f3)
     GR = GM * s[:, None, :]
     gqn = np.einsum("nij,nijk->nk", GR, _dR_dq(P["qn"]))
     qn = P["qn"]
     d_q = (gqn - qn * np.sum(qn * gqn, axis=1, keepdims=True)) / P["qnorm"][:, None]
-    o = P["opacity"]
-    d_logit = g2["d_opacity"] * o * (1.0 - o)
+    d_logit = go * c3 * c2 * o_raw * (1.0 - o_raw)
     # colour: rgb = max(0, sum_k sh_k Y_k(d) + 0.5); clamped channels pass nothing
     deg = P["sh_degree"]
     K = _sh.n_coeffs(deg)
@@ -301,6 +340,10 @@ def chain_abs_bound(scene: dict, P: dict, abs2d: np.ndarray) -> dict:
     Q = np.stack([np.stack([a, b], -1), np.stack([b, c], -1)], -2)
     GQ = np.stack([np.stack([ga, 0.5 * gb], -1), np.stack([0.5 * gb, gc], -1)], -2)
     GS2 = Q @ GQ @ Q
+    go = abs2d[:, 5]
+    o_raw, c3, c2 = P["opacity_raw"], P["coef3"], P["coef2"]
+    if P["mip2d"]:
+        GS2 = GS2 + (go * o_raw * c3)[:, None, None] * _dcoef2(P, absolute=True)
     Tm, Sigma, Rc = A(P["Tm"]), A(P["Sigma"]), A(P["Rc"])
     GSigma = np.transpose(Tm, (0, 2, 1)) @ GS2 @ Tm
     GJ = (2.0 * GS2 @ Tm @ Sigma) @ Rc.T
@@ -314,12 +357,14 @@ def chain_abs_bound(scene: dict, P: dict, abs2d: np.ndarray) -> dict:
     M = Rq * s[:, None, :]
     GM = 2.0 * GSigma @ M
     d_ls = np.einsum("nik,nik->nk", GM, Rq) * s
+    if P["has_filter3d"]:
+        f3 = P["f3"][:, None]
+        d_ls = d_ls + (go * o_raw * c2 * c3)[:, None] * f3 / (s * s + f3)
     GR = GM * s[:, None, :]
     qn = A(P["qn"])
     gqn = np.einsum("nij,nijk->nk", GR, A(_dR_dq(P["qn"])))
     d_q = (gqn + qn * np.sum(qn * gqn, axis=1, keepdims=True)) / P["qnorm"][:, None]
-    o = P["opacity"]
-    d_logit = abs2d[:, 5] * o * (1.0 - o)
+    d_logit = go * c3 * c2 * o_raw * (1.0 - o_raw)
     deg = P["sh_degree"]
     K = _sh.n_coeffs(deg)
     grgb = abs2d[:, 6:9]
@@ -353,8 +398,9 @@ def render_bwd(scene: dict, P: dict, dL_dC: np.ndarray, bg=(0.0, 0.0, 0.0), pixe
 
 
 def loss_weighted(scene: dict, cam, w: np.ndarray, tile: int = 16, sh_degree: int = 3,
-                  bg=(0.0, 0.0, 0.0)) -> float:
+                  bg=(0.0, 0.0, 0.0), mip2d: bool = False, filter3d=None) -> float:
     """L = sum(w * C) over all pixels: the O(1) scalar used for finite differences."""
-    P = _proj.project(scene, cam, tile=tile, sh_degree=sh_degree)
+    P = _proj.project(scene, cam, tile=tile, sh_degree=sh_degree, mip2d=mip2d,
+                      filter3d=filter3d)
     C = render_fwd(P, bg=bg)["image"]
     return float(np.sum(np.asarray(w, F64) * C))
