@@ -67,11 +67,26 @@ typedef struct {
 /* Raster configuration.  tile in {8, 16, 32} pixels; lds_batch in
  * {128, 256, 512} Gaussians staged in LDS per step of the blend kernels;
  * bg is the background colour added as T_final * bg.  The image does not
- * depend on tile or lds_batch (binning is result-neutral). */
+ * depend on tile or lds_batch (binning is result-neutral).
+ *
+ * Mip-Splatting's filters (the backbone family with an anti-aliased primitive
+ * representation that the paper equips, Sec. 5 and the supplementary):
+ *   mip2d 0: Sigma' = J W Sigma W^T J^T + 0.3 I, opacity unchanged (3DGS);
+ *         1: the 2D mip filter, Sigma' = J W Sigma W^T J^T + 0.1 I with the
+ *            opacity scaled by sqrt(det(Sigma' - 0.1 I) / det Sigma').
+ *   filter3d: NULL, or device [n] per-Gaussian 3D filter variances f
+ *         (gs_filter3d_variance): Sigma becomes Sigma + f I and the opacity is
+ *         scaled by prod_i s_i / sqrt(s_i^2 + f).  Read by gs_preprocess and
+ *         by the chain rule of the backward calls, which differentiate
+ *         through both factors (f itself is a constant).
+ * The scaled opacity is the one the cull (< 1/255), the footprint and Eq. 1
+ * use.  Every call of one step must get the same cfg. */
 typedef struct {
   int32_t tile;
   int32_t lds_batch;
   float bg[3];
+  int32_t mip2d;
+  const float* filter3d;
 } gs_raster_cfg;
 
 /* ---------------------------------------------------------------------------
@@ -111,6 +126,19 @@ gs_status gs_bin_sort(int32_t n_views, const gs_camera* cams, const gs_raster_cf
                       int32_t n, const void* proj, int64_t capacity_pairs, void* ws,
                       size_t ws_bytes, uint64_t* keys, uint32_t* vals, uint32_t* ranges,
                       int64_t* n_pairs_dev, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * gs_filter3d_variance: Mip-Splatting's 3D smoothing filter.  For each
+ * Gaussian, nu = the highest sampling rate fx / z over the views whose image
+ * rectangle [0, W] x [0, H] contains its projected centre with z > near; the
+ * variance is scale / nu^2 (scale 0.2 in Mip-Splatting).  Gaussians no view
+ * sees take the largest variance of the seen ones (0 when none is seen).
+ *   means [n,3]; variance [n] output; scratch: device uint32 [1] (overwritten).
+ *   cams: host array [n_views] (the training views), 1 <= n_views <= GS_MAX_VIEWS.
+ * ------------------------------------------------------------------------- */
+gs_status gs_filter3d_variance(int32_t n_views, const gs_camera* cams, int32_t n,
+                               const float* means, float scale, float* variance,
+                               uint32_t* scratch, void* stream);
 
 /* Total tiles over the views for this cfg (host helper for sizing ranges). */
 int64_t gs_total_tiles(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg);

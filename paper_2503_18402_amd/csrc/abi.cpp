@@ -48,9 +48,12 @@ bool build_views(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cf
   if (!cams || !cfg || !out || n_views < 1 || n_views > GS_MAX_VIEWS) return false;
   if (cfg->tile != 8 && cfg->tile != 16 && cfg->tile != 32) return false;
   if (cfg->lds_batch != 128 && cfg->lds_batch != 256 && cfg->lds_batch != 512) return false;
+  if (cfg->mip2d != 0 && cfg->mip2d != 1) return false;
   std::memset(out, 0, sizeof(Views));
   out->n_views = n_views;
   out->tile = cfg->tile;
+  out->mip2d = cfg->mip2d;
+  out->filter3d = cfg->filter3d;
   int64_t tiles = 0, pix = 0;
   for (int v = 0; v < n_views; ++v) {
     const gs_camera& c = cams[v];
@@ -153,6 +156,19 @@ int64_t gs_total_tiles(int32_t n_views, const gs_camera* cams, const gs_raster_c
   Views V;
   if (!build_views(n_views, cams, cfg, &V)) return -1;
   return V.total_tiles;
+}
+
+gs_status gs_filter3d_variance(int32_t n_views, const gs_camera* cams, int32_t n,
+                               const float* means, float scale, float* variance,
+                               uint32_t* scratch, void* stream) {
+  gs_raster_cfg cfg{};  // the cameras only: any valid tiling
+  cfg.tile = 16;
+  cfg.lds_batch = 128;
+  Views V;
+  if (!n_ok(n_views, n) || !build_views(n_views, cams, &cfg, &V)) return GS_ERR_ARG;
+  if (!(scale >= 0.0f) || !std::isfinite(scale)) return GS_ERR_ARG;
+  if (n > 0 && (!means || !variance || !scratch)) return GS_ERR_ARG;
+  return from_hip(launch_filter3d(V, n, means, scale, variance, scratch, as_stream(stream)));
 }
 
 gs_status gs_preprocess(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,

@@ -601,7 +601,14 @@ __device__ __forceinline__ bool chain_grad(const Views& V, const ChainIn& I, int
     for (int j = 0; j < 3; ++j)
       Sg[3 * i + j] =
           M3[3 * i] * M3[3 * j] + M3[3 * i + 1] * M3[3 * j + 1] + M3[3 * i + 2] * M3[3 * j + 2];
+  // Mip-Splatting's 3D filter: Sigma + f I, opacity times c3 = prod s_i / sqrt(s_i^2 + f)
+  const float f3 = V.filter3d ? V.filter3d[g] : 0.0f;
+  Sg[0] += f3;
+  Sg[4] += f3;
+  Sg[8] += f3;
+  const float c3 = V.filter3d ? filter3d_coef(s0, s1, s2, f3) : 1.0f;
   const float o = 1.0f / (1.0f + expf(-I.opacity_logits[g]));
+  const float low = V.mip2d ? kMip2d : kDilation;
   const float* shg = I.sh + size_t(g) * GS_SH_COEFFS * 3;
 
   float dm[3] = {0, 0, 0}, dS[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -642,9 +649,10 @@ __device__ __forceinline__ bool chain_grad(const Views& V, const ChainIn& I, int
 #pragma unroll
       for (int j = 0; j < 3; ++j)
         U[3 * a + j] = Tm[3 * a] * Sg[j] + Tm[3 * a + 1] * Sg[3 + j] + Tm[3 * a + 2] * Sg[6 + j];
-    const float c00 = U[0] * Tm[0] + U[1] * Tm[1] + U[2] * Tm[2] + kDilation;
-    const float c01 = U[0] * Tm[3] + U[1] * Tm[4] + U[2] * Tm[5];
-    const float c11 = U[3] * Tm[3] + U[4] * Tm[4] + U[5] * Tm[5] + kDilation;
+    const float r00 = U[0] * Tm[0] + U[1] * Tm[1] + U[2] * Tm[2];
+    const float r01 = U[0] * Tm[3] + U[1] * Tm[4] + U[2] * Tm[5];
+    const float r11 = U[3] * Tm[3] + U[4] * Tm[4] + U[5] * Tm[5];
+    const float c00 = r00 + low, c01 = r01, c11 = r11 + low;
     const float idet = 1.0f / (c00 * c11 - c01 * c01);
     const float ca = c11 * idet, cb = -c01 * idet, cc = c00 * idet;
 
@@ -652,9 +660,25 @@ __device__ __forceinline__ bool chain_grad(const Views& V, const ChainIn& I, int
     const float ga = gr[2], gbh = 0.5f * gr[3], gc = gr[4];
     const float X00 = ga * ca + gbh * cb, X01 = ga * cb + gbh * cc;
     const float X10 = gbh * ca + gc * cb, X11 = gbh * cb + gc * cc;
-    const float G00 = -(ca * X00 + cb * X10);
-    const float G01 = -0.5f * ((ca * X01 + cb * X11) + (cb * X00 + cc * X10));
-    const float G11 = -(cb * X01 + cc * X11);
+    float G00 = -(ca * X00 + cb * X10);
+    float G01 = -0.5f * ((ca * X01 + cb * X11) + (cb * X00 + cc * X10));
+    float G11 = -(cb * X01 + cc * X11);
+    // the 2D mip filter's opacity factor c2 = sqrt(D1 / D2), D1 = det of the
+    // unfiltered covariance, D2 = det Sigma' = 1 / idet: its gradient joins G'
+    float c2 = 1.0f;
+    if (V.mip2d) {
+      const float d1 = r00 * r11 - r01 * r01;
+      if (d1 > 0.0f) {
+        c2 = sqrtf(d1 * idet);
+        const float id1 = 1.0f / d1;
+        const float gc2 = gr[5] * o * c3;  // dL/dc2
+        G00 += gc2 * (0.5f * c2 * (r11 * id1 - c11 * idet));
+        G01 += gc2 * (0.5f * c2 * r01 * (idet - id1));
+        G11 += gc2 * (0.5f * c2 * (r00 * id1 - c00 * idet));
+      } else {
+        c2 = 0.0f;
+      }
+    }
     // Sigma' = T Sigma T^T: dSigma += T^T G' T ; dT = 2 G' U
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -713,7 +737,7 @@ __device__ __forceinline__ bool chain_grad(const Views& V, const ChainIn& I, int
     dm[1] += (gdy - dy * dd) * dn;
     dm[2] += (gdz - dz * dd) * dn;
 
-    dop += gr[5];
+    dop += V.mip2d ? gr[5] * c2 : gr[5];  // w.r.t. the opacity before the 2D factor
     m2abs += sqrtf(gmx * gmx + gmy * gmy);
   }
 
@@ -731,6 +755,11 @@ __device__ __forceinline__ bool chain_grad(const Views& V, const ChainIn& I, int
 #pragma unroll
     for (int i = 0; i < 3; ++i) dR[3 * i + j] = dMm[3 * i + j] * sc[j];
   }
+  if (V.filter3d) {  // d c3 / d log s_j = c3 f / (s_j^2 + f)
+    const float gc3 = dop * o * c3;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) dls[j] += gc3 * f3 / (sc[j] * sc[j] + f3);
+  }
   const float gw = -2.0f * qz * dR[1] + 2.0f * qy * dR[2] + 2.0f * qz * dR[3] -
                    2.0f * qx * dR[5] - 2.0f * qy * dR[6] + 2.0f * qx * dR[7];
   const float gx = 2.0f * qy * dR[1] + 2.0f * qz * dR[2] + 2.0f * qy * dR[3] - 4.0f * qx * dR[4] -
@@ -744,7 +773,7 @@ __device__ __forceinline__ bool chain_grad(const Views& V, const ChainIn& I, int
   const float qd = qw * gw + qx * gx + qy * gy + qz * gz;
   float4 dq4 = make_float4((gw - qw * qd) * qinv, (gx - qx * qd) * qinv, (gy - qy * qd) * qinv,
                            (gz - qz * qd) * qinv);
-  const float dlogit = dop * o * (1.0f - o);
+  const float dlogit = (V.filter3d ? dop * c3 : dop) * o * (1.0f - o);
   O.dlogit = dlogit;
   O.dq = dq4;
   O.m2abs = m2abs;

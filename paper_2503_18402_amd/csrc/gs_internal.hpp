@@ -19,6 +19,7 @@ constexpr float kAlphaMin = 1.0f / 255.0f;  // skip a Gaussian below this alpha
 constexpr float kAlphaMax = 0.99f;          // alpha clamp
 constexpr float kTMin = 1.0e-4f;            // stop a pixel before T drops below this
 constexpr float kDilation = 0.3f;           // screen-space low-pass added to Sigma'
+constexpr float kMip2d = 0.1f;              // the 2D mip filter's variance (Mip-Splatting)
 constexpr float kLog2e = 1.44269504088896340736f;
 constexpr float kExtRel = 1.0e-3f;          // widening of the footprint box (relative)
 constexpr float kExtAbs = 1.0e-2f;          // and (pixels)
@@ -43,8 +44,14 @@ struct Views {
   int32_t n_views;
   int32_t tile;
   int32_t total_tiles;
-  int32_t pad;
+  int32_t mip2d;            // 1: the 2D mip filter instead of the dilation
+  const float* filter3d;    // per-Gaussian 3D filter variances, or null
 };
+
+// The 3D filter's opacity factor prod_i s_i / sqrt(s_i^2 + f) (1 for f = 0).
+__device__ __forceinline__ float filter3d_coef(float s0, float s1, float s2, float f) {
+  return (s0 * s1 * s2) / sqrtf((s0 * s0 + f) * (s1 * s1 + f) * (s2 * s2 + f));
+}
 
 // ----------------------------------------------------- projected records
 // Per view, for each Gaussian g (all FP32 unless noted):
@@ -179,6 +186,8 @@ struct ProfScope {
 bool build_views(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg, Views* out);
 
 // kernels' host launchers (one per translation unit)
+hipError_t launch_filter3d(const Views& V, int n, const float* means, float scale,
+                          float* variance, uint32_t* scratch, hipStream_t st);
 hipError_t launch_preprocess(const Views& V, int n, int sh_degree, const float* means,
                              const float* log_scales, const float* quats,
                              const float* opacity_logits, const float* sh, char* proj,

@@ -91,17 +91,20 @@ __global__ __launch_bounds__(kPreThreads) void k_preprocess(
   const float m20 = (2.0f * (qx * qz - qw * qy)) * s0;
   const float m21 = (2.0f * (qy * qz + qw * qx)) * s1;
   const float m22 = (1.0f - 2.0f * (qx * qx + qy * qy)) * s2;
-  // Sigma = M M^T (symmetric)
-  const float S00 = m00 * m00 + m01 * m01 + m02 * m02;
+  // Sigma = M M^T (symmetric), plus the 3D filter's variance on the diagonal
+  const float f3 = V.filter3d ? V.filter3d[g] : 0.0f;
+  const float S00 = m00 * m00 + m01 * m01 + m02 * m02 + f3;
   const float S01 = m00 * m10 + m01 * m11 + m02 * m12;
   const float S02 = m00 * m20 + m01 * m21 + m02 * m22;
-  const float S11 = m10 * m10 + m11 * m11 + m12 * m12;
+  const float S11 = m10 * m10 + m11 * m11 + m12 * m12 + f3;
   const float S12 = m10 * m20 + m11 * m21 + m12 * m22;
-  const float S22 = m20 * m20 + m21 * m21 + m22 * m22;
+  const float S22 = m20 * m20 + m21 * m21 + m22 * m22 + f3;
 
-  const float o = 1.0f / (1.0f + expf(-opacity_logits[g]));
+  const float o0 = 1.0f / (1.0f + expf(-opacity_logits[g]));
+  const float o = V.filter3d ? o0 * filter3d_coef(s0, s1, s2, f3) : o0;
   const bool opaque = o >= kAlphaMin;
-  const float k2 = fmaxf(0.0f, 2.0f * logf(255.0f * o));
+  const float k2o = fmaxf(0.0f, 2.0f * logf(255.0f * o));
+  const float low = V.mip2d ? kMip2d : kDilation;  // screen-space low-pass
 
   const int K = (sh_degree + 1) * (sh_degree + 1);
   float shc[GS_SH_COEFFS * 3];
@@ -136,18 +139,25 @@ __global__ __launch_bounds__(kPreThreads) void k_preprocess(
       const float t10 = j11 * cv.R[3] + j12 * cv.R[6];
       const float t11 = j11 * cv.R[4] + j12 * cv.R[7];
       const float t12 = j11 * cv.R[5] + j12 * cv.R[8];
-      // U = T Sigma, Sigma' = U T^T + dilation
+      // U = T Sigma, Sigma' = U T^T + low-pass
       const float u00 = t00 * S00 + t01 * S01 + t02 * S02;
       const float u01 = t00 * S01 + t01 * S11 + t02 * S12;
       const float u02 = t00 * S02 + t01 * S12 + t02 * S22;
       const float u10 = t10 * S00 + t11 * S01 + t12 * S02;
       const float u11 = t10 * S01 + t11 * S11 + t12 * S12;
       const float u12 = t10 * S02 + t11 * S12 + t12 * S22;
-      const float c00 = u00 * t00 + u01 * t01 + u02 * t02 + kDilation;
-      const float c01 = u00 * t10 + u01 * t11 + u02 * t12;
-      const float c11 = u10 * t10 + u11 * t11 + u12 * t12 + kDilation;
+      const float r00 = u00 * t00 + u01 * t01 + u02 * t02;
+      const float r01 = u00 * t10 + u01 * t11 + u02 * t12;
+      const float r11 = u10 * t10 + u11 * t11 + u12 * t12;
+      const float c00 = r00 + low, c01 = r01, c11 = r11 + low;
       const float det = c00 * c11 - c01 * c01;
-      if (det > 0.0f) {
+      // the 2D mip filter keeps the splat's integral: opacity times sqrt(det ratio)
+      float ov = o, k2 = k2o;
+      if (V.mip2d && det > 0.0f) {
+        ov = o * sqrtf(fmaxf(r00 * r11 - r01 * r01, 0.0f) / det);
+        k2 = fmaxf(0.0f, 2.0f * logf(255.0f * ov));
+      }
+      if (det > 0.0f && ov >= kAlphaMin) {
         const float idet = 1.0f / det;
         const float ca = c11 * idet, cb = -c01 * idet, cc = c00 * idet;
         // screen mean in double: float32 spacing at 1000+ px (6e-5 px) would otherwise
@@ -195,7 +205,7 @@ __global__ __launch_bounds__(kPreThreads) void k_preprocess(
         const int ox = (x0 <= x1 ? x0 / T : 0) * T, oy = (y0 <= y1 ? y0 / T : 0) * T;
         const float s = -0.5f * kLog2e;
         r0 = make_float4(float(mux - double(ox)), float(muy - double(oy)), s * ca, -kLog2e * cb);
-        r1 = make_float4(s * cc, o, rgb[0], rgb[1]);
+        r1 = make_float4(s * cc, ov, rgb[0], rgb[1]);
         r2 = make_float4(rgb[2], depth, __uint_as_float(box_pack(x0 < 0 ? 0 : x0, y0 < 0 ? 0 : y0)),
                          __uint_as_float(box_pack(x1 < 0 ? 0 : x1, y1 < 0 ? 0 : y1)));
       }
@@ -208,7 +218,71 @@ __global__ __launch_bounds__(kPreThreads) void k_preprocess(
   }
 }
 
+constexpr int kF3Threads = 256;
+
+// Mip-Splatting's 3D filter: per Gaussian the highest sampling rate fx / z over
+// the views whose image contains its centre; variance scale / nu^2, or -1
+// (unseen) for now.  The block's largest variance goes to *vmax (positive
+// floats order like their bits).
+__global__ __launch_bounds__(kF3Threads) void k_filter3d(Views V, int n,
+                                                         const float* __restrict__ means,
+                                                         float scale, float* __restrict__ var,
+                                                         uint32_t* __restrict__ vmax) {
+  __shared__ uint32_t s_max[kF3Threads / kWave];
+  const int g = blockIdx.x * kF3Threads + threadIdx.x;
+  float r = -1.0f;
+  if (g < n) {
+    const float mx = means[3 * g + 0], my = means[3 * g + 1], mz = means[3 * g + 2];
+    float nu = 0.0f;
+    for (int v = 0; v < V.n_views; ++v) {
+      const DevView& cv = V.v[v];
+      const float z = fmaf(cv.R[6], mx, fmaf(cv.R[7], my, fmaf(cv.R[8], mz, cv.t[2])));
+      if (!(z > cv.near_plane)) continue;
+      const float iz = 1.0f / z;
+      const float xc = fmaf(cv.R[0], mx, fmaf(cv.R[1], my, fmaf(cv.R[2], mz, cv.t[0])));
+      const float yc = fmaf(cv.R[3], mx, fmaf(cv.R[4], my, fmaf(cv.R[5], mz, cv.t[1])));
+      const float u = fmaf(cv.fx * xc, iz, cv.cx), w = fmaf(cv.fy * yc, iz, cv.cy);
+      if (u >= 0.0f && u <= float(cv.W) && w >= 0.0f && w <= float(cv.H))
+        nu = fmaxf(nu, cv.fx * iz);
+    }
+    if (nu > 0.0f) r = scale / (nu * nu);
+    var[g] = r;
+  }
+  // block max of the seen variances, then one atomic per block
+  uint32_t b = r > 0.0f ? __float_as_uint(r) : 0u;
+  for (int off = kWave / 2; off > 0; off >>= 1) b = max(b, uint32_t(__shfl_xor(int(b), off)));
+  if ((threadIdx.x & (kWave - 1)) == 0) s_max[threadIdx.x / kWave] = b;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t m = 0u;
+    for (int k = 0; k < kF3Threads / kWave; ++k) m = max(m, s_max[k]);
+    if (m) atomicMax(vmax, m);
+  }
+}
+
+__global__ __launch_bounds__(64) void k_set_u32(uint32_t* p, uint32_t x) {
+  if (threadIdx.x == 0) *p = x;
+}
+
+__global__ __launch_bounds__(kF3Threads) void k_filter3d_unseen(int n, float* __restrict__ var,
+                                                                const uint32_t* __restrict__ vmax) {
+  const int g = blockIdx.x * kF3Threads + threadIdx.x;
+  if (g < n && var[g] < 0.0f) var[g] = __uint_as_float(*vmax);
+}
+
 }  // namespace
+
+hipError_t launch_filter3d(const Views& V, int n, const float* means, float scale,
+                          float* variance, uint32_t* scratch, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const unsigned nb = unsigned((n + kF3Threads - 1) / kF3Threads);
+  GS_LAUNCH("k_set_u32", k_set_u32, dim3(1), dim3(64), 0, st, scratch, 0u);
+  GS_LAUNCH("k_filter3d", k_filter3d, dim3(nb), dim3(kF3Threads), 0, st, V, n, means, scale,
+            variance, scratch);
+  GS_LAUNCH("k_filter3d_unseen", k_filter3d_unseen, dim3(nb), dim3(kF3Threads), 0, st, n,
+            variance, scratch);
+  return hipGetLastError();
+}
 
 hipError_t launch_preprocess(const Views& V, int n, int sh_degree, const float* means,
                              const float* log_scales, const float* quats,

@@ -35,7 +35,8 @@ class GsCamera(ctypes.Structure):
 
 
 class GsRasterCfg(ctypes.Structure):
-    _fields_ = [("tile", c_int32), ("lds_batch", c_int32), ("bg", c_float * 3)]
+    _fields_ = [("tile", c_int32), ("lds_batch", c_int32), ("bg", c_float * 3),
+                ("mip2d", c_int32), ("filter3d", c_void_p)]
 
 
 class GsKernelTime(ctypes.Structure):
@@ -83,6 +84,7 @@ def lib() -> ctypes.CDLL:
                                                 vp, vp, vp, vp, vp, vp, POINTER(c_void_p),
                                                 POINTER(c_void_p), POINTER(c_float), vp, c_float,
                                                 c_float, c_float, vp, i64, vp, sz, vp]),
+            "gs_filter3d_variance": (i32, [i32, cam_p, i32, vp, c_float, vp, vp, vp]),
             "gs_frequency_map_workspace_bytes": (sz, [i32, i32]),
             "gs_frequency_map": (i32, [i32, i32, i32, vp, vp, vp, sz, vp]),
             "gs_resolution_schedule": (i32, [POINTER(c_double), i32, i32, c_double, c_double, i32,
@@ -151,10 +153,15 @@ def make_cameras(cams) -> ctypes.Array:
     return arr
 
 
-def make_cfg(tile: int = 16, lds_batch: int = 256, bg=(0.0, 0.0, 0.0)) -> GsRasterCfg:
+def make_cfg(tile: int = 16, lds_batch: int = 256, bg=(0.0, 0.0, 0.0), mip2d: bool = False,
+             filter3d=None) -> GsRasterCfg:
+    """filter3d: device float32 [n] 3D filter variances (kept alive by the
+    caller while the cfg is in use) or None."""
     c = GsRasterCfg()
     c.tile, c.lds_batch = int(tile), int(lds_batch)
     c.bg[:] = [float(x) for x in bg]
+    c.mip2d = 1 if mip2d else 0
+    c.filter3d = _ptr(filter3d)
     return c
 
 
@@ -270,6 +277,14 @@ def gs_render_bwd_sparse_adam(*args, **kw):
     their parameters and moments."""
     kw["sparse"] = True
     gs_render_bwd_adam(*args, **kw)
+
+
+def gs_filter3d_variance(cams_c, n, means, scale, variance, scratch, stream=None):
+    """Mip-Splatting's 3D filter variances of n Gaussians [n] from the
+    training views; scratch: device int32/uint32 [1]."""
+    _check("gs_filter3d_variance", lib().gs_filter3d_variance(
+        len(cams_c), cams_c, int(n), _ptr(means), float(scale), _ptr(variance), _ptr(scratch),
+        _stream(stream)))
 
 
 def gs_frequency_map_workspace_bytes(H: int, W: int) -> int:

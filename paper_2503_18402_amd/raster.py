@@ -34,6 +34,7 @@ class Frame:
     final_T: torch.Tensor
     last_contrib: torch.Tensor
     sizes: list = field(default_factory=list)   # (W, H) per view
+    filter3d: object = None      # the 3D filter variances the cfg points at (kept alive)
 
     def images(self):
         """Per-view [3,H,W] views into the concatenated image."""
@@ -64,16 +65,19 @@ def default_capacity(n: int, n_views: int) -> int:
 
 def render(params: dict, cams, tile: int = 16, lds_batch: int = 256, bg=(0.0, 0.0, 0.0),
            sh_degree: int = 3, capacity: int | None = None, want_keys: bool = False,
-           check_capacity: bool = True, stream=None) -> Frame:
+           check_capacity: bool = True, stream=None, mip2d: bool = False,
+           filter3d: torch.Tensor | None = None) -> Frame:
     """Forward pass for the cameras ``cams`` (one launch per kernel for all views).
 
     With ``check_capacity`` the pair count is read back once (one 8-byte copy)
-    and the sort is re-run with a larger buffer if it overflowed.
+    and the sort is re-run with a larger buffer if it overflowed.  ``mip2d``
+    and ``filter3d`` select Mip-Splatting's filters (see gs_raster_cfg); the
+    frame keeps ``filter3d`` alive for the backward.
     """
     dev = params["means"].device
     n = params["means"].shape[0]
     cams_c = gsmi.make_cameras(cams)
-    cfg = gsmi.make_cfg(tile, lds_batch, bg)
+    cfg = gsmi.make_cfg(tile, lds_batch, bg, mip2d=mip2d, filter3d=filter3d)
     nv = len(cams)
     quats = _aligned(params["quats"])
     proj = torch.empty(max(gsmi.gs_proj_bytes(nv, n), 16), dtype=torch.uint8, device=dev)
@@ -101,10 +105,11 @@ def render(params: dict, cams, tile: int = 16, lds_batch: int = 256, bg=(0.0, 0.
     final_T = torch.empty(npx, dtype=torch.float32, device=dev)
     last = torch.empty(npx, dtype=torch.int32, device=dev)
     gsmi.gs_render_fwd(cams_c, cfg, n, proj, ranges, vals, image, final_T, last, stream)
-    return Frame(cams_c=cams_c, cfg=cfg, n=n, sh_degree=sh_degree, proj=proj, vals=vals,
-                 keys=keys, ranges=ranges, n_pairs_dev=n_pairs, capacity=cap, image=image,
-                 final_T=final_T, last_contrib=last,
-                 sizes=[(int(c.width), int(c.height)) for c in cams])
+    fr = Frame(cams_c=cams_c, cfg=cfg, n=n, sh_degree=sh_degree, proj=proj, vals=vals,
+               keys=keys, ranges=ranges, n_pairs_dev=n_pairs, capacity=cap, image=image,
+               final_T=final_T, last_contrib=last,
+               sizes=[(int(c.width), int(c.height)) for c in cams], filter3d=filter3d)
+    return fr
 
 
 def zero_grads(params: dict) -> dict:
@@ -135,7 +140,7 @@ class RasterizeFn(torch.autograd.Function):
     """image = RasterizeFn.apply(means, log_scales, quats, opacity_logits, sh, settings)
 
     ``settings`` is a dict with ``cams`` and optionally tile, lds_batch, bg,
-    sh_degree.  The forward keeps only the frame buffers (projected records,
+    sh_degree, mip2d, filter3d.  The forward keeps only the frame buffers (projected records,
     sorted pair values, ranges, final T and last contributor per pixel); the
     backward recomputes each pixel's blend state from them.
     """
@@ -149,7 +154,8 @@ class RasterizeFn(torch.autograd.Function):
         frame = render(params, settings["cams"], tile=settings.get("tile", 16),
                        lds_batch=settings.get("lds_batch", 256),
                        bg=settings.get("bg", (0.0, 0.0, 0.0)),
-                       sh_degree=settings.get("sh_degree", 3))
+                       sh_degree=settings.get("sh_degree", 3),
+                       mip2d=settings.get("mip2d", False), filter3d=settings.get("filter3d"))
         ctx.frame = frame
         ctx.params = params
         return frame.image.clone()
@@ -189,7 +195,8 @@ class Pipeline:
                  betas=(0.9, 0.999), eps: float = 1e-15, grads: dict | None = None,
                  fused: bool = True, share: "Pipeline | None" = None,
                  state: tuple | None = None, mean2d_abs: torch.Tensor | None = None,
-                 sparse_adam: bool = False):
+                 sparse_adam: bool = False, mip2d: bool = False,
+                 filter3d: torch.Tensor | None = None):
         if sparse_adam and not fused:
             raise ValueError("sparse Adam runs fused with the backward pass")
         self.params = params
@@ -198,13 +205,14 @@ class Pipeline:
         self.n = params["means"].shape[0]
         self.nv = len(self.cams)
         self.cams_c = gsmi.make_cameras(self.cams)
-        self.cfg = gsmi.make_cfg(tile, lds_batch, bg)
+        self.filter3d = filter3d   # kept alive: the cfg holds its address
+        self.cfg = gsmi.make_cfg(tile, lds_batch, bg, mip2d=mip2d, filter3d=filter3d)
         self.sh_degree = sh_degree
         self.npx = sum(int(c.width) * int(c.height) for c in self.cams)
         self.targets = targets.contiguous()
         if capacity is None:
             probe = render(params, self.cams, tile=tile, lds_batch=lds_batch, bg=bg,
-                           sh_degree=sh_degree)
+                           sh_degree=sh_degree, mip2d=mip2d, filter3d=filter3d)
             capacity = int(int(probe.n_pairs_dev.item()) * 1.2) + 4096
             del probe
         self.capacity = int(capacity)

@@ -49,11 +49,15 @@ def grads_np(g: dict) -> dict:
 
 
 def run(scene: dict, cams, tile=16, lds_batch=256, bg=(0.0, 0.0, 0.0), sh_degree=3,
-        upstream=None, want_keys=True, capacity=None):
-    """Forward (and backward if ``upstream`` is given, one [3,H,W] array per view)."""
+        upstream=None, want_keys=True, capacity=None, mip2d=False, filter3d=None):
+    """Forward (and backward if ``upstream`` is given, one [3,H,W] array per view).
+    filter3d: numpy [N] 3D filter variances or None."""
     params = raster.to_device(scene, "cuda")
+    f3 = None if filter3d is None else torch.from_numpy(
+        np.ascontiguousarray(filter3d, np.float32)).cuda()
     frame = raster.render(params, cams, tile=tile, lds_batch=lds_batch, bg=bg,
-                          sh_degree=sh_degree, want_keys=want_keys, capacity=capacity)
+                          sh_degree=sh_degree, want_keys=want_keys, capacity=capacity,
+                          mip2d=mip2d, filter3d=f3)
     grads = None
     if upstream is not None:
         dL = torch.cat([torch.from_numpy(np.ascontiguousarray(u, np.float32)).reshape(-1)

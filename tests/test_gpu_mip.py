@@ -1,0 +1,121 @@
+"""Mip-Splatting's filters on the device (gs_raster_cfg.mip2d / .filter3d and
+gs_filter3d_variance) against the FP64 oracle: image and every parameter
+gradient on config 0 with the 2D mip filter, the 3D smoothing filter and
+both; a two-view batch against the oracle's per-view sum; the 3D filter's
+variances; and the backward fused with Adam against the separate calls.
+The 3D filter variances are seeded inputs given to both sides."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import project, render
+from paper_2503_18402_amd import gsmi, raster, scenes
+from tests import gpu_util as U
+
+pytestmark = pytest.mark.gpu
+
+IMG_TOL = 1e-5
+
+
+def _variances(sc, seed):
+    """Per-Gaussian 3D filter variances between 0.2 and 2 times the smallest
+    squared scale, so the filter changes every Gaussian noticeably."""
+    s2 = np.exp(2.0 * sc["log_scales"].astype(np.float64)).min(axis=1)
+    return (np.random.default_rng(seed).uniform(0.2, 2.0, s2.shape) * s2).astype(np.float32)
+
+
+def _skip(P, F):
+    flagged = np.nonzero(F["flag"].reshape(-1))[0]
+    bad = P["flag_rgb"].any(1) | P["flag_opacity"]
+    if flagged.size:
+        order = render._order(P)
+        B = render._pixel_block(P, order, flagged, P["width"])
+        bad[order[(B["alpha"] >= 0.9 / 255.0).any(axis=0)]] = True
+    return bad
+
+
+@pytest.mark.parametrize("mip2d,use3d", [(True, True), (True, False), (False, True)])
+def test_filtered_render_matches_oracle(mip2d, use3d):
+    sc, cam = scenes.config0()
+    f3 = _variances(sc, 91) if use3d else None
+    w = scenes.random_upstream(cam, seed=92)
+    P = project.project(sc, cam, mip2d=mip2d,
+                        filter3d=None if f3 is None else f3.astype(np.float64))
+    F = render.render_fwd(P)
+    B = render.render_bwd(sc, P, w, with_bound=True)
+    _, frame, g = U.run(sc, [cam], upstream=[w], mip2d=mip2d, filter3d=f3)
+    img = frame.image.view(3, cam.height, cam.width).cpu().numpy()
+    ok = ~F["flag"]
+    assert ok.mean() > 0.99
+    assert np.abs(img - F["image"])[:, ok].max() < IMG_TOL
+    fT = frame.final_T.view(cam.height, cam.width).cpu().numpy()
+    assert np.abs(fT - F["final_T"])[ok].max() < IMG_TOL
+    mask = ~_skip(P, F)
+    # the filtered splats are wider, so the 6-20 guard-band pixels reach more
+    # Gaussians than without the filters (81-97% stay in the check)
+    assert mask.mean() > 0.75
+    for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        U.check_grads(g[name], B["d_" + name], B["bound"]["d_" + name], mask=mask)
+    # the filters change the picture: compare with the plain projection
+    F0 = render.render_fwd(project.project(sc, cam))
+    assert np.abs(F0["image"] - F["image"]).max() > 1e-3
+
+
+def test_filtered_batch_matches_oracle_sum():
+    sc, _ = scenes.config0()
+    base = scenes.orbit_cameras(3, 3.0, 128, 96, 120.0)
+    cams = [base[0], scenes.downscale(base[1], 2)]
+    f3 = _variances(sc, 93)
+    ups = [scenes.random_upstream(c, seed=94 + k) for k, c in enumerate(cams)]
+    _, frame, g = U.run(sc, cams, upstream=ups, mip2d=True, filter3d=f3, want_keys=False)
+    ref, bnd, skip, off = None, None, np.zeros(sc["means"].shape[0], bool), 0
+    for c, u in zip(cams, ups):
+        P = project.project(sc, c, mip2d=True, filter3d=f3.astype(np.float64))
+        F = render.render_fwd(P)
+        B = render.render_bwd(sc, P, u, with_bound=True)
+        npx = 3 * c.width * c.height
+        img = frame.image[off:off + npx].view(3, c.height, c.width).cpu().numpy()
+        assert np.abs(img - F["image"])[:, ~F["flag"]].max() < IMG_TOL
+        off += npx
+        skip |= _skip(P, F)
+        ref = {k: B["d_" + k] for k in raster.PARAM_NAMES} if ref is None else \
+            {k: ref[k] + B["d_" + k] for k in raster.PARAM_NAMES}
+        bnd = {k: B["bound"]["d_" + k] for k in raster.PARAM_NAMES} if bnd is None else \
+            {k: bnd[k] + B["bound"]["d_" + k] for k in raster.PARAM_NAMES}
+    for name in raster.PARAM_NAMES:
+        U.check_grads(g[name], ref[name], bnd[name], mask=~skip)
+
+
+def test_filter3d_variance_matches_oracle():
+    sc, _ = scenes.config0()
+    # two points far above and below the orbit plane: no view sees them
+    means = np.concatenate([sc["means"], np.array([[0.0, 30.0, 0.0], [0.0, -30.0, 0.0]],
+                                                  np.float32)])
+    cams = scenes.orbit_cameras(6, 3.0, 128, 96, 120.0)
+    ref, flag = project.filter3d_variance(means.astype(np.float64), cams, scale=0.2)
+    m = torch.from_numpy(means).cuda()
+    out = torch.full((means.shape[0],), -7.0, device="cuda")
+    scratch = torch.zeros(1, dtype=torch.int32, device="cuda")
+    gsmi.gs_filter3d_variance(gsmi.make_cameras(cams), means.shape[0], m, 0.2, out, scratch)
+    got = out.cpu().numpy().astype(np.float64)
+    assert (~flag).mean() > 0.95
+    assert np.all(np.abs(got - ref)[~flag] <= 1e-5 * ref[~flag])
+    assert ref[-1] == ref.max() and got[-1] == got.max()   # seen by no view: the largest
+    assert abs(got[-1] - ref[-1]) <= 1e-5 * ref[-1]
+    assert (ref[:-2] < ref.max()).any()
+
+
+def test_filtered_fused_step_equals_separate_calls():
+    sc, cam = scenes.config0()
+    f3 = torch.from_numpy(_variances(sc, 95)).cuda()
+    tgt = torch.from_numpy(scenes.uniform_target(cam, seed=96)).reshape(-1).cuda()
+    pa = raster.Pipeline(raster.to_device(sc), [cam], tgt, fused=False, mip2d=True, filter3d=f3)
+    pb = raster.Pipeline(raster.to_device(sc), [cam], tgt, capacity=pa.capacity, fused=True,
+                         mip2d=True, filter3d=f3)
+    for k in range(2):
+        pa.step()
+        pb.step()
+        torch.cuda.synchronize()
+        for name in raster.PARAM_NAMES:
+            assert torch.equal(pa.params[name], pb.params[name]), (k, name)
+            assert torch.equal(pa.m[name], pb.m[name]), (k, name)
