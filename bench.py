@@ -412,10 +412,12 @@ def scheduled_training(torch, raster, scenes, dev, iters):
     """The optimisation loop of the hidden-scene workload: learnable Gaussians
     fitted to 64 views at 1200x800 of a 500k-Gaussian hidden scene (ground
     truth rendered once), ``iters`` iterations, one view per iteration, the
-    backward fused with Adam.  Three loops from the same 50k-Gaussian start:
-    the full method (Eq. 7 resolution schedule, Eq. 4/5 primitive schedule
-    with top-k densification), the resolution schedule alone (every candidate
-    densified) and the backbone (full resolution, every candidate).
+    backward fused with Adam.  Loops from the same 50k-Gaussian start: the
+    full method (Eq. 7 resolution schedule, Eq. 4/5 primitive schedule with
+    top-k densification), the resolution schedule alone (every candidate
+    densified) and the backbone (full resolution, every candidate); then the
+    full method and the backbone again on Mip-Splatting's primitives (2D mip
+    filter, 3D filter recomputed after every densification step).
     Densification every 100 iterations over the first half; the gradient
     threshold is set for the synthetic scene (its gradients sit an order of
     magnitude below a photograph's) so that the backbone grows to about 300k.
@@ -434,16 +436,19 @@ def scheduled_training(torch, raster, scenes, dev, iters):
     init = scenes.make_scene(n_init, seed=6, mean_range=4.0, ls_mu=-4.0, ls_sigma=0.5)
     extent = 6.0 * 1.1   # camera sphere radius with the backbone's 10% margin
     out = {}
-    for name, sched, top_k in (("dashgaussian", True, True), ("resolution_only", True, False),
-                               ("backbone", False, False)):
+    for name, sched, top_k, mip in (("dashgaussian", True, True, False),
+                                    ("resolution_only", True, False, False),
+                                    ("backbone", False, False, False),
+                                    ("mip_dashgaussian", True, True, True),
+                                    ("mip_backbone", False, False, True)):
         params = raster.to_device(init, dev)
         dcfg = train.DensifyConfig(every=100, start=100, stop=iters // 2, extent=extent,
                                    schedule=top_k, grad_thr=grad_thr)
         tr = train.Trainer(params, cams, gt, iters, schedule=sched, densify=dcfg, r_max=r_max,
-                           means_lr=(1.6e-4 * extent, 1.6e-6 * extent))
-        psnr0 = train.psnr(tr.params, cams, gt)
+                           means_lr=(1.6e-4 * extent, 1.6e-6 * extent), mip=mip)
+        psnr0 = train.psnr(tr.params, cams, gt, mip2d=mip, filter3d=tr.filter3d)
         res = tr.run()
-        psnr1 = train.psnr(tr.params, cams, gt)
+        psnr1 = train.psnr(tr.params, cams, gt, mip2d=mip, filter3d=tr.filter3d)
         out[name] = dict(seconds=round(res["seconds"], 3),
                          ms_per_iter=round(1e3 * res["s_per_iter"], 4),
                          densify_seconds=round(res["densify_seconds"], 3),
@@ -461,6 +466,8 @@ def scheduled_training(torch, raster, scenes, dev, iters):
         del tr, params
     for name in ("dashgaussian", "resolution_only"):
         out[name]["speedup_vs_backbone"] = round(out["backbone"]["seconds"] / out[name]["seconds"], 3)
+    out["mip_dashgaussian"]["speedup_vs_backbone"] = round(
+        out["mip_backbone"]["seconds"] / out["mip_dashgaussian"]["seconds"], 3)
     out.update(iters=iters, views=len(cams), width=cams[0].width, height=cams[0].height,
                initial=n_init, hidden=500_000, grad_thr_ndc=grad_thr, r_max=r_max,
                note="X(F_r) normalised per pixel; eager loop, one view per iteration, "

@@ -134,7 +134,8 @@ gs_status gs_bin_sort(int32_t n_views, const gs_camera* cams, const gs_raster_cf
  * variance is scale / nu^2 (scale 0.2 in Mip-Splatting).  Gaussians no view
  * sees take the largest variance of the seen ones (0 when none is seen).
  *   means [n,3]; variance [n] output; scratch: device uint32 [1] (overwritten).
- *   cams: host array [n_views] (the training views), 1 <= n_views <= GS_MAX_VIEWS.
+ *   cams: host array [n_views] (the training views), n_views >= 1 (any number:
+ *   they are taken in launches of GS_MAX_VIEWS).
  * ------------------------------------------------------------------------- */
 gs_status gs_filter3d_variance(int32_t n_views, const gs_camera* cams, int32_t n,
                                const float* means, float scale, float* variance,

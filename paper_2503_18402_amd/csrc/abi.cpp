@@ -1,6 +1,7 @@
 // C ABI of the rasterizer library: argument checks, view tables, dispatch.
 // Every entry point validates its arguments before enqueuing anything and
 // never throws; kernels are enqueued on the caller's stream only.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -164,11 +165,22 @@ gs_status gs_filter3d_variance(int32_t n_views, const gs_camera* cams, int32_t n
   gs_raster_cfg cfg{};  // the cameras only: any valid tiling
   cfg.tile = 16;
   cfg.lds_batch = 128;
-  Views V;
-  if (!n_ok(n_views, n) || !build_views(n_views, cams, &cfg, &V)) return GS_ERR_ARG;
+  if (n_views < 1 || !cams || n < 0) return GS_ERR_ARG;
   if (!(scale >= 0.0f) || !std::isfinite(scale)) return GS_ERR_ARG;
   if (n > 0 && (!means || !variance || !scratch)) return GS_ERR_ARG;
-  return from_hip(launch_filter3d(V, n, means, scale, variance, scratch, as_stream(stream)));
+  // the views in chunks of at most GS_MAX_VIEWS (one kernel argument each)
+  std::vector<Views> chunks;
+  for (int v0 = 0; v0 < n_views; v0 += GS_MAX_VIEWS) {
+    Views V;
+    if (!build_views(std::min(GS_MAX_VIEWS, n_views - v0), cams + v0, &cfg, &V)) return GS_ERR_ARG;
+    chunks.push_back(V);
+  }
+  hipStream_t st = as_stream(stream);
+  for (size_t k = 0; k < chunks.size(); ++k) {
+    const hipError_t e = launch_filter3d_rate(chunks[k], n, k == 0 ? 1 : 0, means, variance, st);
+    if (e != hipSuccess) return from_hip(e);
+  }
+  return from_hip(launch_filter3d_var(n, scale, variance, scratch, st));
 }
 
 gs_status gs_preprocess(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,

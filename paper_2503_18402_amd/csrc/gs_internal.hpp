@@ -186,8 +186,10 @@ struct ProfScope {
 bool build_views(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg, Views* out);
 
 // kernels' host launchers (one per translation unit)
-hipError_t launch_filter3d(const Views& V, int n, const float* means, float scale,
-                          float* variance, uint32_t* scratch, hipStream_t st);
+hipError_t launch_filter3d_rate(const Views& V, int n, int first, const float* means, float* nu,
+                                hipStream_t st);
+hipError_t launch_filter3d_var(int n, float scale, float* variance, uint32_t* scratch,
+                               hipStream_t st);
 hipError_t launch_preprocess(const Views& V, int n, int sh_degree, const float* means,
                              const float* log_scales, const float* quats,
                              const float* opacity_logits, const float* sh, char* proj,

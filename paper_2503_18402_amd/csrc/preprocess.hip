@@ -220,35 +220,42 @@ __global__ __launch_bounds__(kPreThreads) void k_preprocess(
 
 constexpr int kF3Threads = 256;
 
-// Mip-Splatting's 3D filter: per Gaussian the highest sampling rate fx / z over
-// the views whose image contains its centre; variance scale / nu^2, or -1
-// (unseen) for now.  The block's largest variance goes to *vmax (positive
-// floats order like their bits).
-__global__ __launch_bounds__(kF3Threads) void k_filter3d(Views V, int n,
-                                                         const float* __restrict__ means,
-                                                         float scale, float* __restrict__ var,
-                                                         uint32_t* __restrict__ vmax) {
+// Mip-Splatting's 3D filter, pass 1 (per chunk of views): nu[g] = the highest
+// sampling rate fx / z over the views whose image contains the centre in
+// front of the near plane, folded into the previous chunks' value.
+__global__ __launch_bounds__(kF3Threads) void k_filter3d_rate(Views V, int n, int first,
+                                                              const float* __restrict__ means,
+                                                              float* __restrict__ nu_io) {
+  const int g = blockIdx.x * kF3Threads + threadIdx.x;
+  if (g >= n) return;
+  const float mx = means[3 * g + 0], my = means[3 * g + 1], mz = means[3 * g + 2];
+  float nu = first ? 0.0f : nu_io[g];
+  for (int v = 0; v < V.n_views; ++v) {
+    const DevView& cv = V.v[v];
+    const float z = fmaf(cv.R[6], mx, fmaf(cv.R[7], my, fmaf(cv.R[8], mz, cv.t[2])));
+    if (!(z > cv.near_plane)) continue;
+    const float iz = 1.0f / z;
+    const float xc = fmaf(cv.R[0], mx, fmaf(cv.R[1], my, fmaf(cv.R[2], mz, cv.t[0])));
+    const float yc = fmaf(cv.R[3], mx, fmaf(cv.R[4], my, fmaf(cv.R[5], mz, cv.t[1])));
+    const float u = fmaf(cv.fx * xc, iz, cv.cx), w = fmaf(cv.fy * yc, iz, cv.cy);
+    if (u >= 0.0f && u <= float(cv.W) && w >= 0.0f && w <= float(cv.H)) nu = fmaxf(nu, cv.fx * iz);
+  }
+  nu_io[g] = nu;
+}
+
+// Pass 2: variance scale / nu^2, or -1 (unseen) for now; the block's largest
+// variance goes to *vmax (positive floats order like their bits).
+__global__ __launch_bounds__(kF3Threads) void k_filter3d_var(int n, float scale,
+                                                             float* __restrict__ var,
+                                                             uint32_t* __restrict__ vmax) {
   __shared__ uint32_t s_max[kF3Threads / kWave];
   const int g = blockIdx.x * kF3Threads + threadIdx.x;
   float r = -1.0f;
   if (g < n) {
-    const float mx = means[3 * g + 0], my = means[3 * g + 1], mz = means[3 * g + 2];
-    float nu = 0.0f;
-    for (int v = 0; v < V.n_views; ++v) {
-      const DevView& cv = V.v[v];
-      const float z = fmaf(cv.R[6], mx, fmaf(cv.R[7], my, fmaf(cv.R[8], mz, cv.t[2])));
-      if (!(z > cv.near_plane)) continue;
-      const float iz = 1.0f / z;
-      const float xc = fmaf(cv.R[0], mx, fmaf(cv.R[1], my, fmaf(cv.R[2], mz, cv.t[0])));
-      const float yc = fmaf(cv.R[3], mx, fmaf(cv.R[4], my, fmaf(cv.R[5], mz, cv.t[1])));
-      const float u = fmaf(cv.fx * xc, iz, cv.cx), w = fmaf(cv.fy * yc, iz, cv.cy);
-      if (u >= 0.0f && u <= float(cv.W) && w >= 0.0f && w <= float(cv.H))
-        nu = fmaxf(nu, cv.fx * iz);
-    }
+    const float nu = var[g];
     if (nu > 0.0f) r = scale / (nu * nu);
     var[g] = r;
   }
-  // block max of the seen variances, then one atomic per block
   uint32_t b = r > 0.0f ? __float_as_uint(r) : 0u;
   for (int off = kWave / 2; off > 0; off >>= 1) b = max(b, uint32_t(__shfl_xor(int(b), off)));
   if ((threadIdx.x & (kWave - 1)) == 0) s_max[threadIdx.x / kWave] = b;
@@ -264,6 +271,7 @@ __global__ __launch_bounds__(64) void k_set_u32(uint32_t* p, uint32_t x) {
   if (threadIdx.x == 0) *p = x;
 }
 
+// Pass 3: unseen Gaussians take the largest variance (0 if none was seen).
 __global__ __launch_bounds__(kF3Threads) void k_filter3d_unseen(int n, float* __restrict__ var,
                                                                 const uint32_t* __restrict__ vmax) {
   const int g = blockIdx.x * kF3Threads + threadIdx.x;
@@ -272,12 +280,20 @@ __global__ __launch_bounds__(kF3Threads) void k_filter3d_unseen(int n, float* __
 
 }  // namespace
 
-hipError_t launch_filter3d(const Views& V, int n, const float* means, float scale,
-                          float* variance, uint32_t* scratch, hipStream_t st) {
+hipError_t launch_filter3d_rate(const Views& V, int n, int first, const float* means, float* nu,
+                                hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  GS_LAUNCH("k_filter3d_rate", k_filter3d_rate, dim3(unsigned((n + kF3Threads - 1) / kF3Threads)),
+            dim3(kF3Threads), 0, st, V, n, first, means, nu);
+  return hipGetLastError();
+}
+
+hipError_t launch_filter3d_var(int n, float scale, float* variance, uint32_t* scratch,
+                               hipStream_t st) {
   if (n == 0) return hipSuccess;
   const unsigned nb = unsigned((n + kF3Threads - 1) / kF3Threads);
   GS_LAUNCH("k_set_u32", k_set_u32, dim3(1), dim3(64), 0, st, scratch, 0u);
-  GS_LAUNCH("k_filter3d", k_filter3d, dim3(nb), dim3(kF3Threads), 0, st, V, n, means, scale,
+  GS_LAUNCH("k_filter3d_var", k_filter3d_var, dim3(nb), dim3(kF3Threads), 0, st, n, scale,
             variance, scratch);
   GS_LAUNCH("k_filter3d_unseen", k_filter3d_unseen, dim3(nb), dim3(kF3Threads), 0, st, n,
             variance, scratch);

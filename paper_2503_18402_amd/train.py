@@ -82,11 +82,13 @@ def downsample(gt: torch.Tensor, h: int, w: int) -> torch.Tensor:
     return out
 
 
-def psnr(params: dict, cams, gt: torch.Tensor, sh_degree: int = 3, tile: int = 16) -> float:
+def psnr(params: dict, cams, gt: torch.Tensor, sh_degree: int = 3, tile: int = 16,
+         mip2d: bool = False, filter3d: torch.Tensor | None = None) -> float:
     """Mean PSNR over the views at full resolution (images in [0, 1])."""
     vals = []
     for k, c in enumerate(cams):
-        img = raster.render(params, [c], tile=tile, sh_degree=sh_degree).image
+        img = raster.render(params, [c], tile=tile, sh_degree=sh_degree, mip2d=mip2d,
+                            filter3d=filter3d).image
         mse = torch.mean((img.view_as(gt[k]) - gt[k]) ** 2).item()
         vals.append(-10.0 * math.log10(max(mse, 1e-12)))
     return float(np.mean(vals))
@@ -126,20 +128,26 @@ class Trainer:
     (device [N,3,H,W]) seen from ``cams``.  ``means_lr`` = (initial, final)
     position learning rates; ``r_max`` caps the schedule's downsampling factor
     (0: the smaller image side); ``sparse_adam``: Gaussians the iteration's
-    view does not touch keep their parameters and moments."""
+    view does not touch keep their parameters and moments; ``mip``: the
+    Mip-Splatting backbone's primitives (2D mip filter, and the 3D smoothing
+    filter recomputed from the full-resolution views at the start and after
+    every densification step)."""
 
     def __init__(self, params: dict, cams, gt: torch.Tensor, iters: int, schedule: bool = True,
                  a: float = 4.0, m: int = 4, lrs: dict | None = None,
                  means_lr=(1.6e-4, 1.6e-6), sh_degree: int = 3, seed: int = 0,
                  capacity_margin: float = 2.0, norm: str = "mean",
                  densify: DensifyConfig | None = None, r_max: float = 0.0,
-                 sparse_adam: bool = False):
+                 sparse_adam: bool = False, mip: bool = False, filter3d_scale: float = 0.2):
         self.params, self.cams, self.gt, self.iters = params, list(cams), gt, iters
         self.sh_degree = sh_degree
         self.lrs = dict(DEFAULT_LRS if lrs is None else lrs)
         self.means_lr = means_lr
         self.capacity_margin = capacity_margin
         self.sparse_adam = sparse_adam
+        self.mip, self.filter3d_scale = mip, filter3d_scale
+        self.filter3d = None
+        self._f3_scratch = torch.zeros(1, dtype=torch.int32, device=params["means"].device)
         self.sched = (ResolutionSchedule(gt, iters, a=a, m=m, r_max=r_max, norm=norm)
                       if schedule else None)
         self.factors = np.array([self.sched.factor(k) if schedule else 1 for k in range(iters)])
@@ -169,6 +177,9 @@ class Trainer:
         current Gaussians, sharing the optimiser state."""
         n = self.params["means"].shape[0]
         dev = self.params["means"].device
+        if self.mip:
+            self.filter3d = torch.empty(n, device=dev)
+            self.update_filter3d()
         self.mean2d = torch.zeros(n, device=dev)
         self.accum = torch.zeros(n, device=dev)
         self.count = torch.zeros(n, device=dev)
@@ -180,17 +191,26 @@ class Trainer:
             tile = 8 if f >= 2 else 16  # few tiles at low resolution: split them finer
             cap = 0
             for vi in probe_views:
-                probe = raster.render(self.params, [views[vi]], tile=tile, sh_degree=self.sh_degree)
+                probe = raster.render(self.params, [views[vi]], tile=tile, sh_degree=self.sh_degree,
+                                      mip2d=self.mip, filter3d=self.filter3d)
                 cap = max(cap, int(probe.n_pairs_dev.item()))
                 del probe
             pipe = raster.Pipeline(self.params, [views[0]], gt_f[0].reshape(-1), tile=tile,
                                    lds_batch=128, sh_degree=self.sh_degree,
                                    capacity=int(cap * self.capacity_margin) + 4096, lrs=self.lrs,
                                    share=first, state=(self.m, self.v, self.step_dev),
-                                   mean2d_abs=self.mean2d, sparse_adam=self.sparse_adam)
+                                   mean2d_abs=self.mean2d, sparse_adam=self.sparse_adam,
+                                   mip2d=self.mip, filter3d=self.filter3d)
             pipe.pairs_max = torch.zeros(1, dtype=torch.int64, device=dev)
             first = first or pipe
             self.levels[f] = (views, gt_f, pipe)
+
+    def update_filter3d(self):
+        """Recompute the 3D smoothing filter (in place) from the current means
+        and the full-resolution views."""
+        gsmi.gs_filter3d_variance(gsmi.make_cameras(self.cams), self.params["means"].shape[0],
+                                  self.params["means"], self.filter3d_scale, self.filter3d,
+                                  self._f3_scratch)
 
     def _check_capacity(self):
         for _, _, pipe in self.levels.values():
@@ -264,6 +284,8 @@ class Trainer:
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         self._check_capacity()
+        if self.mip:
+            self.update_filter3d()   # for rendering the trained model
         return dict(seconds=wall, s_per_iter=wall / max(1, self.iters),
                     iters_per_factor={int(f): int((self.factors == f).sum())
                                       for f in sorted(set(self.factors.tolist()))},

@@ -86,12 +86,14 @@ def test_filtered_batch_matches_oracle_sum():
         U.check_grads(g[name], ref[name], bnd[name], mask=~skip)
 
 
-def test_filter3d_variance_matches_oracle():
+@pytest.mark.parametrize("n_views", [6, 40])
+def test_filter3d_variance_matches_oracle(n_views):
+    """40 views take two launches (32 + 8): the rate folds across them."""
     sc, _ = scenes.config0()
     # two points far above and below the orbit plane: no view sees them
     means = np.concatenate([sc["means"], np.array([[0.0, 30.0, 0.0], [0.0, -30.0, 0.0]],
                                                   np.float32)])
-    cams = scenes.orbit_cameras(6, 3.0, 128, 96, 120.0)
+    cams = scenes.orbit_cameras(n_views, 3.0, 128, 96, 120.0)
     ref, flag = project.filter3d_variance(means.astype(np.float64), cams, scale=0.2)
     m = torch.from_numpy(means).cuda()
     out = torch.full((means.shape[0],), -7.0, device="cuda")
