@@ -50,7 +50,8 @@ struct Items {  // the (view, Gaussian) items of a preprocess output
 
 constexpr int kXT = 256;        // threads per expansion block
 constexpr int kAggBins = 2048;  // most tiles a block aggregates in LDS
-constexpr int kAggRounds = 8;   // items per aggregating block: kXT * kAggRounds
+constexpr int kAggRounds = 8;   // items per aggregating block: at most kXT * kAggRounds
+constexpr int kAggBlocks = 512; // but no fewer blocks than this while items allow
 
 // Calls f(global tile id, sort key) once for every pair of the items
 // [first, first + kXT).  Every thread of the block must call it.
@@ -534,9 +535,15 @@ hipError_t launch_bin_sort(const Views& V, int n, const char* proj, int64_t cap,
   S.tile = V.tile;
   const int T = V.total_tiles;
   const int64_t nr = 2 * int64_t(T);
-  // LDS aggregation pays where views have few tiles; blocks then take more items
+  // LDS aggregation pays where views have few tiles; blocks then take more
+  // items (fewer global atomics), as long as the grid still fills the chip:
+  // a small scene keeps one round per block
   const bool any_agg = min_view_tiles <= kAggBins;
-  const int rounds = any_agg ? kAggRounds : 1;
+  int rounds = 1;
+  if (any_agg) {
+    const int64_t want = (S.m + int64_t(kXT) * kAggBlocks - 1) / (int64_t(kXT) * kAggBlocks);
+    rounds = int(std::min<int64_t>(std::max<int64_t>(want, 1), kAggRounds));
+  }
   const size_t agg_lds = any_agg ? sizeof(uint32_t) * kAggBins : 0;
   const int agg_bins = any_agg ? kAggBins : 0;
   const unsigned xb = unsigned((S.m + int64_t(kXT) * rounds - 1) / (int64_t(kXT) * rounds));

@@ -188,7 +188,7 @@ class Trainer:
         probe_views = np.linspace(0, len(self.cams) - 1, min(4, len(self.cams))).astype(int)
         for f in sorted(set(self.factors[k0:].tolist()), reverse=True):
             views, gt_f = self.gt_levels[f]
-            tile = 8 if f >= 2 else 16  # few tiles at low resolution: split them finer
+            tile = self.tile_for(f)
             cap = 0
             for vi in probe_views:
                 probe = raster.render(self.params, [views[vi]], tile=tile, sh_degree=self.sh_degree,
@@ -204,6 +204,12 @@ class Trainer:
             pipe.pairs_max = torch.zeros(1, dtype=torch.int64, device=dev)
             first = first or pipe
             self.levels[f] = (views, gt_f, pipe)
+
+    @staticmethod
+    def tile_for(f: int) -> int:
+        """Tile size at downsampling factor f: 8 below full resolution (few
+        tiles: split them finer), 16 at full resolution."""
+        return 8 if f >= 2 else 16
 
     def update_filter3d(self):
         """Recompute the 3D smoothing filter (in place) from the current means
