@@ -83,14 +83,32 @@ __global__ __launch_bounds__(64) void k_step_inc(int32_t* step_dev) {
   if (threadIdx.x == 0) *step_dev += 1;
 }
 
-__global__ __launch_bounds__(256) void k_l1(int64_t n, const float* __restrict__ img,
+__device__ __forceinline__ float l1_sign(float d, float scale) {
+  return (d > 0.0f) ? scale : ((d < 0.0f) ? -scale : 0.0f);
+}
+
+// dL = scale * sign(img - tgt); with `vec` (16-byte aligned arrays) four values
+// per load, the tail of fewer than four one by one.
+__global__ __launch_bounds__(256) void k_l1(int64_t n, int vec, const float* __restrict__ img,
                                             const float* __restrict__ tgt, float scale,
                                             float* __restrict__ dL, float* __restrict__ loss) {
   float acc = 0.0f;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * blockDim.x) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  const int64_t t0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t n4 = vec ? n >> 2 : 0;
+  const float4* __restrict__ I4 = reinterpret_cast<const float4*>(img);
+  const float4* __restrict__ T4 = reinterpret_cast<const float4*>(tgt);
+  float4* __restrict__ D4 = reinterpret_cast<float4*>(dL);
+  for (int64_t i = t0; i < n4; i += stride) {
+    const float4 a = I4[i], b = T4[i];
+    const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z, dw = a.w - b.w;
+    D4[i] = make_float4(l1_sign(dx, scale), l1_sign(dy, scale), l1_sign(dz, scale),
+                        l1_sign(dw, scale));
+    acc += (fabsf(dx) + fabsf(dy)) + (fabsf(dz) + fabsf(dw));
+  }
+  for (int64_t i = 4 * n4 + t0; i < n; i += stride) {
     const float d = img[i] - tgt[i];
-    dL[i] = (d > 0.0f) ? scale : ((d < 0.0f) ? -scale : 0.0f);
+    dL[i] = l1_sign(d, scale);
     acc += fabsf(d);
   }
   if (loss) {
@@ -143,10 +161,12 @@ hipError_t launch_adam(const gs_adam_group* groups, int n_groups, int step, floa
 hipError_t launch_l1(int64_t numel, const float* image, const float* target, float scale,
                      float* dL, float* loss_sum, hipStream_t st) {
   if (numel == 0) return hipSuccess;
-  int64_t blocks = (numel + 255) / 256;
+  const int vec = ((reinterpret_cast<uintptr_t>(image) | reinterpret_cast<uintptr_t>(target) |
+                    reinterpret_cast<uintptr_t>(dL)) & 15u) == 0 ? 1 : 0;
+  int64_t blocks = ((vec ? (numel + 3) / 4 : numel) + 255) / 256;
   if (blocks > 1024) blocks = 1024;  // few blocks: one atomic each for the loss sum
-  GS_LAUNCH("k_l1", k_l1, dim3(unsigned(blocks)), dim3(256), 0, st, numel, image, target, scale,
-                     dL, loss_sum);
+  GS_LAUNCH("k_l1", k_l1, dim3(unsigned(blocks)), dim3(256), 0, st, numel, vec, image, target,
+            scale, dL, loss_sum);
   return hipGetLastError();
 }
 

@@ -252,6 +252,7 @@ class Pipeline:
         self.mean2d_abs = mean2d_abs
         self.fused = fused
         self.sparse_adam = sparse_adam
+        self.track_loss = True   # False: the fused step skips the loss value (gradient only)
         self.graph = None
 
     def forward(self, stream=None):
@@ -295,9 +296,10 @@ class Pipeline:
         """L1 loss gradient, then the backward pass fused with the Adam step
         (device step counter)."""
         p = self.params
-        self.loss.zero_()
+        if self.track_loss:
+            self.loss.zero_()
         gsmi.gs_l1_loss_grad(self.image, self.targets, 1.0 / self.image.numel(), self.dL,
-                             self.loss, stream)
+                             self.loss if self.track_loss else None, stream)
         gsmi.gs_render_bwd_adam(
             self.cams_c, self.cfg, self.n, p["means"], p["log_scales"], p["quats"],
             p["opacity_logits"], p["sh"], self.sh_degree, self.proj, self.ranges, self.vals,

@@ -202,6 +202,7 @@ class Trainer:
                                    mean2d_abs=self.mean2d, sparse_adam=self.sparse_adam,
                                    mip2d=self.mip, filter3d=self.filter3d)
             pipe.pairs_max = torch.zeros(1, dtype=torch.int64, device=dev)
+            pipe.track_loss = False   # the loop needs the gradient, not the loss value
             first = first or pipe
             self.levels[f] = (views, gt_f, pipe)
 
