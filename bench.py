@@ -44,8 +44,8 @@ BWD_FLOP_PER_EVAL = 13 + 3 + 1 + 5 + 3 + 2 + 6 + 2 + 3 + 6 + 10
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--lds-batch", type=int, default=128)
     ap.add_argument("--n", type=int, default=1_000_000)
@@ -118,10 +118,12 @@ def main():
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     fwd_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(steps)]
+    step_ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     ev0.record(stream)
     t0 = time.perf_counter()
     for k in range(steps):
+        step_ev[k].record(stream)
         p = pipe.params
         gsmi.gs_preprocess(pipe.cams_c, pipe.cfg, pipe.n, p["means"], p["log_scales"], p["quats"],
                            p["opacity_logits"], p["sh"], pipe.sh_degree, pipe.proj)
@@ -132,10 +134,15 @@ def main():
                            pipe.image, pipe.final_T, pipe.last)
         fwd_ev[k][1].record(stream)
         pipe.backward_adam()
+    step_ev[steps].record(stream)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1) / steps
+    per_step = np.array([step_ev[k].elapsed_time(step_ev[k + 1]) for k in range(steps)])
+    step_stats = dict(median=round(float(np.median(per_step)), 4),
+                      p10=round(float(np.percentile(per_step, 10)), 4),
+                      p90=round(float(np.percentile(per_step, 90)), 4))
     assert not pipe.overflowed(), "pair capacity overflowed during timing"
     fwd_ms = float(np.mean([a.elapsed_time(b) for a, b in fwd_ev]))
     n_pairs = int(pipe.n_pairs.item())
@@ -234,6 +241,7 @@ def main():
         "steps": steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms, 4),
+        "ms_per_step_stats": step_stats,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -415,9 +423,11 @@ def scheduled_training(torch, raster, scenes, dev, iters):
     backward fused with Adam.  Loops from the same 50k-Gaussian start: the
     full method (Eq. 7 resolution schedule, Eq. 4/5 primitive schedule with
     top-k densification), the resolution schedule alone (every candidate
-    densified) and the backbone (full resolution, every candidate); then the
-    full method and the backbone again on Mip-Splatting's primitives (2D mip
-    filter, 3D filter recomputed after every densification step).
+    densified) and the backbone (full resolution, every candidate); the full
+    method with a fixed budget P_fin = 300k (momentum off, the Revising-3DGS
+    setting); then the full method and the backbone again on Mip-Splatting's
+    primitives (2D mip filter, 3D filter recomputed after every densification
+    step).
     Densification every 100 iterations over the first half; the gradient
     threshold is set for the synthetic scene (its gradients sit an order of
     magnitude below a photograph's) so that the backbone grows to about 300k.
@@ -436,14 +446,16 @@ def scheduled_training(torch, raster, scenes, dev, iters):
     init = scenes.make_scene(n_init, seed=6, mean_range=4.0, ls_mu=-4.0, ls_sigma=0.5)
     extent = 6.0 * 1.1   # camera sphere radius with the backbone's 10% margin
     out = {}
-    for name, sched, top_k, mip in (("dashgaussian", True, True, False),
-                                    ("resolution_only", True, False, False),
-                                    ("backbone", False, False, False),
-                                    ("mip_dashgaussian", True, True, True),
-                                    ("mip_backbone", False, False, True)):
+    for name, sched, top_k, mip, budget in (("dashgaussian", True, True, False, None),
+                                            ("dashgaussian_fixed_budget", True, True, False, 300_000),
+                                            ("resolution_only", True, False, False, None),
+                                            ("backbone", False, False, False, None),
+                                            ("mip_dashgaussian", True, True, True, None),
+                                            ("mip_backbone", False, False, True, None)):
         params = raster.to_device(init, dev)
         dcfg = train.DensifyConfig(every=100, start=100, stop=iters // 2, extent=extent,
-                                   schedule=top_k, grad_thr=grad_thr)
+                                   schedule=top_k, grad_thr=grad_thr, momentum=budget is None,
+                                   p_fin=budget)
         tr = train.Trainer(params, cams, gt, iters, schedule=sched, densify=dcfg, r_max=r_max,
                            means_lr=(1.6e-4 * extent, 1.6e-6 * extent), mip=mip)
         psnr0 = train.psnr(tr.params, cams, gt, mip2d=mip, filter3d=tr.filter3d)
@@ -464,7 +476,7 @@ def scheduled_training(torch, raster, scenes, dev, iters):
             f"({res['densify_seconds']:.2f} s densifying), {res['n_gaussians']} Gaussians, "
             f"PSNR {psnr0:.2f} -> {psnr1:.2f} dB")
         del tr, params
-    for name in ("dashgaussian", "resolution_only"):
+    for name in ("dashgaussian", "dashgaussian_fixed_budget", "resolution_only"):
         out[name]["speedup_vs_backbone"] = round(out["backbone"]["seconds"] / out[name]["seconds"], 3)
     out["mip_dashgaussian"]["speedup_vs_backbone"] = round(
         out["mip_backbone"]["seconds"] / out["mip_dashgaussian"]["seconds"], 3)
