@@ -94,6 +94,8 @@ def psnr(params: dict, cams, gt: torch.Tensor, sh_degree: int = 3, tile: int = 1
     return float(np.mean(vals))
 
 
+P_FIN_INIT_FACTOR = 5.0   # Sec. 4.3: the budget of Eq. 5 starts at 5 P_init
+
 DEFAULT_LRS = dict(means=1.6e-4, log_scales=5e-3, quats=1e-3, opacity_logits=5e-2, sh=2.5e-3,
                    sh_rest=2.5e-3 / 20.0)
 
@@ -159,7 +161,8 @@ class Trainer:
         dev = params["means"].device
         self.p_init = float(params["means"].shape[0])
         if densify is not None:
-            self.p_fin = float(densify.p_fin) if densify.p_fin is not None else 5.0 * self.p_init
+            self.p_fin = (float(densify.p_fin) if densify.p_fin is not None
+                          else P_FIN_INIT_FACTOR * self.p_init)
             self.zgen = torch.Generator(device=dev).manual_seed(densify.seed)
         self.log = []
         self.step_dev = torch.zeros(1, dtype=torch.int32, device=dev)
