@@ -30,9 +30,11 @@ def densify_step(params: dict, m: dict, v: dict, accum: torch.Tensor, count: tor
                               device=dev) for name in PARAM_NAMES}
     newm = {name: torch.empty_like(newp[name]) for name in PARAM_NAMES}
     newv = {name: torch.empty_like(newp[name]) for name in PARAM_NAMES}
+    info = dict(n=n, n_pruned=n_pruned, n_candidates=n_cand, k=k, n_new=n_new)
+    if n_new == 0:  # everything pruned (or nothing given): no rows to write
+        return newp, newm, newv, info
     gsmi.gs_densify_apply(n, [params[k_] for k_ in PARAM_NAMES], [m[k_] for k_ in PARAM_NAMES],
                           [v[k_] for k_ in PARAM_NAMES], z, ws,
                           [newp[k_] for k_ in PARAM_NAMES], [newm[k_] for k_ in PARAM_NAMES],
                           [newv[k_] for k_ in PARAM_NAMES], stream)
-    info = dict(n=n, n_pruned=n_pruned, n_candidates=n_cand, k=k, n_new=n_new)
     return newp, newm, newv, info
