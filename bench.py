@@ -37,8 +37,9 @@ FWD_FLOP_PER_EVAL = 2 + 8 + 1 + 1 + 1 + 2 + 2 + 1 + 6
 # and in the backward: alpha again (13), T recovery 1-a, 1/x, T*inv (3), weight (1),
 # c.dL/dC (5), dL/dalpha (3), colour-behind update (2), colour grads (6), opacity
 # grad (2), dL/dpower and its products with the offsets (3), conic grads (6),
-# mean grads (10)
-BWD_FLOP_PER_EVAL = 13 + 3 + 1 + 5 + 3 + 2 + 6 + 2 + 3 + 6 + 10
+# the two offset sums whose product with the conic is the mean gradient (2; the
+# product itself is per Gaussian, not per evaluation)
+BWD_FLOP_PER_EVAL = 13 + 3 + 1 + 5 + 3 + 2 + 6 + 2 + 3 + 6 + 2
 
 
 def parse():

@@ -3,9 +3,10 @@
 // k_blend_bwd: one workgroup per tile replays the tile's list back to front
 // in LDS-staged batches.  Each pixel starts at its own last contributor with
 // T = final_T and recovers T_i = T_{i+1} / (1 - alpha_i); the colour behind a
-// Gaussian is carried as its dot product with dL/dC.  Per (tile, Gaussian) the
-// nine 2D gradients (mean2D x/y, conic a/b/c, opacity, rgb) are summed over
-// the tile's pixels in a fixed order (wave butterfly, then waves in order)
+// Gaussian is carried as its dot product with dL/dC.  Per (tile, Gaussian) nine
+// 2D terms (the two offset sums sum dL/dpower * (dx, dy), whose product with
+// the conic is the mean2D gradient, then conic a/b/c, opacity, rgb) are summed
+// over the tile's pixels in a fixed order (wave butterfly, then waves in order)
 // and written to that pair's own slot: the pair slots of a Gaussian are
 // contiguous (ordered by Gaussian index, then by tile inside its footprint),
 // so no float atomics are needed and gradients are bit-reproducible.
@@ -21,7 +22,6 @@ namespace gsk {
 namespace {
 
 constexpr int kG = 9;  // 2D gradient components per (tile, Gaussian)
-constexpr float kLn2 = 0.69314718055994530942f;
 
 // ---- wave-wide sums of the nine gradient components, registers only.
 // Halving transposes: a 32-lane swap (v_permlane32_swap) pairs each value with
@@ -160,7 +160,6 @@ __device__ __forceinline__ void bwd_step(BwdPix<TILE>& P, const BwdStage& S, int
   const float4 r1 = S.r1[k];
   const float cb = S.b[k];
   const float o = r1.y;
-  const float A2 = 2.0f * r0.z, C2 = 2.0f * r1.x;
   float acc[kG];
 #pragma unroll
   for (int c = 0; c < kG; ++c) acc[c] = 0.0f;
@@ -192,9 +191,10 @@ __device__ __forceinline__ void bwd_step(BwdPix<TILE>& P, const BwdStage& S, int
       acc[2] = fmaf(dpx, e.dx, acc[2]);
       acc[3] = fmaf(dpx, e.dy, acc[3]);
       acc[4] = fmaf(dpy, e.dy, acc[4]);
-      // (2A dx + B dy), (B dx + 2C dy): derivative of p2 w.r.t. -mean2D
-      acc[0] = fmaf(dpow, fmaf(A2, e.dx, r0.w * e.dy), acc[0]);
-      acc[1] = fmaf(dpow, fmaf(r0.w, e.dx, C2 * e.dy), acc[1]);
+      // the offsets weighted by dpow; the mean gradient is these two sums
+      // times the Gaussian's conic, applied once in the chain rule
+      acc[0] += dpx;
+      acc[1] += dpy;
     }
   }
   if (hit) {  // wave-uniform
@@ -202,11 +202,12 @@ __device__ __forceinline__ void bwd_step(BwdPix<TILE>& P, const BwdStage& S, int
     wave_sum9(acc, qv);
     const uint32_t idx = S.pidx[k];
     if ((lane & 15) == 15 && int64_t(idx) < cap) {
-      // natural-unit conic and mean gradients from the base-2 accumulators
-      // scales of components (0..3) and (4..7): -ln2, -ln2, -1/2, -1 and -1/2, 1, 1, 1
+      // natural-unit conic gradients from the base-2 accumulators; the offset
+      // sums (0, 1) are stored as they are
+      // scales of components (0..3) and (4..7): 1, 1, -1/2, -1 and -1/2, 1, 1, 1
       const int row = lane >> 4;
       const int c0 = ((row & 1) << 1) | (row >> 1);  // 0, 2, 1, 3
-      const float s0 = c0 < 2 ? -kLn2 : (c0 == 2 ? -0.5f : -1.0f);
+      const float s0 = c0 < 2 ? 1.0f : (c0 == 2 ? -0.5f : -1.0f);
       const float s1 = c0 == 0 ? -0.5f : 1.0f;
       float* dst = pair_grad + size_t(idx) * kG;
       dst[c0] = s0 * qv[0];
@@ -699,7 +700,10 @@ __device__ __forceinline__ bool chain_grad(const Views& V, const ChainIn& I, int
     const float dJ02 = dT[0] * cv.R[6] + dT[1] * cv.R[7] + dT[2] * cv.R[8];
     const float dJ11 = dT[3] * cv.R[3] + dT[4] * cv.R[4] + dT[5] * cv.R[5];
     const float dJ12 = dT[3] * cv.R[6] + dT[4] * cv.R[7] + dT[5] * cv.R[8];
-    const float gmx = gr[0], gmy = gr[1];
+    // dL/dmean2D = Q (sum dpow dx, sum dpow dy) with Q the conic (a, b; b, c):
+    // d p2 / d mean = -(2A dx + B dy, B dx + 2C dy) in base 2, and -ln2 (2A, B, 2C)
+    // = (a, b, c)
+    const float gmx = ca * gr[0] + cb * gr[1], gmy = cb * gr[0] + cc * gr[1];
     const float iz3 = iz2 * iz;
     const float gxc = gmx * cv.fx * iz - dJ02 * cv.fx * iz2;
     const float gyc = gmy * cv.fy * iz - dJ12 * cv.fy * iz2;
