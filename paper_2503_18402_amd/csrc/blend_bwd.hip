@@ -179,7 +179,7 @@ __device__ __forceinline__ void bwd_step(BwdPix<TILE>& P, const BwdStage& S, int
       const float Ti = P.T[q] * inv;
       const float wgt = ok ? e.a * Ti : 0.0f;
       const float cg = fmaf(r1.z, P.g0[q], fmaf(r1.w, P.g1[q], cb * P.g2[q]));
-      const float dLda = grad ? Ti * cg - P.SdL[q] * inv : 0.0f;
+      const float dLda = grad ? fmaf(P.T[q], cg, -P.SdL[q]) * inv : 0.0f;  // (T cg - SdL) / (1 - a)
       P.SdL[q] = fmaf(wgt, cg, P.SdL[q]);
       P.T[q] = ok ? Ti : P.T[q];
       acc[6] = fmaf(wgt, P.g0[q], acc[6]);

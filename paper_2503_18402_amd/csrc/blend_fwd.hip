@@ -105,10 +105,11 @@ __global__ __launch_bounds__(WaveShape<TILE>::kThreads) void k_blend_fwd(
         const Alpha e = alpha_at(r0, r1.x, r1.y, pxc[p], pyc[p]);
         const bool ok = e.ok & !done[p];
         if (__ballot(ok) == 0ull) continue;  // no pixel of this lane slot is reached
-        const float Tn = T[p] * (1.0f - e.a);
+        const float aT = e.a * T[p];
+        const float Tn = T[p] - aT;  // T (1 - alpha), reusing the weight's product
         const bool stop = ok & (Tn < kTMin);
         const bool blend = ok & !stop;
-        const float wgt = blend ? e.a * T[p] : 0.0f;
+        const float wgt = blend ? aT : 0.0f;
         C0[p] = fmaf(wgt, r1.z, C0[p]);
         C1[p] = fmaf(wgt, r1.w, C1[p]);
         C2[p] = fmaf(wgt, cb, C2[p]);
@@ -314,10 +315,11 @@ __global__ __launch_bounds__(64 * kFWaves) void k_blend_fwd_long(
             const Alpha e = alpha_at(r0, r1.x, r1.y, px0 + float((q % GX) * 8),
                                      py0 + float((q / GX) * 8));
             const bool ok = e.ok & !done[q];
-            const float Tn = T[q] * (1.0f - e.a);
+            const float aT = e.a * T[q];
+            const float Tn = T[q] - aT;
             const bool stop = ok & (Tn < kTMin);
             const bool blend = ok & !stop;
-            const float wgt = blend ? e.a * T[q] : 0.0f;
+            const float wgt = blend ? aT : 0.0f;
             C0[q] = fmaf(wgt, r1.z, C0[q]);
             C1[q] = fmaf(wgt, r1.w, C1[q]);
             C2[q] = fmaf(wgt, cb, C2[q]);
