@@ -99,8 +99,8 @@ def main():
 
     # ---------------------------------------------------------------- inputs
     log("generating the 1M-Gaussian scene and target")
-    scene, cam = scenes.config1(level=1, n=args.n)
-    tscene = scenes.config1_target_scene(n=args.n)
+    scene, cam = scenes.paper_scale_scene(level=1, n=args.n)
+    tscene = scenes.paper_scale_target_scene(n=args.n)
     params = raster.to_device(scene, dev)
     tparams = raster.to_device(tscene, dev)
     target = raster.render(tparams, [cam], tile=args.tile).image.clone()
@@ -300,7 +300,7 @@ def level_sweep(torch, raster, scenes, params, tparams_scene, tile, lds):
     out = {}
     tparams = raster.to_device(tparams_scene, params["means"].device)
     for r in (8, 4, 2, 1):
-        _, cam = scenes.config1(level=r, n=1)  # camera only
+        _, cam = scenes.paper_scale_scene(level=r, n=1)  # camera only
         tgt = raster.render(tparams, [cam], tile=tile).image.clone()
         p = {k: v.clone() for k, v in params.items()}
         pick = autotune.tune(p, [cam], tgt, reps=3)
@@ -333,23 +333,23 @@ def batched_vs_plain(torch, raster, scenes, params, tscene):
     per-view calls accumulating into one gradient buffer, then the same Adam.
     Both forms use autotuned tile / LDS batch (per mix, per resolution) and are
     captured as HIP graphs; eager times are reported too."""
-    cams = scenes.config3_views()
+    cams = scenes.mixed_resolution_views()
     tparams = raster.to_device(tscene, params["means"].device)
     tgts = [raster.render(tparams, [c]).image.clone() for c in cams]
     del tparams
-    return compare_forms(torch, raster, params, cams, tgts, "16 views (config 3)")
+    return compare_forms(torch, raster, params, cams, tgts, "16 mixed-resolution views")
 
 
 def large_scene(torch, raster, scenes, dev):
     """The large workload: 4M Gaussians, 8 views at 1920x1080 and 8 at 960x540,
     gradients of all 16 views accumulated into one Adam step over 236M floats;
     seeded uniform random targets."""
-    scene, cams = scenes.config4()
+    scene, cams = scenes.large_scene_views()
     params = raster.to_device(scene, dev)
     del scene
     gen = torch.Generator(device=dev).manual_seed(2)
     tgts = [torch.rand(3 * c.width * c.height, generator=gen, device=dev) for c in cams]
-    out = compare_forms(torch, raster, params, cams, tgts, "16 views, 4M Gaussians (config 4)")
+    out = compare_forms(torch, raster, params, cams, tgts, "16 views, 4M Gaussians")
     out["n_gaussians"] = int(params["means"].shape[0])
     return out
 
@@ -438,7 +438,7 @@ def scheduled_training(torch, raster, scenes, dev, iters):
     and the mean full-resolution PSNR over the views."""
     from paper_2503_18402_amd import train
 
-    hidden, cams = scenes.config2_hidden()
+    hidden, cams = scenes.hidden_scene()
     hp = raster.to_device(hidden, dev)
     gt = torch.stack([raster.render(hp, [c]).image.view(3, c.height, c.width).clone()
                       for c in cams])

@@ -27,8 +27,8 @@ import numpy as np
 
 __all__ = [
     "Camera", "make_scene", "look_at", "orbit_cameras", "fibonacci_cameras",
-    "downscale", "config0", "config1", "config2_hidden", "config3_views",
-    "config4", "random_upstream", "uniform_target", "subset",
+    "downscale", "small_scene", "paper_scale_scene", "hidden_scene", "mixed_resolution_views",
+    "large_scene_views", "random_upstream", "uniform_target", "subset",
 ]
 
 
@@ -140,14 +140,14 @@ def downscale(cam: Camera, r: int) -> Camera:
 
 # ---------------------------------------------------------------- workloads
 
-def config0():
+def small_scene():
     """Small single view: 4096 Gaussians in [-1,1]^3, 128x96, fx=fy=120, camera at (0,0,-3)."""
     scene = make_scene(4096, seed=0, mean_range=1.0, ls_mu=-3.5, ls_sigma=0.3)
     cam = look_at((0.0, 0.0, -3.0), (0.0, 0.0, 0.0), 128, 96, 120.0)
     return scene, cam
 
 
-def config1(level: int = 1, n: int = 1_000_000, view: int = 0):
+def paper_scale_scene(level: int = 1, n: int = 1_000_000, view: int = 0):
     """Paper-scale single view: 1M Gaussians in [-4,4]^3, log-scales N(-4.5,0.5),
     1600x1064, fx=fy=1400, orbit radius 6; ``level`` is the downscale factor (8/4/2/1)."""
     scene = make_scene(n, seed=0, mean_range=4.0, ls_mu=-4.5, ls_sigma=0.5)
@@ -155,11 +155,11 @@ def config1(level: int = 1, n: int = 1_000_000, view: int = 0):
     return scene, downscale(cam, level)
 
 
-def config1_target_scene(n: int = 1_000_000):
+def paper_scale_target_scene(n: int = 1_000_000):
     return make_scene(n, seed=1, mean_range=4.0, ls_mu=-4.5, ls_sigma=0.5)
 
 
-def config2_hidden(n: int = 500_000, n_views: int = 64):
+def hidden_scene(n: int = 500_000, n_views: int = 64):
     """Hidden scene for the optimisation loop: 500k Gaussians drawn as the
     paper-scale scene, 64 views on a Fibonacci sphere of radius 6 at 1200x800."""
     scene = make_scene(n, seed=5, mean_range=4.0, ls_mu=-4.5, ls_sigma=0.5)
@@ -167,7 +167,7 @@ def config2_hidden(n: int = 500_000, n_views: int = 64):
     return scene, cams
 
 
-def config3_views():
+def mixed_resolution_views():
     """16 views of the paper-scale scene: 4 each at 200x133, 400x266, 800x532, 1600x1064."""
     base = orbit_cameras(16, 6.0, 1600, 1064, 1400.0)
     cams = []
@@ -176,7 +176,7 @@ def config3_views():
     return cams
 
 
-def config4(n: int = 4_000_000):
+def large_scene_views(n: int = 4_000_000):
     """Large scene: 4M Gaussians in [-20,20]^3, log-scales N(-4,0.6); 8 views at
     1920x1080 (fx=1680) and 8 at 960x540 (fx=840) on an orbit of radius 30."""
     scene = make_scene(n, seed=4, mean_range=20.0, ls_mu=-4.0, ls_sigma=0.6)

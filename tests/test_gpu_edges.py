@@ -29,7 +29,7 @@ def _reach_flagged(P, F):
 
 @pytest.mark.parametrize("tile", [8, 16])
 def test_tiny_and_ragged_views_match_oracle(tile):
-    sc, _ = scenes.config0()
+    sc, _ = scenes.small_scene()
     sc = scenes.subset(sc, slice(0, 1500))
     sizes = [(1, 1), (7, 3), (17, 9), (128, 96)]
     cams = [scenes.look_at((0.3 * k, -0.2, -3.0), (0, 0, 0), w, h, 120.0 * w / 128.0)
@@ -56,7 +56,7 @@ def test_tiny_and_ragged_views_match_oracle(tile):
 
 
 def test_largest_batch_equals_plain_views():
-    sc, _ = scenes.config0()
+    sc, _ = scenes.small_scene()
     sc = scenes.subset(sc, slice(0, 2000))
     cams = scenes.orbit_cameras(gsmi.GS_MAX_VIEWS, 3.0, 64, 48, 60.0)
     ups = [scenes.random_upstream(c, seed=100 + k) for k, c in enumerate(cams)]

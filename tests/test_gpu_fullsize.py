@@ -28,7 +28,7 @@ TILE, BATCH = 16, 128
 
 @pytest.fixture(scope="module")
 def scene1m():
-    sc, _ = scenes.config1(level=1)
+    sc, _ = scenes.paper_scale_scene(level=1)
     return sc
 
 
@@ -45,7 +45,7 @@ def _sample_pixels(cam, n_rand, seed):
 
 @pytest.mark.parametrize("level", [1, 8])
 def test_forward_sampled_pixels(scene1m, level):
-    _, cam = scenes.config1(level=level, n=1)
+    _, cam = scenes.paper_scale_scene(level=level, n=1)
     params = raster.to_device(scene1m, "cuda")
     frame = raster.render(params, [cam], tile=TILE, lds_batch=BATCH)
     torch.cuda.synchronize()
@@ -69,7 +69,7 @@ def test_forward_sampled_pixels(scene1m, level):
 
 
 def test_backward_sparse_upstream(scene1m):
-    _, cam = scenes.config1(level=1, n=1)
+    _, cam = scenes.paper_scale_scene(level=1, n=1)
     pix = _sample_pixels(cam, 20, seed=11)
     rng = np.random.default_rng(12)
     w = np.zeros((3, cam.height * cam.width), np.float32)
@@ -95,8 +95,8 @@ def test_backward_sparse_upstream(scene1m):
         assert not g[name][~touched & ~skip].any()
 
 
-def test_batched_config3_equals_plain_and_oracle(scene1m):
-    cams = scenes.config3_views()
+def test_batched_mixed_views_equal_plain_and_oracle(scene1m):
+    cams = scenes.mixed_resolution_views()
     params = raster.to_device(scene1m, "cuda")
     fb = raster.render(params, cams, tile=TILE, lds_batch=BATCH)
     imgs = fb.images()
@@ -146,7 +146,7 @@ def test_large_scene_batched_sampled_pixels():
     """The 4M-Gaussian workload: all 16 views (8 at 1920x1080, 8 at 960x540) in
     one batched launch, in the bench's launch configuration; sampled pixels of
     one view of each resolution (plus the ragged edges) against the oracle."""
-    sc, cams = scenes.config4()
+    sc, cams = scenes.large_scene_views()
     params = raster.to_device(sc, "cuda")
     fb = raster.render(params, cams, tile=TILE, lds_batch=BATCH)
     imgs = fb.images()

@@ -1,6 +1,6 @@
 """Mip-Splatting's filters on the device (gs_raster_cfg.mip2d / .filter3d and
 gs_filter3d_variance) against the FP64 oracle: image and every parameter
-gradient on config 0 with the 2D mip filter, the 3D smoothing filter and
+gradient on the 4096-Gaussian scene with the 2D mip filter, the 3D smoothing filter and
 both; a two-view batch against the oracle's per-view sum; the 3D filter's
 variances; and the backward fused with Adam against the separate calls.
 The 3D filter variances are seeded inputs given to both sides."""
@@ -36,7 +36,7 @@ def _skip(P, F):
 
 @pytest.mark.parametrize("mip2d,use3d", [(True, True), (True, False), (False, True)])
 def test_filtered_render_matches_oracle(mip2d, use3d):
-    sc, cam = scenes.config0()
+    sc, cam = scenes.small_scene()
     f3 = _variances(sc, 91) if use3d else None
     w = scenes.random_upstream(cam, seed=92)
     P = project.project(sc, cam, mip2d=mip2d,
@@ -62,7 +62,7 @@ def test_filtered_render_matches_oracle(mip2d, use3d):
 
 
 def test_filtered_batch_matches_oracle_sum():
-    sc, _ = scenes.config0()
+    sc, _ = scenes.small_scene()
     base = scenes.orbit_cameras(3, 3.0, 128, 96, 120.0)
     cams = [base[0], scenes.downscale(base[1], 2)]
     f3 = _variances(sc, 93)
@@ -89,7 +89,7 @@ def test_filtered_batch_matches_oracle_sum():
 @pytest.mark.parametrize("n_views", [6, 40])
 def test_filter3d_variance_matches_oracle(n_views):
     """40 views take two launches (32 + 8): the rate folds across them."""
-    sc, _ = scenes.config0()
+    sc, _ = scenes.small_scene()
     # two points far above and below the orbit plane: no view sees them
     means = np.concatenate([sc["means"], np.array([[0.0, 30.0, 0.0], [0.0, -30.0, 0.0]],
                                                   np.float32)])
@@ -108,7 +108,7 @@ def test_filter3d_variance_matches_oracle(n_views):
 
 
 def test_filtered_fused_step_equals_separate_calls():
-    sc, cam = scenes.config0()
+    sc, cam = scenes.small_scene()
     f3 = torch.from_numpy(_variances(sc, 95)).cuda()
     tgt = torch.from_numpy(scenes.uniform_target(cam, seed=96)).reshape(-1).cuda()
     pa = raster.Pipeline(raster.to_device(sc), [cam], tgt, fused=False, mip2d=True, filter3d=f3)

@@ -1,4 +1,4 @@
-"""GPU parity: every call of the C ABI against the FP64 oracle (config 0 and
+"""GPU parity: every call of the C ABI against the FP64 oracle (the 4096-Gaussian scene and
 small edge scenes).  Tolerances: keys / values / ranges bit-exact; images and
 final T within 1e-5 absolute; gradients |g - g_ref| <= 1e-3 |g_ref| + 1e-6
 with an O(1) upstream (L = sum w * C, w ~ U[-1,1]).  Pixels and Gaussians the
@@ -32,8 +32,8 @@ def _near_flagged_gaussians(P, F):
 
 
 @pytest.fixture(scope="module")
-def cfg0():
-    sc, cam = scenes.config0()
+def small():
+    sc, cam = scenes.small_scene()
     w = scenes.random_upstream(cam)
     P = project.project(sc, cam, tile=16)
     F = render.render_fwd(P, want_lists=True)
@@ -41,8 +41,8 @@ def cfg0():
     return dict(sc=sc, cam=cam, w=w, P=P, F=F, B=B)
 
 
-def test_preprocess_matches_oracle(cfg0):
-    sc, cam, P = cfg0["sc"], cfg0["cam"], cfg0["P"]
+def test_preprocess_matches_oracle(small):
+    sc, cam, P = small["sc"], small["cam"], small["P"]
     _, frame, _ = U.run(sc, [cam], upstream=None)
     d = U.decode_proj(frame)
     live = P["tiles_touched"] > 0
@@ -60,11 +60,11 @@ def test_preprocess_matches_oracle(cfg0):
         assert np.array_equal(((d["flags"] >> c) & 1).astype(bool)[live], clamp[live, c])
 
 
-def test_bin_sort_properties(cfg0):
+def test_bin_sort_properties(small):
     """Device keys are sorted, stable (equal keys keep ascending index), carry each
     pair's own depth bits, give every Gaussian exactly its tile count, and the
     ranges cover exactly the runs of each tile."""
-    sc, cam = cfg0["sc"], cfg0["cam"]
+    sc, cam = small["sc"], small["cam"]
     for tile in (8, 16, 32):
         _, frame, _ = U.run(sc, [cam], tile=tile)
         d = U.decode_proj(frame)
@@ -141,8 +141,8 @@ def test_backward_long_lists(n, tile):
         U.check_grads(g[name], B["d_" + name], B["bound"]["d_" + name], mask=~skip)
 
 
-def test_bin_sort_end_to_end_matches_oracle(cfg0):
-    sc, cam, P = cfg0["sc"], cfg0["cam"], cfg0["P"]
+def test_bin_sort_end_to_end_matches_oracle(small):
+    sc, cam, P = small["sc"], small["cam"], small["P"]
     _, frame, _ = U.run(sc, [cam], tile=16)
     gw, gh = -(-cam.width // 16), -(-cam.height // 16)
     k, v, r = binning.bin_sort(P["rect"], P["tiles_touched"], P["depth_f32"], gw, gh)
@@ -159,8 +159,8 @@ def test_bin_sort_end_to_end_matches_oracle(cfg0):
         assert np.array_equal(gk[keep_g], k[keep_o])
 
 
-def test_render_fwd_matches_oracle(cfg0):
-    sc, cam, F = cfg0["sc"], cfg0["cam"], cfg0["F"]
+def test_render_fwd_matches_oracle(small):
+    sc, cam, F = small["sc"], small["cam"], small["F"]
     _, frame, _ = U.run(sc, [cam], tile=16)
     img = frame.image.view(3, cam.height, cam.width).cpu().numpy()
     fT = frame.final_T.view(cam.height, cam.width).cpu().numpy()
@@ -179,10 +179,10 @@ def test_render_fwd_matches_oracle(cfg0):
     assert np.array_equal(gid[ok], F["last_id"][ok])
 
 
-def test_image_independent_of_tile_and_batch(cfg0):
+def test_image_independent_of_tile_and_batch(small):
     """Binning is result-neutral: the LDS batch size changes no bit; the tile size
     changes only the float32 rounding of the mean moved into each tile's frame."""
-    sc, cam = cfg0["sc"], cfg0["cam"]
+    sc, cam = small["sc"], small["cam"]
     ref = None
     for tile in (8, 16, 32):
         per_tile = None
@@ -197,8 +197,8 @@ def test_image_independent_of_tile_and_batch(cfg0):
         assert np.abs(per_tile - ref).max() < 2e-6, tile
 
 
-def test_render_bwd_matches_oracle(cfg0):
-    sc, cam, w, P, F, B = (cfg0[k] for k in ("sc", "cam", "w", "P", "F", "B"))
+def test_render_bwd_matches_oracle(small):
+    sc, cam, w, P, F, B = (small[k] for k in ("sc", "cam", "w", "P", "F", "B"))
     _, frame, g = U.run(sc, [cam], upstream=[w])
     skip = _near_flagged_gaussians(P, F) | P["flag_rgb"].any(1)
     mask = ~skip
@@ -208,17 +208,17 @@ def test_render_bwd_matches_oracle(cfg0):
 
 
 @pytest.mark.parametrize("tile,batch", [(8, 128), (32, 512)])
-def test_render_bwd_other_tiles(cfg0, tile, batch):
-    sc, cam, w, P, F, B = (cfg0[k] for k in ("sc", "cam", "w", "P", "F", "B"))
+def test_render_bwd_other_tiles(small, tile, batch):
+    sc, cam, w, P, F, B = (small[k] for k in ("sc", "cam", "w", "P", "F", "B"))
     _, _, g = U.run(sc, [cam], tile=tile, lds_batch=batch, upstream=[w])
     mask = ~(_near_flagged_gaussians(P, F) | P["flag_rgb"].any(1))
     for name in ("means", "quats", "sh", "log_scales"):
         U.check_grads(g[name], B["d_" + name], B["bound"]["d_" + name], mask=mask)
 
 
-def test_background_and_degree(cfg0):
-    sc = scenes.subset(cfg0["sc"], slice(0, 1500))
-    cam = cfg0["cam"]
+def test_background_and_degree(small):
+    sc = scenes.subset(small["sc"], slice(0, 1500))
+    cam = small["cam"]
     bg = (0.25, 0.5, 0.75)
     for deg in (0, 1, 2):
         P = project.project(sc, cam, sh_degree=deg)
@@ -237,7 +237,7 @@ def test_background_and_degree(cfg0):
 
 
 def test_batched_views_equal_plain():
-    sc, _ = scenes.config0()
+    sc, _ = scenes.small_scene()
     base = scenes.orbit_cameras(4, 3.0, 128, 96, 120.0)
     cams = [base[0], scenes.downscale(base[1], 2), base[2], scenes.downscale(base[3], 4)]
     ups = [scenes.random_upstream(c, seed=20 + k) for k, c in enumerate(cams)]
@@ -262,7 +262,7 @@ def test_batched_views_equal_plain():
 
 
 def test_multiview_grads_match_oracle_sum():
-    sc, _ = scenes.config0()
+    sc, _ = scenes.small_scene()
     sc = scenes.subset(sc, slice(0, 2000))
     cams = scenes.orbit_cameras(3, 3.0, 64, 48, 60.0)
     ups = [scenes.random_upstream(c, seed=40 + k) for k, c in enumerate(cams)]
@@ -317,8 +317,8 @@ def test_adam_matches_oracle():
 # ------------------------------------------------------------------- edges
 
 def test_empty_scene():
-    sc = scenes.subset(scenes.config0()[0], slice(0, 0))
-    cam = scenes.config0()[1]
+    sc = scenes.subset(scenes.small_scene()[0], slice(0, 0))
+    cam = scenes.small_scene()[1]
     _, frame, g = U.run(sc, [cam], upstream=[scenes.random_upstream(cam)])
     assert int(frame.n_pairs_dev.item()) == 0
     assert np.all(frame.image.cpu().numpy() == 0.0)
@@ -329,7 +329,7 @@ def test_empty_scene():
 def test_all_culled_and_behind_camera():
     sc = scenes.make_scene(300, seed=3)
     sc["means"][:, 2] = -5.0          # all behind the camera at z = -3
-    cam = scenes.config0()[1]
+    cam = scenes.small_scene()[1]
     _, frame, g = U.run(sc, [cam], upstream=[scenes.random_upstream(cam)])
     assert int(frame.n_pairs_dev.item()) == 0
     assert np.all(frame.image.cpu().numpy() == 0.0)
@@ -371,8 +371,8 @@ def test_saturating_stack_exit():
     assert abs(fT[16, 16] - 2.0 ** -13) < 1e-9
 
 
-def test_capacity_overflow_reported_and_regrown(cfg0):
-    sc, cam = cfg0["sc"], cfg0["cam"]
+def test_capacity_overflow_reported_and_regrown(small):
+    sc, cam = small["sc"], small["cam"]
     params = raster.to_device(sc, "cuda")
     frame = raster.render(params, [cam], capacity=100, check_capacity=False)
     torch.cuda.synchronize()
@@ -384,8 +384,8 @@ def test_capacity_overflow_reported_and_regrown(cfg0):
     assert torch.equal(frame2.image, ref.image)
 
 
-def test_autograd_function_matches_oracle(cfg0):
-    sc, cam, w, P, F, B = (cfg0[k] for k in ("sc", "cam", "w", "P", "F", "B"))
+def test_autograd_function_matches_oracle(small):
+    sc, cam, w, P, F, B = (small[k] for k in ("sc", "cam", "w", "P", "F", "B"))
     prm = {k: v.requires_grad_(True) for k, v in raster.to_device(sc, "cuda").items()}
     img = raster.RasterizeFn.apply(prm["means"], prm["log_scales"], prm["quats"],
                                    prm["opacity_logits"], prm["sh"], {"cams": [cam]})
@@ -397,8 +397,8 @@ def test_autograd_function_matches_oracle(cfg0):
                       mask=mask)
 
 
-def test_overwrite_equals_accumulate_into_zero(cfg0):
-    sc, cam, w = cfg0["sc"], cfg0["cam"], cfg0["w"]
+def test_overwrite_equals_accumulate_into_zero(small):
+    sc, cam, w = small["sc"], small["cam"], small["w"]
     params = raster.to_device(sc, "cuda")
     frame = raster.render(params, [cam])
     dL = torch.from_numpy(w).cuda().reshape(-1)

@@ -42,8 +42,8 @@ def test_random_rects_match_sorted():
     assert [tuple(int(a) for a in row) for row in r] == ranges
 
 
-def test_config0_projection_pairs():
-    sc, cam = scenes.config0()
+def test_small_scene_projection_pairs():
+    sc, cam = scenes.small_scene()
     sc = scenes.subset(sc, slice(0, 400))
     P = project.project(sc, cam, tile=16)
     gw, gh = (cam.width + 15) // 16, (cam.height + 15) // 16

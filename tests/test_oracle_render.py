@@ -90,7 +90,7 @@ def test_cutoff_ring():
 
 
 def test_weights_sum_and_white():
-    sc, cam = scenes.config0()
+    sc, cam = scenes.small_scene()
     sc = scenes.subset(sc, slice(0, 600))
     sc["sh"][:] = 0.0
     sc["sh"][:, 0, :] = 0.5 / Y00          # every colour the same c (= 1 up to float32)
@@ -105,7 +105,7 @@ def test_weights_sum_and_white():
 
 
 def test_background():
-    sc, cam = scenes.config0()
+    sc, cam = scenes.small_scene()
     sc = scenes.subset(sc, slice(0, 300))
     P = project.project(sc, cam)
     a = render.render_fwd(P)
@@ -116,7 +116,7 @@ def test_background():
 
 
 def test_permutation_invariance():
-    sc, cam = scenes.config0()
+    sc, cam = scenes.small_scene()
     # keep Gaussians whose float32 depths are distinct, so the order is fully determined
     # (equal depths would be ordered by index, which a shuffle changes)
     z = project.project(sc, cam)["depth_f32"]
