@@ -159,7 +159,7 @@ __device__ __forceinline__ void bwd_step(BwdPix<TILE>& P, const BwdStage& S, int
   const float4 r0 = S.r0[k];
   const float4 r1 = S.r1[k];
   const float cb = S.b[k];
-  const float o = r1.y;
+  const float lo = r1.y;  // log2 of the blending opacity
   float acc[kG];
 #pragma unroll
   for (int c = 0; c < kG; ++c) acc[c] = 0.0f;
@@ -169,7 +169,7 @@ __device__ __forceinline__ void bwd_step(BwdPix<TILE>& P, const BwdStage& S, int
     if ((m >> q) & 1u) {
       // branch-free: every lane computes, the decisions select the updates
       const float px = px0 + float((q % GX) * 8), py = py0 + float((q / GX) * 8);
-      const Alpha e = alpha_at(r0, r1.x, o, px, py);
+      const Alpha e = alpha_at(r0, r1.x, lo, px, py);
       const bool ok = e.ok & (pos <= P.last[q]);
       // footprint boxes are conservative: often no pixel of the group is reached
       if (__ballot(ok) == 0ull) continue;
@@ -185,8 +185,8 @@ __device__ __forceinline__ void bwd_step(BwdPix<TILE>& P, const BwdStage& S, int
       acc[6] = fmaf(wgt, P.g0[q], acc[6]);
       acc[7] = fmaf(wgt, P.g1[q], acc[7]);
       acc[8] = fmaf(wgt, P.g2[q], acc[8]);
-      acc[5] = fmaf(dLda, e.G, acc[5]);
       const float dpow = dLda * e.raw;
+      acc[5] += dpow;  // dL/do times o: the chain rule divides by the opacity
       const float dpx = dpow * e.dx, dpy = dpow * e.dy;
       acc[2] = fmaf(dpx, e.dx, acc[2]);
       acc[3] = fmaf(dpx, e.dy, acc[3]);
@@ -666,19 +666,21 @@ __device__ __forceinline__ bool chain_grad(const Views& V, const ChainIn& I, int
     float G11 = -(cb * X01 + cc * X11);
     // the 2D mip filter's opacity factor c2 = sqrt(D1 / D2), D1 = det of the
     // unfiltered covariance, D2 = det Sigma' = 1 / idet: its gradient joins G'
-    float c2 = 1.0f;
+    float c2 = 1.0f, id1 = 0.0f;
     if (V.mip2d) {
       const float d1 = r00 * r11 - r01 * r01;
-      if (d1 > 0.0f) {
-        c2 = sqrtf(d1 * idet);
-        const float id1 = 1.0f / d1;
-        const float gc2 = gr[5] * o * c3;  // dL/dc2
-        G00 += gc2 * (0.5f * c2 * (r11 * id1 - c11 * idet));
-        G01 += gc2 * (0.5f * c2 * r01 * (idet - id1));
-        G11 += gc2 * (0.5f * c2 * (r00 * id1 - c00 * idet));
-      } else {
-        c2 = 0.0f;
-      }
+      c2 = d1 > 0.0f ? sqrtf(d1 * idet) : 0.0f;
+      id1 = d1 > 0.0f ? 1.0f / d1 : 0.0f;
+    }
+    // the blend summed o_b dL/do_b over the pixels (o_b = o c3 c2, the opacity
+    // it blended with): divide by o_b once here
+    const float ob = o * c3 * c2;
+    const float gop = ob > 0.0f ? gr[5] / ob : 0.0f;  // dL/do_b
+    if (V.mip2d && c2 > 0.0f) {
+      const float gc2 = gop * o * c3;  // dL/dc2
+      G00 += gc2 * (0.5f * c2 * (r11 * id1 - c11 * idet));
+      G01 += gc2 * (0.5f * c2 * r01 * (idet - id1));
+      G11 += gc2 * (0.5f * c2 * (r00 * id1 - c00 * idet));
     }
     // Sigma' = T Sigma T^T: dSigma += T^T G' T ; dT = 2 G' U
 #pragma unroll
@@ -741,7 +743,7 @@ __device__ __forceinline__ bool chain_grad(const Views& V, const ChainIn& I, int
     dm[1] += (gdy - dy * dd) * dn;
     dm[2] += (gdz - dz * dd) * dn;
 
-    dop += V.mip2d ? gr[5] * c2 : gr[5];  // w.r.t. the opacity before the 2D factor
+    dop += V.mip2d ? gop * c2 : gop;  // w.r.t. the opacity before the 2D factor
     m2abs += sqrtf(gmx * gmx + gmy * gmy);
   }
 

@@ -35,14 +35,16 @@ __device__ __forceinline__ bool box_overlaps(uint32_t lo, uint32_t hi, int x0, i
   return box_x(lo) <= x1 && box_x(hi) >= x0 && box_y(lo) <= y1 && box_y(hi) >= y0;
 }
 
-// alpha of Gaussian (r0 = (mx, my, A, B), C, o) at pixel centre (px, py), all in
-// the tile's frame, computed without branches.  The Gaussian takes part in the
-// blend at this pixel iff `ok` (quadratic form <= 0 and alpha >= 1/255).
+// alpha of a record at pixel centre (px, py): the record holds the base-2
+// conic (A, B, C) and lo = log2 of the opacity, so o G2D = 2^(p2 + lo) with
+// p2 = A dx^2 + B dx dy + C dy^2.  The pixel takes the Gaussian iff `ok`:
+// p2 <= 0 and o G2D >= 1/255, decided on the exponent, so callers that branch
+// on `ok` before using `a` evaluate the exponential only where it is used.
 struct Alpha {
-  float dx, dy, G, raw, a;
+  float dx, dy, raw, a;
   bool ok;
 };
-__device__ __forceinline__ Alpha alpha_at(const float4 r0, const float C, const float o,
+__device__ __forceinline__ Alpha alpha_at(const float4 r0, const float C, const float lo,
                                           const float px, const float py) {
   Alpha r;
   r.dx = px - r0.x;
@@ -52,10 +54,10 @@ __device__ __forceinline__ Alpha alpha_at(const float4 r0, const float C, const 
   const float t2 = C * r.dy;
   const float t3 = t2 * r.dy;
   const float p2 = fmaf(r.dx, t1, t3);
-  r.G = __builtin_amdgcn_exp2f(p2);
-  r.raw = o * r.G;
+  const float q = p2 + lo;
+  r.ok = (p2 <= 0.0f) & (q >= kLog2AlphaMin);
+  r.raw = __builtin_amdgcn_exp2f(q);
   r.a = fminf(kAlphaMax, r.raw);
-  r.ok = (p2 <= 0.0f) & (r.a >= kAlphaMin);
   return r;
 }
 

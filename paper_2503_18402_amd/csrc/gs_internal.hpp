@@ -16,6 +16,7 @@ namespace gsk {
 // ----------------------------------------------------------------- constants
 // Rasterizer conventions (the paper's Eq. 1 plus its backbones' cutoffs).
 constexpr float kAlphaMin = 1.0f / 255.0f;  // skip a Gaussian below this alpha
+constexpr float kLog2AlphaMin = -7.99435343685885793771f;  // log2(1/255)
 constexpr float kAlphaMax = 0.99f;          // alpha clamp
 constexpr float kTMin = 1.0e-4f;            // stop a pixel before T drops below this
 constexpr float kDilation = 0.3f;           // screen-space low-pass added to Sigma'
@@ -58,7 +59,7 @@ __device__ __forceinline__ float filter3d_coef(float s0, float s1, float s2, flo
 //   rec[3g+0] = (mx, my, A, B)       screen mean relative to the pixel origin of the
 //                                     first tile of the footprint box (tile size of the
 //                                     call); A = -a/2 log2e, B = -b log2e
-//   rec[3g+1] = (C, o, r, g)         C = -c/2 log2e; opacity; colour r, g
+//   rec[3g+1] = (C, lo, r, g)        C = -c/2 log2e; lo = log2(opacity); colour r, g
 //   rec[3g+2] = (b, depth, lo, hi)   colour b; z_f32; pixel box as two u32
 //                                     (x | y << 16) of its inclusive corners
 //   tt[g]     u32 tiles touched (0: culled or off-screen)

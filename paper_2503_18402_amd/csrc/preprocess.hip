@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kPreThreads) void k_preprocess(
         const int ox = (x0 <= x1 ? x0 / T : 0) * T, oy = (y0 <= y1 ? y0 / T : 0) * T;
         const float s = -0.5f * kLog2e;
         r0 = make_float4(float(mux - double(ox)), float(muy - double(oy)), s * ca, -kLog2e * cb);
-        r1 = make_float4(s * cc, ov, rgb[0], rgb[1]);
+        r1 = make_float4(s * cc, log2f(ov), rgb[0], rgb[1]);
         r2 = make_float4(rgb[2], depth, __uint_as_float(box_pack(x0 < 0 ? 0 : x0, y0 < 0 ? 0 : y0)),
                          __uint_as_float(box_pack(x1 < 0 ? 0 : x1, y1 < 0 ? 0 : y1)));
       }

@@ -18,7 +18,8 @@ def align256(x: int) -> int:
 
 def decode_proj(frame, view: int = 0, tile: int | None = None) -> dict:
     """Per-Gaussian records of one view, in the documented layout of the
-    projected-record buffer (rec: 3 float4, then tiles touched, then flags)."""
+    projected-record buffer (rec: 3 float4, then tiles touched, then flags);
+    the record holds log2 of the opacity."""
     n = frame.n
     stride = align256(48 * n) + 2 * align256(4 * n)
     raw = frame.proj.cpu().numpy()[view * stride:(view + 1) * stride]
@@ -36,7 +37,8 @@ def decode_proj(frame, view: int = 0, tile: int | None = None) -> dict:
     origin = np.stack([(box_lo & 0xFFFF) // T * T, (box_lo >> 16) // T * T], 1).astype(np.float64)
     origin[tt == 0] = 0.0
     return dict(mean2d=rec[:, 0:2].astype(np.float64) + origin, conic=conic,
-                opacity=rec[:, 5].astype(np.float64), rgb=rec[:, [6, 7, 8]].astype(np.float64),
+                opacity=np.where(tt > 0, np.exp2(rec[:, 5].astype(np.float64)), 0.0),
+                rgb=rec[:, [6, 7, 8]].astype(np.float64),
                 depth=rec[:, 9].copy(), tt=tt.astype(np.int64), flags=flags, px_box=px_box)
 
 
