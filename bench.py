@@ -31,15 +31,16 @@ HBM_PEAK_GBS = 8000.0
 # 256 CUs x 64 lanes x 2 FLOP (FMA) x 2.4 GHz
 ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 # algorithmic FLOPs per (pixel, Gaussian) evaluation of Eq. 1 in the forward:
-# offset (2), quadratic form (5 mul/fma = 8 FLOP), exp (1), o*G (1), clamp (1),
+# offset (2), quadratic form (5 mul/fma = 8 FLOP), exponent + log2(o) (1), exp (1), clamp (1),
 # two cutoff tests (2), T(1-alpha) (2), alpha*T (1), colour (3 fma = 6)
 FWD_FLOP_PER_EVAL = 2 + 8 + 1 + 1 + 1 + 2 + 2 + 1 + 6
 # and in the backward: alpha again (13), T recovery 1-a, 1/x, T*inv (3), weight (1),
 # c.dL/dC (5), dL/dalpha (3), colour-behind update (2), colour grads (6), opacity
-# grad (2), dL/dpower and its products with the offsets (3), conic grads (6),
-# the two offset sums whose product with the conic is the mean gradient (2; the
-# product itself is per Gaussian, not per evaluation)
-BWD_FLOP_PER_EVAL = 13 + 3 + 1 + 5 + 3 + 2 + 6 + 2 + 3 + 6 + 2
+# grad (1: the sum of dL/dpower, divided by the opacity once per Gaussian), dL/dpower
+# and its products with the offsets (3), conic grads (6), the two offset sums whose
+# product with the conic is the mean gradient (2; the product itself is per
+# Gaussian, not per evaluation)
+BWD_FLOP_PER_EVAL = 13 + 3 + 1 + 5 + 3 + 2 + 6 + 1 + 3 + 6 + 2
 
 
 def parse():
