@@ -84,7 +84,7 @@ __host__ __device__ __forceinline__ int xcd_tile(int b, const RViews& RV) {
 // with tiles alone; its longest lists start first (views are walked fewest
 // tiles first), and splitting them only adds the list-parallel passes' extra
 // work, so such launches skip the long-list kernels altogether.
-constexpr uint32_t kLongList = 96;
+constexpr uint32_t kLongList = 48;
 constexpr int kFewTiles = 2048;
 
 __host__ __device__ inline bool split_long_lists(const RViews& RV, int tile) {
