@@ -17,6 +17,7 @@ namespace {
 struct ProfRec {
   const char* name;
   hipEvent_t a, b;
+  bool failed;  // an event could not be recorded: the collection reports an error
 };
 std::vector<ProfRec> g_recs;
 std::vector<hipEvent_t> g_pool;
@@ -33,8 +34,8 @@ hipEvent_t take_event() {
 }  // namespace
 
 void profile_begin(const char* name, hipStream_t st) {
-  ProfRec r{name, take_event(), nullptr};
-  if (r.a) hipEventRecord(r.a, st);
+  ProfRec r{name, take_event(), nullptr, false};
+  if (r.a && hipEventRecord(r.a, st) != hipSuccess) r.failed = true;
   g_recs.push_back(r);
 }
 
@@ -42,7 +43,7 @@ void profile_end(hipStream_t st) {
   if (g_recs.empty()) return;
   ProfRec& r = g_recs.back();
   r.b = take_event();
-  if (r.b) hipEventRecord(r.b, st);
+  if (r.b && hipEventRecord(r.b, st) != hipSuccess) r.failed = true;
 }
 
 bool build_views(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg, Views* out) {
@@ -113,7 +114,7 @@ int32_t gs_profile_collect(gs_kernel_time* out, int32_t max_entries) {
   bool err = false;
   for (auto& r : g_recs) {
     float ms = 0.0f;
-    if (!r.a || !r.b || hipEventSynchronize(r.b) != hipSuccess ||
+    if (r.failed || !r.a || !r.b || hipEventSynchronize(r.b) != hipSuccess ||
         hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
       err = true;
     }

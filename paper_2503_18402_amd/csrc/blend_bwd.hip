@@ -277,7 +277,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd(
 // The T recovery by division therefore runs over at most one chunk.
 constexpr int kLongWaves = 8;
 constexpr int kMaxChunks = 16;
-constexpr uint32_t kMinChunk = 64;
+constexpr uint32_t kMinChunk = 32;
 constexpr int kLongBatch = 64;
 constexpr int kLongBlocks = 1024;
 

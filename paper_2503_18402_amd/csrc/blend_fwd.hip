@@ -158,7 +158,7 @@ __global__ __launch_bounds__(WaveShape<TILE>::kThreads) void k_blend_fwd(
 //      kernel until the pixel stops.
 constexpr int kFWaves = 8;
 constexpr int kFMaxChunks = 16;
-constexpr uint32_t kFMinChunk = 64;
+constexpr uint32_t kFMinChunk = 32;
 constexpr int kFBatch = 64;
 constexpr int kFLongBlocks = 1024;
 
