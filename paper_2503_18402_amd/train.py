@@ -199,7 +199,7 @@ class Trainer:
                 cap = max(cap, int(probe.n_pairs_dev.item()))
                 del probe
             pipe = raster.Pipeline(self.params, [views[0]], gt_f[0].reshape(-1), tile=tile,
-                                   lds_batch=128, sh_degree=self.sh_degree,
+                                   lds_batch=self.lds_batch_for(f), sh_degree=self.sh_degree,
                                    capacity=int(cap * self.capacity_margin) + 4096, lrs=self.lrs,
                                    share=first, state=(self.m, self.v, self.step_dev),
                                    mean2d_abs=self.mean2d, sparse_adam=self.sparse_adam,
@@ -214,6 +214,11 @@ class Trainer:
         """Tile size at downsampling factor f: 8 below full resolution (few
         tiles: split them finer), 16 at full resolution."""
         return 8 if f >= 2 else 16
+
+    @staticmethod
+    def lds_batch_for(f: int) -> int:
+        """Gaussians staged in LDS per blend step at downsampling factor f."""
+        return 128
 
     def update_filter3d(self):
         """Recompute the 3D smoothing filter (in place) from the current means
