@@ -66,8 +66,11 @@ typedef struct {
 
 /* Raster configuration.  tile in {8, 16, 32} pixels; lds_batch in
  * {128, 256, 512} Gaussians staged in LDS per step of the blend kernels;
- * bg is the background colour added as T_final * bg.  The image does not
- * depend on tile or lds_batch (binning is result-neutral).
+ * bg is the background colour added as T_final * bg.  Binning is
+ * result-neutral: the image does not depend on lds_batch, and across tile
+ * sizes, or between a launch of fewer than 2048 tiles (which splits lists
+ * longer than 48 entries across waves) and one of more, it changes only by
+ * float32 rounding.
  *
  * Mip-Splatting's filters (the backbone family with an anti-aliased primitive
  * representation that the paper equips, Sec. 5 and the supplementary):
