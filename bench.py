@@ -223,7 +223,7 @@ def main():
                              launch_ms=round(kernel_ms["k_blend_fwd"], 4),
                              event_ms_in_timed_loop=round(fwd_ms, 4)))
 
-    extras = {}
+    extras = {"binning": binning_forms(torch, pipe)}
     if not args.no_extras:
         extras["levels"] = level_sweep(torch, raster, scenes, params, tparams_scene=tscene,
                                        tile=args.tile, lds=args.lds_batch)
@@ -291,6 +291,41 @@ def time_pipe(torch, pipe, steps):
     torch.cuda.synchronize()
     assert not pipe.overflowed()
     return e0.elapsed_time(e1) / steps
+
+
+def binning_forms(torch, pipe, reps=20):
+    """gs_bin_sort (pairs bucketed by tile, each tile's list sorted on chip)
+    against gs_bin_sort_radix (stable LSD radix sort of the (tile | depth) keys)
+    on the pipeline's current projected records: time per call and agreement."""
+    from paper_2503_18402_amd import gsmi
+
+    n, cap = pipe.n, pipe.capacity
+    ws = torch.empty(max(gsmi.gs_bin_sort_radix_workspace_bytes(1, n, cap), 16),
+                     dtype=torch.uint8, device=pipe.vals.device)
+    vals = torch.empty_like(pipe.vals)
+    ranges = torch.empty_like(pipe.ranges)
+    npairs = torch.zeros(1, dtype=torch.int64, device=pipe.vals.device)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    bucket = timed(lambda: gsmi.gs_bin_sort(pipe.cams_c, pipe.cfg, n, pipe.proj, cap, pipe.sort_ws,
+                                            None, pipe.vals, pipe.ranges, pipe.n_pairs))
+    radix = timed(lambda: gsmi.gs_bin_sort_radix(pipe.cams_c, pipe.cfg, n, pipe.proj, cap, ws, None,
+                                                 vals, ranges, npairs))
+    npr = int(pipe.n_pairs.item())
+    same = bool(torch.equal(vals[:npr], pipe.vals[:npr]) and torch.equal(ranges, pipe.ranges))
+    log(f"binning: bucket + tile sort {bucket:.3f} ms, LSD radix {radix:.3f} ms, identical {same}")
+    return dict(bucket_tile_sort_ms=round(bucket, 4), lsd_radix_ms=round(radix, 4),
+                identical=same, pairs=npr)
 
 
 def level_sweep(torch, raster, scenes, params, tparams_scene, tile, lds):

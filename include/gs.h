@@ -144,6 +144,17 @@ gs_status gs_filter3d_variance(int32_t n_views, const gs_camera* cams, int32_t n
                                const float* means, float scale, float* variance,
                                uint32_t* scratch, void* stream);
 
+/* gs_bin_sort_radix: the same keys, values, ranges and pair count as
+ * gs_bin_sort, by a stable LSD radix sort with 8-bit digits (the four depth
+ * digits sorted on the visible Gaussians before the pairs are expanded, then
+ * the tile digits on the pairs).  Arguments and errors are those of
+ * gs_bin_sort, with its own workspace size. */
+size_t gs_bin_sort_radix_workspace_bytes(int32_t n_views, int32_t n, int64_t capacity_pairs);
+gs_status gs_bin_sort_radix(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
+                            int32_t n, const void* proj, int64_t capacity_pairs, void* ws,
+                            size_t ws_bytes, uint64_t* keys, uint32_t* vals, uint32_t* ranges,
+                            int64_t* n_pairs_dev, void* stream);
+
 /* Total tiles over the views for this cfg (host helper for sizing ranges). */
 int64_t gs_total_tiles(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg);
 

@@ -21,8 +21,8 @@ LIB = os.path.join(HERE, "libgsmi.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 ARCH = "gfx950"
-SOURCES = ["abi.cpp", "preprocess.hip", "sort.hip", "blend_fwd.hip", "blend_bwd.hip", "adam.hip",
-           "schedule.hip", "densify.hip"]
+SOURCES = ["abi.cpp", "preprocess.hip", "sort.hip", "radix_sort.hip", "blend_fwd.hip",
+           "blend_bwd.hip", "adam.hip", "schedule.hip", "densify.hip"]
 
 
 def hipcc() -> str:

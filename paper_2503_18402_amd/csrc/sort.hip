@@ -465,8 +465,16 @@ __global__ __launch_bounds__(kBigThreads) void k_tile_sort_big(
     int n_tiles, const int64_t* __restrict__ n_eff, const int64_t* __restrict__ n_long,
     uint64_t* __restrict__ bucket,
     uint32_t* __restrict__ vals, uint64_t* __restrict__ keys,
-    const uint32_t* __restrict__ ranges) {
+    uint32_t* __restrict__ ranges) {
   __shared__ uint64_t s[kChunk];
+  // empty tiles read [0, 0): the wave tier leaves them at [p, p) because a
+  // tile's end is its neighbour's start, which must stay until every wave has
+  // read it.  Here every range is final, and the long-list loop below reads
+  // non-empty tiles only.
+  for (uint32_t t = blockIdx.x * kBigThreads + threadIdx.x; t < uint32_t(n_tiles);
+       t += gridDim.x * kBigThreads)
+    if (ranges[2 * size_t(t)] == ranges[2 * size_t(t) + 1])
+      ranges[2 * size_t(t)] = ranges[2 * size_t(t) + 1] = 0u;
   if (*n_eff == 0 || *n_long == 0) return;
   for (uint32_t t = blockIdx.x; t < uint32_t(n_tiles); t += gridDim.x) {
     const uint32_t start = ranges[2 * size_t(t)], end = ranges[2 * size_t(t) + 1];

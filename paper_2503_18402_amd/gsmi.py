@@ -69,6 +69,9 @@ def lib() -> ctypes.CDLL:
             "gs_preprocess": (i32, [i32, cam_p, cfg_p, i32, vp, vp, vp, vp, vp, i32, vp, vp]),
             "gs_bin_sort_workspace_bytes": (sz, [i32, i32, i64]),
             "gs_bin_sort": (i32, [i32, cam_p, cfg_p, i32, vp, i64, vp, sz, vp, vp, vp, vp, vp]),
+            "gs_bin_sort_radix_workspace_bytes": (sz, [i32, i32, i64]),
+            "gs_bin_sort_radix": (i32, [i32, cam_p, cfg_p, i32, vp, i64, vp, sz, vp, vp, vp, vp,
+                                        vp]),
             "gs_render_fwd": (i32, [i32, cam_p, cfg_p, i32, vp, vp, vp, vp, vp, vp, vp]),
             "gs_render_bwd_workspace_bytes": (sz, [i32, i32, i64]),
             "gs_render_bwd": (i32, [i32, cam_p, cfg_p, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp,
@@ -197,6 +200,19 @@ def gs_bin_sort_workspace_bytes(n_views: int, n: int, capacity: int) -> int:
 def gs_bin_sort(cams_c, cfg, n, proj, capacity, ws, keys, vals, ranges, n_pairs_dev,
                 stream=None):
     _check("gs_bin_sort", lib().gs_bin_sort(
+        len(cams_c), cams_c, ctypes.byref(cfg), int(n), _ptr(proj), int(capacity), _ptr(ws),
+        ws.numel() * ws.element_size(), _ptr(keys), _ptr(vals), _ptr(ranges), _ptr(n_pairs_dev),
+        _stream(stream)))
+
+
+def gs_bin_sort_radix_workspace_bytes(n_views: int, n: int, capacity: int) -> int:
+    return int(lib().gs_bin_sort_radix_workspace_bytes(n_views, n, capacity))
+
+
+def gs_bin_sort_radix(cams_c, cfg, n, proj, capacity, ws, keys, vals, ranges, n_pairs_dev,
+                      stream=None):
+    """gs_bin_sort's result by a stable LSD radix sort (its own workspace size)."""
+    _check("gs_bin_sort_radix", lib().gs_bin_sort_radix(
         len(cams_c), cams_c, ctypes.byref(cfg), int(n), _ptr(proj), int(capacity), _ptr(ws),
         ws.numel() * ws.element_size(), _ptr(keys), _ptr(vals), _ptr(ranges), _ptr(n_pairs_dev),
         _stream(stream)))

@@ -415,3 +415,28 @@ def test_overwrite_equals_accumulate_into_zero(small):
     twice = raster.render_backward(params, frame, dL, grads={k: v.clone() for k, v in acc.items()})
     for k in acc:
         assert torch.allclose(twice[k], 2 * acc[k], rtol=1e-6, atol=0), k
+
+
+@pytest.mark.parametrize("tile", [8, 16])
+def test_empty_tiles_have_zero_ranges(tile):
+    """A sparse scene leaves most tiles empty: their ranges are [0, 0), and every
+    range equals the oracle's (R7), for both binning forms."""
+    sc = scenes.subset(scenes.small_scene()[0], slice(0, 60))
+    cam = scenes.small_scene()[1]
+    P = project.project(sc, cam, tile=tile)
+    assert not P["flag_rect"].any()
+    gw, gh = -(-cam.width // tile), -(-cam.height // tile)
+    _, _, r = binning.bin_sort(P["rect"], P["tiles_touched"], P["depth_f32"], gw, gh)
+    assert (r[:, 0] == r[:, 1]).sum() >= 5      # several empty tiles
+    _, frame, _ = U.run(sc, [cam], tile=tile)
+    assert np.array_equal(frame.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2), r)
+    n = 60
+    ws = torch.empty(gsmi.gs_bin_sort_radix_workspace_bytes(1, n, frame.capacity),
+                     dtype=torch.uint8, device="cuda")
+    vals = torch.empty(frame.capacity, dtype=torch.int32, device="cuda")
+    ranges = torch.empty_like(frame.ranges)
+    npairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    gsmi.gs_bin_sort_radix(frame.cams_c, frame.cfg, n, frame.proj, frame.capacity, ws, None, vals,
+                           ranges, npairs)
+    torch.cuda.synchronize()
+    assert np.array_equal(ranges.cpu().numpy().view(np.uint32).reshape(-1, 2), r)
