@@ -131,11 +131,13 @@ def main():
                            p["opacity_logits"], p["sh"], pipe.sh_degree, pipe.proj)
         gsmi.gs_bin_sort(pipe.cams_c, pipe.cfg, pipe.n, pipe.proj, pipe.capacity, pipe.sort_ws,
                          None, pipe.vals, pipe.ranges, pipe.n_pairs)
+        pipe.loss.zero_()
         fwd_ev[k][0].record(stream)
-        gsmi.gs_render_fwd(pipe.cams_c, pipe.cfg, pipe.n, pipe.proj, pipe.ranges, pipe.vals,
-                           pipe.image, pipe.final_T, pipe.last)
+        gsmi.gs_render_fwd_l1(pipe.cams_c, pipe.cfg, pipe.n, pipe.proj, pipe.ranges, pipe.vals,
+                              pipe.image, pipe.final_T, pipe.last, pipe.targets,
+                              1.0 / pipe.image.numel(), pipe.dL, pipe.loss)
         fwd_ev[k][1].record(stream)
-        pipe.backward_adam()
+        pipe.backward_adam(l1_done=True)
     step_ev[steps].record(stream)
     ev1.record(stream)
     torch.cuda.synchronize()

@@ -172,6 +172,22 @@ gs_status gs_render_fwd(int32_t n_views, const gs_camera* cams, const gs_raster_
                         const uint32_t* vals, float* image, float* final_T,
                         uint32_t* last_contrib, void* stream);
 
+/* gs_render_fwd_l1: gs_render_fwd that also writes the L1 loss gradient of
+ * gs_l1_loss_grad beside the image, from the same float values:
+ *   dL_dimage[i] = scale * sign(image[i] - target[i])  (sign(0) = 0)
+ * over every pixel of every view (target and dL_dimage have the image's
+ * layout, device).  If loss_sum (device, [1]) is non-NULL, scale *
+ * sum|image - target| is ADDED to it, one float atomic per workgroup (its last
+ * bits depend on their order; image, final_T, last_contrib and dL_dimage are
+ * bit-identical to gs_render_fwd followed by gs_l1_loss_grad).  It saves that
+ * call's second pass over the image.  GS_ERR_ARG for a NULL target or
+ * dL_dimage, otherwise as gs_render_fwd. */
+gs_status gs_render_fwd_l1(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
+                           int32_t n, const void* proj, const uint32_t* ranges,
+                           const uint32_t* vals, float* image, float* final_T,
+                           uint32_t* last_contrib, const float* target, float scale,
+                           float* dL_dimage, float* loss_sum, void* stream);
+
 /* ---------------------------------------------------------------------------
  * gs_render_bwd: back-propagation of Eq. 1 to the Gaussian parameters
  * (Sec. 3: the process is differentiable and G_i is optimised from the loss).

@@ -247,7 +247,22 @@ gs_status gs_render_fwd(int32_t n_views, const gs_camera* cams, const gs_raster_
   if (!ranges || !image || !final_T || !last_contrib || (n > 0 && !proj)) return GS_ERR_ARG;
   if (n > 0 && !aligned16(proj)) return GS_ERR_ARG;
   return from_hip(launch_render_fwd(V, n, *cfg, static_cast<const char*>(proj), ranges, vals,
-                                    image, final_T, last_contrib, as_stream(stream)));
+                                    image, final_T, last_contrib, L1Fuse{}, as_stream(stream)));
+}
+
+gs_status gs_render_fwd_l1(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
+                           int32_t n, const void* proj, const uint32_t* ranges,
+                           const uint32_t* vals, float* image, float* final_T,
+                           uint32_t* last_contrib, const float* target, float scale,
+                           float* dL_dimage, float* loss_sum, void* stream) {
+  Views V;
+  if (!n_ok(n_views, n) || !build_views(n_views, cams, cfg, &V)) return GS_ERR_ARG;
+  if (!ranges || !image || !final_T || !last_contrib || (n > 0 && !proj)) return GS_ERR_ARG;
+  if (!target || !dL_dimage) return GS_ERR_ARG;
+  if (n > 0 && !aligned16(proj)) return GS_ERR_ARG;
+  const L1Fuse l1{target, dL_dimage, loss_sum, scale};
+  return from_hip(launch_render_fwd(V, n, *cfg, static_cast<const char*>(proj), ranges, vals,
+                                    image, final_T, last_contrib, l1, as_stream(stream)));
 }
 
 size_t gs_render_bwd_workspace_bytes(int32_t n_views, int32_t n, int64_t capacity_pairs) {

@@ -83,10 +83,6 @@ __global__ __launch_bounds__(64) void k_step_inc(int32_t* step_dev) {
   if (threadIdx.x == 0) *step_dev += 1;
 }
 
-__device__ __forceinline__ float l1_sign(float d, float scale) {
-  return (d > 0.0f) ? scale : ((d < 0.0f) ? -scale : 0.0f);
-}
-
 // dL = scale * sign(img - tgt); with `vec` (16-byte aligned arrays) four values
 // per load, the tail of fewer than four one by one.
 __global__ __launch_bounds__(256) void k_l1(int64_t n, int vec, const float* __restrict__ img,

@@ -12,11 +12,41 @@
 namespace gsk {
 namespace {
 
+// The L1 gradient of one pixel's three channels (elements e, e + plane,
+// e + 2 plane), from the values just stored in the image; returns sum |d|.
+__device__ __forceinline__ float l1_pixel(const L1Fuse& l1, int64_t e, int64_t plane, float c0,
+                                          float c1, float c2) {
+  const float d0 = c0 - l1.target[e], d1 = c1 - l1.target[e + plane],
+              d2 = c2 - l1.target[e + 2 * plane];
+  l1.dL[e] = l1_sign(d0, l1.scale);
+  l1.dL[e + plane] = l1_sign(d1, l1.scale);
+  l1.dL[e + 2 * plane] = l1_sign(d2, l1.scale);
+  return (fabsf(d0) + fabsf(d1)) + fabsf(d2);
+}
+
+// scale * (the workgroup's sum of x) added to the loss with one atomic; every
+// thread of the NW-wave workgroup calls it
+template <int NW>
+__device__ __forceinline__ void l1_block_add(const L1Fuse& l1, float x) {
+  __shared__ float s_part[NW];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+  if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.0f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) t += s_part[w];
+    atomicAdd(l1.loss, l1.scale * t);
+  }
+}
+
 template <int TILE, int BATCH>
 __global__ __launch_bounds__(WaveShape<TILE>::kThreads) void k_blend_fwd(
     RViews RV, const char* __restrict__ proj, size_t stride, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ vals, float* __restrict__ image, float* __restrict__ final_T,
-    uint32_t* __restrict__ last_contrib, float bg0, float bg1, float bg2, int skip_long) {
+    uint32_t* __restrict__ last_contrib, float bg0, float bg1, float bg2, int skip_long,
+    L1Fuse l1) {
   using S = WaveShape<TILE>;
   constexpr int NT = S::kThreads, NW = S::kWaves, R = S::kRegion, SUB = S::kSub, P = S::kPix;
   __shared__ float4 s_r0[BATCH];
@@ -127,6 +157,7 @@ __global__ __launch_bounds__(WaveShape<TILE>::kThreads) void k_blend_fwd(
 
   const int64_t pb = RV.pix_base[v];
   const int64_t plane = int64_t(W) * H;
+  float l1_abs = 0.0f;
 #pragma unroll
   for (int j = 0; j < SUB; ++j)
 #pragma unroll
@@ -135,13 +166,17 @@ __global__ __launch_bounds__(WaveShape<TILE>::kThreads) void k_blend_fwd(
       const int x = rx0 + i * 8 + lx, y = ry0 + j * 8 + ly;
       if (x < W && y < H) {
         const int64_t o = int64_t(y) * W + x;
-        image[3 * pb + o] = fmaf(T[p], bg0, C0[p]);
-        image[3 * pb + plane + o] = fmaf(T[p], bg1, C1[p]);
-        image[3 * pb + 2 * plane + o] = fmaf(T[p], bg2, C2[p]);
+        const float c0 = fmaf(T[p], bg0, C0[p]), c1 = fmaf(T[p], bg1, C1[p]),
+                    c2 = fmaf(T[p], bg2, C2[p]);
+        image[3 * pb + o] = c0;
+        image[3 * pb + plane + o] = c1;
+        image[3 * pb + 2 * plane + o] = c2;
         final_T[pb + o] = T[p];
         last_contrib[pb + o] = last[p];
+        if (l1.target) l1_abs += l1_pixel(l1, 3 * pb + o, plane, c0, c1, c2);
       }
     }
+  if (l1.loss) l1_block_add<NW>(l1, l1_abs);
 }
 
 // ---- long lists (low resolutions: few tiles, thousands of entries each): one
@@ -184,7 +219,7 @@ template <int TILE>
 __global__ __launch_bounds__(64 * kFWaves) void k_blend_fwd_long(
     RViews RV, const char* __restrict__ proj, size_t stride, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ vals, float* __restrict__ image, float* __restrict__ final_T,
-    uint32_t* __restrict__ last_contrib, float bg0, float bg1, float bg2) {
+    uint32_t* __restrict__ last_contrib, float bg0, float bg1, float bg2, L1Fuse l1) {
   constexpr int GX = TileShape<TILE>::kGroupsX, Q = TileShape<TILE>::kGroups;
   __shared__ float4 s_r0[kFWaves][kFBatch];
   __shared__ float4 s_r1[kFWaves][kFBatch];
@@ -202,6 +237,7 @@ __global__ __launch_bounds__(64 * kFWaves) void k_blend_fwd_long(
   float4* r1s = s_r1[wv];
   float* bs = s_b[wv];
   uint32_t* ms = s_mask[wv];
+  float l1_abs = 0.0f;  // over the block's tiles
 
   for (int t = blockIdx.x; t < RV.total_tiles; t += gridDim.x) {
     const uint32_t start = ranges[2 * t], end = ranges[2 * t + 1];
@@ -350,22 +386,27 @@ __global__ __launch_bounds__(64 * kFWaves) void k_blend_fwd_long(
         if (x < W && y < H) {
           const float4 st = s_st[q][lane];
           const int64_t o = int64_t(y) * W + x;
-          image[3 * pb + o] = fmaf(st.x, bg0, st.y);
-          image[3 * pb + plane + o] = fmaf(st.x, bg1, st.z);
-          image[3 * pb + 2 * plane + o] = fmaf(st.x, bg2, st.w);
+          const float c0 = fmaf(st.x, bg0, st.y), c1 = fmaf(st.x, bg1, st.z),
+                      c2 = fmaf(st.x, bg2, st.w);
+          image[3 * pb + o] = c0;
+          image[3 * pb + plane + o] = c1;
+          image[3 * pb + 2 * plane + o] = c2;
           final_T[pb + o] = st.x;
           last_contrib[pb + o] = s_last[q][lane];
+          if (l1.target) l1_abs += l1_pixel(l1, 3 * pb + o, plane, c0, c1, c2);
         }
       }
     }
     __syncthreads();  // the block's next tile rewrites the LDS
   }
+  if (l1.loss) l1_block_add<kFWaves>(l1, l1_abs);
 }
 
 template <int TILE>
 hipError_t launch_tile(int batch, const RViews& RV, const char* proj, size_t stride,
                        const uint32_t* ranges, const uint32_t* vals, float* image,
-                       float* final_T, uint32_t* last_contrib, const float* bg, hipStream_t st) {
+                       float* final_T, uint32_t* last_contrib, const float* bg, const L1Fuse& l1,
+                       hipStream_t st) {
   const dim3 grid(unsigned(RV.total_tiles)), block(WaveShape<TILE>::kThreads);
   // launches with few tiles hand long lists to the list-parallel kernel
   const int skip_long = split_long_lists(RV, TILE) ? 1 : 0;
@@ -373,23 +414,23 @@ hipError_t launch_tile(int batch, const RViews& RV, const char* proj, size_t str
     const unsigned nb = unsigned(RV.total_tiles < kFLongBlocks ? RV.total_tiles : kFLongBlocks);
     GS_LAUNCH("k_blend_fwd_long", HIP_KERNEL_NAME(k_blend_fwd_long<TILE <= 16 ? TILE : 16>),
               dim3(nb), dim3(64 * kFWaves), 0, st, RV, proj, stride, ranges, vals, image, final_T,
-              last_contrib, bg[0], bg[1], bg[2]);
+              last_contrib, bg[0], bg[1], bg[2], l1);
   }
   switch (batch) {
     case 128:
       GS_LAUNCH("k_blend_fwd", HIP_KERNEL_NAME(k_blend_fwd<TILE, 128>), grid, block, 0, st, RV, proj,
                          stride, ranges, vals, image, final_T, last_contrib, bg[0], bg[1], bg[2],
-                         skip_long);
+                         skip_long, l1);
       break;
     case 256:
       GS_LAUNCH("k_blend_fwd", HIP_KERNEL_NAME(k_blend_fwd<TILE, 256>), grid, block, 0, st, RV, proj,
                          stride, ranges, vals, image, final_T, last_contrib, bg[0], bg[1], bg[2],
-                         skip_long);
+                         skip_long, l1);
       break;
     default:
       GS_LAUNCH("k_blend_fwd", HIP_KERNEL_NAME(k_blend_fwd<TILE, 512>), grid, block, 0, st, RV, proj,
                          stride, ranges, vals, image, final_T, last_contrib, bg[0], bg[1], bg[2],
-                         skip_long);
+                         skip_long, l1);
       break;
   }
   return hipGetLastError();
@@ -399,20 +440,21 @@ hipError_t launch_tile(int batch, const RViews& RV, const char* proj, size_t str
 
 hipError_t launch_render_fwd(const Views& V, int n, const gs_raster_cfg& cfg, const char* proj,
                              const uint32_t* ranges, const uint32_t* vals, float* image,
-                             float* final_T, uint32_t* last_contrib, hipStream_t st) {
+                             float* final_T, uint32_t* last_contrib, const L1Fuse& l1,
+                             hipStream_t st) {
   if (V.total_tiles == 0) return hipSuccess;
   const RViews RV = make_rviews(V);
   const size_t stride = ProjLayout(n).stride;
   switch (cfg.tile) {
     case 8:
       return launch_tile<8>(cfg.lds_batch, RV, proj, stride, ranges, vals, image, final_T,
-                            last_contrib, cfg.bg, st);
+                            last_contrib, cfg.bg, l1, st);
     case 16:
       return launch_tile<16>(cfg.lds_batch, RV, proj, stride, ranges, vals, image, final_T,
-                             last_contrib, cfg.bg, st);
+                             last_contrib, cfg.bg, l1, st);
     default:
       return launch_tile<32>(cfg.lds_batch, RV, proj, stride, ranges, vals, image, final_T,
-                             last_contrib, cfg.bg, st);
+                             last_contrib, cfg.bg, l1, st);
   }
 }
 

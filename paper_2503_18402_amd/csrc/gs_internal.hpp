@@ -205,9 +205,25 @@ hipError_t launch_bin_sort_radix(const Views& V, int n, const char* proj, int64_
                                  uint64_t* keys, uint32_t* vals, uint32_t* ranges,
                                  int64_t* n_pairs_dev, hipStream_t st);
 
+// L1 loss gradient of the backbones, dL = scale * sign(image - target) (sign(0) = 0).
+__host__ __device__ __forceinline__ float l1_sign(float d, float scale) {
+  return (d > 0.0f) ? scale : ((d < 0.0f) ? -scale : 0.0f);
+}
+
+// The same gradient written by the forward blend beside each image value it
+// stores (the image layout); with `loss`, scale * sum |image - target| is added
+// to it, one float atomic per workgroup.  target == nullptr: the forward only.
+struct L1Fuse {
+  const float* target;
+  float* dL;
+  float* loss;
+  float scale;
+};
+
 hipError_t launch_render_fwd(const Views& V, int n, const gs_raster_cfg& cfg, const char* proj,
                              const uint32_t* ranges, const uint32_t* vals, float* image,
-                             float* final_T, uint32_t* last_contrib, hipStream_t st);
+                             float* final_T, uint32_t* last_contrib, const L1Fuse& l1,
+                             hipStream_t st);
 
 size_t render_bwd_ws_bytes(int n_views, int n, int64_t cap);
 hipError_t launch_render_bwd(const Views& V, int n, const gs_raster_cfg& cfg,

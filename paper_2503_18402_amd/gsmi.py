@@ -73,6 +73,8 @@ def lib() -> ctypes.CDLL:
             "gs_bin_sort_radix": (i32, [i32, cam_p, cfg_p, i32, vp, i64, vp, sz, vp, vp, vp, vp,
                                         vp]),
             "gs_render_fwd": (i32, [i32, cam_p, cfg_p, i32, vp, vp, vp, vp, vp, vp, vp]),
+            "gs_render_fwd_l1": (i32, [i32, cam_p, cfg_p, i32, vp, vp, vp, vp, vp, vp, vp,
+                                       c_float, vp, vp, vp]),
             "gs_render_bwd_workspace_bytes": (sz, [i32, i32, i64]),
             "gs_render_bwd": (i32, [i32, cam_p, cfg_p, i32, vp, vp, vp, vp, vp, i32, vp, vp, vp,
                                     vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, i64, vp, sz, vp]),
@@ -223,6 +225,14 @@ def gs_render_fwd(cams_c, cfg, n, proj, ranges, vals, image, final_T, last_contr
     _check("gs_render_fwd", lib().gs_render_fwd(
         len(cams_c), cams_c, ctypes.byref(cfg), int(n), _ptr(proj), _ptr(ranges), _ptr(vals),
         _ptr(image), _ptr(final_T), _ptr(last_contrib), _stream(stream)))
+
+
+def gs_render_fwd_l1(cams_c, cfg, n, proj, ranges, vals, image, final_T, last_contrib, target,
+                     scale, dL_dimage, loss_sum=None, stream=None):
+    _check("gs_render_fwd_l1", lib().gs_render_fwd_l1(
+        len(cams_c), cams_c, ctypes.byref(cfg), int(n), _ptr(proj), _ptr(ranges), _ptr(vals),
+        _ptr(image), _ptr(final_T), _ptr(last_contrib), _ptr(target), float(scale),
+        _ptr(dL_dimage), _ptr(loss_sum), _stream(stream)))
 
 
 def gs_render_bwd_workspace_bytes(n_views: int, n: int, capacity: int) -> int:

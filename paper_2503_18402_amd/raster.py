@@ -176,9 +176,9 @@ class Pipeline:
     """Preallocated buffers for one training step over a fixed set of views.
 
     ``step()`` enqueues the whole hot path on the current stream with no host
-    synchronisation and no allocation: preprocess, bin_sort, render_fwd, L1
-    loss gradient against ``targets``, render_bwd and one fused Adam step over
-    all parameter groups.  Every view of the set goes into one launch per
+    synchronisation and no allocation: preprocess, bin_sort, render_fwd with
+    the L1 loss gradient against ``targets`` (one ``gs_render_fwd_l1`` call),
+    render_bwd and one fused Adam step over all parameter groups.  Every view of the set goes into one launch per
     kernel.  ``overflowed()`` reads the pair count once to check the capacity
     after the fact; a captured HIP graph of ``step()`` replays the same work.
 
@@ -255,23 +255,40 @@ class Pipeline:
         self.track_loss = True   # False: the fused step skips the loss value (gradient only)
         self.graph = None
 
-    def forward(self, stream=None):
+    def forward(self, stream=None, l1: bool = False):
+        """Preprocess, bin_sort and the forward blend.  With ``l1`` the forward also
+        writes the L1 loss gradient (``gs_render_fwd_l1``; the loss value too when
+        ``track_loss``), so the backward that follows is called with ``l1_done``."""
         p = self.params
         gsmi.gs_preprocess(self.cams_c, self.cfg, self.n, p["means"], p["log_scales"],
                            p["quats"], p["opacity_logits"], p["sh"], self.sh_degree, self.proj,
                            stream)
         gsmi.gs_bin_sort(self.cams_c, self.cfg, self.n, self.proj, self.capacity, self.sort_ws,
                          None, self.vals, self.ranges, self.n_pairs, stream)
-        gsmi.gs_render_fwd(self.cams_c, self.cfg, self.n, self.proj, self.ranges, self.vals,
-                           self.image, self.final_T, self.last, stream)
+        if l1:
+            if self.track_loss:
+                self.loss.zero_()
+            gsmi.gs_render_fwd_l1(self.cams_c, self.cfg, self.n, self.proj, self.ranges,
+                                  self.vals, self.image, self.final_T, self.last, self.targets,
+                                  1.0 / self.image.numel(), self.dL,
+                                  self.loss if self.track_loss else None, stream)
+        else:
+            gsmi.gs_render_fwd(self.cams_c, self.cfg, self.n, self.proj, self.ranges, self.vals,
+                               self.image, self.final_T, self.last, stream)
 
-    def backward(self, stream=None, accumulate: bool = False):
-        """L1 loss gradient and gs_render_bwd; gradients are written, or added to
-        ``self.grads`` with ``accumulate`` (several views sharing one buffer)."""
-        p, g = self.params, self.grads
-        self.loss.zero_()
+    def _l1(self, stream):
+        if self.track_loss:
+            self.loss.zero_()
         gsmi.gs_l1_loss_grad(self.image, self.targets, 1.0 / self.image.numel(), self.dL,
-                             self.loss, stream)
+                             self.loss if self.track_loss else None, stream)
+
+    def backward(self, stream=None, accumulate: bool = False, l1_done: bool = False):
+        """L1 loss gradient (unless the forward wrote it: ``l1_done``) and
+        gs_render_bwd; gradients are written, or added to ``self.grads`` with
+        ``accumulate`` (several views sharing one buffer)."""
+        p, g = self.params, self.grads
+        if not l1_done:
+            self._l1(stream)
         gsmi.gs_render_bwd(self.cams_c, self.cfg, self.n, p["means"], p["log_scales"],
                            p["quats"], p["opacity_logits"], p["sh"], self.sh_degree, self.proj,
                            self.ranges, self.vals, self.final_T, self.last, self.dL, g["means"],
@@ -292,14 +309,12 @@ class Pipeline:
             gsmi.gs_adam_step(groups, step, self.betas[0], self.betas[1], self.eps, stream)
         self.step_no += 1
 
-    def backward_adam(self, stream=None):
-        """L1 loss gradient, then the backward pass fused with the Adam step
-        (device step counter)."""
+    def backward_adam(self, stream=None, l1_done: bool = False):
+        """L1 loss gradient (unless ``l1_done``), then the backward pass fused with
+        the Adam step (device step counter)."""
         p = self.params
-        if self.track_loss:
-            self.loss.zero_()
-        gsmi.gs_l1_loss_grad(self.image, self.targets, 1.0 / self.image.numel(), self.dL,
-                             self.loss if self.track_loss else None, stream)
+        if not l1_done:
+            self._l1(stream)
         gsmi.gs_render_bwd_adam(
             self.cams_c, self.cfg, self.n, p["means"], p["log_scales"], p["quats"],
             p["opacity_logits"], p["sh"], self.sh_degree, self.proj, self.ranges, self.vals,
@@ -315,13 +330,13 @@ class Pipeline:
             self.graph.replay()
             self.step_no += 1
             return
-        self.forward(stream)
-        if self.fused and adam_step is None:
-            self.backward_adam(stream)
-        elif self.sparse_adam:
+        if self.sparse_adam and adam_step is not None:
             raise ValueError("sparse Adam takes its step count from the device counter")
+        self.forward(stream, l1=True)
+        if self.fused and adam_step is None:
+            self.backward_adam(stream, l1_done=True)
         else:
-            self.backward(stream)
+            self.backward(stream, l1_done=True)
             self.adam(stream, adam_step)
 
     def set_view(self, cam, target: torch.Tensor):
@@ -338,16 +353,16 @@ class Pipeline:
     def capture(self):
         """Capture one whole step into a HIP graph; later ``step()`` calls replay it.
         The capacity must already be large enough (``overflowed()`` checks after)."""
-        self.forward()                   # warm every code path once (no parameter update)
-        self.backward()
+        self.forward(l1=True)            # warm every code path once (no parameter update)
+        self.backward(l1_done=True)
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
-            self.forward()
+            self.forward(l1=True)
             if self.fused:
-                self.backward_adam()
+                self.backward_adam(l1_done=True)
             else:
-                self.backward()
+                self.backward(l1_done=True)
                 self.adam()
         self.step_no -= 1                # capturing ran nothing
         self.graph = g

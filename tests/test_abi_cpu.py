@@ -94,6 +94,13 @@ def test_argument_errors(L):
     assert L.gs_adam_step(grp, 9, 1, 0.9, 0.999, 1e-15, None) == 1
     assert L.gs_adam_step(grp, 1, 1, 1.0, 0.999, 1e-15, None) == 1
     assert L.gs_l1_loss_grad(-1, 16, 16, 1.0, 16, None, None) == 1
+    # forward with the L1 gradient: a null target or gradient, a bad tile
+    assert L.gs_render_fwd_l1(1, cams, ctypes.byref(good), 10, 256, 256, 256, 256, 256, 256,
+                              None, 1.0, 256, None, None) == 1
+    assert L.gs_render_fwd_l1(1, cams, ctypes.byref(good), 10, 256, 256, 256, 256, 256, 256,
+                              256, 1.0, None, None, None) == 1
+    assert L.gs_render_fwd_l1(1, cams, ctypes.byref(gsmi.make_cfg(12, 256)), 10, 256, 256, 256,
+                              256, 256, 256, 256, 1.0, 256, None, None) == 1
     # fused backward + Adam: null moment table, a null moment, bad beta, misaligned SH moments
     ptrs = (ctypes.c_void_p * 5)(*([256] * 5))
     lrs = (ctypes.c_float * 6)(*([1e-3] * 6))
