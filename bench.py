@@ -27,7 +27,8 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-# FP32 vector peak without packed-FP32 instructions (this build disables them):
+# FP32 vector peak without packed-FP32 instructions (the library is compiled with them
+# disabled):
 # 256 CUs x 64 lanes x 2 FLOP (FMA) x 2.4 GHz
 ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 # algorithmic FLOPs per (pixel, Gaussian) evaluation of Eq. 1 in the forward:
@@ -82,8 +83,8 @@ def log(msg):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path shards by "
-              "views across GPUs but no multi-GPU run is part of this build.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path would shard "
+              "by views across GPUs, which is not implemented.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2503_18402_amd import gsmi, raster, scenes
