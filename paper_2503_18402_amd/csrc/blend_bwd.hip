@@ -498,10 +498,23 @@ __global__ __launch_bounds__(256) void k_pair_sum(const char* __restrict__ proj,
   for (int c = 0; c < kG; ++c) s[c] = 0.0f;
   const bool coop = tt > uint32_t(kCoopSlots);
   if (!coop) {
+    // four slots' loads in flight per step (a lane past its last slot reloads
+    // slot k, which exists); the sums still add slot after slot in order
     const float* pg = pair_grad + size_t(off) * kG;
-    for (uint32_t k = 0; k < tt; ++k)
+    for (uint32_t k = 0; k < tt; k += 4) {
+      float x[4][kG];
 #pragma unroll
-      for (int c = 0; c < kG; ++c) s[c] += pg[size_t(k) * kG + c];
+      for (int u = 0; u < 4; ++u) {
+        const float* q = pg + size_t(k + u < tt ? k + u : k) * kG;
+#pragma unroll
+        for (int c = 0; c < kG; ++c) x[u][c] = q[c];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (k + u < tt)
+#pragma unroll
+          for (int c = 0; c < kG; ++c) s[c] += x[u][c];
+    }
   }
   // the wave's long items, one after the other (all lanes take part)
   for (uint64_t bm = __ballot(coop); bm != 0ull; bm &= bm - 1ull) {
