@@ -571,8 +571,10 @@ struct ChainOut {
 };
 
 // Chains Gaussian g's 2D gradients of every view to its parameters.  Returns
-// false, leaving O untouched, when no view has a pair of g.
-__device__ __forceinline__ bool chain_grad(const Views& V, const ChainIn& I, int g, ChainOut& O) {
+// false, leaving O untouched, when no view has a pair of g.  sh_row: g's 48
+// SH coefficients (in LDS), or nullptr to read them from I.sh.
+__device__ __forceinline__ bool chain_grad(const Views& V, const ChainIn& I, int g, ChainOut& O,
+                                           const float* sh_row = nullptr) {
   const ProjLayout L(I.n);
   const int64_t M = int64_t(V.n_views) * I.n;
   const int K = (I.sh_degree + 1) * (I.sh_degree + 1);
@@ -623,7 +625,7 @@ __device__ __forceinline__ bool chain_grad(const Views& V, const ChainIn& I, int
   const float c3 = V.filter3d ? filter3d_coef(s0, s1, s2, f3) : 1.0f;
   const float o = 1.0f / (1.0f + expf(-I.opacity_logits[g]));
   const float low = V.mip2d ? kMip2d : kDilation;
-  const float* shg = I.sh + size_t(g) * GS_SH_COEFFS * 3;
+  const float* shg = sh_row ? sh_row : I.sh + size_t(g) * GS_SH_COEFFS * 3;
 
   float dm[3] = {0, 0, 0}, dS[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   float dop = 0.0f, m2abs = 0.0f;
@@ -811,11 +813,29 @@ __global__ __launch_bounds__(128) void k_chain(Views V, ChainIn I, int accumulat
                                                float* __restrict__ d_opacity_logits,
                                                float* __restrict__ d_sh,
                                                float* __restrict__ d_mean2d_abs) {
+  // the block's SH coefficients staged in LDS as in k_chain_adam
+  constexpr int F = GS_SH_COEFFS * 3, kRow = F + 1;
+  __shared__ float s_sh[128 * kRow];
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  {
+    const int g0 = blockIdx.x * blockDim.x;
+    const int rows = (I.n - g0 < 128) ? I.n - g0 : 128;
+    const float4* src = reinterpret_cast<const float4*>(I.sh + size_t(g0) * F);
+    for (int i = threadIdx.x; i < rows * (F / 4); i += 128) {
+      const float4 q = src[i];
+      const int f = 4 * i, row = f / F, k = f - row * F;
+      float* d = s_sh + row * kRow + k;
+      d[0] = q.x;
+      d[1] = q.y;
+      d[2] = q.z;
+      d[3] = q.w;
+    }
+  }
+  __syncthreads();
   if (g >= I.n) return;
   ChainOut O;
   float* dshg = d_sh + size_t(g) * GS_SH_COEFFS * 3;
-  if (!chain_grad(V, I, g, O)) {
+  if (!chain_grad(V, I, g, O, s_sh + threadIdx.x * kRow)) {
     if (!accumulate) {
       for (int k = 0; k < 3; ++k) d_means[3 * g + k] = d_log_scales[3 * g + k] = 0.0f;
       reinterpret_cast<float4*>(d_quats)[g] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -876,14 +896,35 @@ struct AdamGroups {
 
 __global__ __launch_bounds__(kCA) void k_chain_adam(Views V, ChainIn I, AdamGroups A,
                                                     float* __restrict__ d_mean2d_abs) {
-  __shared__ float4 s_g[kCA * GS_SH_COEFFS * 3 / 4];
+  // the block's SH coefficients arrive in LDS with coalesced 16-byte loads (rows
+  // of an odd stride, conflict-free) for the chain rule's direction term; the
+  // same LDS then holds the SH gradients for the Adam loop
+  constexpr int F = GS_SH_COEFFS * 3, kRow = F + 1;
+  __shared__ __align__(16) float s_buf[kCA * kRow];
+  float4* s_g = reinterpret_cast<float4*>(s_buf);
   __shared__ float s_c[2];
   __shared__ int s_upd[kCA];
   if (threadIdx.x == 0) adam_bias(A.step_dev, A.b1, A.b2, s_c[0], s_c[1]);
   const int g = blockIdx.x * kCA + threadIdx.x;
+  {
+    const int g0 = blockIdx.x * kCA;
+    const int rows = (I.n - g0 < kCA) ? I.n - g0 : kCA;
+    const float4* src = reinterpret_cast<const float4*>(I.sh + size_t(g0) * F);
+    for (int i = threadIdx.x; i < rows * (F / 4); i += kCA) {
+      const float4 q = src[i];
+      const int f = 4 * i, row = f / F, k = f - row * F;
+      float* d = s_buf + row * kRow + k;
+      d[0] = q.x;
+      d[1] = q.y;
+      d[2] = q.z;
+      d[3] = q.w;
+    }
+  }
+  __syncthreads();
   ChainOut O;
   bool have = false;
-  if (g < I.n) have = chain_grad(V, I, g, O);
+  if (g < I.n) have = chain_grad(V, I, g, O, s_buf + threadIdx.x * kRow);
+  __syncthreads();  // every row is read before the gradients overwrite the LDS
   const bool upd = have || !A.sparse;
   s_upd[threadIdx.x] = upd ? 1 : 0;
   if (!have) {
