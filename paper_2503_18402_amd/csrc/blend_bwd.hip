@@ -228,7 +228,8 @@ __global__ __launch_bounds__(64) void k_blend_bwd(
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const float* __restrict__ final_T, const uint32_t* __restrict__ last_contrib,
     const float* __restrict__ dL_dimage, const uint32_t* __restrict__ grad_off,
-    float* __restrict__ pair_grad, int64_t cap, float bg0, float bg1, float bg2, int skip_long) {
+    float* __restrict__ pair_grad, int64_t cap, float bg0, float bg1, float bg2, int skip_long,
+    const uint32_t* __restrict__ order) {
   __shared__ float4 s_r0[BATCH];
   __shared__ float4 s_r1[BATCH];
   __shared__ float s_b[BATCH];
@@ -236,7 +237,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd(
   __shared__ uint32_t s_pidx[BATCH];
   const BwdStage S{s_r0, s_r1, s_b, s_mask, s_pidx};
 
-  const int t = xcd_tile(blockIdx.x, RV);
+  const int t = order ? int(order[blockIdx.x]) : xcd_tile(blockIdx.x, RV);
   const uint32_t start = ranges[2 * t], end = ranges[2 * t + 1];
   const int v = view_of_tile(RV, t);
   if (skip_long && end - start > long_list_threshold<TILE>(RV, v)) return;
@@ -1022,19 +1023,101 @@ struct BwdWs {
   }
 };
 
+// ---- static balancing of the one-wave-per-tile backward.  All of its waves
+// are resident at once, so a SIMD's time is the sum of its waves' work, and
+// tiles dealt out in index order leave the busiest SIMD about 1.2x the mean.
+// k_tile_cost estimates each tile's work from the forward's last_contrib (the
+// evaluations per lane plus a per-entry term for the walk length);
+// k_tile_order ranks the tiles by it (256 buckets, heaviest first) and deals
+// the ranks out in rounds of kOrderRound blocks, every other round reversed,
+// so that blocks b and b + kOrderRound pair a heavy tile with a light one.
+// Which block takes which tile changes no result.
+constexpr int kOrderRound = 256;
+
+template <int TILE>
+__global__ __launch_bounds__(64) void k_tile_cost(RViews RV,
+                                                  const uint32_t* __restrict__ last_contrib,
+                                                  uint32_t* __restrict__ cost) {
+  constexpr int GX = TileShape<TILE>::kGroupsX, Q = TileShape<TILE>::kGroups;
+  const int t = blockIdx.x;
+  const int v = view_of_tile(RV, t);
+  const int lt = t - RV.tile_base[v];
+  const int gw = RV.gw[v], W = RV.W[v], H = RV.H[v];
+  const int tx = lt % gw, ty = lt / gw;
+  const int lane = threadIdx.x, lx = lane & 7, ly = lane >> 3;
+  uint32_t sum = 0, mx = 0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int x = tx * TILE + (q % GX) * 8 + lx, y = ty * TILE + (q / GX) * 8 + ly;
+    const uint32_t l = (x < W && y < H) ? last_contrib[RV.pix_base[v] + int64_t(y) * W + x] : 0u;
+    sum += l;
+    mx = max(mx, l);
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    sum += uint32_t(__shfl_xor(int(sum), d, 64));
+    mx = max(mx, uint32_t(__shfl_xor(int(mx), d, 64)));
+  }
+  if (lane == 0) cost[t] = sum / 64u + mx / 2u;
+}
+
+__global__ __launch_bounds__(1024) void k_tile_order(int n_tiles, const uint32_t* __restrict__ cost,
+                                                     uint32_t* __restrict__ order) {
+  __shared__ uint32_t s_hist[256], s_off[256], s_max;
+  const int tid = threadIdx.x;
+  if (tid < 256) s_hist[tid] = 0u;
+  if (tid == 0) s_max = 0u;
+  __syncthreads();
+  uint32_t mx = 0;
+  for (int i = tid; i < n_tiles; i += 1024) mx = max(mx, cost[i]);
+  atomicMax(&s_max, mx);
+  __syncthreads();
+  const uint64_t top = uint64_t(s_max) + 1u;
+  auto bucket = [&](uint32_t c) { return 255u - uint32_t(uint64_t(c) * 256u / top); };
+  for (int i = tid; i < n_tiles; i += 1024) atomicAdd(&s_hist[bucket(cost[i])], 1u);
+  __syncthreads();
+  // exclusive scan of the 256 bucket counts: four waves, then their totals
+  __shared__ uint32_t s_wsum[4];
+  uint32_t inc = 0;
+  if (tid < 256) {
+    const int lane = tid & 63;
+    inc = s_hist[tid];
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += y;
+    }
+    if (lane == 63) s_wsum[tid >> 6] = inc;
+  }
+  __syncthreads();
+  if (tid < 256) {
+    uint32_t before = 0;
+    for (int w = 0; w < (tid >> 6); ++w) before += s_wsum[w];
+    s_off[tid] = before + inc - s_hist[tid];
+  }
+  __syncthreads();
+  const int full = n_tiles / kOrderRound;  // complete rounds
+  for (int i = tid; i < n_tiles; i += 1024) {
+    const int r = int(atomicAdd(&s_off[bucket(cost[i])], 1u));  // rank, heaviest first
+    const int round = r / kOrderRound, j = r - round * kOrderRound;
+    const int b = (round < full && (round & 1)) ? round * kOrderRound + (kOrderRound - 1 - j) : r;
+    order[b] = uint32_t(i);
+  }
+}
+
 template <int TILE>
 void launch_bwd_tile(int batch, dim3 grid, const RViews& RV, int n, const char* proj,
                      size_t stride, const uint32_t* ranges, const uint32_t* vals,
                      const float* final_T, const uint32_t* last_contrib, const float* dL,
                      const uint32_t* goff, float* pairs, int64_t cap, const float* bg,
-                     hipStream_t st) {
+                     const uint32_t* order, hipStream_t st) {
   const dim3 block(64);
   // launches with few tiles hand long lists to the list-parallel kernel
   const int split = split_long_lists(RV, TILE) ? 1 : 0;
 #define GS_BWD_LAUNCH(B)                                                                       \
   GS_LAUNCH("k_blend_bwd", HIP_KERNEL_NAME(k_blend_bwd<TILE, B>), grid, block, 0, st, RV, n, proj,   \
                      stride, ranges, vals, final_T, last_contrib, dL, goff, pairs, cap, bg[0], \
-                     bg[1], bg[2], split)
+                     bg[1], bg[2], split, split ? nullptr : order)
   switch (batch) {
     case 128: GS_BWD_LAUNCH(128); break;
     case 256: GS_BWD_LAUNCH(256); break;
@@ -1076,18 +1159,43 @@ hipError_t bwd_to_planes(const Views& V, int n, const gs_raster_cfg& cfg, const 
   if (V.total_tiles > 0) {
     const RViews RV = make_rviews(V);
     const dim3 grid(unsigned(V.total_tiles));
+    // the balanced tile order (launches without list-parallel tiles), kept in
+    // the 2D-gradient planes, which k_pair_sum writes only after the blend
+    const uint32_t* order = nullptr;
+    const size_t T = size_t(V.total_tiles);
+    if (!split_long_lists(RV, cfg.tile) && size_t(4) * kG * size_t(M) >= 8 * T) {
+      uint32_t* cost = reinterpret_cast<uint32_t*>(ws + B.g2d);
+      uint32_t* ord = cost + T;
+      switch (cfg.tile) {
+        case 8:
+          GS_LAUNCH("k_tile_cost", HIP_KERNEL_NAME(k_tile_cost<8>), grid, dim3(64), 0, st, RV,
+                    last_contrib, cost);
+          break;
+        case 16:
+          GS_LAUNCH("k_tile_cost", HIP_KERNEL_NAME(k_tile_cost<16>), grid, dim3(64), 0, st, RV,
+                    last_contrib, cost);
+          break;
+        default:
+          GS_LAUNCH("k_tile_cost", HIP_KERNEL_NAME(k_tile_cost<32>), grid, dim3(64), 0, st, RV,
+                    last_contrib, cost);
+          break;
+      }
+      GS_LAUNCH("k_tile_order", k_tile_order, dim3(1), dim3(1024), 0, st, V.total_tiles, cost,
+                ord);
+      order = ord;
+    }
     switch (cfg.tile) {
       case 8:
         launch_bwd_tile<8>(cfg.lds_batch, grid, RV, n, proj, L.stride, ranges, vals, final_T,
-                           last_contrib, dL_dimage, goff, pairs, cap, cfg.bg, st);
+                           last_contrib, dL_dimage, goff, pairs, cap, cfg.bg, order, st);
         break;
       case 16:
         launch_bwd_tile<16>(cfg.lds_batch, grid, RV, n, proj, L.stride, ranges, vals, final_T,
-                            last_contrib, dL_dimage, goff, pairs, cap, cfg.bg, st);
+                            last_contrib, dL_dimage, goff, pairs, cap, cfg.bg, order, st);
         break;
       default:
         launch_bwd_tile<32>(cfg.lds_batch, grid, RV, n, proj, L.stride, ranges, vals, final_T,
-                            last_contrib, dL_dimage, goff, pairs, cap, cfg.bg, st);
+                            last_contrib, dL_dimage, goff, pairs, cap, cfg.bg, order, st);
         break;
     }
   }
