@@ -1026,55 +1026,27 @@ struct BwdWs {
 // ---- static balancing of the one-wave-per-tile backward.  All of its waves
 // are resident at once, so a SIMD's time is the sum of its waves' work, and
 // tiles dealt out in index order leave the busiest SIMD about 1.2x the mean.
-// k_tile_cost estimates each tile's work from the forward's last_contrib (the
-// evaluations per lane plus a per-entry term for the walk length);
-// k_tile_order ranks the tiles by it (256 buckets, heaviest first) and deals
-// the ranks out in rounds of kOrderRound blocks, every other round reversed,
-// so that blocks b and b + kOrderRound pair a heavy tile with a light one.
-// Which block takes which tile changes no result.
+// k_tile_order ranks the tiles by their list length (256 buckets, longest
+// first) and deals the ranks out in rounds of kOrderRound blocks, every other
+// round reversed, so that blocks b and b + kOrderRound pair a heavy tile with
+// a light one.  Which block takes which tile changes no result.
 constexpr int kOrderRound = 256;
 
-template <int TILE>
-__global__ __launch_bounds__(64) void k_tile_cost(RViews RV,
-                                                  const uint32_t* __restrict__ last_contrib,
-                                                  uint32_t* __restrict__ cost) {
-  constexpr int GX = TileShape<TILE>::kGroupsX, Q = TileShape<TILE>::kGroups;
-  const int t = blockIdx.x;
-  const int v = view_of_tile(RV, t);
-  const int lt = t - RV.tile_base[v];
-  const int gw = RV.gw[v], W = RV.W[v], H = RV.H[v];
-  const int tx = lt % gw, ty = lt / gw;
-  const int lane = threadIdx.x, lx = lane & 7, ly = lane >> 3;
-  uint32_t sum = 0, mx = 0;
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int x = tx * TILE + (q % GX) * 8 + lx, y = ty * TILE + (q / GX) * 8 + ly;
-    const uint32_t l = (x < W && y < H) ? last_contrib[RV.pix_base[v] + int64_t(y) * W + x] : 0u;
-    sum += l;
-    mx = max(mx, l);
-  }
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    sum += uint32_t(__shfl_xor(int(sum), d, 64));
-    mx = max(mx, uint32_t(__shfl_xor(int(mx), d, 64)));
-  }
-  if (lane == 0) cost[t] = sum / 64u + mx / 2u;
-}
-
-__global__ __launch_bounds__(1024) void k_tile_order(int n_tiles, const uint32_t* __restrict__ cost,
+__global__ __launch_bounds__(1024) void k_tile_order(int n_tiles, const uint32_t* __restrict__ ranges,
                                                      uint32_t* __restrict__ order) {
+  auto cost = [&](int i) { return ranges[2 * i + 1] - ranges[2 * i]; };
   __shared__ uint32_t s_hist[256], s_off[256], s_max;
   const int tid = threadIdx.x;
   if (tid < 256) s_hist[tid] = 0u;
   if (tid == 0) s_max = 0u;
   __syncthreads();
   uint32_t mx = 0;
-  for (int i = tid; i < n_tiles; i += 1024) mx = max(mx, cost[i]);
+  for (int i = tid; i < n_tiles; i += 1024) mx = max(mx, cost(i));
   atomicMax(&s_max, mx);
   __syncthreads();
   const uint64_t top = uint64_t(s_max) + 1u;
   auto bucket = [&](uint32_t c) { return 255u - uint32_t(uint64_t(c) * 256u / top); };
-  for (int i = tid; i < n_tiles; i += 1024) atomicAdd(&s_hist[bucket(cost[i])], 1u);
+  for (int i = tid; i < n_tiles; i += 1024) atomicAdd(&s_hist[bucket(cost(i))], 1u);
   __syncthreads();
   // exclusive scan of the 256 bucket counts: four waves, then their totals
   __shared__ uint32_t s_wsum[4];
@@ -1098,7 +1070,7 @@ __global__ __launch_bounds__(1024) void k_tile_order(int n_tiles, const uint32_t
   __syncthreads();
   const int full = n_tiles / kOrderRound;  // complete rounds
   for (int i = tid; i < n_tiles; i += 1024) {
-    const int r = int(atomicAdd(&s_off[bucket(cost[i])], 1u));  // rank, heaviest first
+    const int r = int(atomicAdd(&s_off[bucket(cost(i))], 1u));  // rank, heaviest first
     const int round = r / kOrderRound, j = r - round * kOrderRound;
     const int b = (round < full && (round & 1)) ? round * kOrderRound + (kOrderRound - 1 - j) : r;
     order[b] = uint32_t(i);
@@ -1163,24 +1135,9 @@ hipError_t bwd_to_planes(const Views& V, int n, const gs_raster_cfg& cfg, const 
     // the 2D-gradient planes, which k_pair_sum writes only after the blend
     const uint32_t* order = nullptr;
     const size_t T = size_t(V.total_tiles);
-    if (!split_long_lists(RV, cfg.tile) && size_t(4) * kG * size_t(M) >= 8 * T) {
-      uint32_t* cost = reinterpret_cast<uint32_t*>(ws + B.g2d);
-      uint32_t* ord = cost + T;
-      switch (cfg.tile) {
-        case 8:
-          GS_LAUNCH("k_tile_cost", HIP_KERNEL_NAME(k_tile_cost<8>), grid, dim3(64), 0, st, RV,
-                    last_contrib, cost);
-          break;
-        case 16:
-          GS_LAUNCH("k_tile_cost", HIP_KERNEL_NAME(k_tile_cost<16>), grid, dim3(64), 0, st, RV,
-                    last_contrib, cost);
-          break;
-        default:
-          GS_LAUNCH("k_tile_cost", HIP_KERNEL_NAME(k_tile_cost<32>), grid, dim3(64), 0, st, RV,
-                    last_contrib, cost);
-          break;
-      }
-      GS_LAUNCH("k_tile_order", k_tile_order, dim3(1), dim3(1024), 0, st, V.total_tiles, cost,
+    if (!split_long_lists(RV, cfg.tile) && size_t(4) * kG * size_t(M) >= 4 * T) {
+      uint32_t* ord = reinterpret_cast<uint32_t*>(ws + B.g2d);
+      GS_LAUNCH("k_tile_order", k_tile_order, dim3(1), dim3(1024), 0, st, V.total_tiles, ranges,
                 ord);
       order = ord;
     }
