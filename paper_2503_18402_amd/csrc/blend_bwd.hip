@@ -999,15 +999,6 @@ struct GoffDst {
   __device__ void operator()(int64_t i, uint32_t pos, uint32_t) const { off[i] = pos; }
 };
 
-__global__ __launch_bounds__(256) void k_zero_pairs(float* __restrict__ p,
-                                                    const int64_t* __restrict__ total,
-                                                    int64_t cap) {
-  const int64_t np = (*total < cap) ? *total : cap;
-  const int64_t m = np * kG;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < m;
-       i += int64_t(gridDim.x) * blockDim.x)
-    p[i] = 0.0f;
-}
 
 struct BwdWs {
   size_t goff, bsum, total, g2d, pairs, bytes;
@@ -1026,14 +1017,16 @@ struct BwdWs {
 // ---- static balancing of the one-wave-per-tile backward.  All of its waves
 // are resident at once, so a SIMD's time is the sum of its waves' work, and
 // tiles dealt out in index order leave the busiest SIMD about 1.2x the mean.
-// k_tile_order ranks the tiles by their list length (256 buckets, longest
-// first) and deals the ranks out in rounds of kOrderRound blocks, every other
-// round reversed, so that blocks b and b + kOrderRound pair a heavy tile with
-// a light one.  Which block takes which tile changes no result.
+// Block 0 of k_zero_pairs ranks the tiles by their list length (256 buckets,
+// longest first) and deals the ranks out in rounds of kOrderRound blocks,
+// every other round reversed, so that blocks b and b + kOrderRound pair a
+// heavy tile with a light one.  Which block takes which tile changes no
+// result.
 constexpr int kOrderRound = 256;
 
-__global__ __launch_bounds__(1024) void k_tile_order(int n_tiles, const uint32_t* __restrict__ ranges,
-                                                     uint32_t* __restrict__ order) {
+// one 1024-thread block; every thread of the block calls it
+__device__ void tile_order_block(int n_tiles, const uint32_t* __restrict__ ranges,
+                                 uint32_t* __restrict__ order) {
   auto cost = [&](int i) { return ranges[2 * i + 1] - ranges[2 * i]; };
   __shared__ uint32_t s_hist[256], s_off[256], s_max;
   const int tid = threadIdx.x;
@@ -1075,6 +1068,25 @@ __global__ __launch_bounds__(1024) void k_tile_order(int n_tiles, const uint32_t
     const int b = (round < full && (round & 1)) ? round * kOrderRound + (kOrderRound - 1 - j) : r;
     order[b] = uint32_t(i);
   }
+}
+
+// Blocks 1.. clear the pair slots [0, min(total, cap)); block 0 meanwhile
+// writes the backward's tile order when `order` is set.
+constexpr int kZeroBlocks = 512;
+__global__ __launch_bounds__(1024) void k_zero_pairs(float* __restrict__ p,
+                                                     const int64_t* __restrict__ total,
+                                                     int64_t cap, int n_tiles,
+                                                     const uint32_t* __restrict__ ranges,
+                                                     uint32_t* __restrict__ order) {
+  if (blockIdx.x == 0) {
+    if (order) tile_order_block(n_tiles, ranges, order);
+    return;
+  }
+  const int64_t np = (*total < cap) ? *total : cap;
+  const int64_t m = np * kG;
+  for (int64_t i = int64_t(blockIdx.x - 1) * blockDim.x + threadIdx.x; i < m;
+       i += int64_t(gridDim.x - 1) * blockDim.x)
+    p[i] = 0.0f;
 }
 
 template <int TILE>
@@ -1127,20 +1139,17 @@ hipError_t bwd_to_planes(const Views& V, int n, const gs_raster_cfg& cfg, const 
   hipError_t e = scan_exclusive(TTSrc{proj, L.stride, L.tt, n}, GoffDst{goff}, Count{nullptr, M},
                                 M, reinterpret_cast<uint32_t*>(ws + B.bsum), total, nullptr, st);
   if (e != hipSuccess) return e;
-  GS_LAUNCH("k_zero_pairs", k_zero_pairs, dim3(2048), dim3(256), 0, st, pairs, total, cap);
+  // the balanced tile order (launches without list-parallel tiles), kept in the
+  // 2D-gradient planes, which k_pair_sum writes only after the blend
+  const RViews RV = make_rviews(V);
+  const size_t T = size_t(V.total_tiles);
+  uint32_t* order = nullptr;
+  if (T > 0 && !split_long_lists(RV, cfg.tile) && size_t(4) * kG * size_t(M) >= 4 * T)
+    order = reinterpret_cast<uint32_t*>(ws + B.g2d);
+  GS_LAUNCH("k_zero_pairs", k_zero_pairs, dim3(1 + kZeroBlocks), dim3(1024), 0, st, pairs, total,
+            cap, V.total_tiles, ranges, order);
   if (V.total_tiles > 0) {
-    const RViews RV = make_rviews(V);
     const dim3 grid(unsigned(V.total_tiles));
-    // the balanced tile order (launches without list-parallel tiles), kept in
-    // the 2D-gradient planes, which k_pair_sum writes only after the blend
-    const uint32_t* order = nullptr;
-    const size_t T = size_t(V.total_tiles);
-    if (!split_long_lists(RV, cfg.tile) && size_t(4) * kG * size_t(M) >= 4 * T) {
-      uint32_t* ord = reinterpret_cast<uint32_t*>(ws + B.g2d);
-      GS_LAUNCH("k_tile_order", k_tile_order, dim3(1), dim3(1024), 0, st, V.total_tiles, ranges,
-                ord);
-      order = ord;
-    }
     switch (cfg.tile) {
       case 8:
         launch_bwd_tile<8>(cfg.lds_batch, grid, RV, n, proj, L.stride, ranges, vals, final_T,
