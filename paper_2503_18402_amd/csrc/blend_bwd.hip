@@ -905,7 +905,8 @@ __global__ __launch_bounds__(kCA) void k_chain_adam(Views V, ChainIn I, AdamGrou
   float4* s_g = reinterpret_cast<float4*>(s_buf);
   __shared__ float s_c[2];
   __shared__ int s_upd[kCA];
-  if (threadIdx.x == 0) adam_bias(A.step_dev, A.b1, A.b2, s_c[0], s_c[1]);
+  // the count was advanced for this step by k_zero_pairs, earlier in the same call
+  if (threadIdx.x == 0) adam_bias(A.step_dev, A.b1, A.b2, s_c[0], s_c[1], 0);
   const int g = blockIdx.x * kCA + threadIdx.x;
   {
     const int g0 = blockIdx.x * kCA;
@@ -1071,14 +1072,17 @@ __device__ void tile_order_block(int n_tiles, const uint32_t* __restrict__ range
 }
 
 // Blocks 1.. clear the pair slots [0, min(total, cap)); block 0 meanwhile
-// writes the backward's tile order when `order` is set.
+// writes the backward's tile order when `order` is set and, for the backward
+// fused with Adam, advances the device step count (`step_dev`) once.
 constexpr int kZeroBlocks = 512;
 __global__ __launch_bounds__(1024) void k_zero_pairs(float* __restrict__ p,
                                                      const int64_t* __restrict__ total,
                                                      int64_t cap, int n_tiles,
                                                      const uint32_t* __restrict__ ranges,
-                                                     uint32_t* __restrict__ order) {
+                                                     uint32_t* __restrict__ order,
+                                                     int32_t* __restrict__ step_dev) {
   if (blockIdx.x == 0) {
+    if (step_dev && threadIdx.x == 0) *step_dev += 1;
     if (order) tile_order_block(n_tiles, ranges, order);
     return;
   }
@@ -1129,7 +1133,7 @@ namespace {
 hipError_t bwd_to_planes(const Views& V, int n, const gs_raster_cfg& cfg, const char* proj,
                          const uint32_t* ranges, const uint32_t* vals, const float* final_T,
                          const uint32_t* last_contrib, const float* dL_dimage, int64_t cap,
-                         char* ws, float** g2d_out, hipStream_t st) {
+                         char* ws, float** g2d_out, int32_t* step_dev, hipStream_t st) {
   const int64_t M = int64_t(V.n_views) * n;
   const BwdWs B(M, cap);
   uint32_t* goff = reinterpret_cast<uint32_t*>(ws + B.goff);
@@ -1147,7 +1151,7 @@ hipError_t bwd_to_planes(const Views& V, int n, const gs_raster_cfg& cfg, const 
   if (T > 0 && !split_long_lists(RV, cfg.tile) && size_t(4) * kG * size_t(M) >= 4 * T)
     order = reinterpret_cast<uint32_t*>(ws + B.g2d);
   GS_LAUNCH("k_zero_pairs", k_zero_pairs, dim3(1 + kZeroBlocks), dim3(1024), 0, st, pairs, total,
-            cap, V.total_tiles, ranges, order);
+            cap, V.total_tiles, ranges, order, step_dev);
   if (V.total_tiles > 0) {
     const dim3 grid(unsigned(V.total_tiles));
     switch (cfg.tile) {
@@ -1186,7 +1190,7 @@ hipError_t launch_render_bwd(const Views& V, int n, const gs_raster_cfg& cfg,
   if (int64_t(V.n_views) * n == 0) return hipSuccess;
   float* g2d = nullptr;
   hipError_t e = bwd_to_planes(V, n, cfg, proj, ranges, vals, final_T, last_contrib, dL_dimage,
-                               cap, static_cast<char*>(ws), &g2d, st);
+                               cap, static_cast<char*>(ws), &g2d, nullptr, st);
   if (e != hipSuccess) return e;
   const ChainIn I{means, log_scales, quats, opacity_logits, sh, proj, g2d, n, sh_degree};
   GS_LAUNCH("k_chain", k_chain, dim3(unsigned((n + 127) / 128)), dim3(128), 0, st, V, I,
@@ -1204,7 +1208,7 @@ hipError_t launch_render_bwd_adam(const Views& V, int n, const gs_raster_cfg& cf
   if (n > 0) {
     float* g2d = nullptr;
     hipError_t e = bwd_to_planes(V, n, cfg, proj, ranges, vals, final_T, last_contrib,
-                                 dL_dimage, cap, static_cast<char*>(ws), &g2d, st);
+                                 dL_dimage, cap, static_cast<char*>(ws), &g2d, A.step_dev, st);
     if (e != hipSuccess) return e;
     const ChainIn I{means, log_scales, quats, opacity_logits, sh, proj, g2d, n, sh_degree};
     AdamGroups G{};
@@ -1222,6 +1226,7 @@ hipError_t launch_render_bwd_adam(const Views& V, int n, const gs_raster_cfg& cf
     G.sparse = A.sparse;
     GS_LAUNCH("k_chain_adam", k_chain_adam, dim3(unsigned((n + kCA - 1) / kCA)), dim3(kCA), 0,
               st, V, I, G, d_mean2d_abs);
+    return hipGetLastError();  // k_zero_pairs advanced the step count
   }
   return launch_step_inc(A.step_dev, st);
 }

@@ -135,9 +135,11 @@ __device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, 
 }
 
 // bias corrections of step t = *step_dev + 1
+// bias corrections of step t = *step_dev + ahead (ahead = 1 before the count
+// is advanced for this step, 0 after)
 __device__ inline void adam_bias(const int32_t* step_dev, float b1, float b2, float& c1,
-                                 float& c2) {
-  const double t = double(*step_dev + 1);
+                                 float& c2, int ahead = 1) {
+  const double t = double(*step_dev + ahead);
   c1 = float(1.0 / (1.0 - pow(double(b1), t)));
   c2 = float(1.0 / (1.0 - pow(double(b2), t)));
 }
