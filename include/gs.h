@@ -263,8 +263,12 @@ gs_status gs_adam_step_device(const gs_adam_group* groups, int32_t n_groups, int
  *     applies to the SH degree-0 coefficients (values 0..2 of a Gaussian's
  *     48) and lr[5] to the higher degrees.  lr[5] = lr[4] gives the update of
  *     gs_adam_step_device with one SH group.
- *   step_dev: device int32; step t = *step_dev + 1 is taken, then the counter
- *     is incremented on the stream (see gs_adam_step_device).
+ *   step_dev: device int32 step counter (0 before the first step).  The call
+ *     advances it by one on the stream, in the first kernel it launches,
+ *     before any update, and takes step t = its new value; afterwards it
+ *     equals the counter gs_adam_step_device leaves.  If a later launch of
+ *     the call fails (GS_ERR_DEVICE), the counter may have advanced without
+ *     an update.
  *   The other arguments are those of gs_render_bwd, with the same workspace.
  * ------------------------------------------------------------------------- */
 gs_status gs_render_bwd_adam(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
@@ -284,8 +288,8 @@ gs_status gs_render_bwd_adam(int32_t n_views, const gs_camera* cams, const gs_ra
  * of the n_views views -- culled, behind the camera or off every image --
  * keeps its parameters and both moments unchanged; every other Gaussian takes
  * exactly the update of gs_render_bwd_adam, bias-corrected with the global
- * step t = *step_dev + 1, even where its gradient is zero.  The counter
- * advances once per call.  d_mean2d_abs, when given, is written for every
+ * step t (the counter's value on entry plus one), even where its gradient is
+ * zero.  The counter advances once per call, as in gs_render_bwd_adam.  d_mean2d_abs, when given, is written for every
  * Gaussian (0 for the untouched ones).  Arguments, layouts, alignment and
  * errors are those of gs_render_bwd_adam.
  * ------------------------------------------------------------------------- */

@@ -143,3 +143,25 @@ def downsample_aa(img, h: int, w: int) -> np.ndarray:
     x = np.asarray(img, dtype=np.float64)
     Wy, Wx = aa_weights(x.shape[1], h), aa_weights(x.shape[2], w)
     return np.stack([Wy @ x[c] @ Wx.T for c in range(x.shape[0])])
+
+
+# --------------------------------------------- the position learning rate
+def position_lr(k: int, factors, lr_init: float, lr_final: float) -> float:
+    """Learning rate of the Gaussian means at iteration k (supplementary,
+    "Learning Rate"): held at its initial value during the low-resolution
+    stage and allowed to decay only from i* = argmin_i {floor(r^(i)) = 1}.
+
+    ``factors`` is the integer factor floor(r^(i)) rendered at each of the S
+    iterations i = 0..S-1.  Reading (the paper names the switch point, not
+    the decay): from i* on, the rate decays as in the 3DGS backbone, the
+    exponential (log-linear) interpolation from lr_init to lr_final, here
+    spread over the remaining iterations, so that it reaches lr_final at
+    i = S.  Without a full-resolution iteration the rate never decays."""
+    f = np.asarray(factors)
+    S = f.shape[0]
+    full = [i for i in range(S) if int(f[i]) == 1]
+    if not full or k <= full[0]:
+        return float(lr_init)
+    i_star = full[0]
+    t = (k - i_star) / (S - i_star)
+    return float(np.exp((1.0 - t) * np.log(lr_init) + t * np.log(lr_final)))

@@ -134,7 +134,6 @@ __device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, 
   p -= lr * mh / (sqrtf(vh) + A.eps);
 }
 
-// bias corrections of step t = *step_dev + 1
 // bias corrections of step t = *step_dev + ahead (ahead = 1 before the count
 // is advanced for this step, 0 after)
 __device__ inline void adam_bias(const int32_t* step_dev, float b1, float b2, float& c1,

@@ -165,6 +165,7 @@ class Trainer:
                           else P_FIN_INIT_FACTOR * self.p_init)
             self.zgen = torch.Generator(device=dev).manual_seed(densify.seed)
         self.log = []
+        self.lr_log = []   # the position learning rate given to each iteration's step
         self.step_dev = torch.zeros(1, dtype=torch.int32, device=dev)
         self.m = {k: torch.zeros_like(params[k]) for k in raster.PARAM_NAMES}
         self.v = {k: torch.zeros_like(params[k]) for k in raster.PARAM_NAMES}
@@ -233,16 +234,22 @@ class Trainer:
                 raise RuntimeError("pair capacity overflowed during training")
 
     def means_lr_at(self, k: int) -> float:
-        lo, hi = self.means_lr
-        if k < self.k_full:
-            return lo
+        """Position learning rate at iteration k (supplementary, "Learning
+        Rate"): the initial value up to the first iteration rendered at
+        floor(r) = 1, then the backbone's exponential decay to the final value
+        over the remaining iterations."""
+        lr0, lr1 = self.means_lr
+        if k <= self.k_full:
+            return lr0
         t = (k - self.k_full) / max(1, self.iters - self.k_full)
-        return math.exp((1.0 - t) * math.log(lo) + t * math.log(hi))
+        return math.exp((1.0 - t) * math.log(lr0) + t * math.log(lr1))
 
     def _densify(self, k: int):
         from .densify import densify_step
         c = self.dcfg
-        r = self.sched.r(k) if self.sched is not None else 1.0
+        # Eq. 4 takes the modulated factor floor(r^(i)), the one rendered at
+        # iteration k (Sec. 5, "Implementation Details")
+        r = float(self.factors[k])
 
         def k_of(kept, cand):
             if not c.schedule:
@@ -291,6 +298,7 @@ class Trainer:
             views, gt_f, pipe = self.levels[f]
             pipe.set_view(views[v], gt_f[v])
             pipe.lrs["means"] = self.means_lr_at(k)
+            self.lr_log.append(pipe.lrs["means"])
             pipe.step()
             torch.maximum(pipe.pairs_max, pipe.n_pairs, out=pipe.pairs_max)
             if c is not None and k < stop:

@@ -51,6 +51,14 @@ def test_schedule_factors_match_oracle_and_training_improves():
     after = train.psnr(params, cams, gt)
     assert after > before + 0.5, (before, after)
     assert sum(out["iters_per_factor"].values()) == iters
+    # the position learning rate each iteration ran with (supplementary, "Learning
+    # Rate"): held until the first floor(r) = 1 iteration, then decaying
+    assert not near.any()
+    want = [O.position_lr(k, ref, *tr.means_lr) for k in range(iters)]
+    assert len(tr.lr_log) == iters
+    assert np.allclose(tr.lr_log, want, rtol=1e-12, atol=0.0)
+    k_star = int(np.argmax(ref == 1))
+    assert tr.lr_log[k_star] == tr.means_lr[0] and tr.lr_log[k_star + 1] < tr.means_lr[0]
 
 
 def test_unscheduled_loop_renders_full_resolution():
@@ -66,11 +74,17 @@ def test_unscheduled_loop_renders_full_resolution():
 def test_densifying_loop_follows_eq4_eq5(scheduled):
     """DashGaussian mode: every densification step takes
     k = clamp(round(P_i) - N', 0, candidates) with P_fin from Eq. 5 (momentum,
-    starting at 5 P_init) and P_i from Eq. 4 at the step's r; the backbone mode
-    (full resolution, no schedule) densifies every candidate."""
+    starting at 5 P_init) and P_i from Eq. 4 at the modulated factor
+    floor(r(k)) of the oracle's schedule for the same views (Sec. 5,
+    "Implementation Details"); the backbone mode (full resolution, no
+    schedule) densifies every candidate."""
     from oracle import densify as OD
     cams = scenes.fibonacci_cameras(8, 3.0, 160, 120, 150.0)
-    gt = torch.from_numpy(_gt(cams, seed=75)).cuda()
+    gt_np = _gt(cams, seed=75)
+    gt = torch.from_numpy(gt_np).cuda()
+    if scheduled:
+        r_o, s_o, _ = O.schedule_knots(O.magnitude_map(gt_np.astype(np.float64)), 300, a=4.0,
+                                       m=4, norm="mean")
     params = raster.to_device(scenes.make_scene(3000, seed=76, mean_range=1.0, ls_mu=-3.0,
                                                 ls_sigma=0.4), "cuda")
     dcfg = train.DensifyConfig(every=40, start=40, stop=200, grad_thr=2e-4, min_opacity=0.005,
@@ -85,7 +99,9 @@ def test_densifying_loop_follows_eq4_eq5(scheduled):
         kept = e["n"] - e["n_pruned"]
         if scheduled:
             p_fin = OD.budget_update(p_fin, e["n_candidates"])
-            target = OD.primitive_target(e["iteration"], 300, e["r"], 3000.0, p_fin)
+            r_floor = O.render_factor(e["iteration"], r_o, s_o)
+            assert e["r"] == r_floor
+            target = OD.primitive_target(e["iteration"], 300, float(r_floor), 3000.0, p_fin)
             want = int(max(0, min(int(round(target)) - kept, e["n_candidates"])))
             assert e["p_fin"] == pytest.approx(p_fin)
         else:

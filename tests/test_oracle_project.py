@@ -121,3 +121,64 @@ def test_culls():
     P = project.project(sc, cam)
     assert list(P["live"]) == [False, False, True, False]
     assert list(P["tiles_touched"] > 0) == [False, False, True, False]
+
+
+def test_world_to_camera_on_a_hand_built_camera():
+    # camera at (2, 0, 0) looking at the origin along -x, image +y = world +y:
+    # rows of R are the camera axes in world coordinates, x_c = R (x - c)
+    R = np.array([[0.0, 0.0, 1.0], [0.0, 1.0, 0.0], [-1.0, 0.0, 0.0]], np.float32)
+    t = np.array([0.0, 0.0, 2.0], np.float32)
+    cam = scenes.Camera(R=R, t=t, fx=100.0, fy=80.0, cx=32.0, cy=24.0, width=64, height=48)
+    sc = scenes.make_scene(4, seed=8)
+    sc["means"][:] = [[0, 0, 0], [0, 0, 1], [1, 0, 0], [0, 1, 0]]
+    P = project.project(sc, cam)
+    want_xc = np.array([[0, 0, 2], [1, 0, 2], [0, 0, 1], [0, 1, 2]], np.float64)
+    assert np.abs(P["xc"] - want_xc).max() < 1e-12
+    want_uv = np.array([[32, 24], [32 + 100 / 2, 24], [32, 24], [32, 24 + 80 / 2]], np.float64)
+    assert np.abs(P["mean2d"] - want_uv).max() < 1e-12
+    assert np.array_equal(P["depth_f32"], np.float32([2, 2, 1, 2]))
+
+
+def test_anisotropic_projection_matches_projected_samples():
+    """The splat of a small anisotropic Gaussian seen by a rotated, off-axis
+    camera: project 10^6 samples of the 3D Gaussian through the pinhole and
+    compare their mean and covariance with mean2D and Sigma' - 0.3 I (Sec. 3:
+    G is splatted to G2D).  The EWA form is the first-order (Jacobian)
+    approximation of the pinhole map, so with scales of 0.5-2% of the depth
+    the second-order bias is far below the Monte-Carlo error (checked in
+    whitened units, where both are O(1/sqrt(N)) and O((s/z)^2)).  A
+    transposed camera rotation, in x_c or in J W Sigma W^T J^T, moves the
+    mean by pixels and rotates the covariance: both fail by orders of
+    magnitude."""
+    rng = np.random.default_rng(17)
+    cam = scenes.look_at((1.3, -0.8, -3.5), (0.2, 0.1, 0.3), 640, 480, 900.0, fy=780.0,
+                         down=(0.2, 1.0, 0.1))
+    Rw, tw = cam.R.astype(np.float64), cam.t.astype(np.float64)
+    assert np.abs(Rw - np.diag(np.diag(Rw))).max() > 0.2     # a genuinely rotated camera
+    sc = scenes.make_scene(6, seed=18)
+    sc["means"][:] = rng.uniform(-0.6, 0.6, size=(6, 3)).astype(np.float32)
+    sc["log_scales"][:] = np.log(rng.uniform(0.01, 0.06, size=(6, 3))).astype(np.float32)
+    P = project.project(sc, cam)
+    N = 1_000_000
+    corr, ratio = [], []
+    for i in range(6):
+        q = sc["quats"][i].astype(np.float64)
+        Rq = Rotation.from_quat(q[[1, 2, 3, 0]] / np.linalg.norm(q)).as_matrix()
+        s = np.exp(sc["log_scales"][i].astype(np.float64))
+        x = sc["means"][i].astype(np.float64) + (rng.standard_normal((N, 3)) * s) @ Rq.T
+        xc = x @ Rw.T + tw
+        uv = np.stack([cam.fx * xc[:, 0] / xc[:, 2] + cam.cx,
+                       cam.fy * xc[:, 1] / xc[:, 2] + cam.cy], 1)
+        mean = uv.mean(0)
+        cov = np.cov(uv.T)
+        c00, c01, c11 = P["cov2d"][i]
+        lin = np.array([[c00 - 0.3, c01], [c01, c11 - 0.3]])
+        # whiten by the linearised covariance: the sample covariance becomes ~I
+        ev, V = np.linalg.eigh(lin)
+        Wh = V @ np.diag(ev ** -0.5) @ V.T
+        assert np.abs(Wh @ cov @ Wh - np.eye(2)).max() < 6e-3, i
+        assert np.abs(Wh @ (mean - P["mean2d"][i])).max() < 6e-3, i
+        corr.append(abs(c01) / math.sqrt((c00 - 0.3) * (c11 - 0.3)))
+        ratio.append(ev.max() / ev.min())
+    # the footprints are anisotropic and tilted, so the check has teeth
+    assert max(corr) > 0.5 and np.median(corr) > 0.2 and max(ratio) > 3.0, (corr, ratio)

@@ -133,3 +133,45 @@ def test_one_over_f_spectrum_places_r_m():
     r_mean = O.schedule_knots(M, 100, a=4.0, m=1, norm="mean")[0][1]
     assert r_sum == pytest.approx(4.0 ** (1 / 3), rel=0.05)
     assert r_mean == pytest.approx(4.0, rel=0.05)
+
+
+# ---- the position learning rate (supplementary, "Learning Rate")
+LR0, LR1 = 1.6e-4, 1.6e-6
+
+
+def test_position_lr_is_held_until_the_first_full_resolution_iteration():
+    # a schedule of 4 -> 2 -> 1 with the first full-resolution iteration at 60
+    factors = [4] * 25 + [3] * 10 + [2] * 25 + [1] * 40
+    S = len(factors)
+    i_star = next(i for i, f in enumerate(factors) if f == 1)   # brute-force argmin
+    assert i_star == 60
+    for k in range(i_star + 1):
+        assert O.position_lr(k, factors, LR0, LR1) == LR0
+    assert O.position_lr(i_star + 1, factors, LR0, LR1) < LR0
+    # decays monotonically and reaches the final value at the end
+    lrs = [O.position_lr(k, factors, LR0, LR1) for k in range(i_star, S + 1)]
+    assert all(b < a for a, b in zip(lrs, lrs[1:]))
+    assert lrs[-1] == pytest.approx(LR1, rel=1e-12)
+
+
+def test_position_lr_decay_is_log_linear():
+    # the backbone's decay is exponential: log(lr) is linear in the iteration,
+    # so the midpoint of the decaying stretch sits at the geometric mean
+    factors = [2] * 20 + [1] * 80
+    mid = 20 + 40
+    assert O.position_lr(mid, factors, LR0, LR1) == pytest.approx(math.sqrt(LR0 * LR1), rel=1e-12)
+    logs = np.log([O.position_lr(k, factors, LR0, LR1) for k in range(20, 101)])
+    assert np.abs(np.diff(logs, 2)).max() < 1e-12
+    # a linear decay would put the midpoint at the arithmetic mean instead
+    assert abs(O.position_lr(mid, factors, LR0, LR1) - 0.5 * (LR0 + LR1)) > 1e-5
+
+
+def test_position_lr_special_cases():
+    # every iteration at full resolution: the backbone's decay from iteration 0,
+    # lr0 (lr1 / lr0)^(k / S)
+    S = 50
+    for k in (0, 1, 17, 49, 50):
+        want = LR0 * (LR1 / LR0) ** (k / S)
+        assert O.position_lr(k, [1] * S, LR0, LR1) == pytest.approx(want, rel=1e-12)
+    # never at full resolution: the rate is never allowed to decay
+    assert all(O.position_lr(k, [2] * S, LR0, LR1) == LR0 for k in range(S + 1))
