@@ -76,6 +76,18 @@ def _pixel_block(P, order, pix, W):
                 keep=keep, Tbefore=Tbefore, Tincl=Tincl, stop=stop, cols=cols)
 
 
+def _guard_flags(B: dict) -> np.ndarray:
+    """Pixels of a block with a discrete decision, up to and including the stop
+    column, inside the float32 guard band (alpha vs 1/255, T' vs 1e-4, the
+    0.99 clamp, power at 0)."""
+    upto = B["cols"] <= B["stop"][:, None]
+    near_cut = np.abs(B["alpha"] / ALPHA_MIN - 1.0) < ALPHA_GUARD
+    near_T = np.abs(B["Tincl"] / T_MIN - 1.0) < T_GUARD
+    near_clamp = B["valid"] & (np.abs(B["raw"] / ALPHA_MAX - 1.0) < CLAMP_GUARD)
+    near_pow = B["valid"] & (B["power"] > -1e-12)
+    return ((near_cut | near_T | near_clamp | near_pow) & upto).any(axis=1)
+
+
 def render_fwd(P: dict, bg=(0.0, 0.0, 0.0), pixels=None, chunk: int = 256,
                want_lists: bool = False) -> dict:
     """Blend every requested pixel (default: all, row-major).
@@ -109,13 +121,7 @@ def render_fwd(P: dict, bg=(0.0, 0.0, 0.0), pixels=None, chunk: int = 256,
         has = B["keep"].any(axis=1)
         lastcol = B["keep"].shape[1] - 1 - np.argmax(B["keep"][:, ::-1], axis=1)
         last[s:s + len(blk)] = np.where(has, order[lastcol] if len(order) else -1, -1)
-        # guard bands on the discrete decisions up to (and including) the stop column
-        upto = B["cols"] <= B["stop"][:, None]
-        near_cut = np.abs(B["alpha"] / ALPHA_MIN - 1.0) < ALPHA_GUARD
-        near_T = np.abs(B["Tincl"] / T_MIN - 1.0) < T_GUARD
-        near_clamp = B["valid"] & (np.abs(B["raw"] / ALPHA_MAX - 1.0) < CLAMP_GUARD)
-        near_pow = B["valid"] & (B["power"] > -1e-12)
-        flag[s:s + len(blk)] = ((near_cut | near_T | near_clamp | near_pow) & upto).any(axis=1)
+        flag[s:s + len(blk)] = _guard_flags(B)
         if want_lists:
             for r in range(len(blk)):
                 lists.append(order[B["keep"][r]])
@@ -132,6 +138,58 @@ def render_fwd(P: dict, bg=(0.0, 0.0, 0.0), pixels=None, chunk: int = 256,
     return out
 
 
+def _bwd_block(P: dict, cand: np.ndarray, blk: np.ndarray, g: np.ndarray, bg: np.ndarray):
+    """Backward of the pixels ``blk`` (dL/dC rows ``g`` [p,3]) over the Gaussians
+    ``cand`` taken in that order: per-candidate sums of the 2D gradients and of
+    the absolute values of their terms (the error scale)."""
+    W = P["width"]
+    rgb = P["rgb"][cand]
+    o = P["opacity"][cand]
+    a, b, c = P["conic"][cand, 0], P["conic"][cand, 1], P["conic"][cand, 2]
+    B = _pixel_block(P, cand, blk, W)
+    keep = B["keep"]
+    alpha = np.where(keep, B["alpha"], 0.0)
+    T = B["Tbefore"]
+    w = alpha * T                                         # [p,n]
+    Tf = np.prod(np.where(keep, 1.0 - alpha, 1.0), axis=1)
+    # colour behind each Gaussian: sum over later blended ones + T_final * bg
+    contrib_c = w[:, :, None] * rgb[None, :, :]           # [p,n,3]
+    rev = np.cumsum(contrib_c[:, ::-1, :], axis=1)[:, ::-1, :]
+    behind = rev - contrib_c + (Tf[:, None] * 1.0)[:, :, None] * bg[None, None, :]
+    dC_dalpha = T[:, :, None] * rgb[None, :, :] - behind / (1.0 - alpha)[:, :, None]
+    dL_dalpha = np.where(keep, np.einsum("pnc,pc->pn", dC_dalpha, g), 0.0)
+    unclamped = keep & (B["raw"] <= ALPHA_MAX)
+    G = B["G"]
+    dL_dpow = np.where(unclamped, dL_dalpha * o[None, :] * G, 0.0)
+    dx, dy = B["dx"], B["dy"]
+    terms = [dL_dpow * (a[None, :] * dx + b[None, :] * dy),
+             dL_dpow * (b[None, :] * dx + c[None, :] * dy),
+             dL_dpow * (-0.5 * dx * dx), dL_dpow * (-dx * dy), dL_dpow * (-0.5 * dy * dy),
+             np.where(unclamped, dL_dalpha * G, 0.0),
+             w * g[:, 0:1], w * g[:, 1:2], w * g[:, 2:3]]
+    return dict(d_mean=np.stack([terms[0].sum(axis=0), terms[1].sum(axis=0)], 1),
+                d_con=np.stack([terms[2].sum(axis=0), terms[3].sum(axis=0),
+                                terms[4].sum(axis=0)], 1),
+                d_op=terms[5].sum(axis=0), d_rgb=np.einsum("pn,pc->nc", w, g),
+                abs2d=np.stack([np.abs(t).sum(axis=0) for t in terms], 1),
+                contrib=keep.any(axis=0))
+
+
+def _bwd_out(n: int) -> dict:
+    return dict(d_mean2d=np.zeros((n, 2)), d_conic=np.zeros((n, 3)), d_opacity=np.zeros(n),
+                d_rgb=np.zeros((n, 3)), contrib=np.zeros(n, bool), abs2d=np.zeros((n, 9)))
+
+
+def _bwd_add(out: dict, cand: np.ndarray, r: dict):
+    """Add one block's per-candidate sums (``cand`` holds no index twice)."""
+    out["d_mean2d"][cand] += r["d_mean"]
+    out["d_conic"][cand] += r["d_con"]
+    out["d_opacity"][cand] += r["d_op"]
+    out["d_rgb"][cand] += r["d_rgb"]
+    out["abs2d"][cand] += r["abs2d"]
+    out["contrib"][cand] |= r["contrib"]
+
+
 def render_bwd_2d(P: dict, dL_dC: np.ndarray, bg=(0.0, 0.0, 0.0), pixels=None,
                   chunk: int = 256) -> dict:
     """Gradients of L w.r.t. the per-Gaussian 2D quantities.
@@ -145,58 +203,94 @@ def render_bwd_2d(P: dict, dL_dC: np.ndarray, bg=(0.0, 0.0, 0.0), pixels=None,
     pix = np.arange(W * H) if pixels is None else np.asarray(pixels, np.int64)
     g_all = np.asarray(dL_dC, F64).reshape(3, -1)
     order = _order(P)
-    rgb = P["rgb"][order]
-    o = P["opacity"][order]
-    a, b, c = P["conic"][order, 0], P["conic"][order, 1], P["conic"][order, 2]
     bg = np.asarray(bg, F64)
-    d_mean = np.zeros((len(order), 2))
-    d_con = np.zeros((len(order), 3))
-    d_op = np.zeros(len(order))
-    d_rgb = np.zeros((len(order), 3))
-    abs2d = np.zeros((len(order), 9))
-    contrib = np.zeros(len(order), bool)
+    out = _bwd_out(n)
     for s in range(0, pix.shape[0], chunk):
         blk = pix[s:s + chunk]
-        g = g_all[:, s:s + len(blk)].T                       # [p,3]
-        B = _pixel_block(P, order, blk, W)
-        keep = B["keep"]
-        alpha = np.where(keep, B["alpha"], 0.0)
-        T = B["Tbefore"]
-        w = alpha * T                                         # [p,n]
-        Tf = np.prod(np.where(keep, 1.0 - alpha, 1.0), axis=1)
-        # colour behind each Gaussian: sum over later blended ones + T_final * bg
-        contrib_c = w[:, :, None] * rgb[None, :, :]           # [p,n,3]
-        rev = np.cumsum(contrib_c[:, ::-1, :], axis=1)[:, ::-1, :]
-        behind = rev - contrib_c + (Tf[:, None] * 1.0)[:, :, None] * bg[None, None, :]
-        dC_dalpha = T[:, :, None] * rgb[None, :, :] - behind / (1.0 - alpha)[:, :, None]
-        dL_dalpha = np.where(keep, np.einsum("pnc,pc->pn", dC_dalpha, g), 0.0)
-        d_rgb += np.einsum("pn,pc->nc", w, g)
-        unclamped = keep & (B["raw"] <= ALPHA_MAX)
-        G = B["G"]
-        d_op += np.where(unclamped, dL_dalpha * G, 0.0).sum(axis=0)
-        dL_dpow = np.where(unclamped, dL_dalpha * o[None, :] * G, 0.0)
-        dx, dy = B["dx"], B["dy"]
-        d_con[:, 0] += (dL_dpow * (-0.5 * dx * dx)).sum(axis=0)
-        d_con[:, 1] += (dL_dpow * (-dx * dy)).sum(axis=0)
-        d_con[:, 2] += (dL_dpow * (-0.5 * dy * dy)).sum(axis=0)
-        terms = [dL_dpow * (a[None, :] * dx + b[None, :] * dy),
-                 dL_dpow * (b[None, :] * dx + c[None, :] * dy),
-                 dL_dpow * (-0.5 * dx * dx), dL_dpow * (-dx * dy), dL_dpow * (-0.5 * dy * dy),
-                 np.where(unclamped, dL_dalpha * G, 0.0),
-                 w * g[:, 0:1], w * g[:, 1:2], w * g[:, 2:3]]
-        d_mean[:, 0] += terms[0].sum(axis=0)
-        d_mean[:, 1] += terms[1].sum(axis=0)
-        for k in range(9):
-            abs2d[:, k] += np.abs(terms[k]).sum(axis=0)
-        contrib |= keep.any(axis=0)
-    out = dict(d_mean2d=np.zeros((n, 2)), d_conic=np.zeros((n, 3)), d_opacity=np.zeros(n),
-               d_rgb=np.zeros((n, 3)), contrib=np.zeros(n, bool), abs2d=np.zeros((n, 9)))
-    out["abs2d"][order] = abs2d
-    out["d_mean2d"][order] = d_mean
-    out["d_conic"][order] = d_con
-    out["d_opacity"][order] = d_op
-    out["d_rgb"][order] = d_rgb
-    out["contrib"][order] = contrib
+        _bwd_add(out, order, _bwd_block(P, order, blk, g_all[:, s:s + len(blk)].T, bg))
+    return out
+
+
+# ---------------------------------------------------------------- binned form
+def tile_candidates(P: dict):
+    """For each tile of the view (row-major), the live Gaussians whose
+    conservative footprint box covers it, in ascending (z_f32, index) order.
+    Every other Gaussian has alpha < 1/255 at each of the tile's pixel
+    centres, so it is skipped there: blending only these candidates gives the
+    same pixels as the brute force over all Gaussians."""
+    T, W, H = P["tile"], P["width"], P["height"]
+    gw, gh = -(-W // T), -(-H // T)
+    order = _order(P)
+    order = order[P["tiles_touched"][order] > 0]
+    r = P["rect"][order]
+    out = []
+    for ty in range(gh):
+        row = order[(r[:, 1] <= ty) & (r[:, 3] >= ty)]
+        rr = P["rect"][row]
+        for tx in range(gw):
+            out.append(row[(rr[:, 0] <= tx) & (rr[:, 2] >= tx)])
+    return out
+
+
+def tile_pixels(P: dict, t: int) -> np.ndarray:
+    """Row-major pixel indices of tile t (ragged at the right and bottom edges)."""
+    T, W, H = P["tile"], P["width"], P["height"]
+    gw = -(-W // T)
+    ty, tx = divmod(t, gw)
+    ys = np.arange(ty * T, min(H, (ty + 1) * T))
+    xs = np.arange(tx * T, min(W, (tx + 1) * T))
+    return (ys[:, None] * W + xs[None, :]).ravel()
+
+
+def render_fwd_binned(P: dict, bg=(0.0, 0.0, 0.0), tiles=None, cands=None) -> dict:
+    """``render_fwd`` over all pixels of the given tiles (default: every tile),
+    each pixel blending only its tile's candidates.  Returns image [3,npix],
+    final_T, n_contrib, last_id and the guard-band flag for the pixels
+    ``pixels`` (tile after tile, row-major inside each)."""
+    cands = tile_candidates(P) if cands is None else cands
+    tiles = range(len(cands)) if tiles is None else tiles
+    bg = np.asarray(bg, F64)
+    pix, img, fT, ncon, last, flag = [], [], [], [], [], []
+    for t in tiles:
+        blk = tile_pixels(P, t)
+        cand = cands[t]
+        pix.append(blk)
+        if len(cand) == 0:   # nothing reaches the tile: the background
+            img.append(np.repeat(bg[:, None], len(blk), axis=1))
+            fT.append(np.ones(len(blk)))
+            ncon.append(np.zeros(len(blk), np.int64))
+            last.append(np.full(len(blk), -1, np.int64))
+            flag.append(np.zeros(len(blk), bool))
+            continue
+        B = _pixel_block(P, cand, blk, P["width"])
+        w = np.where(B["keep"], B["alpha"] * B["Tbefore"], 0.0)
+        Tf = np.prod(np.where(B["keep"], 1.0 - B["alpha"], 1.0), axis=1)
+        img.append((w @ P["rgb"][cand]).T + Tf[None, :] * bg[:, None])
+        fT.append(Tf)
+        ncon.append(B["keep"].sum(axis=1))
+        has = B["keep"].any(axis=1)
+        lastcol = B["keep"].shape[1] - 1 - np.argmax(B["keep"][:, ::-1], axis=1)
+        last.append(np.where(has, cand[lastcol] if len(cand) else -1, -1))
+        flag.append(_guard_flags(B))
+    cat = lambda xs, ax=0: np.concatenate(xs, axis=ax) if xs else np.zeros(0)
+    return dict(pixels=cat(pix).astype(np.int64), image=cat(img, 1).reshape(3, -1),
+                final_T=cat(fT), n_contrib=cat(ncon).astype(np.int64),
+                last_id=cat(last).astype(np.int64), flag=cat(flag).astype(bool))
+
+
+def render_bwd_2d_binned(P: dict, dL_dC: np.ndarray, bg=(0.0, 0.0, 0.0), tiles=None,
+                         cands=None) -> dict:
+    """``render_bwd_2d`` with every pixel of the given tiles (default: all)
+    blending only its tile's candidates; ``dL_dC`` is [3,H,W]."""
+    cands = tile_candidates(P) if cands is None else cands
+    tiles = range(len(cands)) if tiles is None else tiles
+    g_all = np.asarray(dL_dC, F64).reshape(3, -1)
+    bg = np.asarray(bg, F64)
+    out = _bwd_out(P["mean2d"].shape[0])
+    for t in tiles:
+        blk = tile_pixels(P, t)
+        if len(cands[t]):
+            _bwd_add(out, cands[t], _bwd_block(P, cands[t], blk, g_all[:, blk].T, bg))
     return out
 
 

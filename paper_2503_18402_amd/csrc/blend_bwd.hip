@@ -1019,11 +1019,10 @@ struct BwdWs {
 // are resident at once, so a SIMD's time is the sum of its waves' work, and
 // tiles dealt out in index order leave the busiest SIMD about 1.2x the mean.
 // Block 0 of k_zero_pairs ranks the tiles by their list length (256 buckets,
-// longest first) and deals the ranks out in rounds of kOrderRound blocks,
-// every other round reversed, so that blocks b and b + kOrderRound pair a
-// heavy tile with a light one.  Which block takes which tile changes no
-// result.
-constexpr int kOrderRound = 256;
+// longest first) and deals the ranks out with order_block (rounds of
+// kOrderRound blocks, every other round reversed), so that blocks b and
+// b + kOrderRound pair a heavy tile with a light one.  Which block takes
+// which tile changes no result.
 
 // one 1024-thread block; every thread of the block calls it
 __device__ void tile_order_block(int n_tiles, const uint32_t* __restrict__ ranges,
@@ -1062,12 +1061,9 @@ __device__ void tile_order_block(int n_tiles, const uint32_t* __restrict__ range
     s_off[tid] = before + inc - s_hist[tid];
   }
   __syncthreads();
-  const int full = n_tiles / kOrderRound;  // complete rounds
   for (int i = tid; i < n_tiles; i += 1024) {
     const int r = int(atomicAdd(&s_off[bucket(cost(i))], 1u));  // rank, heaviest first
-    const int round = r / kOrderRound, j = r - round * kOrderRound;
-    const int b = (round < full && (round & 1)) ? round * kOrderRound + (kOrderRound - 1 - j) : r;
-    order[b] = uint32_t(i);
+    order[order_block(r, n_tiles)] = uint32_t(i);
   }
 }
 

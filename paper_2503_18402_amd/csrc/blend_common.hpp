@@ -74,6 +74,19 @@ __host__ __device__ __forceinline__ int xcd_tile(int b, const RViews& RV) {
   return RV.tile_base[RV.order[k]] + RV.xcd_start[x][k] + (idx - RV.xcd_off[x][k]);
 }
 
+// The backward's balanced tile order: tiles ranked by list length (rank 0 the
+// heaviest) are dealt to blocks in rounds of kOrderRound, every other
+// complete round reversed, so that blocks b and b + kOrderRound (which the
+// round-robin dispatch places on the same SIMDs) pair a heavy tile with a
+// light one.  Block of rank r; a bijection on [0, n_tiles).
+constexpr int kOrderRound = 256;
+
+__host__ __device__ __forceinline__ int order_block(int r, int n_tiles) {
+  const int full = n_tiles / kOrderRound;  // complete rounds
+  const int round = r / kOrderRound, j = r - round * kOrderRound;
+  return (round < full && (round & 1)) ? round * kOrderRound + (kOrderRound - 1 - j) : r;
+}
+
 // List-parallel blending, for launches with few tiles: when the whole launch
 // has fewer than kFewTiles tiles (a low-resolution view on its own), lists
 // longer than kLongList go to the list-parallel kernels (tiles of 8 and 16

@@ -3,6 +3,7 @@ and decode its opaque per-view records for comparison with the oracle."""
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
 import torch
@@ -69,33 +70,63 @@ def run(scene: dict, cams, tile=16, lds_batch=256, bg=(0.0, 0.0, 0.0), sh_degree
     return params, frame, grads
 
 
-def grad_violations(g, ref, rel=1e-3, abs_=1e-6, mask=None):
-    """Elements breaking |g - ref| <= rel |ref| + abs (rows in ``mask`` are skipped)."""
-    g = np.asarray(g, np.float64)
-    ref = np.asarray(ref, np.float64)
-    bad = np.abs(g - ref) > rel * np.abs(ref) + abs_
-    if mask is not None:
-        bad = bad & mask.reshape(mask.shape + (1,) * (bad.ndim - 1))
-    return bad
+def zero_flagged(w, F):
+    """The upstream dL/dC (a [3,H,W] image, or [3,P] at the oracle's sampled
+    pixels) with zeros at every pixel the oracle flags: one whose float32
+    decisions (alpha vs 1/255, T vs 1e-4, the 0.99 clamp) sit inside the guard
+    band.  Each pixel's part of every gradient is proportional to its
+    upstream, so with dL/dC = 0 there both sides take nothing from those
+    pixels and every Gaussian stays in the gradient check."""
+    w = np.array(w, dtype=np.float32, copy=True)
+    w.reshape(3, -1)[:, np.asarray(F["flag"]).reshape(-1)] = 0.0
+    return w
 
 
-def check_grads(g, ref, bound, mask=None, rel=1e-3, abs_=1e-6, cond=1e-3, max_frac=1e-3):
-    """Gradient parity.  Every element must satisfy
-        |g - ref| <= rel |ref| + abs + cond * S
-    where S is the oracle's scale of the terms summed into that element (a
-    float32 result that cancels down from large terms carries an error
-    proportional to S); and the elements breaking the plain rule
-    |g - ref| <= rel |ref| + abs must be at most ``max_frac`` of the checked
-    ones.  Returns the number of plain-rule violations."""
+def gaussian_flags(P):
+    """Gaussians with a per-Gaussian float32 decision in its guard band, which no
+    upstream can neutralise: a colour channel at the clamp at 0 (the SH
+    gradient is zeroed on one side only) or the opacity at the 1/255 cull."""
+    return P["flag_rgb"].any(1) | P["flag_opacity"]
+
+
+# Every check_grads call of the session: test, parameter, elements checked,
+# plain-rule violations and the worst error relative to each bound.
+RECORDS: list[dict] = []
+
+
+# Some mean-gradient elements cancel down to 1e-4 of the terms summed into them
+# (pixels on both sides of the centre, with upstreams of both signs); their
+# float32 accumulation error, a few ulps of the term scale S, can then exceed
+# 1e-3 of the result.  Tests where the plain rule failed for such an element
+# allow this fraction of the mean gradients to fall back on the 1e-5 S bound.
+MEANS_CANCELLATION_FRAC = 1e-3
+
+
+def check_grads(g, ref, bound, mask=None, rel=1e-3, abs_=1e-6, cond=1e-5, max_frac=0.0,
+                name=""):
+    """Gradient parity.  The plain rule is |g - ref| <= rel |ref| + abs for every
+    element; up to ``max_frac`` of the checked elements may break it, and those
+    must still satisfy
+        |g - ref| <= rel |ref| + abs + cond * S,
+    S the oracle's scale of the terms summed into that element (a float32
+    result that cancels down from large terms carries an error proportional
+    to S; 1e-5 S is about 80 ulps of it).  Every call is recorded in RECORDS;
+    returns the number of plain-rule violations."""
     g = np.asarray(g, np.float64)
     ref = np.asarray(ref, np.float64)
     err = np.abs(g - ref)
     m = np.ones(g.shape, bool) if mask is None else np.broadcast_to(
         mask.reshape(mask.shape + (1,) * (g.ndim - 1)), g.shape)
-    loose = (err > rel * np.abs(ref) + abs_ + cond * np.asarray(bound)) & m
-    assert not loose.any(), ("gradient outside the conditioned bound", int(loose.sum()),
+    plain = rel * np.abs(ref) + abs_
+    strict = (err > plain) & m
+    loose = (err > plain + cond * np.asarray(bound)) & m
+    RECORDS.append(dict(test=os.environ.get("PYTEST_CURRENT_TEST", "").split(" ")[0],
+                        param=name, checked=int(m.sum()), plain_violations=int(strict.sum()),
+                        worst_plain=float((err / plain)[m].max(initial=0.0)),
+                        worst_conditioned=float((err / (plain + cond * np.asarray(bound)))[m]
+                                                .max(initial=0.0))))
+    assert not loose.any(), ("gradient outside the conditioned bound", name, int(loose.sum()),
                              np.argwhere(loose)[:5].tolist())
-    strict = (err > rel * np.abs(ref) + abs_) & m
-    assert strict.sum() <= max_frac * m.sum(), ("too many plain-rule violations",
-                                                int(strict.sum()), int(m.sum()))
+    assert strict.sum() <= max_frac * m.sum(), ("plain-rule violations", name, int(strict.sum()),
+                                                int(m.sum()), np.argwhere(strict)[:5].tolist())
     return int(strict.sum())

@@ -1,7 +1,9 @@
 // Host check of the blend kernels' block -> tile mapping (blend_common.hpp):
 // for random mixes of view sizes it must be a bijection on [0, total tiles),
 // walk every XCD's share of a view contiguously, and reach the views in order
-// of increasing tile count.  Prints "ok" or the first failure; exit code 0/1.
+// of increasing tile count; and the backward's balanced rank -> block deal
+// (order_block) must be a bijection for every tile count.  Prints "ok" or
+// the first failure; exit code 0/1.
 #include <cstdio>
 #include <random>
 #include <vector>
@@ -48,6 +50,26 @@ int main() {
           return 1;
         }
       }
+  }
+  // the backward's balanced order: ranks -> blocks is a bijection for any
+  // tile count, pairs rank r of an odd complete round with block
+  // round * kOrderRound + (kOrderRound - 1 - j), and keeps the last partial round
+  for (int trial = 0; trial < 4000; ++trial) {
+    const int n = trial < 2100 ? trial : 1 + int(rng() % 200000);
+    std::vector<int> seen(n, 0);
+    for (int r = 0; r < n; ++r) {
+      const int b = gsk::order_block(r, n);
+      if (b < 0 || b >= n || seen[b]++) {
+        std::printf("order n=%d: rank %d -> block %d repeated or out of range\n", n, r, b);
+        return 1;
+      }
+      const int round = r / gsk::kOrderRound;
+      const bool rev = (round & 1) && (round + 1) * gsk::kOrderRound <= n;
+      if ((b / gsk::kOrderRound != round) || (rev != (b != r))) {
+        std::printf("order n=%d: rank %d -> block %d outside its round\n", n, r, b);
+        return 1;
+      }
+    }
   }
   std::printf("ok\n");
   return 0;

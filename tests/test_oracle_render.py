@@ -241,3 +241,32 @@ def test_error_scale_bounds_every_gradient():
     g[0, 14, 16] = 1.0
     B1 = render.render_bwd(sc, P, g)
     assert np.allclose(B1["g2d"]["abs2d"][:, 6], np.abs(B1["g2d"]["d_rgb"][:, 0]))
+
+
+@pytest.mark.parametrize("tile", [16, 8])
+def test_binned_form_equals_brute_force(tile):
+    """The binned oracle (each tile blends only the Gaussians whose conservative
+    footprint box covers it) gives the brute force's pixels and 2D gradients on
+    the 4096-Gaussian scene: every skipped Gaussian has alpha < 1/255 at the
+    tile's pixels, so only zero terms drop out of the sums."""
+    sc, cam = scenes.small_scene()
+    P = project.project(sc, cam, tile=tile)
+    Fb = render.render_fwd_binned(P)
+    F = render.render_fwd(P)
+    pix = Fb["pixels"]
+    assert np.array_equal(np.sort(pix), np.arange(cam.width * cam.height))
+    assert np.abs(Fb["image"] - F["image"].reshape(3, -1)[:, pix]).max() < 1e-12
+    assert np.abs(Fb["final_T"] - F["final_T"].reshape(-1)[pix]).max() < 1e-12
+    assert np.array_equal(Fb["last_id"], F["last_id"].reshape(-1)[pix])
+    assert np.array_equal(Fb["n_contrib"], F["n_contrib"].reshape(-1)[pix])
+    # a skipped Gaussian could only add flags (alpha just below the cutoff)
+    assert not (Fb["flag"] & ~F["flag"].reshape(-1)[pix]).any()
+    assert Fb["flag"].sum() == F["flag"].sum()
+    w = scenes.random_upstream(cam, seed=3)
+    Gb = render.render_bwd_2d_binned(P, w)
+    G = render.render_bwd_2d(P, w)
+    assert np.array_equal(Gb["contrib"], G["contrib"])
+    scale = G["abs2d"].max(axis=1, keepdims=True) + 1e-300
+    for k in ("d_mean2d", "d_conic", "d_opacity", "d_rgb"):
+        d = np.abs(Gb[k] - G[k]).reshape(len(scale), -1)
+        assert (d <= 1e-12 * scale).all(), k
