@@ -27,8 +27,9 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-# FP32 vector peak without packed-FP32 instructions (the library is compiled with them
-# disabled):
+# MI355X's published FP32 vector peak (packed FP32: two FMAs per lane and cycle)
+FP32_PEAK_TFLOPS = 157.3
+# the same without packed-FP32 instructions, which the library is compiled without:
 # 256 CUs x 64 lanes x 2 FLOP (FMA) x 2.4 GHz
 ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 # algorithmic FLOPs per (pixel, Gaussian) evaluation of Eq. 1 in the forward:
@@ -53,9 +54,11 @@ def parse():
     ap.add_argument("--lds-batch", type=int, default=128)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--cpu-pixels", type=int, default=16)
     ap.add_argument("--train-iters", type=int, default=6000,
                     help="iterations of the scheduled-training comparison (0: skip)")
+    ap.add_argument("--train-ablations", action="store_true",
+                    help="also run the ablation loops (fixed budget, resolution only, "
+                         "Mip-Splatting primitives)")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 4M-Gaussian, 16-view workload")
     ap.add_argument("--no-extras", action="store_true", help="skip levels and batched form")
@@ -86,6 +89,12 @@ def main():
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path would shard "
               "by views across GPUs, which is not implemented.", file=sys.stderr)
         sys.exit(2)
+    # the host baseline first: its worker processes are forked before anything
+    # touches the GPU
+    cpu = None
+    if not (args.no_cpu or args.training_only or args.profile_steps):
+        log("timing the FP64 oracle on the host cores")
+        cpu = cpu_baseline()
     import torch
     from paper_2503_18402_amd import gsmi, raster, scenes
 
@@ -96,7 +105,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.training_only:
-        print(json.dumps(scheduled_training(torch, raster, scenes, dev, args.train_iters)))
+        print(json.dumps(scheduled_training(torch, raster, scenes, dev, args.train_iters,
+                                            args.train_ablations)))
         return
 
     # ---------------------------------------------------------------- inputs
@@ -216,13 +226,16 @@ def main():
     fwd_tf = evals * FWD_FLOP_PER_EVAL / (kernel_ms["k_blend_fwd"] / 1e3) / 1e12
     algo_bytes = 40 * n_pairs + 24 * W * H   # records of the pairs + per-pixel state
     roofline = dict(kernel="k_blend_bwd", bound="alu", achieved=round(bwd_tf, 3),
-                    peak=round(ALU_PEAK_TFLOPS, 1), unit="TFLOP/s",
-                    frac=round(bwd_tf / ALU_PEAK_TFLOPS, 4),
+                    peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(bwd_tf / FP32_PEAK_TFLOPS, 4),
+                    frac_nonpacked=round(bwd_tf / ALU_PEAK_TFLOPS, 4),
+                    peak_nonpacked=round(ALU_PEAK_TFLOPS, 1),
                     traffic=read_traffic("k_blend_bwd", srcs), evals=evals,
                     flop_per_eval=BWD_FLOP_PER_EVAL, launch_ms=round(bwd_ms, 4),
                     hbm_frac_algorithmic=round(algo_bytes / (bwd_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                     fwd=dict(kernel="k_blend_fwd", achieved=round(fwd_tf, 3),
-                             frac=round(fwd_tf / ALU_PEAK_TFLOPS, 4),
+                             frac=round(fwd_tf / FP32_PEAK_TFLOPS, 4),
+                             frac_nonpacked=round(fwd_tf / ALU_PEAK_TFLOPS, 4),
                              launch_ms=round(kernel_ms["k_blend_fwd"], 4),
                              event_ms_in_timed_loop=round(fwd_ms, 4)))
 
@@ -234,9 +247,8 @@ def main():
         if not args.no_large:
             extras["large"] = large_scene(torch, raster, scenes, dev)
         if args.train_iters > 0:
-            extras["training"] = scheduled_training(torch, raster, scenes, dev, args.train_iters)
-
-    cpu = None if args.no_cpu else cpu_baseline(scene, cam, args.cpu_pixels)
+            extras["training"] = scheduled_training(torch, raster, scenes, dev, args.train_iters,
+                                                    args.train_ablations)
 
     out = {
         "metric": "fwd+bwd Mpix/s at 1M Gaussians 1600x1064; batched vs plain it/s at oracle tol",
@@ -456,18 +468,18 @@ def compare_forms(torch, raster, params, cams, tgts, label):
                      "16 per-view gradients and then runs the separate Adam step")
 
 
-def scheduled_training(torch, raster, scenes, dev, iters):
+def scheduled_training(torch, raster, scenes, dev, iters, ablations=False):
     """The optimisation loop of the hidden-scene workload: learnable Gaussians
     fitted to 64 views at 1200x800 of a 500k-Gaussian hidden scene (ground
-    truth rendered once), ``iters`` iterations, one view per iteration, the
-    backward fused with Adam.  Loops from the same 50k-Gaussian start: the
-    full method (Eq. 7 resolution schedule, Eq. 4/5 primitive schedule with
-    top-k densification), the resolution schedule alone (every candidate
-    densified) and the backbone (full resolution, every candidate); the full
-    method with a fixed budget P_fin = 300k (momentum off, the Revising-3DGS
-    setting); then the full method and the backbone again on Mip-Splatting's
-    primitives (2D mip filter, 3D filter recomputed after every densification
-    step).
+    truth rendered once), ``iters`` iterations, one view per iteration.  From
+    the same 50k-Gaussian start: the full method (Eq. 7 resolution schedule,
+    Eq. 4/5 primitive schedule with top-k densification) as the fused
+    pipeline step and as the autograd form (RasterizeFn under a torch L1 loss,
+    loss.backward(), then the Adam step), and the backbone (full resolution,
+    every candidate densified) for the time comparison.  With ``ablations``
+    also: a fixed budget P_fin = 300k (momentum off, the Revising-3DGS
+    setting), the resolution schedule alone, and the full method and the
+    backbone on Mip-Splatting's primitives.
     Densification every 100 iterations over the first half; the gradient
     threshold is set for the synthetic scene (its gradients sit an order of
     magnitude below a photograph's) so that the backbone grows to about 300k.
@@ -485,19 +497,24 @@ def scheduled_training(torch, raster, scenes, dev, iters):
     n_init, grad_thr, r_max = 50_000, 2e-5, 4.0
     init = scenes.make_scene(n_init, seed=6, mean_range=4.0, ls_mu=-4.0, ls_sigma=0.5)
     extent = 6.0 * 1.1   # camera sphere radius with the backbone's 10% margin
+    # name: (resolution schedule, top-k densification, Mip primitives, fixed budget, autograd)
+    loops = [("dashgaussian", True, True, False, None, False),
+             ("dashgaussian_autograd", True, True, False, None, True),
+             ("backbone", False, False, False, None, False)]
+    if ablations:
+        loops += [("dashgaussian_fixed_budget", True, True, False, 300_000, False),
+                  ("resolution_only", True, False, False, None, False),
+                  ("mip_dashgaussian", True, True, True, None, False),
+                  ("mip_backbone", False, False, True, None, False)]
     out = {}
-    for name, sched, top_k, mip, budget in (("dashgaussian", True, True, False, None),
-                                            ("dashgaussian_fixed_budget", True, True, False, 300_000),
-                                            ("resolution_only", True, False, False, None),
-                                            ("backbone", False, False, False, None),
-                                            ("mip_dashgaussian", True, True, True, None),
-                                            ("mip_backbone", False, False, True, None)):
+    for name, sched, top_k, mip, budget, autograd in loops:
         params = raster.to_device(init, dev)
         dcfg = train.DensifyConfig(every=100, start=100, stop=iters // 2, extent=extent,
                                    schedule=top_k, grad_thr=grad_thr, momentum=budget is None,
                                    p_fin=budget)
         tr = train.Trainer(params, cams, gt, iters, schedule=sched, densify=dcfg, r_max=r_max,
-                           means_lr=(1.6e-4 * extent, 1.6e-6 * extent), mip=mip)
+                           means_lr=(1.6e-4 * extent, 1.6e-6 * extent), mip=mip,
+                           autograd=autograd)
         psnr0 = train.psnr(tr.params, cams, gt, mip2d=mip, filter3d=tr.filter3d)
         res = tr.run()
         psnr1 = train.psnr(tr.params, cams, gt, mip2d=mip, filter3d=tr.filter3d)
@@ -506,7 +523,9 @@ def scheduled_training(torch, raster, scenes, dev, iters):
                          densify_seconds=round(res["densify_seconds"], 3),
                          densify_steps=res["densify_steps"], n_gaussians=res["n_gaussians"],
                          iters_per_factor=res["iters_per_factor"], psnr_init=round(psnr0, 3),
-                         psnr=round(psnr1, 3))
+                         psnr=round(psnr1, 3),
+                         form="RasterizeFn (torch.autograd.Function)" if autograd else
+                              "fused pipeline step")
         if sched:
             out[name]["r_knots"] = [round(float(x), 4) for x in tr.sched.r_knots]
             out[name]["s_knots"] = [round(float(x), 2) for x in tr.sched.s_knots]
@@ -516,45 +535,103 @@ def scheduled_training(torch, raster, scenes, dev, iters):
             f"({res['densify_seconds']:.2f} s densifying), {res['n_gaussians']} Gaussians, "
             f"PSNR {psnr0:.2f} -> {psnr1:.2f} dB")
         del tr, params
-    for name in ("dashgaussian", "dashgaussian_fixed_budget", "resolution_only"):
-        out[name]["speedup_vs_backbone"] = round(out["backbone"]["seconds"] / out[name]["seconds"], 3)
-    out["mip_dashgaussian"]["speedup_vs_backbone"] = round(
-        out["mip_backbone"]["seconds"] / out["mip_dashgaussian"]["seconds"], 3)
+    for name in out:
+        if name != "backbone" and not name.startswith("mip_"):
+            out[name]["speedup_vs_backbone"] = round(out["backbone"]["seconds"] /
+                                                     out[name]["seconds"], 3)
+    if "mip_dashgaussian" in out:
+        out["mip_dashgaussian"]["speedup_vs_backbone"] = round(
+            out["mip_backbone"]["seconds"] / out["mip_dashgaussian"]["seconds"], 3)
     out.update(iters=iters, views=len(cams), width=cams[0].width, height=cams[0].height,
                initial=n_init, hidden=500_000, grad_thr_ndc=grad_thr, r_max=r_max,
-               note="X(F_r) normalised per pixel; eager loop, one view per iteration, "
-                    "backward fused with Adam; L1 loss")
+               note="X(F_r) normalised per pixel; one view per iteration; L1 loss")
     return out
 
 
-def cpu_baseline(scene, cam, n_pix):
-    """The FP64 oracle on the host: projection and chain rule over all 1M
-    Gaussians timed whole, the per-pixel blend forward + backward timed on
-    ``n_pix`` random pixels and scaled to the full frame."""
+# ---- the FP64 oracle on the host (a baseline, not a target).  Workers are
+# forked before anything touches the GPU and run numpy only.
+_CPU = {}
+
+
+def _oracle_tiles(tiles):
+    """Worker: binned oracle forward + backward over ``tiles`` of the view in
+    _CPU; returns the 2D gradient sums of the Gaussians it touched."""
+    from threadpoolctl import threadpool_limits
+    from oracle import render
+
+    P, cands, w = _CPU["P"], _CPU["cands"], _CPU["w"]
+    with threadpool_limits(1):
+        render.render_fwd_binned(P, tiles=tiles, cands=cands)
+        g = render.render_bwd_2d_binned(P, w, tiles=tiles, cands=cands)
+    idx = np.nonzero(g["contrib"])[0]
+    return idx, {k: g[k][idx] for k in ("d_mean2d", "d_conic", "d_opacity", "d_rgb", "abs2d")}
+
+
+def cpu_baseline(one_core_tiles=(48, 12, 6)):
+    """The FP64 oracle's fwd + bwd of the paper-scale view (1M Gaussians) at the
+    schedule's levels r = 1, 4, 8, whole frames: projection, binned blend
+    forward and backward (each tile blends its footprint candidates, which
+    gives the brute force's result) and the chain rule to the parameters.  The
+    blend runs on every host core (a process per core, tiles dealt round
+    robin); projection and chain rule are single-threaded numpy.  One core:
+    ``one_core_tiles`` tiles per level, spread over the list lengths, timed on
+    one process and scaled by list entries to the frame."""
+    import multiprocessing as mp
     from threadpoolctl import threadpool_limits
     from oracle import project, render
+    from paper_2503_18402_amd import scenes
 
-    rng = np.random.default_rng(0)
-    pix = rng.choice(cam.width * cam.height, n_pix, replace=False)
-    g = rng.uniform(-1.0, 1.0, size=(3, n_pix))
-    with threadpool_limits(1):
+    cores = len(os.sched_getaffinity(0))
+    scene, _ = scenes.paper_scale_scene(level=1)
+    levels = {}
+    for r, n1 in zip((1, 4, 8), one_core_tiles):
+        _, cam = scenes.paper_scale_scene(level=r, n=1)
         t0 = time.perf_counter()
-        P = project.project(scene, cam)
+        with threadpool_limits(1):
+            P = project.project(scene, cam, tile=16)
+            cands = render.tile_candidates(P)
         t1 = time.perf_counter()
-        render.render_fwd(P, pixels=pix, chunk=4)
-        g2 = render.render_bwd_2d(P, g, pixels=pix, chunk=4)
+        w = np.random.default_rng(3).uniform(-1.0, 1.0, size=(3, cam.height, cam.width))
+        _CPU.update(P=P, cands=cands, w=w)
+        lens = np.array([len(c) for c in cands])
+        chunks = [list(range(k, len(cands), cores)) for k in range(cores)]
+        with mp.get_context("fork").Pool(cores) as pool:
+            parts = pool.map(_oracle_tiles, chunks)
         t2 = time.perf_counter()
-        render.chain_to_3d(scene, P, g2)
+        g2 = {k: np.zeros((scene["means"].shape[0],) + v.shape[1:])
+              for k, v in parts[0][1].items()}
+        for idx, vals in parts:
+            for k, v in vals.items():
+                g2[k][idx] += v
+        with threadpool_limits(1):
+            render.chain_to_3d(scene, P, g2)
         t3 = time.perf_counter()
-    per_px = (t2 - t1) / n_pix
-    full = (t1 - t0) + (t3 - t2) + per_px * cam.width * cam.height
-    log(f"oracle: project {t1 - t0:.1f}s, {per_px:.3f} s/pixel, chain {t3 - t2:.1f}s")
-    return dict(value=round(cam.width * cam.height / full / 1e6, 8), unit="Mpix/s", cores=1,
-                kind="oracle",
-                sample=f"{n_pix} random pixels of the 1600x1064 view (1M Gaussians): projection "
-                       f"and chain rule over all Gaussians timed whole, per-pixel fwd+bwd "
-                       f"({per_px:.3f} s/pixel) scaled to {cam.width * cam.height} pixels",
-                seconds=round(t3 - t0, 2))
+        # one core: a sample of tiles spread over the list lengths, scaled by entries
+        pick = np.argsort(lens)[np.linspace(0, len(lens) - 1, n1).astype(int)]
+        ta = time.perf_counter()
+        _oracle_tiles(list(pick))
+        tb = time.perf_counter()
+        blend_1core = (tb - ta) * lens.sum() / max(1, lens[pick].sum())
+        whole = t3 - t0
+        one = (t1 - t0) + (t3 - t2) + blend_1core
+        px = cam.width * cam.height
+        levels[f"r{r}"] = dict(width=cam.width, height=cam.height, seconds_all_cores=round(whole, 2),
+                               mpix_per_s_all_cores=round(px / whole / 1e6, 6),
+                               seconds_one_core=round(one, 2),
+                               mpix_per_s_one_core=round(px / one / 1e6, 6),
+                               project_s=round(t1 - t0, 2), blend_s_all_cores=round(t2 - t1, 2),
+                               chain_s=round(t3 - t2, 2), list_entries=int(lens.sum()),
+                               one_core_sample_tiles=int(n1))
+        log(f"oracle r={r}: {whole:.1f} s on {cores} cores, {one:.1f} s on one core (est.)")
+        _CPU.clear()
+        del P, cands
+    head = levels["r1"]
+    return dict(value=head["mpix_per_s_all_cores"], unit="Mpix/s", cores=cores, kind="oracle",
+                sample="whole 1600x1064 frame of the 1M-Gaussian view (the headline workload): "
+                       "FP64 projection, binned blend fwd+bwd on every core, chain rule; "
+                       "also whole frames at r=4 and r=8, and one core estimated from a "
+                       "sample of tiles per level",
+                one_core_mpix_per_s=head["mpix_per_s_one_core"], levels=levels)
 
 
 if __name__ == "__main__":

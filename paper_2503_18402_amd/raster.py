@@ -143,6 +143,12 @@ class RasterizeFn(torch.autograd.Function):
     sh_degree, mip2d, filter3d.  The forward keeps only the frame buffers (projected records,
     sorted pair values, ranges, final T and last contributor per pixel); the
     backward recomputes each pixel's blend state from them.
+
+    Optional settings for a training loop: ``capacity`` (pair capacity) with
+    ``check_capacity`` False skips the forward's read-back of the pair count
+    (the caller checks the frame's ``n_pairs_dev`` later); ``mean2d_abs`` (a
+    device [n] tensor) receives the backward's |dL/dmean2D| statistic (added
+    to it); the forward stores its frame in ``settings["frame"]``.
     """
 
     @staticmethod
@@ -155,14 +161,19 @@ class RasterizeFn(torch.autograd.Function):
                        lds_batch=settings.get("lds_batch", 256),
                        bg=settings.get("bg", (0.0, 0.0, 0.0)),
                        sh_degree=settings.get("sh_degree", 3),
-                       mip2d=settings.get("mip2d", False), filter3d=settings.get("filter3d"))
+                       mip2d=settings.get("mip2d", False), filter3d=settings.get("filter3d"),
+                       capacity=settings.get("capacity"),
+                       check_capacity=settings.get("check_capacity", True))
         ctx.frame = frame
         ctx.params = params
+        ctx.mean2d_abs = settings.get("mean2d_abs")
+        if "frame" in settings:
+            settings["frame"] = frame
         return frame.image.clone()
 
     @staticmethod
     def backward(ctx, dL_dimage):
-        g = render_backward(ctx.params, ctx.frame, dL_dimage.float())
+        g = render_backward(ctx.params, ctx.frame, dL_dimage.float(), mean2d_abs=ctx.mean2d_abs)
         return g["means"], g["log_scales"], g["quats"], g["opacity_logits"], g["sh"], None
 
 

@@ -15,6 +15,14 @@ full-resolution iteration on.  With ``schedule=False`` every iteration renders
 at full resolution and the position rate decays from the start: the
 backbone's loop, for comparison.
 
+Two forms of the step: the fused pipeline (``raster.Pipeline``: the L1
+gradient written by the forward kernel, the backward fused with Adam), and,
+with ``autograd=True``, the differentiable rasterizer as a
+``torch.autograd.Function`` (``raster.RasterizeFn``) under a torch L1 loss and
+``loss.backward()``, followed by the library's multi-group Adam step.  Both
+take the same operations in the same order, so they give the same parameters
+bit for bit.
+
 Everything here marshals buffers and calls the C ABI; the arithmetic runs in
 the library's kernels.
 """
@@ -140,13 +148,18 @@ class Trainer:
                  means_lr=(1.6e-4, 1.6e-6), sh_degree: int = 3, seed: int = 0,
                  capacity_margin: float = 2.0, norm: str = "mean",
                  densify: DensifyConfig | None = None, r_max: float = 0.0,
-                 sparse_adam: bool = False, mip: bool = False, filter3d_scale: float = 0.2):
+                 sparse_adam: bool = False, mip: bool = False, filter3d_scale: float = 0.2,
+                 autograd: bool = False):
         self.params, self.cams, self.gt, self.iters = params, list(cams), gt, iters
         self.sh_degree = sh_degree
         self.lrs = dict(DEFAULT_LRS if lrs is None else lrs)
         self.means_lr = means_lr
         self.capacity_margin = capacity_margin
+        if autograd and sparse_adam:
+            raise ValueError("sparse Adam runs fused with the backward pass")
         self.sparse_adam = sparse_adam
+        self.autograd = autograd
+        self.leaves = None
         self.mip, self.filter3d_scale = mip, filter3d_scale
         self.filter3d = None
         self._f3_scratch = torch.zeros(1, dtype=torch.int32, device=params["means"].device)
@@ -199,9 +212,19 @@ class Trainer:
                                       mip2d=self.mip, filter3d=self.filter3d)
                 cap = max(cap, int(probe.n_pairs_dev.item()))
                 del probe
+            capacity = int(cap * self.capacity_margin) + 4096
+            if self.autograd:
+                settings = dict(cams=[views[0]], tile=tile, lds_batch=self.lds_batch_for(f),
+                                sh_degree=self.sh_degree, mip2d=self.mip, filter3d=self.filter3d,
+                                capacity=capacity, check_capacity=False,
+                                mean2d_abs=self.mean2d, frame=None)
+                pairs_max = torch.zeros(1, dtype=torch.int64, device=dev)
+                self.levels[f] = (views, gt_f, dict(settings=settings, capacity=capacity,
+                                                    pairs_max=pairs_max))
+                continue
             pipe = raster.Pipeline(self.params, [views[0]], gt_f[0].reshape(-1), tile=tile,
                                    lds_batch=self.lds_batch_for(f), sh_degree=self.sh_degree,
-                                   capacity=int(cap * self.capacity_margin) + 4096, lrs=self.lrs,
+                                   capacity=capacity, lrs=self.lrs,
                                    share=first, state=(self.m, self.v, self.step_dev),
                                    mean2d_abs=self.mean2d, sparse_adam=self.sparse_adam,
                                    mip2d=self.mip, filter3d=self.filter3d)
@@ -229,9 +252,61 @@ class Trainer:
                                   self._f3_scratch)
 
     def _check_capacity(self):
-        for _, _, pipe in self.levels.values():
-            if int(pipe.pairs_max.item()) > pipe.capacity:
+        for _, _, lvl in self.levels.values():
+            pmax, cap = ((lvl["pairs_max"], lvl["capacity"]) if self.autograd
+                         else (lvl.pairs_max, lvl.capacity))
+            if int(pmax.item()) > cap:
                 raise RuntimeError("pair capacity overflowed during training")
+
+    # ---- the autograd form.  The SH coefficients are two leaves, degree 0 and
+    # the higher degrees, so that Adam takes them as separate groups with their
+    # own learning rates (the fused step's lr[4] and lr[5]).
+    GROUPS6 = ("means", "log_scales", "quats", "opacity_logits", "sh_dc", "sh_rest")
+
+    def _split(self):
+        p, L = self.params, {}
+        for n in raster.PARAM_NAMES[:4]:
+            L[n] = p[n].detach().requires_grad_(True)
+        L["sh_dc"] = p["sh"][:, :1].clone().requires_grad_(True)
+        L["sh_rest"] = p["sh"][:, 1:].clone().requires_grad_(True)
+        self.leaves = L
+        self.m6, self.v6 = {}, {}
+        for d6, d5 in ((self.m6, self.m), (self.v6, self.v)):
+            for n in raster.PARAM_NAMES[:4]:
+                d6[n] = d5[n]
+            d6["sh_dc"] = d5["sh"][:, :1].clone()
+            d6["sh_rest"] = d5["sh"][:, 1:].clone()
+
+    def _merge(self):
+        L = self.leaves
+        for n in raster.PARAM_NAMES[:4]:
+            self.params[n] = L[n].detach()
+        self.params["sh"] = torch.cat([L["sh_dc"].detach(), L["sh_rest"].detach()], 1)
+        for d6, d5 in ((self.m6, self.m), (self.v6, self.v)):
+            d5["sh"] = torch.cat([d6["sh_dc"], d6["sh_rest"]], 1)
+        self.leaves = None
+
+    def _autograd_step(self, k: int, f: int, v: int):
+        views, gt_f, lvl = self.levels[f]
+        L, st = self.leaves, lvl["settings"]
+        st["cams"] = [views[v]]
+        self.mean2d.zero_()
+        sh = torch.cat([L["sh_dc"], L["sh_rest"]], 1)
+        img = raster.RasterizeFn.apply(L["means"], L["log_scales"], L["quats"],
+                                       L["opacity_logits"], sh, st)
+        loss = (img - gt_f[v].reshape(-1)).abs().mean()
+        loss.backward()
+        lr = [self.means_lr_at(k), self.lrs["log_scales"], self.lrs["quats"],
+              self.lrs["opacity_logits"], self.lrs["sh"], self.lrs.get("sh_rest", self.lrs["sh"])]
+        gsmi.gs_adam_step_device([(L[n], L[n].grad, self.m6[n], self.v6[n], lr[i])
+                                  for i, n in enumerate(self.GROUPS6)], self.step_dev,
+                                 0.9, 0.999, 1e-15)
+        for n in self.GROUPS6:
+            L[n].grad = None
+        frame = st["frame"]
+        torch.maximum(lvl["pairs_max"], frame.n_pairs_dev, out=lvl["pairs_max"])
+        self.lr_log.append(lr[0])
+        return frame
 
     def means_lr_at(self, k: int) -> float:
         """Position learning rate at iteration k (supplementary, "Learning
@@ -260,6 +335,8 @@ class Trainer:
             return int(round(target)) - kept
 
         self._check_capacity()
+        if self.autograd:
+            self._merge()
         n = self.params["means"].shape[0]
         z = torch.randn(n, 2, 3, generator=self.zgen, device=self.accum.device)
         newp, newm, newv, info = densify_step(self.params, self.m, self.v, self.accum, self.count,
@@ -272,6 +349,8 @@ class Trainer:
         info.update(iteration=k, r=r, p_fin=getattr(self, "p_fin", None))
         self.log.append(info)
         self._build_levels(k)
+        if self.autograd:
+            self._split()
 
     def run(self) -> dict:
         """Run all iterations; returns the wall time (and the part of it spent
@@ -282,6 +361,8 @@ class Trainer:
         c = self.dcfg
         stop = (c.stop if c.stop is not None else self.iters // 2) if c else 0
         t_densify = 0.0
+        if self.autograd:
+            self._split()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(self.iters):
@@ -295,17 +376,25 @@ class Trainer:
                 order = list(self.rng.permutation(n_views))
             v = order.pop()
             f = int(self.factors[k])
-            views, gt_f, pipe = self.levels[f]
-            pipe.set_view(views[v], gt_f[v])
-            pipe.lrs["means"] = self.means_lr_at(k)
-            self.lr_log.append(pipe.lrs["means"])
-            pipe.step()
-            torch.maximum(pipe.pairs_max, pipe.n_pairs, out=pipe.pairs_max)
+            if self.autograd:
+                views = self.levels[f][0]
+                frame = self._autograd_step(k, f, v)
+                n_now, proj = frame.n, frame.proj
+            else:
+                views, gt_f, pipe = self.levels[f]
+                pipe.set_view(views[v], gt_f[v])
+                pipe.lrs["means"] = self.means_lr_at(k)
+                self.lr_log.append(pipe.lrs["means"])
+                pipe.step()
+                torch.maximum(pipe.pairs_max, pipe.n_pairs, out=pipe.pairs_max)
+                n_now, proj = pipe.n, pipe.proj
             if c is not None and k < stop:
-                gsmi.gs_densify_stats(1, pipe.n, pipe.proj, self.mean2d, self.accum, self.count,
+                gsmi.gs_densify_stats(1, n_now, proj, self.mean2d, self.accum, self.count,
                                       scale=0.5 * views[v].width)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        if self.autograd:
+            self._merge()
         self._check_capacity()
         if self.mip:
             self.update_filter3d()   # for rendering the trained model

@@ -109,3 +109,32 @@ def test_densifying_loop_follows_eq4_eq5(scheduled):
         assert e["k"] == want and e["n_new"] == kept + want
         n_prev = e["n_new"]
     assert out["n_gaussians"] > 3000
+
+
+def test_autograd_loop_equals_fused_loop():
+    """The optimisation loop through the torch.autograd.Function (RasterizeFn
+    under a torch L1 loss and loss.backward(), then the multi-group Adam step)
+    against the fused pipeline loop, from the same start, under both schedules
+    with densification: the same parameters, Adam moments, position learning
+    rates and densification decisions, bit for bit (the two forms run the same
+    operations in the same order)."""
+    cams = scenes.fibonacci_cameras(6, 3.0, 128, 96, 120.0)
+    gt = torch.from_numpy(_gt(cams, seed=77)).cuda()
+    sc = scenes.make_scene(3000, seed=78, mean_range=1.0, ls_mu=-3.0, ls_sigma=0.4)
+    runs = {}
+    for autograd in (False, True):
+        params = raster.to_device(sc, "cuda")
+        dcfg = train.DensifyConfig(every=30, start=30, stop=70, grad_thr=2e-4, extent=3.3)
+        tr = train.Trainer(params, cams, gt, 90, schedule=True, densify=dcfg, autograd=autograd,
+                           seed=5)
+        out = tr.run()
+        runs[autograd] = (tr, out)
+    (a, oa), (b, ob) = runs[False], runs[True]
+    assert len(a.log) == 2 and [e["n_new"] for e in a.log] == [e["n_new"] for e in b.log]
+    assert oa["n_gaussians"] > 3000 and oa["iters_per_factor"] == ob["iters_per_factor"]
+    assert len(set(a.factors.tolist())) > 1
+    assert a.lr_log == b.lr_log
+    for name in raster.PARAM_NAMES:
+        assert torch.equal(a.params[name], b.params[name]), name
+        assert torch.equal(a.m[name], b.m[name]), name
+        assert torch.equal(a.v[name], b.v[name]), name
