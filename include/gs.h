@@ -130,6 +130,29 @@ gs_status gs_bin_sort(int32_t n_views, const gs_camera* cams, const gs_raster_cf
                       size_t ws_bytes, uint64_t* keys, uint32_t* vals, uint32_t* ranges,
                       int64_t* n_pairs_dev, void* stream);
 
+/* gs_bin_sort_noalloc: gs_bin_sort for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same keys, values, ranges and pair count as
+ * gs_bin_sort, with the workspace taken from a static device array of the
+ * library instead of a `ws` argument.
+ *   capacity_pairs: 0 .. GS_BIN_SORT_NOALLOC_MAX_PAIRS (2^22); a larger value
+ *     returns GS_ERR_CAPACITY and enqueues nothing.  The array holds 8 bytes
+ *     per pair of that maximum plus 256 bytes (32 MiB + 256 B) on every GPU
+ *     the library runs on, until the process ends.
+ *   The call allocates nothing (no hipMalloc, no hipFree).  Its first call on
+ *   a device looks up that device's copy of the array with the device
+ *   current; the current device must be the one `stream` belongs to.
+ *   All calls on one GPU share its one array: calls that overlap on a GPU
+ *   (several streams, several host threads) race and corrupt each other's
+ *   results, so serialise them.  Nothing in the array needs clearing between
+ *   calls: each call writes every byte of it that it reads.
+ *   The other arguments, outputs and errors are those of gs_bin_sort. */
+#define GS_BIN_SORT_NOALLOC_MAX_PAIRS (1 << 22)
+gs_status gs_bin_sort_noalloc(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
+                              int32_t n, const void* proj, int64_t capacity_pairs,
+                              uint64_t* keys, uint32_t* vals, uint32_t* ranges,
+                              int64_t* n_pairs_dev, void* stream);
+
 /* ---------------------------------------------------------------------------
  * gs_filter3d_variance: Mip-Splatting's 3D smoothing filter.  For each
  * Gaussian, nu = the highest sampling rate fx / z over the views whose image

@@ -218,6 +218,21 @@ gs_status gs_bin_sort(int32_t n_views, const gs_camera* cams, const gs_raster_cf
                                   vals, ranges, n_pairs_dev, as_stream(stream)));
 }
 
+gs_status gs_bin_sort_noalloc(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
+                              int32_t n, const void* proj, int64_t capacity_pairs,
+                              uint64_t* keys, uint32_t* vals, uint32_t* ranges,
+                              int64_t* n_pairs_dev, void* stream) {
+  Views V;
+  if (!n_ok(n_views, n) || !build_views(n_views, cams, cfg, &V)) return GS_ERR_ARG;
+  if (capacity_pairs < 0) return GS_ERR_ARG;
+  if (capacity_pairs > GS_BIN_SORT_NOALLOC_MAX_PAIRS) return GS_ERR_CAPACITY;
+  if (!ranges || !n_pairs_dev || (n > 0 && !proj) || (capacity_pairs > 0 && !vals))
+    return GS_ERR_ARG;
+  if (n > 0 && !aligned16(proj)) return GS_ERR_ARG;
+  return from_hip(launch_bin_sort_noalloc(V, n, static_cast<const char*>(proj), capacity_pairs,
+                                          keys, vals, ranges, n_pairs_dev, as_stream(stream)));
+}
+
 size_t gs_bin_sort_radix_workspace_bytes(int32_t n_views, int32_t n, int64_t capacity_pairs) {
   if (!n_ok(n_views, n) || capacity_pairs < 0 || capacity_pairs >= (int64_t(1) << 32)) return 0;
   return bin_sort_radix_ws_bytes(n_views, n, capacity_pairs);

@@ -201,6 +201,9 @@ size_t bin_sort_ws_bytes(int n_views, int n, int64_t cap);
 hipError_t launch_bin_sort(const Views& V, int n, const char* proj, int64_t cap, void* ws,
                            uint64_t* keys, uint32_t* vals, uint32_t* ranges,
                            int64_t* n_pairs_dev, hipStream_t st);
+hipError_t launch_bin_sort_noalloc(const Views& V, int n, const char* proj, int64_t cap,
+                                   uint64_t* keys, uint32_t* vals, uint32_t* ranges,
+                                   int64_t* n_pairs_dev, hipStream_t st);
 size_t bin_sort_radix_ws_bytes(int n_views, int n, int64_t cap);
 hipError_t launch_bin_sort_radix(const Views& V, int n, const char* proj, int64_t cap, void* ws,
                                  uint64_t* keys, uint32_t* vals, uint32_t* ranges,

@@ -28,6 +28,7 @@
 // The pair expansion spreads each wave's pairs evenly over its 64 lanes, so a
 // Gaussian with a footprint of thousands of tiles does not serialise on one lane.
 #include <algorithm>
+#include <mutex>
 
 #include "scan.hpp"
 
@@ -511,9 +512,54 @@ struct WsLayout {
   }
 };
 
+// ---- the no-allocation form (gs_bin_sort_noalloc): the workspace of a call
+// of at most GS_BIN_SORT_NOALLOC_MAX_PAIRS pairs of capacity lives in this
+// file-scope device array, one copy per GPU.  Host code never passes the
+// array's name to a kernel (on the host it only names the symbol): the
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kNoAllocBytes = 256 + 8 * size_t(GS_BIN_SORT_NOALLOC_MAX_PAIRS);
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// The current device's copy of `scratch`, looked up on the first call on that
+// device (with it current) and kept until the process ends.
+hipError_t scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (p == nullptr) return hipErrorInvalidSymbol;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
+}
+
 }  // namespace
 
 size_t bin_sort_ws_bytes(int, int, int64_t cap) { return WsLayout(cap).total; }
+
+hipError_t launch_bin_sort_noalloc(const Views& V, int n, const char* proj, int64_t cap,
+                                   uint64_t* keys, uint32_t* vals, uint32_t* ranges,
+                                   int64_t* n_pairs_dev, hipStream_t st) {
+  if (cap < 0 || cap > GS_BIN_SORT_NOALLOC_MAX_PAIRS || WsLayout(cap).total > kNoAllocBytes)
+    return hipErrorInvalidValue;  // the caller rejects this first
+  void* ws = nullptr;
+  const hipError_t e = scratch_address(&ws);
+  if (e != hipSuccess) return e;
+  // every call writes each scratch byte it reads (the counts in the tile scan,
+  // the bucket slots [0, pairs) in the bucket pass) before reading it, so
+  // nothing is cleared
+  return launch_bin_sort(V, n, proj, cap, ws, keys, vals, ranges, n_pairs_dev, st);
+}
 
 hipError_t launch_bin_sort(const Views& V, int n, const char* proj, int64_t cap, void* ws_,
                            uint64_t* keys, uint32_t* vals, uint32_t* ranges,

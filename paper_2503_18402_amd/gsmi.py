@@ -69,6 +69,7 @@ def lib() -> ctypes.CDLL:
             "gs_preprocess": (i32, [i32, cam_p, cfg_p, i32, vp, vp, vp, vp, vp, i32, vp, vp]),
             "gs_bin_sort_workspace_bytes": (sz, [i32, i32, i64]),
             "gs_bin_sort": (i32, [i32, cam_p, cfg_p, i32, vp, i64, vp, sz, vp, vp, vp, vp, vp]),
+            "gs_bin_sort_noalloc": (i32, [i32, cam_p, cfg_p, i32, vp, i64, vp, vp, vp, vp, vp]),
             "gs_bin_sort_radix_workspace_bytes": (sz, [i32, i32, i64]),
             "gs_bin_sort_radix": (i32, [i32, cam_p, cfg_p, i32, vp, i64, vp, sz, vp, vp, vp, vp,
                                         vp]),
@@ -205,6 +206,16 @@ def gs_bin_sort(cams_c, cfg, n, proj, capacity, ws, keys, vals, ranges, n_pairs_
         len(cams_c), cams_c, ctypes.byref(cfg), int(n), _ptr(proj), int(capacity), _ptr(ws),
         ws.numel() * ws.element_size(), _ptr(keys), _ptr(vals), _ptr(ranges), _ptr(n_pairs_dev),
         _stream(stream)))
+
+
+GS_BIN_SORT_NOALLOC_MAX_PAIRS = 1 << 22
+
+
+def gs_bin_sort_noalloc(cams_c, cfg, n, proj, capacity, keys, vals, ranges, n_pairs_dev,
+                        stream=None):
+    _check("gs_bin_sort_noalloc", lib().gs_bin_sort_noalloc(
+        len(cams_c), cams_c, ctypes.byref(cfg), int(n), _ptr(proj), int(capacity), _ptr(keys),
+        _ptr(vals), _ptr(ranges), _ptr(n_pairs_dev), _stream(stream)))
 
 
 def gs_bin_sort_radix_workspace_bytes(n_views: int, n: int, capacity: int) -> int:

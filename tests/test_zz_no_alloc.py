@@ -1,0 +1,88 @@
+"""gs_bin_sort_noalloc (the binning whose workspace is a static device array
+of the library) against gs_bin_sort on the same inputs: keys, values, tile
+ranges and the pair count bit for bit, on two calls in a row, the second with
+a smaller input (the array keeps what the first call left in it), then a
+capacity overflow reported as gs_bin_sort reports it, and a capacity above
+the array's maximum rejected before anything is enqueued."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2503_18402_amd import gsmi, raster, scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _prepare(sc, cams, tile):
+    params = raster.to_device(sc, "cuda")
+    n = params["means"].shape[0]
+    cams_c = gsmi.make_cameras(cams)
+    cfg = gsmi.make_cfg(tile, 256)
+    proj = torch.empty(max(gsmi.gs_proj_bytes(len(cams), n), 16), dtype=torch.uint8,
+                       device="cuda")
+    gsmi.gs_preprocess(cams_c, cfg, n, params["means"], params["log_scales"], params["quats"],
+                       params["opacity_logits"], params["sh"], 3, proj)
+    return cams_c, cfg, n, proj
+
+
+def _outputs(cams_c, cfg, cap):
+    tiles = gsmi.gs_total_tiles(cams_c, cfg)
+    return (torch.full((max(cap, 1),), -1, dtype=torch.int64, device="cuda"),
+            torch.full((max(cap, 1),), -1, dtype=torch.int32, device="cuda"),
+            torch.full((2 * tiles,), -1, dtype=torch.int32, device="cuda"),
+            torch.full((1,), -1, dtype=torch.int64, device="cuda"))
+
+
+def _both(cams_c, cfg, n, proj, cap):
+    ws = torch.empty(gsmi.gs_bin_sort_workspace_bytes(len(cams_c), n, cap), dtype=torch.uint8,
+                     device="cuda")
+    ref = _outputs(cams_c, cfg, cap)
+    gsmi.gs_bin_sort(cams_c, cfg, n, proj, cap, ws, *ref)
+    got = _outputs(cams_c, cfg, cap)
+    gsmi.gs_bin_sort_noalloc(cams_c, cfg, n, proj, cap, *got)
+    torch.cuda.synchronize()
+    return ref, got
+
+
+def _same(ref, got):
+    keys_r, vals_r, ranges_r, np_r = (t.cpu().numpy() for t in ref)
+    keys_g, vals_g, ranges_g, np_g = (t.cpu().numpy() for t in got)
+    assert np_g[0] == np_r[0]
+    if np_r[0] <= len(keys_r):       # keys and values are valid only without overflow
+        m = int(np_r[0])
+        assert np.array_equal(keys_g[:m], keys_r[:m])
+        assert np.array_equal(vals_g[:m], vals_r[:m])
+    assert np.array_equal(ranges_g, ranges_r)
+    return int(np_r[0])
+
+
+def test_noalloc_bin_sort_equals_bin_sort_on_successive_calls():
+    sc, _ = scenes.small_scene()
+    base = scenes.orbit_cameras(3, 3.0, 128, 96, 120.0)
+    # first call: three views of 4096 Gaussians at 8-pixel tiles
+    big = _prepare(sc, base, 8)
+    ref, got = _both(*big, 200_000)
+    p_big = _same(ref, got)
+    assert p_big > 20_000
+    # second call, smaller: 700 Gaussians, one ragged view, 16-pixel tiles
+    small = _prepare(scenes.subset(sc, slice(0, 700)),
+                     [scenes.look_at((0.3, -0.2, -3.0), (0, 0, 0), 70, 45, 70.0)], 16)
+    ref, got = _both(*small, 5_000)
+    p_small = _same(ref, got)
+    assert 0 < p_small < p_big // 10
+    # capacity overflow: the pair count is reported, ranges are left [0, 0)
+    ref, got = _both(*big, 1000)
+    assert _same(ref, got) == p_big
+    assert not got[2].cpu().numpy().any()
+
+
+def test_noalloc_bin_sort_rejects_capacity_above_its_maximum():
+    sc, cam = scenes.small_scene()
+    cams_c, cfg, n, proj = _prepare(sc, [cam], 16)
+    out = _outputs(cams_c, cfg, 1)
+    with pytest.raises(gsmi.GsError) as e:
+        gsmi.gs_bin_sort_noalloc(cams_c, cfg, n, proj, gsmi.GS_BIN_SORT_NOALLOC_MAX_PAIRS + 1,
+                                 *out)
+    assert e.value.status == 2     # GS_ERR_CAPACITY
+    torch.cuda.synchronize()
+    assert int(out[3].item()) == -1   # nothing was enqueued
