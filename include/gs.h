@@ -135,10 +135,11 @@ gs_status gs_bin_sort(int32_t n_views, const gs_camera* cams, const gs_raster_cf
  * forbid allocation).  Same keys, values, ranges and pair count as
  * gs_bin_sort, with the workspace taken from a static device array of the
  * library instead of a `ws` argument.
- *   capacity_pairs: 0 .. GS_BIN_SORT_NOALLOC_MAX_PAIRS (2^22); a larger value
- *     returns GS_ERR_CAPACITY and enqueues nothing.  The array holds 8 bytes
- *     per pair of that maximum plus 256 bytes (32 MiB + 256 B) on every GPU
- *     the library runs on, until the process ends.
+ *   capacity_pairs: 0 .. GS_BIN_SORT_NOALLOC_MAX_PAIRS (2^22), and
+ *   n_views * n: at most GS_BIN_SORT_NOALLOC_MAX_ITEMS (2^23); larger values
+ *     return GS_ERR_CAPACITY and enqueue nothing.  The array holds 12 bytes
+ *     per pair of that maximum plus 4 bytes per 256 items and 256 bytes
+ *     (48.1 MiB) on every GPU the library runs on, until the process ends.
  *   The call allocates nothing (no hipMalloc, no hipFree).  Its first call on
  *   a device looks up that device's copy of the array with the device
  *   current; the current device must be the one `stream` belongs to.
@@ -148,6 +149,7 @@ gs_status gs_bin_sort(int32_t n_views, const gs_camera* cams, const gs_raster_cf
  *   calls: each call writes every byte of it that it reads.
  *   The other arguments, outputs and errors are those of gs_bin_sort. */
 #define GS_BIN_SORT_NOALLOC_MAX_PAIRS (1 << 22)
+#define GS_BIN_SORT_NOALLOC_MAX_ITEMS (1 << 23)
 gs_status gs_bin_sort_noalloc(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
                               int32_t n, const void* proj, int64_t capacity_pairs,
                               uint64_t* keys, uint32_t* vals, uint32_t* ranges,

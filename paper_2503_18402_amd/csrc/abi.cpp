@@ -225,7 +225,9 @@ gs_status gs_bin_sort_noalloc(int32_t n_views, const gs_camera* cams, const gs_r
   Views V;
   if (!n_ok(n_views, n) || !build_views(n_views, cams, cfg, &V)) return GS_ERR_ARG;
   if (capacity_pairs < 0) return GS_ERR_ARG;
-  if (capacity_pairs > GS_BIN_SORT_NOALLOC_MAX_PAIRS) return GS_ERR_CAPACITY;
+  if (capacity_pairs > GS_BIN_SORT_NOALLOC_MAX_PAIRS ||
+      int64_t(n_views) * n > GS_BIN_SORT_NOALLOC_MAX_ITEMS)
+    return GS_ERR_CAPACITY;
   if (!ranges || !n_pairs_dev || (n > 0 && !proj) || (capacity_pairs > 0 && !vals))
     return GS_ERR_ARG;
   if (n > 0 && !aligned16(proj)) return GS_ERR_ARG;

@@ -8,22 +8,28 @@
 // correct sort produces it.  Instead of sorting all pairs globally on every key
 // digit, the pairs are bucketed by tile and each tile's (short) list is sorted
 // on chip:
-//   1. count:  one atomic increment per pair on its tile's counter;
+//   0. offsets: each pair's position in index order (Gaussian by Gaussian,
+//              tiles row-major in its box) from a scan of the tile counts;
+//   1. count:  one atomic increment per pair on its tile's counter; the
+//              value it returns is the pair's rank in its tile, kept at the
+//              pair's index-order position;
 //   2. scan:   one block scans the counters into each tile's first slot and
 //              checks the pair total against the capacity;
-//   3. bucket: every pair claims a slot of its tile through an atomic cursor
-//              that counts down from the tile's end, and stores the 64-bit
-//              sort key (bits(depth_f32) << 32) | Gaussian index there;
+//   3. bucket: every pair stores the 64-bit sort key
+//              (bits(depth_f32) << 32) | Gaussian index at its tile's first
+//              slot plus its rank: no atomics;
 //   4. sort:   one block per tile sorts its keys with a bitonic network in LDS
 //              (lists longer than one LDS chunk also run the network's long
 //              strides through global memory) and writes the values, and the
 //              keys when asked for.
 // The slot order after step 3 depends on atomic timing; after step 4 it does
-// not.  The counters, cursors and first slots live in the caller's ranges
-// array (ranges[2t] = first slot, ranges[2t+1] = counter, then cursor, then
-// end), so the workspace holds only the bucketed keys and three counts.  The
-// cursor returns the slot itself: a pair never reads the line its atomic
-// updates.
+// not.  Blocks whose views have few tiles (low resolutions, thousands of pairs
+// per tile) count in LDS first and reserve one slot range per touched tile in
+// step 3 instead, through a cursor that starts after the tile's ranked pairs.
+// The counters, cursors and first slots live in the caller's ranges array
+// (during steps 1-3: ranges[2t] = ranked count, then first slot; ranges[2t+1]
+// = LDS-counted count, then cursor, then end), so the workspace holds the
+// bucketed keys, the ranks, the offsets' block sums and three counts.
 //
 // The pair expansion spreads each wave's pairs evenly over its 64 lanes, so a
 // Gaussian with a footprint of thousands of tiles does not serialise on one lane.
@@ -54,11 +60,14 @@ constexpr int kAggBins = 2048;  // most tiles a block aggregates in LDS
 constexpr int kAggRounds = 8;   // items per aggregating block: at most kXT * kAggRounds
 constexpr int kAggBlocks = 512; // but no fewer blocks than this while items allow
 
-// Calls f(global tile id, sort key) once for every pair of the items
-// [first, first + kXT).  Every thread of the block must call it.
+// Calls f(global tile id, sort key, index-order position) once for every pair
+// of the items [first, first + kXT), whose first pair sits at index-order
+// position pbase.  Every thread of the block must call it.  Returns the
+// items' pair count.
 template <class F>
-__device__ inline void for_each_pair(const Items& S, int64_t first, F&& f) {
+__device__ inline uint32_t for_each_pair(const Items& S, int64_t first, uint32_t pbase, F&& f) {
   __shared__ uint32_t s_end[kXT];   // inclusive prefix of pair counts within the wave
+  __shared__ uint32_t s_wtot[kXT / 64];
   __shared__ uint32_t s_base[kXT];  // global id of the footprint's first tile
   __shared__ uint32_t s_w[kXT];     // footprint width in tiles
   __shared__ uint32_t s_gw[kXT];    // tile-grid width of the item's view
@@ -83,6 +92,7 @@ __device__ inline void for_each_pair(const Items& S, int64_t first, F&& f) {
     }
   }
   const uint32_t inc = wave_incl_scan(cnt);
+  if (lane == 63) s_wtot[threadIdx.x >> 6] = inc;
   s_end[threadIdx.x] = inc;
   s_base[threadIdx.x] = base;
   s_w[threadIdx.x] = w;
@@ -90,6 +100,13 @@ __device__ inline void for_each_pair(const Items& S, int64_t first, F&& f) {
   s_key[threadIdx.x] = key;
   __syncthreads();
   const uint32_t total = __shfl(inc, 63, 64);
+  uint32_t wbase = pbase, all = 0;
+#pragma unroll
+  for (int w = 0; w < kXT / 64; ++w) {
+    const uint32_t t = s_wtot[w];
+    wbase += (w < (threadIdx.x >> 6)) ? t : 0u;
+    all += t;
+  }
   for (uint32_t j = uint32_t(lane); j < total; j += 64) {
     // the item owning the wave's j-th pair: the first k with s_end[k] > j
     int k = 0;
@@ -99,9 +116,37 @@ __device__ inline void for_each_pair(const Items& S, int64_t first, F&& f) {
     const uint32_t local = j - (k > 0 ? s_end[w0 + k - 1] : 0u);
     const uint32_t wk = s_w[w0 + k];
     const uint32_t ty = local / wk, tx = local - ty * wk;
-    f(s_base[w0 + k] + ty * s_gw[w0 + k] + tx, s_key[w0 + k]);
+    f(s_base[w0 + k] + ty * s_gw[w0 + k] + tx, s_key[w0 + k], wbase + j);
   }
   __syncthreads();  // the arrays are rewritten by the next call
+  return all;
+}
+
+// Pair count of each block's items (the block decomposition of k_tile_count
+// and k_bucket); k_scan_spine then turns them into each block's first
+// index-order position.
+__global__ __launch_bounds__(kXT) void k_tile_reduce(Items S, int rounds,
+                                                     uint32_t* __restrict__ block_pairs) {
+  __shared__ uint32_t s_w[kXT / 64];
+  const int64_t i0 = int64_t(blockIdx.x) * kXT * rounds;
+  uint32_t acc = 0;
+  for (int r = 0; r < rounds; ++r) {
+    const int64_t i = i0 + int64_t(r) * kXT + threadIdx.x;
+    if (i < S.m) {
+      const int64_t v = i / S.n, g = i - v * S.n;
+      acc += reinterpret_cast<const uint32_t*>(S.proj + size_t(v) * S.stride + S.tt_off)[g];
+    }
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) acc += uint32_t(__shfl_xor(int(acc), d, 64));
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int w = 0; w < kXT / 64; ++w) t += s_w[w];
+    block_pairs[blockIdx.x] = t;
+  }
 }
 
 // A block takes kXT * rounds consecutive items.  When the tiles of the views
@@ -128,27 +173,38 @@ __device__ inline BlockSpan block_span(const Items& S, int rounds, int agg_bins)
 }
 
 __global__ __launch_bounds__(kXT) void k_tile_count(Items S, int rounds, int agg_bins,
-                                                    uint32_t* __restrict__ ranges) {
+                                                    const uint32_t* __restrict__ block_pos,
+                                                    int64_t cap, uint32_t* __restrict__ ranges,
+                                                    uint32_t* __restrict__ rank) {
   extern __shared__ uint32_t s_bins[];
   const BlockSpan B = block_span(S, rounds, agg_bins);
   if (B.agg) {
     for (int b = threadIdx.x; b < B.span; b += kXT) s_bins[b] = 0u;
     __syncthreads();
     for (int64_t c = B.i0; c < B.i1; c += kXT)
-      for_each_pair(S, c, [&](uint32_t t, uint64_t) { atomicAdd(&s_bins[t - B.t_lo], 1u); });
+      for_each_pair(S, c, 0u,
+                    [&](uint32_t t, uint64_t, uint32_t) { atomicAdd(&s_bins[t - B.t_lo], 1u); });
     for (int b = threadIdx.x; b < B.span; b += kXT)
       if (s_bins[b]) atomicAdd(&ranges[2 * size_t(B.t_lo + b) + 1], s_bins[b]);
   } else {
+    // the returned count is the pair's rank among its tile's ranked pairs
+    uint32_t pos = block_pos[blockIdx.x];
     for (int64_t c = B.i0; c < B.i1; c += kXT)
-      for_each_pair(S, c, [&](uint32_t t, uint64_t) { atomicAdd(&ranges[2 * size_t(t) + 1], 1u); });
+      pos += for_each_pair(S, c, pos, [&](uint32_t t, uint64_t, uint32_t p) {
+        const uint32_t r = atomicAdd(&ranges[2 * size_t(t)], 1u);
+        if (int64_t(p) < cap) rank[p] = r;
+      });
   }
 }
 
-// Places every pair's key in its tile's bucket.  The cursors count down from
-// the tile ends; with LDS bins the block first reserves one contiguous slot
-// range per touched tile, then ranks its pairs inside it with LDS atomics.
+// Places every pair's key in its tile's bucket: a ranked pair at the tile's
+// first slot plus its rank; with LDS bins the block first reserves one
+// contiguous slot range per touched tile from the tile's cursor (which starts
+// after the ranked pairs), then ranks its pairs inside it with LDS atomics.
 __global__ __launch_bounds__(kXT) void k_bucket(Items S, int rounds, int agg_bins,
                                                 const int64_t* __restrict__ n_eff,
+                                                const uint32_t* __restrict__ block_pos,
+                                                const uint32_t* __restrict__ rank,
                                                 uint32_t* __restrict__ ranges,
                                                 uint64_t* __restrict__ bucket) {
   extern __shared__ uint32_t s_bins[];
@@ -158,27 +214,31 @@ __global__ __launch_bounds__(kXT) void k_bucket(Items S, int rounds, int agg_bin
     for (int b = threadIdx.x; b < B.span; b += kXT) s_bins[b] = 0u;
     __syncthreads();
     for (int64_t c = B.i0; c < B.i1; c += kXT)
-      for_each_pair(S, c, [&](uint32_t t, uint64_t) { atomicAdd(&s_bins[t - B.t_lo], 1u); });
+      for_each_pair(S, c, 0u,
+                    [&](uint32_t t, uint64_t, uint32_t) { atomicAdd(&s_bins[t - B.t_lo], 1u); });
     for (int b = threadIdx.x; b < B.span; b += kXT) {
       const uint32_t k = s_bins[b];
-      if (k) s_bins[b] = atomicSub(&ranges[2 * size_t(B.t_lo + b) + 1], k) - k;
+      if (k) s_bins[b] = atomicAdd(&ranges[2 * size_t(B.t_lo + b) + 1], k);
     }
     __syncthreads();
     for (int64_t c = B.i0; c < B.i1; c += kXT)
-      for_each_pair(S, c, [&](uint32_t t, uint64_t key) {
+      for_each_pair(S, c, 0u, [&](uint32_t t, uint64_t key, uint32_t) {
         bucket[atomicAdd(&s_bins[t - B.t_lo], 1u)] = key;
       });
   } else {
+    uint32_t pos = block_pos[blockIdx.x];
     for (int64_t c = B.i0; c < B.i1; c += kXT)
-      for_each_pair(S, c, [&](uint32_t t, uint64_t key) {
-        bucket[atomicSub(&ranges[2 * size_t(t) + 1], 1u) - 1u] = key;
+      pos += for_each_pair(S, c, pos, [&](uint32_t t, uint64_t key, uint32_t p) {
+        bucket[ranges[2 * size_t(t)] + rank[p]] = key;
       });
   }
 }
 
-// One block: ranges[2t] = exclusive prefix of the counters ranges[2t+1] and
-// ranges[2t+1] = that prefix plus the count (the cursor start), the pair
-// total, and whether it fits the capacity.  Sums are 64-bit, so an
+// One block: with c_t = ranges[2t] (ranked pairs) + ranges[2t+1] (pairs of
+// LDS-counting blocks), ranges[2t] = exclusive prefix of c (the tile's first
+// slot) and ranges[2t+1] = that prefix plus the ranked pairs (where the
+// LDS-counting blocks' cursor starts); the pair total, and whether it fits
+// the capacity.  Sums are 64-bit, so an
 // overflowing total is always detected.
 constexpr int kTS = 1024;
 constexpr int kTSItems = 8;
@@ -204,11 +264,12 @@ __global__ __launch_bounds__(kTS) void k_tile_scan(uint32_t* __restrict__ ranges
   uint64_t carry = 0;
   for (int base = 0; base < n_tiles; base += kTS * kTSItems) {
     const int i0 = base + threadIdx.x * kTSItems;
-    uint32_t c[kTSItems];
+    uint32_t c[kTSItems], cr[kTSItems];
     uint64_t s = 0;
 #pragma unroll
     for (int k = 0; k < kTSItems; ++k) {
-      c[k] = (i0 + k < n_tiles) ? ranges[2 * size_t(i0 + k) + 1] : 0u;
+      cr[k] = (i0 + k < n_tiles) ? ranges[2 * size_t(i0 + k)] : 0u;
+      c[k] = cr[k] + ((i0 + k < n_tiles) ? ranges[2 * size_t(i0 + k) + 1] : 0u);
       s += c[k];
     }
     const uint64_t inc = wave_incl_scan64(s);
@@ -227,7 +288,7 @@ __global__ __launch_bounds__(kTS) void k_tile_scan(uint32_t* __restrict__ ranges
     for (int k = 0; k < kTSItems; ++k) {
       if (i0 + k < n_tiles) {
         ranges[2 * size_t(i0 + k)] = uint32_t(ex);
-        ranges[2 * size_t(i0 + k) + 1] = uint32_t(ex + c[k]);
+        ranges[2 * size_t(i0 + k) + 1] = uint32_t(ex + cr[k]);
       }
       ex += c[k];
     }
@@ -502,12 +563,14 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int6
 }
 
 struct WsLayout {
-  size_t cnt, bucket, total;
-  explicit WsLayout(int64_t cap) {
+  size_t cnt, bucket, rank, bpos, total;
+  WsLayout(int64_t m, int64_t cap) {
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
     cnt = take(8 * 4);
     bucket = take(8 * size_t(cap));
+    rank = take(4 * size_t(cap));
+    bpos = take(4 * (size_t((m + kXT - 1) / kXT) + 1));  // per expansion block
     total = o;
   }
 };
@@ -517,7 +580,11 @@ struct WsLayout {
 // file-scope device array, one copy per GPU.  Host code never passes the
 // array's name to a kernel (on the host it only names the symbol): the
 // device address comes from hipGetSymbolAddress, once per device.
-constexpr size_t kNoAllocBytes = 256 + 8 * size_t(GS_BIN_SORT_NOALLOC_MAX_PAIRS);
+constexpr size_t align256c(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr size_t kNoAllocBytes =
+    256 + align256c(8 * size_t(GS_BIN_SORT_NOALLOC_MAX_PAIRS)) +
+    align256c(4 * size_t(GS_BIN_SORT_NOALLOC_MAX_PAIRS)) +
+    align256c(4 * (size_t(GS_BIN_SORT_NOALLOC_MAX_ITEMS + kXT - 1) / kXT + 1));
 static __device__ __align__(256) char scratch[kNoAllocBytes];
 
 constexpr int kMaxDevices = 64;
@@ -545,26 +612,31 @@ hipError_t scratch_address(void** out) {
 
 }  // namespace
 
-size_t bin_sort_ws_bytes(int, int, int64_t cap) { return WsLayout(cap).total; }
+size_t bin_sort_ws_bytes(int n_views, int n, int64_t cap) {
+  return WsLayout(int64_t(n_views) * n, cap).total;
+}
 
 hipError_t launch_bin_sort_noalloc(const Views& V, int n, const char* proj, int64_t cap,
                                    uint64_t* keys, uint32_t* vals, uint32_t* ranges,
                                    int64_t* n_pairs_dev, hipStream_t st) {
-  if (cap < 0 || cap > GS_BIN_SORT_NOALLOC_MAX_PAIRS || WsLayout(cap).total > kNoAllocBytes)
+  const int64_t m = int64_t(V.n_views) * n;
+  if (cap < 0 || cap > GS_BIN_SORT_NOALLOC_MAX_PAIRS || m > GS_BIN_SORT_NOALLOC_MAX_ITEMS ||
+      WsLayout(m, cap).total > kNoAllocBytes)
     return hipErrorInvalidValue;  // the caller rejects this first
   void* ws = nullptr;
   const hipError_t e = scratch_address(&ws);
   if (e != hipSuccess) return e;
-  // every call writes each scratch byte it reads (the counts in the tile scan,
-  // the bucket slots [0, pairs) in the bucket pass) before reading it, so
-  // nothing is cleared
+  // every call writes each scratch byte it reads before reading it (the counts
+  // in the tile scan, the block offsets in the reduce pass, the ranks in the
+  // count pass, the bucket slots [0, pairs) in the bucket pass), so nothing is
+  // cleared
   return launch_bin_sort(V, n, proj, cap, ws, keys, vals, ranges, n_pairs_dev, st);
 }
 
 hipError_t launch_bin_sort(const Views& V, int n, const char* proj, int64_t cap, void* ws_,
                            uint64_t* keys, uint32_t* vals, uint32_t* ranges,
                            int64_t* n_pairs_dev, hipStream_t st) {
-  const WsLayout W(cap);
+  const WsLayout W(int64_t(V.n_views) * n, cap);
   char* ws = static_cast<char*>(ws_);
   int64_t* counts = reinterpret_cast<int64_t*>(ws + W.cnt);
   int64_t* n_tot = counts + 0;
@@ -572,6 +644,8 @@ hipError_t launch_bin_sort(const Views& V, int n, const char* proj, int64_t cap,
   int64_t* n_long = counts + 2;
   int64_t* n_mid = counts + 3;
   uint64_t* bucket = reinterpret_cast<uint64_t*>(ws + W.bucket);
+  uint32_t* rank = reinterpret_cast<uint32_t*>(ws + W.rank);
+  uint32_t* bpos = reinterpret_cast<uint32_t*>(ws + W.bpos);
   const ProjLayout L(n);
   Items S{};
   int min_view_tiles = 1 << 30;
@@ -604,14 +678,22 @@ hipError_t launch_bin_sort(const Views& V, int n, const char* proj, int64_t cap,
 
   GS_LAUNCH("k_fill_u32", k_fill_u32, dim3(unsigned(nr / 256 + 1 < 4096 ? nr / 256 + 1 : 4096)),
             dim3(256), 0, st, ranges, nr, 0u);
-  if (xb > 0)
+  if (xb > 0) {
+    // index-order positions of each block's first pair (only blocks that rank
+    // their pairs read them: none when every view has at most agg_bins tiles)
+    if (T > agg_bins) {
+      GS_LAUNCH("k_tile_reduce", k_tile_reduce, dim3(xb), dim3(kXT), 0, st, S, rounds, bpos);
+      GS_LAUNCH("k_scan_spine", k_scan_spine, dim3(1), dim3(kScanThreads), 0, st, bpos,
+                Count{nullptr, int64_t(xb) * kScanTile}, nullptr, nullptr);
+    }
     GS_LAUNCH("k_tile_count", k_tile_count, dim3(xb), dim3(kXT), agg_lds, st, S, rounds, agg_bins,
-              ranges);
+              bpos, cap, ranges, rank);
+  }
   GS_LAUNCH("k_tile_scan", k_tile_scan, dim3(1), dim3(kTS), 0, st, ranges, T, cap, n_tot, n_eff,
             n_long, n_mid, n_pairs_dev);
   if (xb > 0)
     GS_LAUNCH("k_bucket", k_bucket, dim3(xb), dim3(kXT), agg_lds, st, S, rounds, agg_bins, n_eff,
-              ranges, bucket);
+              bpos, rank, ranges, bucket);
   GS_LAUNCH("k_tile_sort_wave", k_tile_sort_wave, dim3(unsigned((T + 3) / 4)), dim3(256), 0, st,
             T, n_tot, n_eff, n_mid, n_long, bucket, vals, keys, ranges);
   GS_LAUNCH("k_tile_sort_mid", k_tile_sort_mid, dim3(unsigned(T < kMidBlocks ? T : kMidBlocks)),

@@ -209,6 +209,7 @@ def gs_bin_sort(cams_c, cfg, n, proj, capacity, ws, keys, vals, ranges, n_pairs_
 
 
 GS_BIN_SORT_NOALLOC_MAX_PAIRS = 1 << 22
+GS_BIN_SORT_NOALLOC_MAX_ITEMS = 1 << 23
 
 
 def gs_bin_sort_noalloc(cams_c, cfg, n, proj, capacity, keys, vals, ranges, n_pairs_dev,

@@ -87,6 +87,15 @@ def test_argument_errors(L):
     need = gsmi.gs_bin_sort_workspace_bytes(1, 10, 100)
     assert L.gs_bin_sort(1, cams, ctypes.byref(good), 10, 16, 100, 256, need - 1, None, 16, 16,
                          16, None) == 2
+    # the no-allocation binning: capacity or items beyond its array -> GS_ERR_CAPACITY,
+    # a negative capacity -> GS_ERR_ARG (checked before anything touches a device)
+    mx = gsmi.GS_BIN_SORT_NOALLOC_MAX_PAIRS
+    assert L.gs_bin_sort_noalloc(1, cams, ctypes.byref(good), 10, 16, mx + 1, None, 16, 16, 16,
+                                 None) == 2
+    assert L.gs_bin_sort_noalloc(1, cams, ctypes.byref(good), gsmi.GS_BIN_SORT_NOALLOC_MAX_ITEMS
+                                 + 1, 16, 100, None, 16, 16, 16, None) == 2
+    assert L.gs_bin_sort_noalloc(1, cams, ctypes.byref(good), 10, 16, -1, None, 16, 16, 16,
+                                 None) == 1
     # adam: step 0, too many groups, bad beta
     grp = (gsmi.GsAdamGroup * 1)()
     grp[0].numel = 0

@@ -84,5 +84,10 @@ def test_noalloc_bin_sort_rejects_capacity_above_its_maximum():
         gsmi.gs_bin_sort_noalloc(cams_c, cfg, n, proj, gsmi.GS_BIN_SORT_NOALLOC_MAX_PAIRS + 1,
                                  *out)
     assert e.value.status == 2     # GS_ERR_CAPACITY
+    # more (view, Gaussian) items than the array's block offsets hold
+    with pytest.raises(gsmi.GsError) as e:
+        gsmi.gs_bin_sort_noalloc(cams_c, cfg, gsmi.GS_BIN_SORT_NOALLOC_MAX_ITEMS + 1, proj, 1,
+                                 *out)
+    assert e.value.status == 2
     torch.cuda.synchronize()
     assert int(out[3].item()) == -1   # nothing was enqueued
