@@ -1018,19 +1018,22 @@ struct BwdWs {
 // ---- static balancing of the one-wave-per-tile backward.  All of its waves
 // are resident at once, so a SIMD's time is the sum of its waves' work, and
 // tiles dealt out in index order leave the busiest SIMD about 1.2x the mean.
-// Block 0 of k_zero_pairs ranks the tiles by their list length (256 buckets,
-// longest first) and deals the ranks out with order_block (rounds of
-// kOrderRound blocks, every other round reversed), so that blocks b and
-// b + kOrderRound pair a heavy tile with a light one.  Which block takes
+// Block 0 of k_zero_pairs ranks each XCD's share of the tiles by list length
+// (256 buckets, longest first) and deals the ranks to that XCD's blocks with
+// order_block (rounds of 32 of its blocks, every other round reversed), so
+// that blocks b and b + 256 pair a heavy tile with a light one while every
+// XCD keeps the contiguous share of each view that xcd_tile gives it (the
+// Gaussians of neighbouring tiles then meet in one L2).  Which block takes
 // which tile changes no result.
 
 // one 1024-thread block; every thread of the block calls it
-__device__ void tile_order_block(int n_tiles, const uint32_t* __restrict__ ranges,
+__device__ void tile_order_block(const RViews& RV, const uint32_t* __restrict__ ranges,
                                  uint32_t* __restrict__ order) {
+  const int n_tiles = RV.total_tiles;
   auto cost = [&](int i) { return ranges[2 * i + 1] - ranges[2 * i]; };
-  __shared__ uint32_t s_hist[256], s_off[256], s_max;
+  __shared__ uint32_t s_hist[kXcds][256], s_off[kXcds][256], s_max;
   const int tid = threadIdx.x;
-  if (tid < 256) s_hist[tid] = 0u;
+  for (int i = tid; i < kXcds * 256; i += 1024) (&s_hist[0][0])[i] = 0u;
   if (tid == 0) s_max = 0u;
   __syncthreads();
   uint32_t mx = 0;
@@ -1039,31 +1042,42 @@ __device__ void tile_order_block(int n_tiles, const uint32_t* __restrict__ range
   __syncthreads();
   const uint64_t top = uint64_t(s_max) + 1u;
   auto bucket = [&](uint32_t c) { return 255u - uint32_t(uint64_t(c) * 256u / top); };
-  for (int i = tid; i < n_tiles; i += 1024) atomicAdd(&s_hist[bucket(cost(i))], 1u);
+  for (int i = tid; i < n_tiles; i += 1024) {
+    int idx;
+    const int x = xcd_of_tile(i, RV, idx);
+    atomicAdd(&s_hist[x][bucket(cost(i))], 1u);
+  }
   __syncthreads();
-  // exclusive scan of the 256 bucket counts: four waves, then their totals
-  __shared__ uint32_t s_wsum[4];
-  uint32_t inc = 0;
-  if (tid < 256) {
-    const int lane = tid & 63;
-    inc = s_hist[tid];
+  // exclusive scan of each XCD's 256 bucket counts: wave w of the first eight
+  // scans XCD w's histogram, four values per lane
+  const int lane = tid & 63, w = tid >> 6;
+  if (w < kXcds) {
+    uint32_t v[4], sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] = s_hist[w][4 * lane + k];
+      sum += v[k];
+    }
+    uint32_t inc = sum;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
       const uint32_t y = __shfl_up(inc, d, 64);
       if (lane >= d) inc += y;
     }
-    if (lane == 63) s_wsum[tid >> 6] = inc;
-  }
-  __syncthreads();
-  if (tid < 256) {
-    uint32_t before = 0;
-    for (int w = 0; w < (tid >> 6); ++w) before += s_wsum[w];
-    s_off[tid] = before + inc - s_hist[tid];
+    uint32_t ex = inc - sum;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      s_off[w][4 * lane + k] = ex;
+      ex += v[k];
+    }
   }
   __syncthreads();
   for (int i = tid; i < n_tiles; i += 1024) {
-    const int r = int(atomicAdd(&s_off[bucket(cost(i))], 1u));  // rank, heaviest first
-    order[order_block(r, n_tiles)] = uint32_t(i);
+    int idx;
+    const int x = xcd_of_tile(i, RV, idx);
+    const int n_x = RV.xcd_off[x][RV.n_views];  // tiles (and blocks) of XCD x
+    const int r = int(atomicAdd(&s_off[x][bucket(cost(i))], 1u));  // rank, heaviest first
+    order[order_block(r, n_x) * kXcds + x] = uint32_t(i);
   }
 }
 
@@ -1073,13 +1087,13 @@ __device__ void tile_order_block(int n_tiles, const uint32_t* __restrict__ range
 constexpr int kZeroBlocks = 512;
 __global__ __launch_bounds__(1024) void k_zero_pairs(float* __restrict__ p,
                                                      const int64_t* __restrict__ total,
-                                                     int64_t cap, int n_tiles,
+                                                     int64_t cap, RViews RV,
                                                      const uint32_t* __restrict__ ranges,
                                                      uint32_t* __restrict__ order,
                                                      int32_t* __restrict__ step_dev) {
   if (blockIdx.x == 0) {
     if (step_dev && threadIdx.x == 0) *step_dev += 1;
-    if (order) tile_order_block(n_tiles, ranges, order);
+    if (order) tile_order_block(RV, ranges, order);
     return;
   }
   const int64_t np = (*total < cap) ? *total : cap;
@@ -1147,7 +1161,7 @@ hipError_t bwd_to_planes(const Views& V, int n, const gs_raster_cfg& cfg, const 
   if (T > 0 && !split_long_lists(RV, cfg.tile) && size_t(4) * kG * size_t(M) >= 4 * T)
     order = reinterpret_cast<uint32_t*>(ws + B.g2d);
   GS_LAUNCH("k_zero_pairs", k_zero_pairs, dim3(1 + kZeroBlocks), dim3(1024), 0, st, pairs, total,
-            cap, V.total_tiles, ranges, order, step_dev);
+            cap, RV, ranges, order, step_dev);
   if (V.total_tiles > 0) {
     const dim3 grid(unsigned(V.total_tiles));
     switch (cfg.tile) {

@@ -74,17 +74,37 @@ __host__ __device__ __forceinline__ int xcd_tile(int b, const RViews& RV) {
   return RV.tile_base[RV.order[k]] + RV.xcd_start[x][k] + (idx - RV.xcd_off[x][k]);
 }
 
-// The backward's balanced tile order: tiles ranked by list length (rank 0 the
-// heaviest) are dealt to blocks in rounds of kOrderRound, every other
-// complete round reversed, so that blocks b and b + kOrderRound (which the
-// round-robin dispatch places on the same SIMDs) pair a heavy tile with a
-// light one.  Block of rank r; a bijection on [0, n_tiles).
-constexpr int kOrderRound = 256;
+// The inverse of xcd_tile: the XCD whose share holds global tile t and the
+// tile's index in that XCD's walk (block = index * 8 + XCD).
+__host__ __device__ __forceinline__ int xcd_of_tile(int t, const RViews& RV, int& idx) {
+  int v = 0;
+  for (int k = 1; k < RV.n_views; ++k) v = (RV.tile_base[k] <= t) ? k : v;
+  int pos = 0;
+  for (int k = 0; k < RV.n_views; ++k) pos = (RV.order[k] == v) ? k : pos;
+  const int l = t - RV.tile_base[v];
+  // a view's shares are contiguous in XCD order; the last one starting at or
+  // before l holds it (an empty share starts where the next one does, and the
+  // last XCD's share starts before the view's end only when it is not empty)
+  int x = 0;
+  for (int j = 1; j < kXcds; ++j) x = (RV.xcd_start[j][pos] <= l) ? j : x;
+  idx = RV.xcd_off[x][pos] + (l - RV.xcd_start[x][pos]);
+  return x;
+}
 
-__host__ __device__ __forceinline__ int order_block(int r, int n_tiles) {
-  const int full = n_tiles / kOrderRound;  // complete rounds
-  const int round = r / kOrderRound, j = r - round * kOrderRound;
-  return (round < full && (round & 1)) ? round * kOrderRound + (kOrderRound - 1 - j) : r;
+// The backward's balanced tile order.  Within each XCD's share (the tiles
+// xcd_tile gives it, so neighbouring tiles still meet in one L2), tiles
+// ranked by list length (rank 0 the heaviest) are dealt to the XCD's blocks
+// in rounds of kOrderRound / 8, every other complete round reversed, so that
+// blocks b and b + kOrderRound (which the round-robin dispatch places on the
+// same SIMDs) pair a heavy tile with a light one.  Index in the XCD's walk of
+// rank r among its n tiles; a bijection on [0, n).
+constexpr int kOrderRound = 256;
+constexpr int kXcdRound = kOrderRound / kXcds;
+
+__host__ __device__ __forceinline__ int order_block(int r, int n, int round_len = kXcdRound) {
+  const int full = n / round_len;  // complete rounds
+  const int round = r / round_len, j = r - round * round_len;
+  return (round < full && (round & 1)) ? round * round_len + (round_len - 1 - j) : r;
 }
 
 // List-parallel blending, for launches with few tiles: when the whole launch

@@ -1,8 +1,8 @@
 // Host check of the blend kernels' block -> tile mapping (blend_common.hpp):
 // for random mixes of view sizes it must be a bijection on [0, total tiles),
 // walk every XCD's share of a view contiguously, and reach the views in order
-// of increasing tile count; and the backward's balanced rank -> block deal
-// (order_block) must be a bijection for every tile count.  Prints "ok" or
+// of increasing tile count; xcd_of_tile must invert it; and the backward's
+// balanced rank -> block deal (order_block, per XCD) must be a bijection.  Prints "ok" or
 // the first failure; exit code 0/1.
 #include <cstdio>
 #include <random>
@@ -36,9 +36,30 @@ int main() {
                     b, t, total);
         return 1;
       }
+      int idx = -1;
+      const int x = gsk::xcd_of_tile(t, R, idx);
+      if (x != b % gsk::kXcds || idx != b / gsk::kXcds) {
+        std::printf("trial %d: tile %d of block %d maps back to XCD %d index %d\n", trial, t, b,
+                    x, idx);
+        return 1;
+      }
       int v = 0;
       for (int k = 1; k < V.n_views; ++k) v = (V.v[k].tile_base <= t) ? k : v;
       if (first_block[v] < 0) first_block[v] = b;
+    }
+    // the backward's balanced order: each XCD's ranks dealt to its own blocks
+    // cover every block exactly once
+    std::vector<int> hit(total, 0);
+    for (int x = 0; x < gsk::kXcds; ++x) {
+      const int n_x = R.xcd_off[x][V.n_views];
+      for (int r = 0; r < n_x; ++r) {
+        const int b = gsk::order_block(r, n_x) * gsk::kXcds + x;
+        if (b < 0 || b >= total || hit[b]++) {
+          std::printf("trial %d: XCD %d rank %d -> block %d repeated or out of range\n", trial,
+                      x, r, b);
+          return 1;
+        }
+      }
     }
     // a view with fewer tiles never starts after a view with more tiles
     for (int a = 0; a < V.n_views; ++a)
@@ -58,7 +79,7 @@ int main() {
     const int n = trial < 2100 ? trial : 1 + int(rng() % 200000);
     std::vector<int> seen(n, 0);
     for (int r = 0; r < n; ++r) {
-      const int b = gsk::order_block(r, n);
+      const int b = gsk::order_block(r, n, gsk::kOrderRound);
       if (b < 0 || b >= n || seen[b]++) {
         std::printf("order n=%d: rank %d -> block %d repeated or out of range\n", n, r, b);
         return 1;
