@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 4M-Gaussian, 16-view workload")
     ap.add_argument("--no-extras", action="store_true", help="skip levels and batched form")
+    ap.add_argument("--no-spatial", action="store_true",
+                    help="keep the scenes in generation order instead of the spatial order")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run warmup + this many steps (for rocprofv3), no extras")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -114,6 +116,10 @@ def main():
     scene, cam = scenes.paper_scale_scene(level=1, n=args.n)
     tscene = scenes.paper_scale_target_scene(n=args.n)
     params = raster.to_device(scene, dev)
+    if not args.no_spatial:
+        # stored along the Morton curve of the means (gs_spatial_order); the
+        # rendering does not depend on the order
+        _, params = raster.spatial_order(params)
     tparams = raster.to_device(tscene, dev)
     target = raster.render(tparams, [cam], tile=args.tile).image.clone()
     del tparams
@@ -245,10 +251,10 @@ def main():
                                        tile=args.tile, lds=args.lds_batch)
         extras["batched"] = batched_vs_plain(torch, raster, scenes, params, tscene)
         if not args.no_large:
-            extras["large"] = large_scene(torch, raster, scenes, dev)
+            extras["large"] = large_scene(torch, raster, scenes, dev, not args.no_spatial)
         if args.train_iters > 0:
             extras["training"] = scheduled_training(torch, raster, scenes, dev, args.train_iters,
-                                                    args.train_ablations)
+                                                    args.train_ablations, not args.no_spatial)
 
     out = {
         "metric": "fwd+bwd Mpix/s at 1M Gaussians 1600x1064; batched vs plain it/s at oracle tol",
@@ -267,7 +273,8 @@ def main():
         "config": {"workload": "1M Gaussians, one 1600x1064 view, full step: preprocess, "
                                "bin/sort, blend fwd, L1, blend bwd, chain rule fused with Adam",
                    "n_gaussians": args.n, "width": W, "height": H, "tile": args.tile,
-                   "lds_batch": args.lds_batch, "pairs": n_pairs, "wall_s": round(wall, 3)},
+                   "lds_batch": args.lds_batch, "pairs": n_pairs, "wall_s": round(wall, 3),
+                   "storage_order": "index" if args.no_spatial else "spatial (Morton)"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernel_ms_per_step": breakdown,
@@ -391,13 +398,15 @@ def batched_vs_plain(torch, raster, scenes, params, tscene):
     return compare_forms(torch, raster, params, cams, tgts, "16 mixed-resolution views")
 
 
-def large_scene(torch, raster, scenes, dev):
+def large_scene(torch, raster, scenes, dev, spatial=True):
     """The large workload: 4M Gaussians, 8 views at 1920x1080 and 8 at 960x540,
     gradients of all 16 views accumulated into one Adam step over 236M floats;
     seeded uniform random targets."""
     scene, cams = scenes.large_scene_views()
     params = raster.to_device(scene, dev)
     del scene
+    if spatial:
+        _, params = raster.spatial_order(params)
     gen = torch.Generator(device=dev).manual_seed(2)
     tgts = [torch.rand(3 * c.width * c.height, generator=gen, device=dev) for c in cams]
     out = compare_forms(torch, raster, params, cams, tgts, "16 views, 4M Gaussians")
@@ -468,7 +477,7 @@ def compare_forms(torch, raster, params, cams, tgts, label):
                      "16 per-view gradients and then runs the separate Adam step")
 
 
-def scheduled_training(torch, raster, scenes, dev, iters, ablations=False):
+def scheduled_training(torch, raster, scenes, dev, iters, ablations=False, spatial=True):
     """The optimisation loop of the hidden-scene workload: learnable Gaussians
     fitted to 64 views at 1200x800 of a 500k-Gaussian hidden scene (ground
     truth rendered once), ``iters`` iterations, one view per iteration.  From
@@ -514,7 +523,7 @@ def scheduled_training(torch, raster, scenes, dev, iters, ablations=False):
                                    p_fin=budget)
         tr = train.Trainer(params, cams, gt, iters, schedule=sched, densify=dcfg, r_max=r_max,
                            means_lr=(1.6e-4 * extent, 1.6e-6 * extent), mip=mip,
-                           autograd=autograd)
+                           autograd=autograd, spatial=spatial)
         psnr0 = train.psnr(tr.params, cams, gt, mip2d=mip, filter3d=tr.filter3d)
         res = tr.run()
         psnr1 = train.psnr(tr.params, cams, gt, mip2d=mip, filter3d=tr.filter3d)

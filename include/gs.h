@@ -180,6 +180,36 @@ gs_status gs_bin_sort_radix(int32_t n_views, const gs_camera* cams, const gs_ras
                             size_t ws_bytes, uint64_t* keys, uint32_t* vals, uint32_t* ranges,
                             int64_t* n_pairs_dev, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Spatial storage order.  Nothing the calls above compute depends on the order
+ * in which the Gaussians are stored, except the tie-break of exactly equal
+ * depths, which follows the stored index.  Stored along a space-filling
+ * curve, consecutive Gaussians sit close together in space, which the binning
+ * (fewer global counter atomics), sparse Adam and the preprocess (long runs
+ * of Gaussians outside a view) and the blends (fewer cache lines per tile
+ * list) all profit from.
+ *
+ * gs_spatial_order: perm [n] u32 (device, output) = the Gaussians sorted by
+ *   the Morton code of their means: per axis, the cell
+ *   q = min(1023, floor((m - lo) * (1024 / (hi - lo)))) in the means'
+ *   bounding box [lo, hi] (each operation rounded to float32 in that order;
+ *   a flat axis gives cell 0), the ten bits of q_x, q_y, q_z interleaved (x
+ *   lowest); ties keep ascending index.  perm[k] is the index of the k-th
+ *   Gaussian in that order.  means [n,3] device.  ws: at least
+ *   gs_spatial_order_workspace_bytes(n) bytes.  n >= 0.
+ * gs_gather_rows: for each of n_arrays (<= 16) device arrays of n rows of
+ *   row_floats[a] (1..64) floats, dst[a] row i = src[a] row perm[i]: applies
+ *   the order to the parameters (and Adam moments).  src, dst, row_floats:
+ *   host arrays of n_arrays entries; dst must not overlap src.  An entry
+ *   perm[i] >= n leaves row i of every dst unwritten.
+ * ------------------------------------------------------------------------- */
+size_t gs_spatial_order_workspace_bytes(int32_t n);
+gs_status gs_spatial_order(int32_t n, const float* means, void* ws, size_t ws_bytes,
+                           uint32_t* perm, void* stream);
+gs_status gs_gather_rows(int32_t n, const uint32_t* perm, int32_t n_arrays,
+                         const float* const* src, float* const* dst, const int32_t* row_floats,
+                         void* stream);
+
 /* Total tiles over the views for this cfg (host helper for sizing ranges). */
 int64_t gs_total_tiles(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg);
 

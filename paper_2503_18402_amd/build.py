@@ -22,7 +22,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 
 ARCH = "gfx950"
 SOURCES = ["abi.cpp", "preprocess.hip", "sort.hip", "radix_sort.hip", "blend_fwd.hip",
-           "blend_bwd.hip", "adam.hip", "schedule.hip", "densify.hip"]
+           "blend_bwd.hip", "adam.hip", "schedule.hip", "densify.hip", "order.hip"]
 
 
 def hipcc() -> str:

@@ -235,6 +235,30 @@ gs_status gs_bin_sort_noalloc(int32_t n_views, const gs_camera* cams, const gs_r
                                           keys, vals, ranges, n_pairs_dev, as_stream(stream)));
 }
 
+size_t gs_spatial_order_workspace_bytes(int32_t n) {
+  return n < 0 ? 0 : spatial_order_ws_bytes(n);
+}
+
+gs_status gs_spatial_order(int32_t n, const float* means, void* ws, size_t ws_bytes,
+                           uint32_t* perm, void* stream) {
+  if (n < 0 || (n > 0 && (!means || !ws || !perm))) return GS_ERR_ARG;
+  if (ws_bytes < spatial_order_ws_bytes(n)) return GS_ERR_CAPACITY;
+  return from_hip(launch_spatial_order(n, means, ws, perm, as_stream(stream)));
+}
+
+gs_status gs_gather_rows(int32_t n, const uint32_t* perm, int32_t n_arrays,
+                         const float* const* src, float* const* dst, const int32_t* row_floats,
+                         void* stream) {
+  if (n < 0 || n_arrays < 0 || n_arrays > kGatherMaxArrays) return GS_ERR_ARG;
+  if (n == 0 || n_arrays == 0) return GS_OK;
+  if (!perm || !src || !dst || !row_floats) return GS_ERR_ARG;
+  for (int a = 0; a < n_arrays; ++a) {
+    if (!src[a] || !dst[a] || row_floats[a] < 1 || row_floats[a] > kGatherMaxRow) return GS_ERR_ARG;
+    if (int64_t(n) * row_floats[a] >= (int64_t(1) << 40)) return GS_ERR_ARG;
+  }
+  return from_hip(launch_gather_rows(n, perm, n_arrays, src, dst, row_floats, as_stream(stream)));
+}
+
 size_t gs_bin_sort_radix_workspace_bytes(int32_t n_views, int32_t n, int64_t capacity_pairs) {
   if (!n_ok(n_views, n) || capacity_pairs < 0 || capacity_pairs >= (int64_t(1) << 32)) return 0;
   return bin_sort_radix_ws_bytes(n_views, n, capacity_pairs);

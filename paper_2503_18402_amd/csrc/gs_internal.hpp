@@ -209,6 +209,25 @@ hipError_t launch_bin_sort_radix(const Views& V, int n, const char* proj, int64_
                                  uint64_t* keys, uint32_t* vals, uint32_t* ranges,
                                  int64_t* n_pairs_dev, hipStream_t st);
 
+// One stable LSD radix pass over (key, value) u32 pairs on key bits
+// [shift, shift + bits), bits <= 8 (radix_sort.hip).  n = *cnt.dev or cnt.host
+// elements, at most max_n; hist holds radix_hist_words(max_n) u32,
+// digit_total 256.
+struct Count;
+hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
+                      Count cnt, int64_t max_n, int shift, int bits, uint32_t* hist,
+                      uint32_t* digit_total, hipStream_t st);
+size_t radix_hist_words(int64_t max_n);
+
+// spatial storage order (order.hip)
+size_t spatial_order_ws_bytes(int n);
+hipError_t launch_spatial_order(int n, const float* means, void* ws, uint32_t* perm,
+                                hipStream_t st);
+constexpr int kGatherMaxArrays = 16;
+constexpr int kGatherMaxRow = 64;
+hipError_t launch_gather_rows(int n, const uint32_t* perm, int n_arrays, const float* const* src,
+                              float* const* dst, const int32_t* row_floats, hipStream_t st);
+
 // L1 loss gradient of the backbones, dL = scale * sign(image - target) (sign(0) = 0).
 __host__ __device__ __forceinline__ float l1_sign(float d, float scale) {
   return (d > 0.0f) ? scale : ((d < 0.0f) ? -scale : 0.0f);

@@ -46,35 +46,144 @@ __device__ inline void sh_basis(float x, float y, float z, int deg, float* Y) {
 constexpr int kPreThreads = 128;
 constexpr int kShStride = GS_SH_COEFFS * 3 + 1;  // odd LDS stride: conflict-free rows
 
-__global__ __launch_bounds__(kPreThreads) void k_preprocess(
-    Views V, int n, int sh_degree, const float* __restrict__ means,
-    const float* __restrict__ log_scales, const float* __restrict__ quats,
-    const float* __restrict__ opacity_logits, const float* __restrict__ sh,
-    char* __restrict__ proj) {
-  // the block's SH coefficients (192 B per Gaussian) arrive through LDS with
-  // coalesced 16-byte loads instead of 192-byte strided rows per thread
-  __shared__ float s_sh[kPreThreads * kShStride];
-  const int g0 = blockIdx.x * kPreThreads;
-  const int g = g0 + threadIdx.x;
-  {
-    constexpr int F = GS_SH_COEFFS * 3;
-    const int cnt4 = (min(kPreThreads, n - g0) * F) / 4;
-    const float4* src = reinterpret_cast<const float4*>(sh + size_t(g0) * F);
-    for (int i = threadIdx.x; i < cnt4; i += kPreThreads) {
-      const float4 q = src[i];
-      const int f = 4 * i, row = f / F, k = f - row * F;
-      float* d = s_sh + row * kShStride + k;
-      d[0] = q.x;
-      d[1] = q.y;
-      d[2] = q.z;
-      d[3] = q.w;
-    }
-  }
-  __syncthreads();
-  if (g >= n) return;
-  const ProjLayout L(n);
+// The view-independent part of a Gaussian: covariance and opacity.
+struct Gauss3 {
+  float mx, my, mz;
+  float S00, S01, S02, S11, S12, S22;
+  float o, k2o;
+  bool opaque;
+};
 
-  const float mx = means[3 * g + 0], my = means[3 * g + 1], mz = means[3 * g + 2];
+// One view's splat without the colour: the record words, the tile count, and
+// the unit viewing direction for the colour (has_colour: the splat passed the
+// culls that precede the footprint, so a colour is evaluated for it).
+struct Splat {
+  float4 r0, r1, r2;
+  uint32_t count;
+  bool has_colour;
+  float dx, dy, dz;
+};
+
+__device__ __forceinline__ Splat splat_geometry(const DevView& cv, const Gauss3& G, int tile,
+                                                int mip2d) {
+  Splat P;
+  P.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+  P.r1 = P.r0;
+  P.r2 = P.r0;
+  P.count = 0;
+  P.has_colour = false;
+  P.dx = P.dy = P.dz = 0.0f;
+  const float mx = G.mx, my = G.my, mz = G.mz;
+  // depth: the exact float32 sequence that defines the sort key
+  const float depth = __fadd_rn(
+      __fadd_rn(__fadd_rn(__fmul_rn(cv.R[6], mx), __fmul_rn(cv.R[7], my)),
+                __fmul_rn(cv.R[8], mz)),
+      cv.t[2]);
+  if (!(G.opaque && depth > cv.near_plane)) return P;
+  const float xc = fmaf(cv.R[0], mx, fmaf(cv.R[1], my, fmaf(cv.R[2], mz, cv.t[0])));
+  const float yc = fmaf(cv.R[3], mx, fmaf(cv.R[4], my, fmaf(cv.R[5], mz, cv.t[1])));
+  const float iz = 1.0f / depth;
+  const float j00 = cv.fx * iz, j11 = cv.fy * iz;
+  const float j02 = -cv.fx * xc * iz * iz, j12 = -cv.fy * yc * iz * iz;
+  // T = J W (2x3)
+  const float t00 = j00 * cv.R[0] + j02 * cv.R[6];
+  const float t01 = j00 * cv.R[1] + j02 * cv.R[7];
+  const float t02 = j00 * cv.R[2] + j02 * cv.R[8];
+  const float t10 = j11 * cv.R[3] + j12 * cv.R[6];
+  const float t11 = j11 * cv.R[4] + j12 * cv.R[7];
+  const float t12 = j11 * cv.R[5] + j12 * cv.R[8];
+  // U = T Sigma, Sigma' = U T^T + low-pass
+  const float u00 = t00 * G.S00 + t01 * G.S01 + t02 * G.S02;
+  const float u01 = t00 * G.S01 + t01 * G.S11 + t02 * G.S12;
+  const float u02 = t00 * G.S02 + t01 * G.S12 + t02 * G.S22;
+  const float u10 = t10 * G.S00 + t11 * G.S01 + t12 * G.S02;
+  const float u11 = t10 * G.S01 + t11 * G.S11 + t12 * G.S12;
+  const float u12 = t10 * G.S02 + t11 * G.S12 + t12 * G.S22;
+  const float r00 = u00 * t00 + u01 * t01 + u02 * t02;
+  const float r01 = u00 * t10 + u01 * t11 + u02 * t12;
+  const float r11 = u10 * t10 + u11 * t11 + u12 * t12;
+  const float low = mip2d ? kMip2d : kDilation;  // screen-space low-pass
+  const float c00 = r00 + low, c01 = r01, c11 = r11 + low;
+  const float det = c00 * c11 - c01 * c01;
+  // the 2D mip filter keeps the splat's integral: opacity times sqrt(det ratio)
+  float ov = G.o, k2 = G.k2o;
+  if (mip2d && det > 0.0f) {
+    ov = G.o * sqrtf(fmaxf(r00 * r11 - r01 * r01, 0.0f) / det);
+    k2 = fmaxf(0.0f, 2.0f * logf(255.0f * ov));
+  }
+  if (!(det > 0.0f && ov >= kAlphaMin)) return P;
+  P.has_colour = true;
+  const float idet = 1.0f / det;
+  const float ca = c11 * idet, cb = -c01 * idet, cc = c00 * idet;
+  // screen mean in double: float32 spacing at 1000+ px (6e-5 px) would otherwise
+  // dominate the error of every pixel offset near the Gaussian
+  const double xd = double(cv.R[0]) * mx + double(cv.R[1]) * my + double(cv.R[2]) * mz +
+                    double(cv.t[0]);
+  const double yd = double(cv.R[3]) * mx + double(cv.R[4]) * my + double(cv.R[5]) * mz +
+                    double(cv.t[1]);
+  const double zd = double(cv.R[6]) * mx + double(cv.R[7]) * my + double(cv.R[8]) * mz +
+                    double(cv.t[2]);
+  const double mux = double(cv.fx) * xd / zd + double(cv.cx);
+  const double muy = double(cv.fy) * yd / zd + double(cv.cy);
+  // the viewing direction of the colour
+  float dx = mx - cv.campos[0], dy = my - cv.campos[1], dz = mz - cv.campos[2];
+  const float dn = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+  P.dx = dx * dn;
+  P.dy = dy * dn;
+  P.dz = dz * dn;
+  // conservative footprint box of the alpha >= 1/255 ellipse
+  const double ex = double(sqrtf(k2 * c00) * (1.0f + kExtRel) + kExtAbs);
+  const double ey = double(sqrtf(k2 * c11) * (1.0f + kExtRel) + kExtAbs);
+  const double lox = (mux - ex) - 0.5, hix = (mux + ex) - 0.5;
+  const double loy = (muy - ey) - 0.5, hiy = (muy + ey) - 0.5;
+  const double Wd = double(cv.W), Hd = double(cv.H);
+  const int x0 = max(int(ceil(fmin(fmax(lox, -2.0), Wd + 2.0))), 0);
+  const int x1 = min(int(floor(fmin(fmax(hix, -2.0), Wd + 2.0))), cv.W - 1);
+  const int y0 = max(int(ceil(fmin(fmax(loy, -2.0), Hd + 2.0))), 0);
+  const int y1 = min(int(floor(fmin(fmax(hiy, -2.0), Hd + 2.0))), cv.H - 1);
+  const int T = tile;
+  if (x0 <= x1 && y0 <= y1) P.count = uint32_t((x1 / T - x0 / T + 1) * (y1 / T - y0 / T + 1));
+  // the mean is stored relative to the origin of the first tile of the footprint
+  const int ox = (x0 <= x1 ? x0 / T : 0) * T, oy = (y0 <= y1 ? y0 / T : 0) * T;
+  const float s = -0.5f * kLog2e;
+  P.r0 = make_float4(float(mux - double(ox)), float(muy - double(oy)), s * ca, -kLog2e * cb);
+  P.r1 = make_float4(s * cc, log2f(ov), 0.0f, 0.0f);
+  P.r2 = make_float4(0.0f, depth, __uint_as_float(box_pack(x0 < 0 ? 0 : x0, y0 < 0 ? 0 : y0)),
+                     __uint_as_float(box_pack(x1 < 0 ? 0 : x1, y1 < 0 ? 0 : y1)));
+  return P;
+}
+
+// The SH colour of a splat along its viewing direction into the record words
+// (clamped channels flagged); shc holds the coefficients, zero above the degree.
+__device__ __forceinline__ void splat_colour(Splat& P, const float* shc, int sh_degree,
+                                             uint32_t& flags) {
+  float Y[GS_SH_COEFFS];
+#pragma unroll
+  for (int k = 0; k < GS_SH_COEFFS; ++k) Y[k] = 0.0f;
+  sh_basis(P.dx, P.dy, P.dz, sh_degree, Y);
+  float rgb[3];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    // coefficients above the degree are zero in shc and Y
+    float acc = 0.0f;
+#pragma unroll
+    for (int k = 0; k < GS_SH_COEFFS; ++k) acc = fmaf(Y[k], shc[3 * k + ch], acc);
+    acc += 0.5f;
+    if (acc < 0.0f) { flags |= 1u << ch; acc = 0.0f; }
+    rgb[ch] = acc;
+  }
+  P.r1.z = rgb[0];
+  P.r1.w = rgb[1];
+  P.r2.x = rgb[2];
+}
+
+__device__ __forceinline__ Gauss3 load_gauss(const Views& V, int g, const float* means,
+                                             const float* log_scales, const float* quats,
+                                             const float* opacity_logits) {
+  Gauss3 G;
+  G.mx = means[3 * g + 0];
+  G.my = means[3 * g + 1];
+  G.mz = means[3 * g + 2];
   const float s0 = expf(log_scales[3 * g + 0]);
   const float s1 = expf(log_scales[3 * g + 1]);
   const float s2 = expf(log_scales[3 * g + 2]);
@@ -93,128 +202,102 @@ __global__ __launch_bounds__(kPreThreads) void k_preprocess(
   const float m22 = (1.0f - 2.0f * (qx * qx + qy * qy)) * s2;
   // Sigma = M M^T (symmetric), plus the 3D filter's variance on the diagonal
   const float f3 = V.filter3d ? V.filter3d[g] : 0.0f;
-  const float S00 = m00 * m00 + m01 * m01 + m02 * m02 + f3;
-  const float S01 = m00 * m10 + m01 * m11 + m02 * m12;
-  const float S02 = m00 * m20 + m01 * m21 + m02 * m22;
-  const float S11 = m10 * m10 + m11 * m11 + m12 * m12 + f3;
-  const float S12 = m10 * m20 + m11 * m21 + m12 * m22;
-  const float S22 = m20 * m20 + m21 * m21 + m22 * m22 + f3;
-
+  G.S00 = m00 * m00 + m01 * m01 + m02 * m02 + f3;
+  G.S01 = m00 * m10 + m01 * m11 + m02 * m12;
+  G.S02 = m00 * m20 + m01 * m21 + m02 * m22;
+  G.S11 = m10 * m10 + m11 * m11 + m12 * m12 + f3;
+  G.S12 = m10 * m20 + m11 * m21 + m12 * m22;
+  G.S22 = m20 * m20 + m21 * m21 + m22 * m22 + f3;
   const float o0 = 1.0f / (1.0f + expf(-opacity_logits[g]));
-  const float o = V.filter3d ? o0 * filter3d_coef(s0, s1, s2, f3) : o0;
-  const bool opaque = o >= kAlphaMin;
-  const float k2o = fmaxf(0.0f, 2.0f * logf(255.0f * o));
-  const float low = V.mip2d ? kMip2d : kDilation;  // screen-space low-pass
+  G.o = V.filter3d ? o0 * filter3d_coef(s0, s1, s2, f3) : o0;
+  G.opaque = G.o >= kAlphaMin;
+  G.k2o = fmaxf(0.0f, 2.0f * logf(255.0f * G.o));
+  return G;
+}
 
+// The block's SH coefficients (192 B per Gaussian) arrive through LDS with
+// coalesced 16-byte loads instead of 192-byte strided rows per thread; rows
+// whose s_need entry is zero are skipped (left unread).
+__device__ __forceinline__ void stage_sh(float* s_sh, const float* __restrict__ sh, int g0,
+                                         int rows, const int* s_need) {
+  constexpr int F = GS_SH_COEFFS * 3;
+  const float4* src = reinterpret_cast<const float4*>(sh + size_t(g0) * F);
+  for (int i = threadIdx.x; i < rows * (F / 4); i += kPreThreads) {
+    const int f = 4 * i, row = f / F, k = f - row * F;
+    if (s_need && !s_need[row]) continue;
+    const float4 q = src[i];
+    float* d = s_sh + row * kShStride + k;
+    d[0] = q.x;
+    d[1] = q.y;
+    d[2] = q.z;
+    d[3] = q.w;
+  }
+}
+
+__global__ __launch_bounds__(kPreThreads) void k_preprocess(
+    Views V, int n, int sh_degree, const float* __restrict__ means,
+    const float* __restrict__ log_scales, const float* __restrict__ quats,
+    const float* __restrict__ opacity_logits, const float* __restrict__ sh,
+    char* __restrict__ proj) {
+  __shared__ float s_sh[kPreThreads * kShStride];
+  __shared__ int s_need[kPreThreads];
+  const int g0 = blockIdx.x * kPreThreads;
+  const int g = g0 + threadIdx.x;
+  const int rows = min(kPreThreads, n - g0);
+  const ProjLayout L(n);
   const int K = (sh_degree + 1) * (sh_degree + 1);
   float shc[GS_SH_COEFFS * 3];
   const float* shg = s_sh + threadIdx.x * kShStride;
+
+  if (V.n_views == 1) {
+    // one view: the geometry first, then only the rows of Gaussians with a
+    // footprint tile come through LDS (with the Gaussians stored in spatial
+    // order, the ones outside the view form long runs of skipped rows)
+    Splat P{};
+    bool live = false;
+    if (g < n) {
+      const Gauss3 G = load_gauss(V, g, means, log_scales, quats, opacity_logits);
+      P = splat_geometry(V.v[0], G, V.tile, V.mip2d);
+      live = P.count > 0;
+    }
+    s_need[threadIdx.x] = live ? 1 : 0;
+    __syncthreads();
+    stage_sh(s_sh, sh, g0, rows, s_need);
+    __syncthreads();
+    if (g >= n) return;
+    uint32_t flags = 0;
+    if (live) {
+#pragma unroll
+      for (int k = 0; k < GS_SH_COEFFS * 3; ++k) shc[k] = (k < 3 * K) ? shg[k] : 0.0f;
+      splat_colour(P, shc, sh_degree, flags);
+    }
+    float4* rec = reinterpret_cast<float4*>(proj + L.rec) + 3 * size_t(g);
+    rec[0] = P.r0;
+    rec[1] = P.r1;
+    rec[2] = P.r2;
+    reinterpret_cast<uint32_t*>(proj + L.tt)[g] = P.count;
+    reinterpret_cast<uint32_t*>(proj + L.flags)[g] = flags;
+    return;
+  }
+
+  // several views: every row is staged once, the views looped in registers
+  stage_sh(s_sh, sh, g0, rows, nullptr);
+  __syncthreads();
+  if (g >= n) return;
+  const Gauss3 G = load_gauss(V, g, means, log_scales, quats, opacity_logits);
 #pragma unroll
   for (int k = 0; k < GS_SH_COEFFS * 3; ++k) shc[k] = (k < 3 * K) ? shg[k] : 0.0f;
-
   for (int v = 0; v < V.n_views; ++v) {
-    const DevView& cv = V.v[v];
     char* base = proj + size_t(v) * L.stride;
+    Splat P = splat_geometry(V.v[v], G, V.tile, V.mip2d);
+    uint32_t flags = 0;
+    if (P.has_colour) splat_colour(P, shc, sh_degree, flags);
     float4* rec = reinterpret_cast<float4*>(base + L.rec) + 3 * size_t(g);
-    uint32_t* tt = reinterpret_cast<uint32_t*>(base + L.tt);
-    uint32_t* fl = reinterpret_cast<uint32_t*>(base + L.flags);
-
-    // depth: the exact float32 sequence that defines the sort key
-    const float depth = __fadd_rn(
-        __fadd_rn(__fadd_rn(__fmul_rn(cv.R[6], mx), __fmul_rn(cv.R[7], my)),
-                  __fmul_rn(cv.R[8], mz)),
-        cv.t[2]);
-    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
-    uint32_t count = 0, flags = 0;
-    if (opaque && depth > cv.near_plane) {
-      const float xc = fmaf(cv.R[0], mx, fmaf(cv.R[1], my, fmaf(cv.R[2], mz, cv.t[0])));
-      const float yc = fmaf(cv.R[3], mx, fmaf(cv.R[4], my, fmaf(cv.R[5], mz, cv.t[1])));
-      const float iz = 1.0f / depth;
-      const float j00 = cv.fx * iz, j11 = cv.fy * iz;
-      const float j02 = -cv.fx * xc * iz * iz, j12 = -cv.fy * yc * iz * iz;
-      // T = J W (2x3)
-      const float t00 = j00 * cv.R[0] + j02 * cv.R[6];
-      const float t01 = j00 * cv.R[1] + j02 * cv.R[7];
-      const float t02 = j00 * cv.R[2] + j02 * cv.R[8];
-      const float t10 = j11 * cv.R[3] + j12 * cv.R[6];
-      const float t11 = j11 * cv.R[4] + j12 * cv.R[7];
-      const float t12 = j11 * cv.R[5] + j12 * cv.R[8];
-      // U = T Sigma, Sigma' = U T^T + low-pass
-      const float u00 = t00 * S00 + t01 * S01 + t02 * S02;
-      const float u01 = t00 * S01 + t01 * S11 + t02 * S12;
-      const float u02 = t00 * S02 + t01 * S12 + t02 * S22;
-      const float u10 = t10 * S00 + t11 * S01 + t12 * S02;
-      const float u11 = t10 * S01 + t11 * S11 + t12 * S12;
-      const float u12 = t10 * S02 + t11 * S12 + t12 * S22;
-      const float r00 = u00 * t00 + u01 * t01 + u02 * t02;
-      const float r01 = u00 * t10 + u01 * t11 + u02 * t12;
-      const float r11 = u10 * t10 + u11 * t11 + u12 * t12;
-      const float c00 = r00 + low, c01 = r01, c11 = r11 + low;
-      const float det = c00 * c11 - c01 * c01;
-      // the 2D mip filter keeps the splat's integral: opacity times sqrt(det ratio)
-      float ov = o, k2 = k2o;
-      if (V.mip2d && det > 0.0f) {
-        ov = o * sqrtf(fmaxf(r00 * r11 - r01 * r01, 0.0f) / det);
-        k2 = fmaxf(0.0f, 2.0f * logf(255.0f * ov));
-      }
-      if (det > 0.0f && ov >= kAlphaMin) {
-        const float idet = 1.0f / det;
-        const float ca = c11 * idet, cb = -c01 * idet, cc = c00 * idet;
-        // screen mean in double: float32 spacing at 1000+ px (6e-5 px) would otherwise
-        // dominate the error of every pixel offset near the Gaussian
-        const double xd = double(cv.R[0]) * mx + double(cv.R[1]) * my + double(cv.R[2]) * mz +
-                          double(cv.t[0]);
-        const double yd = double(cv.R[3]) * mx + double(cv.R[4]) * my + double(cv.R[5]) * mz +
-                          double(cv.t[1]);
-        const double zd = double(cv.R[6]) * mx + double(cv.R[7]) * my + double(cv.R[8]) * mz +
-                          double(cv.t[2]);
-        const double mux = double(cv.fx) * xd / zd + double(cv.cx);
-        const double muy = double(cv.fy) * yd / zd + double(cv.cy);
-        // colour along the viewing direction
-        float dx = mx - cv.campos[0], dy = my - cv.campos[1], dz = mz - cv.campos[2];
-        const float dn = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
-        dx *= dn; dy *= dn; dz *= dn;
-        float Y[GS_SH_COEFFS];
-#pragma unroll
-        for (int k = 0; k < GS_SH_COEFFS; ++k) Y[k] = 0.0f;
-        sh_basis(dx, dy, dz, sh_degree, Y);
-        float rgb[3];
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-          // coefficients above the degree are zero in shc and Y
-          float acc = 0.0f;
-#pragma unroll
-          for (int k = 0; k < GS_SH_COEFFS; ++k) acc = fmaf(Y[k], shc[3 * k + ch], acc);
-          acc += 0.5f;
-          if (acc < 0.0f) { flags |= 1u << ch; acc = 0.0f; }
-          rgb[ch] = acc;
-        }
-        // conservative footprint box of the alpha >= 1/255 ellipse
-        const double ex = double(sqrtf(k2 * c00) * (1.0f + kExtRel) + kExtAbs);
-        const double ey = double(sqrtf(k2 * c11) * (1.0f + kExtRel) + kExtAbs);
-        const double lox = (mux - ex) - 0.5, hix = (mux + ex) - 0.5;
-        const double loy = (muy - ey) - 0.5, hiy = (muy + ey) - 0.5;
-        const double Wd = double(cv.W), Hd = double(cv.H);
-        const int x0 = max(int(ceil(fmin(fmax(lox, -2.0), Wd + 2.0))), 0);
-        const int x1 = min(int(floor(fmin(fmax(hix, -2.0), Wd + 2.0))), cv.W - 1);
-        const int y0 = max(int(ceil(fmin(fmax(loy, -2.0), Hd + 2.0))), 0);
-        const int y1 = min(int(floor(fmin(fmax(hiy, -2.0), Hd + 2.0))), cv.H - 1);
-        const int T = V.tile;
-        if (x0 <= x1 && y0 <= y1) count = uint32_t((x1 / T - x0 / T + 1) * (y1 / T - y0 / T + 1));
-        // the mean is stored relative to the origin of the first tile of the footprint
-        const int ox = (x0 <= x1 ? x0 / T : 0) * T, oy = (y0 <= y1 ? y0 / T : 0) * T;
-        const float s = -0.5f * kLog2e;
-        r0 = make_float4(float(mux - double(ox)), float(muy - double(oy)), s * ca, -kLog2e * cb);
-        r1 = make_float4(s * cc, log2f(ov), rgb[0], rgb[1]);
-        r2 = make_float4(rgb[2], depth, __uint_as_float(box_pack(x0 < 0 ? 0 : x0, y0 < 0 ? 0 : y0)),
-                         __uint_as_float(box_pack(x1 < 0 ? 0 : x1, y1 < 0 ? 0 : y1)));
-      }
-    }
-    rec[0] = r0;
-    rec[1] = r1;
-    rec[2] = r2;
-    tt[g] = count;
-    fl[g] = flags;
+    rec[0] = P.r0;
+    rec[1] = P.r1;
+    rec[2] = P.r2;
+    reinterpret_cast<uint32_t*>(base + L.tt)[g] = P.count;
+    reinterpret_cast<uint32_t*>(base + L.flags)[g] = flags;
   }
 }
 

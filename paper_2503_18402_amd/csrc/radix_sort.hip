@@ -150,6 +150,8 @@ __global__ __launch_bounds__(kRT) void k_radix_scatter(
   }
 }
 
+}  // namespace
+
 // One LSD pass on (key, value) u32 pairs: bits [shift, shift+bits), bits <= 8.
 hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                       Count cnt, int64_t max_n, int shift, int bits, uint32_t* hist,
@@ -164,6 +166,10 @@ hipError_t radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, 
                      cnt, shift, bits, hist, digit_total);
   return hipGetLastError();
 }
+
+size_t radix_hist_words(int64_t max_n) { return 256 * size_t((max_n + kRTile - 1) / kRTile); }
+
+namespace {
 
 // ---------------------------------------------------------------- functors
 struct VisSrc {  // 1 for every (view, Gaussian) item with a non-empty footprint

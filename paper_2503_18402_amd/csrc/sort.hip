@@ -60,10 +60,10 @@ constexpr int kAggBins = 2048;  // most tiles a block aggregates in LDS
 constexpr int kAggRounds = 8;   // items per aggregating block: at most kXT * kAggRounds
 constexpr int kAggBlocks = 512; // but no fewer blocks than this while items allow
 
-// Calls f(global tile id, sort key, index-order position) once for every pair
-// of the items [first, first + kXT), whose first pair sits at index-order
-// position pbase.  Every thread of the block must call it.  Returns the
-// items' pair count.
+// Calls f(global tile id, sort key, index-order position, tile x | tile y << 16
+// in its view's grid) once for every pair of the items [first, first + kXT),
+// whose first pair sits at index-order position pbase.  Every thread of the
+// block must call it.  Returns the items' pair count.
 template <class F>
 __device__ inline uint32_t for_each_pair(const Items& S, int64_t first, uint32_t pbase, F&& f) {
   __shared__ uint32_t s_end[kXT];   // inclusive prefix of pair counts within the wave
@@ -72,9 +72,10 @@ __device__ inline uint32_t for_each_pair(const Items& S, int64_t first, uint32_t
   __shared__ uint32_t s_w[kXT];     // footprint width in tiles
   __shared__ uint32_t s_gw[kXT];    // tile-grid width of the item's view
   __shared__ uint64_t s_key[kXT];   // bits(depth) << 32 | Gaussian index
+  __shared__ uint32_t s_xy[kXT];    // footprint's first tile: x | y << 16
   const int lane = threadIdx.x & 63, w0 = threadIdx.x & ~63;
   const int64_t i = first + threadIdx.x;
-  uint32_t cnt = 0, base = 0, w = 1, gw = 1;
+  uint32_t cnt = 0, base = 0, w = 1, gw = 1, xy = 0;
   uint64_t key = 0;
   if (i < S.m) {
     const int64_t v = i / S.n, g = i - v * S.n;
@@ -88,6 +89,7 @@ __device__ inline uint32_t for_each_pair(const Items& S, int64_t first, uint32_t
       cnt = w * uint32_t(ty1 - ty0 + 1);
       gw = uint32_t(S.TI.gw[v]);
       base = uint32_t(S.TI.tile_base[v]) + uint32_t(ty0) * gw + uint32_t(tx0);
+      xy = uint32_t(tx0) | (uint32_t(ty0) << 16);
       key = (uint64_t(__float_as_uint(r2.y)) << 32) | uint64_t(g);
     }
   }
@@ -98,6 +100,7 @@ __device__ inline uint32_t for_each_pair(const Items& S, int64_t first, uint32_t
   s_w[threadIdx.x] = w;
   s_gw[threadIdx.x] = gw;
   s_key[threadIdx.x] = key;
+  s_xy[threadIdx.x] = xy;
   __syncthreads();
   const uint32_t total = __shfl(inc, 63, 64);
   uint32_t wbase = pbase, all = 0;
@@ -116,7 +119,8 @@ __device__ inline uint32_t for_each_pair(const Items& S, int64_t first, uint32_t
     const uint32_t local = j - (k > 0 ? s_end[w0 + k - 1] : 0u);
     const uint32_t wk = s_w[w0 + k];
     const uint32_t ty = local / wk, tx = local - ty * wk;
-    f(s_base[w0 + k] + ty * s_gw[w0 + k] + tx, s_key[w0 + k], wbase + j);
+    f(s_base[w0 + k] + ty * s_gw[w0 + k] + tx, s_key[w0 + k], wbase + j,
+      s_xy[w0 + k] + tx + (ty << 16));
   }
   __syncthreads();  // the arrays are rewritten by the next call
   return all;
@@ -149,26 +153,89 @@ __global__ __launch_bounds__(kXT) void k_tile_reduce(Items S, int rounds,
   }
 }
 
-// A block takes kXT * rounds consecutive items.  When the tiles of the views
-// its items belong to number at most agg_bins (low resolutions, where every
-// tile collects thousands of pairs and same-counter atomics serialise), the
-// block counts its pairs per tile in LDS first and issues one global atomic
-// per touched tile; otherwise every pair goes to the global counters.
+// A block takes kXT * rounds consecutive items.  It counts its pairs per tile
+// in LDS first and issues one global atomic per touched tile when its pairs
+// fall on at most agg_bins tiles that it can index:
+//   - all tiles of the views its items belong to (low resolutions, where
+//     every tile collects thousands of pairs and same-counter atomics
+//     serialise), bin = tile - first tile of those views; or
+//   - for items of one view, the bounding rectangle of their footprints'
+//     tiles (Gaussians stored close together in space, as the spatial order
+//     stores them, cover few tiles), bin = row-major cell of that rectangle.
+// Otherwise every pair goes to the global counters and ranks itself there.
 struct BlockSpan {
-  int64_t i0, i1;  // items
-  int32_t t_lo;    // first tile of the block's views
-  bool agg;        // LDS bins in use (block-uniform)
-  int32_t span;
+  int64_t i0, i1;    // items
+  int32_t mode;      // 0: global counters, 1: the views' tiles, 2: the rectangle
+  int32_t t_lo;      // mode 1: first tile of the block's views
+  int32_t bx0, by0, bw, gw, base;  // mode 2: rectangle origin and width; view grid
+  int32_t span;      // bins in use
+  __device__ int bin(uint32_t t, uint32_t xy) const {
+    return mode == 1 ? int(t) - t_lo
+                     : (int(xy >> 16) - by0) * bw + (int(xy & 0xffffu) - bx0);
+  }
+  __device__ uint32_t tile_of(int b) const {
+    if (mode == 1) return uint32_t(t_lo + b);
+    const int y = b / bw, x = b - y * bw;
+    return uint32_t(base + (by0 + y) * gw + bx0 + x);
+  }
 };
 
+// every thread of the block must call it
 __device__ inline BlockSpan block_span(const Items& S, int rounds, int agg_bins) {
-  BlockSpan b;
+  BlockSpan b{};
   b.i0 = int64_t(blockIdx.x) * kXT * rounds;
   b.i1 = (b.i0 + int64_t(kXT) * rounds < S.m) ? b.i0 + int64_t(kXT) * rounds : S.m;
   const int v0 = int(b.i0 / S.n), v1 = int((b.i1 - 1) / S.n);
   b.t_lo = S.TI.tile_base[v0];
   b.span = S.TI.tile_end[v1] - b.t_lo;
-  b.agg = b.span <= agg_bins;
+  b.mode = b.span <= agg_bins ? 1 : 0;
+  if (b.mode == 1 || v0 != v1 || agg_bins == 0) return b;  // block-uniform
+  // the tile rectangle of the block's footprints
+  int x0 = 1 << 30, y0 = 1 << 30, x1 = -1, y1 = -1;
+  const char* pv = S.proj + size_t(v0) * S.stride;
+  for (int64_t i = b.i0 + threadIdx.x; i < b.i1; i += kXT) {
+    const int64_t g = i - int64_t(v0) * S.n;
+    if (reinterpret_cast<const uint32_t*>(pv + S.tt_off)[g] > 0u) {
+      const float4 r2 = reinterpret_cast<const float4*>(pv)[3 * g + 2];
+      const uint32_t lo = __float_as_uint(r2.z), hi = __float_as_uint(r2.w);
+      x0 = min(x0, box_x(lo) / S.tile);
+      y0 = min(y0, box_y(lo) / S.tile);
+      x1 = max(x1, box_x(hi) / S.tile);
+      y1 = max(y1, box_y(hi) / S.tile);
+    }
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    x0 = min(x0, __shfl_xor(x0, d, 64));
+    y0 = min(y0, __shfl_xor(y0, d, 64));
+    x1 = max(x1, __shfl_xor(x1, d, 64));
+    y1 = max(y1, __shfl_xor(y1, d, 64));
+  }
+  __shared__ int s_r[4][kXT / 64];
+  if ((threadIdx.x & 63) == 0) {
+    s_r[0][threadIdx.x >> 6] = x0;
+    s_r[1][threadIdx.x >> 6] = y0;
+    s_r[2][threadIdx.x >> 6] = x1;
+    s_r[3][threadIdx.x >> 6] = y1;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < kXT / 64; ++w) {
+    x0 = min(x0, s_r[0][w]);
+    y0 = min(y0, s_r[1][w]);
+    x1 = max(x1, s_r[2][w]);
+    y1 = max(y1, s_r[3][w]);
+  }
+  __syncthreads();  // s_r is rewritten by the next call
+  if (x1 >= x0 && int64_t(x1 - x0 + 1) * (y1 - y0 + 1) <= agg_bins) {
+    b.mode = 2;
+    b.bx0 = x0;
+    b.by0 = y0;
+    b.bw = x1 - x0 + 1;
+    b.gw = S.TI.gw[v0];
+    b.base = S.TI.tile_base[v0];
+    b.span = b.bw * (y1 - y0 + 1);
+  }
   return b;
 }
 
@@ -178,19 +245,20 @@ __global__ __launch_bounds__(kXT) void k_tile_count(Items S, int rounds, int agg
                                                     uint32_t* __restrict__ rank) {
   extern __shared__ uint32_t s_bins[];
   const BlockSpan B = block_span(S, rounds, agg_bins);
-  if (B.agg) {
+  if (B.mode) {
     for (int b = threadIdx.x; b < B.span; b += kXT) s_bins[b] = 0u;
     __syncthreads();
     for (int64_t c = B.i0; c < B.i1; c += kXT)
-      for_each_pair(S, c, 0u,
-                    [&](uint32_t t, uint64_t, uint32_t) { atomicAdd(&s_bins[t - B.t_lo], 1u); });
+      for_each_pair(S, c, 0u, [&](uint32_t t, uint64_t, uint32_t, uint32_t xy) {
+        atomicAdd(&s_bins[B.bin(t, xy)], 1u);
+      });
     for (int b = threadIdx.x; b < B.span; b += kXT)
-      if (s_bins[b]) atomicAdd(&ranges[2 * size_t(B.t_lo + b) + 1], s_bins[b]);
+      if (s_bins[b]) atomicAdd(&ranges[2 * size_t(B.tile_of(b)) + 1], s_bins[b]);
   } else {
     // the returned count is the pair's rank among its tile's ranked pairs
     uint32_t pos = block_pos[blockIdx.x];
     for (int64_t c = B.i0; c < B.i1; c += kXT)
-      pos += for_each_pair(S, c, pos, [&](uint32_t t, uint64_t, uint32_t p) {
+      pos += for_each_pair(S, c, pos, [&](uint32_t t, uint64_t, uint32_t p, uint32_t) {
         const uint32_t r = atomicAdd(&ranges[2 * size_t(t)], 1u);
         if (int64_t(p) < cap) rank[p] = r;
       });
@@ -210,25 +278,26 @@ __global__ __launch_bounds__(kXT) void k_bucket(Items S, int rounds, int agg_bin
   extern __shared__ uint32_t s_bins[];
   if (*n_eff == 0) return;  // capacity overflow (or no pairs): nothing to place
   const BlockSpan B = block_span(S, rounds, agg_bins);
-  if (B.agg) {
+  if (B.mode) {
     for (int b = threadIdx.x; b < B.span; b += kXT) s_bins[b] = 0u;
     __syncthreads();
     for (int64_t c = B.i0; c < B.i1; c += kXT)
-      for_each_pair(S, c, 0u,
-                    [&](uint32_t t, uint64_t, uint32_t) { atomicAdd(&s_bins[t - B.t_lo], 1u); });
+      for_each_pair(S, c, 0u, [&](uint32_t t, uint64_t, uint32_t, uint32_t xy) {
+        atomicAdd(&s_bins[B.bin(t, xy)], 1u);
+      });
     for (int b = threadIdx.x; b < B.span; b += kXT) {
       const uint32_t k = s_bins[b];
-      if (k) s_bins[b] = atomicAdd(&ranges[2 * size_t(B.t_lo + b) + 1], k);
+      if (k) s_bins[b] = atomicAdd(&ranges[2 * size_t(B.tile_of(b)) + 1], k);
     }
     __syncthreads();
     for (int64_t c = B.i0; c < B.i1; c += kXT)
-      for_each_pair(S, c, 0u, [&](uint32_t t, uint64_t key, uint32_t) {
-        bucket[atomicAdd(&s_bins[t - B.t_lo], 1u)] = key;
+      for_each_pair(S, c, 0u, [&](uint32_t t, uint64_t key, uint32_t, uint32_t xy) {
+        bucket[atomicAdd(&s_bins[B.bin(t, xy)], 1u)] = key;
       });
   } else {
     uint32_t pos = block_pos[blockIdx.x];
     for (int64_t c = B.i0; c < B.i1; c += kXT)
-      pos += for_each_pair(S, c, pos, [&](uint32_t t, uint64_t key, uint32_t p) {
+      pos += for_each_pair(S, c, pos, [&](uint32_t t, uint64_t key, uint32_t p, uint32_t) {
         bucket[ranges[2 * size_t(t)] + rank[p]] = key;
       });
   }
@@ -672,8 +741,10 @@ hipError_t launch_bin_sort(const Views& V, int n, const char* proj, int64_t cap,
     const int64_t want = (S.m + int64_t(kXT) * kAggBlocks - 1) / (int64_t(kXT) * kAggBlocks);
     rounds = int(std::min<int64_t>(std::max<int64_t>(want, 1), kAggRounds));
   }
-  const size_t agg_lds = any_agg ? sizeof(uint32_t) * kAggBins : 0;
-  const int agg_bins = any_agg ? kAggBins : 0;
+  // every launch may aggregate: whole views of few tiles, or the tile rectangle
+  // of a block of Gaussians that sit close together
+  const size_t agg_lds = sizeof(uint32_t) * kAggBins;
+  const int agg_bins = kAggBins;
   const unsigned xb = unsigned((S.m + int64_t(kXT) * rounds - 1) / (int64_t(kXT) * rounds));
 
   GS_LAUNCH("k_fill_u32", k_fill_u32, dim3(unsigned(nr / 256 + 1 < 4096 ? nr / 256 + 1 : 4096)),

@@ -70,6 +70,9 @@ def lib() -> ctypes.CDLL:
             "gs_bin_sort_workspace_bytes": (sz, [i32, i32, i64]),
             "gs_bin_sort": (i32, [i32, cam_p, cfg_p, i32, vp, i64, vp, sz, vp, vp, vp, vp, vp]),
             "gs_bin_sort_noalloc": (i32, [i32, cam_p, cfg_p, i32, vp, i64, vp, vp, vp, vp, vp]),
+            "gs_spatial_order_workspace_bytes": (sz, [i32]),
+            "gs_spatial_order": (i32, [i32, vp, vp, sz, vp, vp]),
+            "gs_gather_rows": (i32, [i32, vp, i32, vp, vp, vp, vp]),
             "gs_bin_sort_radix_workspace_bytes": (sz, [i32, i32, i64]),
             "gs_bin_sort_radix": (i32, [i32, cam_p, cfg_p, i32, vp, i64, vp, sz, vp, vp, vp, vp,
                                         vp]),
@@ -217,6 +220,25 @@ def gs_bin_sort_noalloc(cams_c, cfg, n, proj, capacity, keys, vals, ranges, n_pa
     _check("gs_bin_sort_noalloc", lib().gs_bin_sort_noalloc(
         len(cams_c), cams_c, ctypes.byref(cfg), int(n), _ptr(proj), int(capacity), _ptr(keys),
         _ptr(vals), _ptr(ranges), _ptr(n_pairs_dev), _stream(stream)))
+
+
+def gs_spatial_order_workspace_bytes(n: int) -> int:
+    return int(lib().gs_spatial_order_workspace_bytes(int(n)))
+
+
+def gs_spatial_order(n, means, ws, perm, stream=None):
+    _check("gs_spatial_order", lib().gs_spatial_order(
+        int(n), _ptr(means), _ptr(ws), ws.numel() * ws.element_size(), _ptr(perm),
+        _stream(stream)))
+
+
+def gs_gather_rows(n, perm, src, dst, stream=None):
+    """src, dst: lists of device float tensors of n rows each (row = numel / n)."""
+    k = len(src)
+    rows = [(t.numel() // n) if n else 1 for t in src]
+    _check("gs_gather_rows", lib().gs_gather_rows(
+        int(n), _ptr(perm), k, (c_void_p * k)(*[_ptr(t) for t in src]),
+        (c_void_p * k)(*[_ptr(t) for t in dst]), (c_int32 * k)(*rows), _stream(stream)))
 
 
 def gs_bin_sort_radix_workspace_bytes(n_views: int, n: int, capacity: int) -> int:

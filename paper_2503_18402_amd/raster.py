@@ -177,6 +177,30 @@ class RasterizeFn(torch.autograd.Function):
         return g["means"], g["log_scales"], g["quats"], g["opacity_logits"], g["sh"], None
 
 
+def spatial_order(params: dict, *moments: dict, stream=None):
+    """The Gaussians re-stored in the Morton order of their means
+    (gs_spatial_order, then gs_gather_rows over the parameters and any Adam
+    moment dicts given).  Returns (perm, params, *moments) as new tensors;
+    perm[k] is the old index of the k-th Gaussian.  Rendering results do not
+    depend on the order (ties of exactly equal depth follow the index)."""
+    n = params["means"].shape[0]
+    dev = params["means"].device
+    perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    ws = torch.empty(max(gsmi.gs_spatial_order_workspace_bytes(n), 16), dtype=torch.uint8,
+                     device=dev)
+    gsmi.gs_spatial_order(n, params["means"], ws, perm, stream)
+    groups = [params] + list(moments)
+    src = [g[k].contiguous() for g in groups for k in PARAM_NAMES]
+    dst = [torch.empty_like(t) for t in src]
+    if n > 0:
+        gsmi.gs_gather_rows(n, perm, src, dst, stream)
+    out, i = [], 0
+    for _ in groups:
+        out.append({k: dst[i + j] for j, k in enumerate(PARAM_NAMES)})
+        i += len(PARAM_NAMES)
+    return (perm[:n], *out)
+
+
 def to_device(scene: dict, device="cuda") -> dict:
     """numpy scene -> contiguous float32 device tensors."""
     return {k: torch.from_numpy(scene[k]).to(device=device, dtype=torch.float32).contiguous()

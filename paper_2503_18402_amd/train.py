@@ -149,8 +149,14 @@ class Trainer:
                  capacity_margin: float = 2.0, norm: str = "mean",
                  densify: DensifyConfig | None = None, r_max: float = 0.0,
                  sparse_adam: bool = False, mip: bool = False, filter3d_scale: float = 0.2,
-                 autograd: bool = False):
+                 autograd: bool = False, spatial: bool = True):
         self.params, self.cams, self.gt, self.iters = params, list(cams), gt, iters
+        # Gaussians stored in the spatial (Morton) order of their means, restored
+        # after every densification step (the caller's dict is updated in place)
+        self.spatial = spatial
+        if spatial:
+            _, ordered = raster.spatial_order(params)
+            params.update(ordered)
         self.sh_degree = sh_degree
         self.lrs = dict(DEFAULT_LRS if lrs is None else lrs)
         self.means_lr = means_lr
@@ -342,6 +348,8 @@ class Trainer:
         newp, newm, newv, info = densify_step(self.params, self.m, self.v, self.accum, self.count,
                                               z, c.grad_thr, c.min_opacity,
                                               c.percent_dense * c.extent, k_of)
+        if self.spatial:
+            _, newp, newm, newv = raster.spatial_order(newp, newm, newv)
         for name in raster.PARAM_NAMES:
             self.params[name] = newp[name]
             self.m[name] = newm[name]

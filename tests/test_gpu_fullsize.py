@@ -21,7 +21,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import binning, project, render
+from oracle import binning, project, render, spatial
 from paper_2503_18402_amd import gsmi, raster, scenes
 from tests import gpu_util as U
 
@@ -95,8 +95,10 @@ def test_backward_sparse_upstream(scene1m):
         assert not g[name][~touched & ~skip].any()
 
 
-@pytest.mark.parametrize("level,tile", [(1, 16), (1, 8), (8, 16), (8, 8)])
-def test_keys_and_ranges_match_oracle(scene1m, level, tile):
+@pytest.mark.parametrize("level,tile,order", [(1, 16, "index"), (1, 8, "index"),
+                                              (8, 16, "index"), (8, 8, "index"),
+                                              (1, 16, "spatial"), (1, 8, "spatial")])
+def test_keys_and_ranges_match_oracle(scene1m, level, tile, order):
     """The sorted (tile | depth) keys, their Gaussian ids and the tile ranges of
     the 1M-Gaussian view against the oracle's binning over its own FP64
     footprint boxes (stable sort of the keys emitted in index order).  A
@@ -104,8 +106,13 @@ def test_keys_and_ranges_match_oracle(scene1m, level, tile):
     boundary (about 1 in 1000) may cover one tile more or less on the device:
     its pairs are removed on both sides, and tiles holding such a pair are left
     out of the range-length comparison.  Device ranges must delimit exactly
-    the runs of their tile in the device's keys, [0, 0) when empty."""
+    the runs of their tile in the device's keys, [0, 0) when empty.  The
+    "spatial" cases store the scene in the oracle's Morton order first: the
+    binning's blocks then count most of their pairs in LDS over the tile
+    rectangle of their footprints."""
     _, cam = scenes.paper_scale_scene(level=level, n=1)
+    if order == "spatial":
+        scene1m = scenes.subset(scene1m, spatial.morton_order(scene1m["means"]))
     P = project.project(scene1m, cam, tile=tile)
     gw, gh = -(-cam.width // tile), -(-cam.height // tile)
     k, v, r = binning.bin_sort(P["rect"], P["tiles_touched"], P["depth_f32"], gw, gh)
