@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 4M-Gaussian, 16-view workload")
     ap.add_argument("--no-extras", action="store_true", help="skip levels and batched form")
+    ap.add_argument("--graphs", action="store_true",
+                    help="training loops replay one HIP graph per level instead of stepping eagerly")
     ap.add_argument("--no-spatial", action="store_true",
                     help="keep the scenes in generation order instead of the spatial order")
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -108,7 +110,8 @@ def main():
     torch.cuda.set_device(dev)
     if args.training_only:
         print(json.dumps(scheduled_training(torch, raster, scenes, dev, args.train_iters,
-                                            args.train_ablations)))
+                                            args.train_ablations, not args.no_spatial,
+                                            args.graphs)))
         return
 
     # ---------------------------------------------------------------- inputs
@@ -254,7 +257,8 @@ def main():
             extras["large"] = large_scene(torch, raster, scenes, dev, not args.no_spatial)
         if args.train_iters > 0:
             extras["training"] = scheduled_training(torch, raster, scenes, dev, args.train_iters,
-                                                    args.train_ablations, not args.no_spatial)
+                                                    args.train_ablations, not args.no_spatial,
+                                                    args.graphs)
 
     out = {
         "metric": "fwd+bwd Mpix/s at 1M Gaussians 1600x1064; batched vs plain it/s at oracle tol",
@@ -477,7 +481,8 @@ def compare_forms(torch, raster, params, cams, tgts, label):
                      "16 per-view gradients and then runs the separate Adam step")
 
 
-def scheduled_training(torch, raster, scenes, dev, iters, ablations=False, spatial=True):
+def scheduled_training(torch, raster, scenes, dev, iters, ablations=False, spatial=True,
+                       graphs=False):
     """The optimisation loop of the hidden-scene workload: learnable Gaussians
     fitted to 64 views at 1200x800 of a 500k-Gaussian hidden scene (ground
     truth rendered once), ``iters`` iterations, one view per iteration.  From
@@ -523,7 +528,7 @@ def scheduled_training(torch, raster, scenes, dev, iters, ablations=False, spati
                                    p_fin=budget)
         tr = train.Trainer(params, cams, gt, iters, schedule=sched, densify=dcfg, r_max=r_max,
                            means_lr=(1.6e-4 * extent, 1.6e-6 * extent), mip=mip,
-                           autograd=autograd, spatial=spatial)
+                           autograd=autograd, spatial=spatial, graphs=graphs)
         psnr0 = train.psnr(tr.params, cams, gt, mip2d=mip, filter3d=tr.filter3d)
         res = tr.run()
         psnr1 = train.psnr(tr.params, cams, gt, mip2d=mip, filter3d=tr.filter3d)
@@ -534,7 +539,9 @@ def scheduled_training(torch, raster, scenes, dev, iters, ablations=False, spati
                          iters_per_factor=res["iters_per_factor"], psnr_init=round(psnr0, 3),
                          psnr=round(psnr1, 3),
                          form="RasterizeFn (torch.autograd.Function)" if autograd else
-                              "fused pipeline step")
+                              ("fused pipeline step, one HIP graph replay per iteration"
+                               if graphs else "fused pipeline step"),
+                         storage_order="spatial" if spatial else "index")
         if sched:
             out[name]["r_knots"] = [round(float(x), 4) for x in tr.sched.r_knots]
             out[name]["s_knots"] = [round(float(x), 2) for x in tr.sched.s_knots]

@@ -90,6 +90,20 @@ typedef struct {
   float bg[3];
   int32_t mip2d;
   const float* filter3d;
+  /* Device-side step parameters, so that one captured HIP graph of a training
+   * step replays for any view and learning rate (all NULL: not used):
+   *   cam_table, cam_index: device gs_camera [k] and device int32 [1]; with
+   *     both set (n_views must be 1, else GS_ERR_ARG), every call takes view
+   *     0's pose and intrinsics (R, t, fx, fy, cx, cy, near_plane) from
+   *     cam_table[*cam_index] when it runs, and cams[0] gives only width and
+   *     height (every table entry must have that size).  gs_render_fwd_l1
+   *     then reads its target at target + (*cam_index) * 3 * width * height:
+   *     a stack of the table's views' targets.
+   *   adam_lr: device float [6]: the fused backward + Adam calls take their
+   *     learning rates from it instead of their host lr array. */
+  const gs_camera* cam_table;
+  const int32_t* cam_index;
+  const float* adam_lr;
 } gs_raster_cfg;
 
 /* ---------------------------------------------------------------------------
@@ -317,7 +331,8 @@ gs_status gs_adam_step_device(const gs_adam_group* groups, int32_t n_groups, int
  *   lr: host array of 6 learning rates: the five groups, except that lr[4]
  *     applies to the SH degree-0 coefficients (values 0..2 of a Gaussian's
  *     48) and lr[5] to the higher degrees.  lr[5] = lr[4] gives the update of
- *     gs_adam_step_device with one SH group.
+ *     gs_adam_step_device with one SH group.  May be NULL when cfg->adam_lr
+ *     gives them on the device.
  *   step_dev: device int32 step counter (0 before the first step).  The call
  *     advances it by one on the stream, in the first kernel it launches,
  *     before any update, and takes step t = its new value; afterwards it

@@ -56,6 +56,11 @@ bool build_views(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cf
   out->tile = cfg->tile;
   out->mip2d = cfg->mip2d;
   out->filter3d = cfg->filter3d;
+  // a device camera table drives view 0 of a one-view call
+  if ((cfg->cam_table == nullptr) != (cfg->cam_index == nullptr)) return false;
+  if (cfg->cam_table && n_views != 1) return false;
+  out->cam_table = cfg->cam_table;
+  out->cam_index = cfg->cam_index;
   int64_t tiles = 0, pix = 0;
   for (int v = 0; v < n_views; ++v) {
     const gs_camera& c = cams[v];
@@ -301,7 +306,9 @@ gs_status gs_render_fwd_l1(int32_t n_views, const gs_camera* cams, const gs_rast
   if (!ranges || !image || !final_T || !last_contrib || (n > 0 && !proj)) return GS_ERR_ARG;
   if (!target || !dL_dimage) return GS_ERR_ARG;
   if (n > 0 && !aligned16(proj)) return GS_ERR_ARG;
-  const L1Fuse l1{target, dL_dimage, loss_sum, scale};
+  // with a camera table the target is the table's view's entry of a stack
+  const L1Fuse l1{target, dL_dimage, loss_sum, scale, cfg->cam_index,
+                  3 * int64_t(cams[0].width) * cams[0].height};
   return from_hip(launch_render_fwd(V, n, *cfg, static_cast<const char*>(proj), ranges, vals,
                                     image, final_T, last_contrib, l1, as_stream(stream)));
 }
@@ -379,8 +386,9 @@ gs_status render_bwd_adam(int32_t n_views, const gs_camera* cams, const gs_raste
   if (!n_ok(n_views, n) || !build_views(n_views, cams, cfg, &V)) return GS_ERR_ARG;
   if (sh_degree < 0 || sh_degree > 3) return GS_ERR_ARG;
   if (capacity_pairs < 0 || capacity_pairs >= (int64_t(1) << 32)) return GS_ERR_ARG;
-  if (!ranges || !final_T || !last_contrib || !dL_dimage || !ws || !m || !v || !lr || !step_dev)
+  if (!ranges || !final_T || !last_contrib || !dL_dimage || !ws || !m || !v || !step_dev)
     return GS_ERR_ARG;
+  if (!lr && !cfg->adam_lr) return GS_ERR_ARG;
   if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps >= 0.0f))
     return GS_ERR_ARG;
   FusedAdam A{};
@@ -389,7 +397,8 @@ gs_status render_bwd_adam(int32_t n_views, const gs_camera* cams, const gs_raste
     A.m[k] = m[k];
     A.v[k] = v[k];
   }
-  for (int k = 0; k < 6; ++k) A.lr[k] = lr[k];
+  for (int k = 0; k < 6; ++k) A.lr[k] = lr ? lr[k] : 0.0f;
+  A.lr_dev = cfg->adam_lr;
   if (n > 0 && (!means || !log_scales || !quats || !opacity_logits || !sh || !proj))
     return GS_ERR_ARG;
   if (n > 0 && (!aligned16(quats) || !aligned16(sh) || !aligned16(proj) || !aligned16(ws) ||

@@ -642,7 +642,7 @@ __device__ __forceinline__ bool chain_grad(const Views& V, const ChainIn& I, int
 #pragma unroll
     for (int c = 0; c < kG; ++c) gr[c] = I.g2d[c * M + int64_t(v) * I.n + g];
     const uint32_t flags = reinterpret_cast<const uint32_t*>(base + L.flags)[g];
-    const DevView& cv = V.v[v];
+    const DevView cv = view_at(V, v);
 
     // ---- recompute the projection of this view
     const float xc = fmaf(cv.R[0], mx, fmaf(cv.R[1], my, fmaf(cv.R[2], mz, cv.t[0])));
@@ -890,6 +890,7 @@ struct AdamGroups {
   float* m[5];
   float* v[5];
   float lr[6];  // the five groups; lr[4] for the SH degree-0 terms, lr[5] for the rest
+  const float* lr_dev;  // device copy of lr, read instead when set
   float b1, b2, eps;
   const int32_t* step_dev;
   int sparse;  // 1: Gaussians with no pair in any view keep p, m and v unchanged
@@ -905,8 +906,11 @@ __global__ __launch_bounds__(kCA) void k_chain_adam(Views V, ChainIn I, AdamGrou
   float4* s_g = reinterpret_cast<float4*>(s_buf);
   __shared__ float s_c[2];
   __shared__ int s_upd[kCA];
-  // the count was advanced for this step by k_zero_pairs, earlier in the same call
+  // the count was advanced for this step by k_zero_pairs, earlier in the same call;
+  // the learning rates come from the device when lr_dev is set
+  __shared__ float lr[6];
   if (threadIdx.x == 0) adam_bias(A.step_dev, A.b1, A.b2, s_c[0], s_c[1], 0);
+  if (threadIdx.x < 6) lr[threadIdx.x] = A.lr_dev ? A.lr_dev[threadIdx.x] : A.lr[threadIdx.x];
   const int g = blockIdx.x * kCA + threadIdx.x;
   {
     const int g0 = blockIdx.x * kCA;
@@ -948,20 +952,20 @@ __global__ __launch_bounds__(kCA) void k_chain_adam(Views V, ChainIn I, AdamGrou
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const int j = 3 * g + k;
-      adam_one(A.p[0][j], O.dm[k], A.m[0][j], A.v[0][j], A.lr[0], C);
-      adam_one(A.p[1][j], O.dls[k], A.m[1][j], A.v[1][j], A.lr[1], C);
+      adam_one(A.p[0][j], O.dm[k], A.m[0][j], A.v[0][j], lr[0], C);
+      adam_one(A.p[1][j], O.dls[k], A.m[1][j], A.v[1][j], lr[1], C);
     }
     float4 p4 = reinterpret_cast<float4*>(A.p[2])[g];
     float4 m4 = reinterpret_cast<float4*>(A.m[2])[g];
     float4 v4 = reinterpret_cast<float4*>(A.v[2])[g];
-    adam_one(p4.x, O.dq.x, m4.x, v4.x, A.lr[2], C);
-    adam_one(p4.y, O.dq.y, m4.y, v4.y, A.lr[2], C);
-    adam_one(p4.z, O.dq.z, m4.z, v4.z, A.lr[2], C);
-    adam_one(p4.w, O.dq.w, m4.w, v4.w, A.lr[2], C);
+    adam_one(p4.x, O.dq.x, m4.x, v4.x, lr[2], C);
+    adam_one(p4.y, O.dq.y, m4.y, v4.y, lr[2], C);
+    adam_one(p4.z, O.dq.z, m4.z, v4.z, lr[2], C);
+    adam_one(p4.w, O.dq.w, m4.w, v4.w, lr[2], C);
     reinterpret_cast<float4*>(A.p[2])[g] = p4;
     reinterpret_cast<float4*>(A.m[2])[g] = m4;
     reinterpret_cast<float4*>(A.v[2])[g] = v4;
-    adam_one(A.p[3][g], O.dlogit, A.m[3][g], A.v[3][g], A.lr[3], C);
+    adam_one(A.p[3][g], O.dlogit, A.m[3][g], A.v[3][g], lr[3], C);
   }
   // SH: the block's contiguous slab of 48 values per Gaussian, float4 per lane
   const int g0 = blockIdx.x * kCA;
@@ -976,10 +980,10 @@ __global__ __launch_bounds__(kCA) void k_chain_adam(Views V, ChainIn I, AdamGrou
     const float4 gg = s_g[j];
     // values 0..2 of a Gaussian's 48 are its degree-0 coefficients
     const int e = (4 * j) % (GS_SH_COEFFS * 3);
-    adam_one(p.x, gg.x, m.x, v.x, e + 0 < 3 ? A.lr[4] : A.lr[5], C);
-    adam_one(p.y, gg.y, m.y, v.y, e + 1 < 3 ? A.lr[4] : A.lr[5], C);
-    adam_one(p.z, gg.z, m.z, v.z, e + 2 < 3 ? A.lr[4] : A.lr[5], C);
-    adam_one(p.w, gg.w, m.w, v.w, A.lr[5], C);
+    adam_one(p.x, gg.x, m.x, v.x, e + 0 < 3 ? lr[4] : lr[5], C);
+    adam_one(p.y, gg.y, m.y, v.y, e + 1 < 3 ? lr[4] : lr[5], C);
+    adam_one(p.z, gg.z, m.z, v.z, e + 2 < 3 ? lr[4] : lr[5], C);
+    adam_one(p.w, gg.w, m.w, v.w, lr[5], C);
     P[j] = p;
     Mm[j] = m;
     Vv[j] = v;
@@ -1229,6 +1233,7 @@ hipError_t launch_render_bwd_adam(const Views& V, int n, const gs_raster_cfg& cf
       G.v[k] = A.v[k];
     }
     for (int k = 0; k < 6; ++k) G.lr[k] = A.lr[k];
+    G.lr_dev = A.lr_dev;
     G.b1 = A.b1;
     G.b2 = A.b2;
     G.eps = A.eps;

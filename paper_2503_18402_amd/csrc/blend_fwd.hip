@@ -16,8 +16,8 @@ namespace {
 // e + 2 plane), from the values just stored in the image; returns sum |d|.
 __device__ __forceinline__ float l1_pixel(const L1Fuse& l1, int64_t e, int64_t plane, float c0,
                                           float c1, float c2) {
-  const float d0 = c0 - l1.target[e], d1 = c1 - l1.target[e + plane],
-              d2 = c2 - l1.target[e + 2 * plane];
+  const float* tgt = l1.index ? l1.target + int64_t(*l1.index) * l1.stride : l1.target;
+  const float d0 = c0 - tgt[e], d1 = c1 - tgt[e + plane], d2 = c2 - tgt[e + 2 * plane];
   l1.dL[e] = l1_sign(d0, l1.scale);
   l1.dL[e + plane] = l1_sign(d1, l1.scale);
   l1.dL[e + 2 * plane] = l1_sign(d2, l1.scale);

@@ -47,7 +47,38 @@ struct Views {
   int32_t total_tiles;
   int32_t mip2d;            // 1: the 2D mip filter instead of the dilation
   const float* filter3d;    // per-Gaussian 3D filter variances, or null
+  const gs_camera* cam_table;  // with cam_index: view 0's camera, read when the kernel runs
+  const int32_t* cam_index;
 };
+
+// View v's camera: the host-built entry, or (view 0 with a device camera
+// table) the table's entry, with the camera centre -R^T t computed in double
+// and rounded once, as the host does.  The entry is the same for every lane:
+// its fields are moved to scalar registers so the lookup costs no VGPRs.
+__device__ __forceinline__ float uniform_f(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
+__device__ inline DevView view_at(const Views& V, int v) {
+  DevView d = V.v[v];
+  if (V.cam_table) {
+    const gs_camera& c = V.cam_table[__builtin_amdgcn_readfirstlane(*V.cam_index)];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) d.R[k] = uniform_f(c.R[k]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d.t[k] = uniform_f(c.t[k]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      d.campos[k] = uniform_f(float(-(double(c.R[k]) * c.t[0] + double(c.R[3 + k]) * c.t[1] +
+                                      double(c.R[6 + k]) * c.t[2])));
+    d.fx = uniform_f(c.fx);
+    d.fy = uniform_f(c.fy);
+    d.cx = uniform_f(c.cx);
+    d.cy = uniform_f(c.cy);
+    d.near_plane = uniform_f(c.near_plane);
+  }
+  return d;
+}
 
 // The 3D filter's opacity factor prod_i s_i / sqrt(s_i^2 + f) (1 for f = 0).
 __device__ __forceinline__ float filter3d_coef(float s0, float s1, float s2, float f) {
@@ -241,6 +272,8 @@ struct L1Fuse {
   float* dL;
   float* loss;
   float scale;
+  const int32_t* index;  // with a camera table: target += *index * stride
+  int64_t stride;
 };
 
 hipError_t launch_render_fwd(const Views& V, int n, const gs_raster_cfg& cfg, const char* proj,
@@ -263,6 +296,7 @@ struct FusedAdam {  // the five parameter groups' moments and learning rates
   float* m[5];
   float* v[5];
   float lr[6];  // lr[4]: SH degree-0 coefficients, lr[5]: the higher degrees
+  const float* lr_dev;  // device [6] learning rates, read instead of lr when set
   float b1, b2, eps;
   int32_t* step_dev;
   int sparse;  // 1: leave Gaussians with no pair in any view untouched (sparse Adam)

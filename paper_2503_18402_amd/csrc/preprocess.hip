@@ -257,7 +257,7 @@ __global__ __launch_bounds__(kPreThreads) void k_preprocess(
     bool live = false;
     if (g < n) {
       const Gauss3 G = load_gauss(V, g, means, log_scales, quats, opacity_logits);
-      P = splat_geometry(V.v[0], G, V.tile, V.mip2d);
+      P = splat_geometry(view_at(V, 0), G, V.tile, V.mip2d);
       live = P.count > 0;
     }
     s_need[threadIdx.x] = live ? 1 : 0;
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(kPreThreads) void k_preprocess(
   for (int k = 0; k < GS_SH_COEFFS * 3; ++k) shc[k] = (k < 3 * K) ? shg[k] : 0.0f;
   for (int v = 0; v < V.n_views; ++v) {
     char* base = proj + size_t(v) * L.stride;
-    Splat P = splat_geometry(V.v[v], G, V.tile, V.mip2d);
+    Splat P = splat_geometry(view_at(V, v), G, V.tile, V.mip2d);
     uint32_t flags = 0;
     if (P.has_colour) splat_colour(P, shc, sh_degree, flags);
     float4* rec = reinterpret_cast<float4*>(base + L.rec) + 3 * size_t(g);

@@ -36,7 +36,8 @@ class GsCamera(ctypes.Structure):
 
 class GsRasterCfg(ctypes.Structure):
     _fields_ = [("tile", c_int32), ("lds_batch", c_int32), ("bg", c_float * 3),
-                ("mip2d", c_int32), ("filter3d", c_void_p)]
+                ("mip2d", c_int32), ("filter3d", c_void_p), ("cam_table", c_void_p),
+                ("cam_index", c_void_p), ("adam_lr", c_void_p)]
 
 
 class GsKernelTime(ctypes.Structure):
@@ -163,15 +164,27 @@ def make_cameras(cams) -> ctypes.Array:
 
 
 def make_cfg(tile: int = 16, lds_batch: int = 256, bg=(0.0, 0.0, 0.0), mip2d: bool = False,
-             filter3d=None) -> GsRasterCfg:
-    """filter3d: device float32 [n] 3D filter variances (kept alive by the
-    caller while the cfg is in use) or None."""
+             filter3d=None, cam_table=None, cam_index=None, adam_lr=None) -> GsRasterCfg:
+    """filter3d: device float32 [n] 3D filter variances or None; cam_table
+    (from camera_table), cam_index (device int32 [1]) and adam_lr (device
+    float32 [6]): the device-side step parameters of gs_raster_cfg.  The caller
+    keeps every tensor alive while the cfg is in use."""
     c = GsRasterCfg()
     c.tile, c.lds_batch = int(tile), int(lds_batch)
     c.bg[:] = [float(x) for x in bg]
     c.mip2d = 1 if mip2d else 0
     c.filter3d = _ptr(filter3d)
+    c.cam_table = _ptr(cam_table)
+    c.cam_index = _ptr(cam_index)
+    c.adam_lr = _ptr(adam_lr)
     return c
+
+
+def camera_table(cams, device="cuda") -> torch.Tensor:
+    """The cameras as a device array of gs_camera structs (uint8 tensor)."""
+    arr = make_cameras(cams)
+    raw = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8)
+    return raw.to(device)
 
 
 # ------------------------------------------------------ the C entry points

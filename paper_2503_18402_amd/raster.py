@@ -231,7 +231,8 @@ class Pipeline:
                  fused: bool = True, share: "Pipeline | None" = None,
                  state: tuple | None = None, mean2d_abs: torch.Tensor | None = None,
                  sparse_adam: bool = False, mip2d: bool = False,
-                 filter3d: torch.Tensor | None = None):
+                 filter3d: torch.Tensor | None = None, cam_table: torch.Tensor | None = None,
+                 cam_index: torch.Tensor | None = None, adam_lr: torch.Tensor | None = None):
         if sparse_adam and not fused:
             raise ValueError("sparse Adam runs fused with the backward pass")
         self.params = params
@@ -240,12 +241,20 @@ class Pipeline:
         self.n = params["means"].shape[0]
         self.nv = len(self.cams)
         self.cams_c = gsmi.make_cameras(self.cams)
-        self.filter3d = filter3d   # kept alive: the cfg holds its address
-        self.cfg = gsmi.make_cfg(tile, lds_batch, bg, mip2d=mip2d, filter3d=filter3d)
+        # kept alive: the cfg holds their addresses.  With a camera table (one view),
+        # every call takes view 0's camera from cam_table[*cam_index] and the L1
+        # target from the stack `targets` at that index; with adam_lr the fused
+        # Adam step reads its learning rates from the device
+        self.filter3d, self.cam_table, self.cam_index, self.adam_lr = (filter3d, cam_table,
+                                                                      cam_index, adam_lr)
+        self.cfg = gsmi.make_cfg(tile, lds_batch, bg, mip2d=mip2d, filter3d=filter3d,
+                                 cam_table=cam_table, cam_index=cam_index, adam_lr=adam_lr)
         self.sh_degree = sh_degree
         self.npx = sum(int(c.width) * int(c.height) for c in self.cams)
         self.targets = targets.contiguous()
         if capacity is None:
+            if cam_table is not None:
+                raise ValueError("a pipeline with a camera table needs its capacity")
             probe = render(params, self.cams, tile=tile, lds_batch=lds_batch, bg=bg,
                            sh_degree=sh_degree, mip2d=mip2d, filter3d=filter3d)
             capacity = int(int(probe.n_pairs_dev.item()) * 1.2) + 4096

@@ -76,3 +76,46 @@ def test_autotune_pick_renders_the_same_image():
         img = f.image.view(3, cams[0].height, cams[0].width).cpu().numpy()
         assert np.abs(img - F["image"])[:, ok].max() < 1e-5, (tile, batch)
     assert autotune.tune(params, cams, tgt) is res      # cached
+
+
+def test_camera_table_step_equals_host_camera_step():
+    """A one-view pipeline whose camera, L1 target and Adam learning rates come
+    from device tables (gs_raster_cfg.cam_table / cam_index / adam_lr), captured
+    once as a graph and replayed with the view index and learning rates changed
+    between replays, against the eager steps with the host camera of the same
+    views: parameters, moments and image bit for bit after every step."""
+    from paper_2503_18402_amd import gsmi
+    base = scenes.orbit_cameras(4, 3.0, 160, 120, 150.0)
+    sc, _, _ = _setup(n=12000)
+    tg = torch.stack([torch.from_numpy(scenes.uniform_target(c, seed=60 + k)).cuda()
+                      for k, c in enumerate(base)])
+    lrs = dict(means=1.6e-4, log_scales=5e-3, quats=1e-3, opacity_logits=5e-2, sh=2.5e-3,
+               sh_rest=2.5e-3 / 20)
+    cap = 8 * 12000
+    pa = raster.Pipeline(raster.to_device(sc), [base[0]], tg[0].reshape(-1), lrs=dict(lrs),
+                         capacity=cap)
+    idx = torch.zeros(1, dtype=torch.int32, device="cuda")
+    lr_dev = torch.zeros(6, dtype=torch.float32, device="cuda")
+    table = gsmi.camera_table(base)
+    pb = raster.Pipeline(raster.to_device(sc), [base[0]], tg.reshape(-1), lrs=dict(lrs),
+                         capacity=cap, cam_table=table, cam_index=idx,
+                         adam_lr=lr_dev)
+    pa.track_loss = pb.track_loss = False
+    pb.capture()
+    for k, view in enumerate((2, 0, 3, 2, 1)):
+        means_lr = 1.6e-4 * (0.7 ** k)
+        pa.set_view(base[view], tg[view])
+        pa.lrs["means"] = means_lr
+        pa.step()
+        idx.fill_(view)                                   # eager work between replays
+        lr_dev.copy_(torch.tensor([means_lr, lrs["log_scales"], lrs["quats"],
+                                   lrs["opacity_logits"], lrs["sh"], lrs["sh_rest"]],
+                                  dtype=torch.float32))
+        pb.step()
+        torch.cuda.synchronize()
+        assert not pa.overflowed() and not pb.overflowed()
+        assert torch.equal(pa.image, pb.image), (k, view)
+        for name in raster.PARAM_NAMES:
+            assert torch.equal(pa.params[name], pb.params[name]), (k, name)
+            assert torch.equal(pa.m[name], pb.m[name]), (k, name)
+            assert torch.equal(pa.v[name], pb.v[name]), (k, name)

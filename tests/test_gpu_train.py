@@ -138,3 +138,32 @@ def test_autograd_loop_equals_fused_loop():
         assert torch.equal(a.params[name], b.params[name]), name
         assert torch.equal(a.m[name], b.m[name]), name
         assert torch.equal(a.v[name], b.v[name]), name
+
+
+def test_graph_loop_equals_eager_loop():
+    """The fused loop replayed from one HIP graph per resolution level (views,
+    targets and learning rates in device tables) against the same loop run
+    eagerly with host cameras, under both schedules with densification (which
+    re-captures the graphs): parameters, moments, learning rates and
+    densification decisions bit for bit."""
+    cams = scenes.fibonacci_cameras(6, 3.0, 128, 96, 120.0)
+    gt = torch.from_numpy(_gt(cams, seed=79)).cuda()
+    sc = scenes.make_scene(3000, seed=80, mean_range=1.0, ls_mu=-3.0, ls_sigma=0.4)
+    runs = {}
+    for graphs in (False, True):
+        params = raster.to_device(sc, "cuda")
+        dcfg = train.DensifyConfig(every=30, start=30, stop=70, grad_thr=2e-4, extent=3.3)
+        tr = train.Trainer(params, cams, gt, 90, schedule=True, densify=dcfg, graphs=graphs,
+                           seed=7)
+        out = tr.run()
+        runs[graphs] = (tr, out)
+    (a, oa), (b, ob) = runs[False], runs[True]
+    assert b.graph_of and not a.graph_of
+    assert [e["n_new"] for e in a.log] == [e["n_new"] for e in b.log] and len(a.log) == 2
+    assert oa["iters_per_factor"] == ob["iters_per_factor"] and len(oa["iters_per_factor"]) > 1
+    assert a.lr_log == b.lr_log
+    assert int(b.k_dev.item()) == 90
+    for name in raster.PARAM_NAMES:
+        assert torch.equal(a.params[name], b.params[name]), name
+        assert torch.equal(a.m[name], b.m[name]), name
+        assert torch.equal(a.v[name], b.v[name]), name
