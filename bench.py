@@ -66,6 +66,8 @@ def parse():
                     help="training loops replay one HIP graph per level instead of stepping eagerly")
     ap.add_argument("--no-spatial", action="store_true",
                     help="keep the scenes in generation order instead of the spatial order")
+    ap.add_argument("--train-spatial", action="store_true",
+                    help="training loops keep their Gaussians in the spatial order")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run warmup + this many steps (for rocprofv3), no extras")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -110,7 +112,7 @@ def main():
     torch.cuda.set_device(dev)
     if args.training_only:
         print(json.dumps(scheduled_training(torch, raster, scenes, dev, args.train_iters,
-                                            args.train_ablations, not args.no_spatial,
+                                            args.train_ablations, args.train_spatial,
                                             args.graphs)))
         return
 
@@ -257,7 +259,7 @@ def main():
             extras["large"] = large_scene(torch, raster, scenes, dev, not args.no_spatial)
         if args.train_iters > 0:
             extras["training"] = scheduled_training(torch, raster, scenes, dev, args.train_iters,
-                                                    args.train_ablations, not args.no_spatial,
+                                                    args.train_ablations, args.train_spatial,
                                                     args.graphs)
 
     out = {
@@ -356,7 +358,8 @@ def binning_forms(torch, pipe, reps=20):
 
 def level_sweep(torch, raster, scenes, params, tparams_scene, tile, lds):
     """The plain single-view step at each downscale level of the schedule (8/4/2/1),
-    autotuned per level and replayed from a HIP graph."""
+    autotuned per level and replayed from a HIP graph, with dense and with sparse
+    Adam, and the two binning routes timed on the level's records."""
     from paper_2503_18402_amd import autotune, gsmi
 
     out = {}
@@ -378,13 +381,23 @@ def level_sweep(torch, raster, scenes, params, tparams_scene, tile, lds):
         kt = gsmi.gs_profile_collect()
         gsmi.gs_profile_enable(False)
         pipe.graph = graph
-        top = sorted(kt.items(), key=lambda kv: -kv[1][1])[:8]
+        top = sorted(kt.items(), key=lambda kv: -kv[1][1])[:12]
+        bins = binning_forms(torch, pipe, reps=10)
+        # the same step with sparse Adam (rows of Gaussians with no footprint skipped)
+        ps = raster.Pipeline({k: v.clone() for k, v in params.items()}, [cam], tgt,
+                             tile=pick["tile"], lds_batch=pick["lds_batch"],
+                             capacity=pipe.capacity, sparse_adam=True)
+        ps.capture()
+        ms_sparse = time_pipe(torch, ps, 10)
         out[f"r{r}"] = dict(width=cam.width, height=cam.height, ms_per_step=round(ms, 4),
                             mpix_per_s=round(cam.width * cam.height / (ms / 1e3) / 1e6, 2),
+                            ms_per_step_sparse_adam=round(ms_sparse, 4),
                             tile=pick["tile"], lds_batch=pick["lds_batch"],
-                            kernel_ms=({k: round(v[1] / 5, 4) for k, v in top}))
-        log(f"level r={r}: {ms:.3f} ms/step (tile {pick['tile']}, batch {pick['lds_batch']})")
-        del pipe, p
+                            kernel_ms=({k: round(v[1] / 5, 4) for k, v in top}),
+                            binning=bins)
+        log(f"level r={r}: {ms:.3f} ms/step, sparse Adam {ms_sparse:.3f} "
+            f"(tile {pick['tile']}, batch {pick['lds_batch']})")
+        del pipe, ps, p
     return out
 
 
@@ -481,7 +494,7 @@ def compare_forms(torch, raster, params, cams, tgts, label):
                      "16 per-view gradients and then runs the separate Adam step")
 
 
-def scheduled_training(torch, raster, scenes, dev, iters, ablations=False, spatial=True,
+def scheduled_training(torch, raster, scenes, dev, iters, ablations=False, spatial=False,
                        graphs=False):
     """The optimisation loop of the hidden-scene workload: learnable Gaussians
     fitted to 64 views at 1200x800 of a 500k-Gaussian hidden scene (ground

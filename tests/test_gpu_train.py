@@ -144,7 +144,8 @@ def test_graph_loop_equals_eager_loop():
     """The fused loop replayed from one HIP graph per resolution level (views,
     targets and learning rates in device tables) against the same loop run
     eagerly with host cameras, under both schedules with densification (which
-    re-captures the graphs): parameters, moments, learning rates and
+    re-captures the graphs), Gaussians kept in the spatial order (re-sorted
+    after each densification): parameters, moments, learning rates and
     densification decisions bit for bit."""
     cams = scenes.fibonacci_cameras(6, 3.0, 128, 96, 120.0)
     gt = torch.from_numpy(_gt(cams, seed=79)).cuda()
@@ -154,7 +155,7 @@ def test_graph_loop_equals_eager_loop():
         params = raster.to_device(sc, "cuda")
         dcfg = train.DensifyConfig(every=30, start=30, stop=70, grad_thr=2e-4, extent=3.3)
         tr = train.Trainer(params, cams, gt, 90, schedule=True, densify=dcfg, graphs=graphs,
-                           seed=7)
+                           seed=7, spatial=True)
         out = tr.run()
         runs[graphs] = (tr, out)
     (a, oa), (b, ob) = runs[False], runs[True]
