@@ -70,6 +70,9 @@ def parse():
                     help="training loops keep their Gaussians in the spatial order")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run warmup + this many steps (for rocprofv3), no extras")
+    ap.add_argument("--level", type=int, default=1, choices=(1, 2, 4, 8),
+                    help="with --profile-steps: profile the step at this downscale level "
+                         "of the headline view")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--training-only", action="store_true",
@@ -91,6 +94,9 @@ def log(msg):
 
 def main():
     args = parse()
+    if args.level != 1 and not args.profile_steps:
+        print("--level is for profiling runs (--profile-steps)", file=sys.stderr)
+        sys.exit(2)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path would shard "
               "by views across GPUs, which is not implemented.", file=sys.stderr)
@@ -118,7 +124,7 @@ def main():
 
     # ---------------------------------------------------------------- inputs
     log("generating the 1M-Gaussian scene and target")
-    scene, cam = scenes.paper_scale_scene(level=1, n=args.n)
+    scene, cam = scenes.paper_scale_scene(level=args.level, n=args.n)
     tscene = scenes.paper_scale_target_scene(n=args.n)
     params = raster.to_device(scene, dev)
     if not args.no_spatial:

@@ -807,6 +807,39 @@ __device__ __forceinline__ bool chain_grad(const Views& V, const ChainIn& I, int
   return true;
 }
 
+// The block's SH rows staged in LDS with coalesced 16-byte loads (rows of an
+// odd stride, conflict-free), only for the Gaussians with a pair in some view:
+// the others leave the chain rule at once and never read their row (in the
+// spatial storage order whole blocks of them skip the load).  Every thread of
+// the block must call it; it ends with a barrier.
+template <int T>
+__device__ inline void stage_sh_needed(const Views& V, const ChainIn& I, int g0, float* s_buf,
+                                       int* s_need) {
+  constexpr int F = GS_SH_COEFFS * 3, kRow = F + 1;
+  const int g = g0 + int(threadIdx.x);
+  bool any = false;
+  if (g < I.n) {
+    const ProjLayout L(I.n);
+    for (int v = 0; v < V.n_views; ++v)
+      any |= reinterpret_cast<const uint32_t*>(I.proj + size_t(v) * L.stride + L.tt)[g] > 0u;
+  }
+  s_need[threadIdx.x] = any ? 1 : 0;
+  __syncthreads();
+  const int rows = (I.n - g0 < T) ? I.n - g0 : T;
+  const float4* src = reinterpret_cast<const float4*>(I.sh + size_t(g0) * F);
+  for (int i = threadIdx.x; i < rows * (F / 4); i += T) {
+    const int f = 4 * i, row = f / F, k = f - row * F;
+    if (!s_need[row]) continue;
+    const float4 q = src[i];
+    float* d = s_buf + row * kRow + k;
+    d[0] = q.x;
+    d[1] = q.y;
+    d[2] = q.z;
+    d[3] = q.w;
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(128) void k_chain(Views V, ChainIn I, int accumulate,
                                                float* __restrict__ d_means,
                                                float* __restrict__ d_log_scales,
@@ -817,22 +850,9 @@ __global__ __launch_bounds__(128) void k_chain(Views V, ChainIn I, int accumulat
   // the block's SH coefficients staged in LDS as in k_chain_adam
   constexpr int F = GS_SH_COEFFS * 3, kRow = F + 1;
   __shared__ float s_sh[128 * kRow];
+  __shared__ int s_need[128];
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  {
-    const int g0 = blockIdx.x * blockDim.x;
-    const int rows = (I.n - g0 < 128) ? I.n - g0 : 128;
-    const float4* src = reinterpret_cast<const float4*>(I.sh + size_t(g0) * F);
-    for (int i = threadIdx.x; i < rows * (F / 4); i += 128) {
-      const float4 q = src[i];
-      const int f = 4 * i, row = f / F, k = f - row * F;
-      float* d = s_sh + row * kRow + k;
-      d[0] = q.x;
-      d[1] = q.y;
-      d[2] = q.z;
-      d[3] = q.w;
-    }
-  }
-  __syncthreads();
+  stage_sh_needed<128>(V, I, blockIdx.x * blockDim.x, s_sh, s_need);
   if (g >= I.n) return;
   ChainOut O;
   float* dshg = d_sh + size_t(g) * GS_SH_COEFFS * 3;
@@ -896,11 +916,12 @@ struct AdamGroups {
   int sparse;  // 1: Gaussians with no pair in any view keep p, m and v unchanged
 };
 
-__global__ __launch_bounds__(kCA) void k_chain_adam(Views V, ChainIn I, AdamGroups A,
-                                                    float* __restrict__ d_mean2d_abs) {
-  // the block's SH coefficients arrive in LDS with coalesced 16-byte loads (rows
-  // of an odd stride, conflict-free) for the chain rule's direction term; the
-  // same LDS then holds the SH gradients for the Adam loop
+// memory-bound: at most 168 VGPRs, so three waves fit per SIMD
+__global__ __launch_bounds__(kCA) __attribute__((amdgpu_waves_per_eu(3))) void k_chain_adam(
+    Views V, ChainIn I, AdamGroups A, float* __restrict__ d_mean2d_abs) {
+  // the block's SH coefficients arrive in LDS (stage_sh_needed) for the chain
+  // rule's direction term; the same LDS then holds the SH gradients for the
+  // Adam loop
   constexpr int F = GS_SH_COEFFS * 3, kRow = F + 1;
   __shared__ __align__(16) float s_buf[kCA * kRow];
   float4* s_g = reinterpret_cast<float4*>(s_buf);
@@ -912,21 +933,7 @@ __global__ __launch_bounds__(kCA) void k_chain_adam(Views V, ChainIn I, AdamGrou
   if (threadIdx.x == 0) adam_bias(A.step_dev, A.b1, A.b2, s_c[0], s_c[1], 0);
   if (threadIdx.x < 6) lr[threadIdx.x] = A.lr_dev ? A.lr_dev[threadIdx.x] : A.lr[threadIdx.x];
   const int g = blockIdx.x * kCA + threadIdx.x;
-  {
-    const int g0 = blockIdx.x * kCA;
-    const int rows = (I.n - g0 < kCA) ? I.n - g0 : kCA;
-    const float4* src = reinterpret_cast<const float4*>(I.sh + size_t(g0) * F);
-    for (int i = threadIdx.x; i < rows * (F / 4); i += kCA) {
-      const float4 q = src[i];
-      const int f = 4 * i, row = f / F, k = f - row * F;
-      float* d = s_buf + row * kRow + k;
-      d[0] = q.x;
-      d[1] = q.y;
-      d[2] = q.z;
-      d[3] = q.w;
-    }
-  }
-  __syncthreads();
+  stage_sh_needed<kCA>(V, I, blockIdx.x * kCA, s_buf, s_upd);
   ChainOut O;
   bool have = false;
   if (g < I.n) have = chain_grad(V, I, g, O, s_buf + threadIdx.x * kRow);
