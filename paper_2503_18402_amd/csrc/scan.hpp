@@ -68,20 +68,45 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(Src src, Count cnt
 }
 
 // One block: exclusive scan of the per-block sums in place; writes the total.
+// Chunks of kScanTile sums: coalesced loads into LDS, 16 consecutive sums per
+// thread, so a spine of up to 4096 blocks is one pass.
 static __global__ __launch_bounds__(kScanThreads) void k_scan_spine(uint32_t* block_sums, Count cnt,
                                                              int64_t* total_out,
                                                              uint32_t* total_out32) {
+  __shared__ uint32_t s_v[kScanTile];
   __shared__ uint32_t s_tmp[4];
   const int64_t n = cnt.get();
   const int64_t nb = (n + kScanTile - 1) / kScanTile;
   uint32_t carry = 0;
-  for (int64_t c = 0; c < nb; c += kScanThreads) {
-    const int64_t i = c + threadIdx.x;
-    const uint32_t x = (i < nb) ? block_sums[i] : 0u;
+  for (int64_t c = 0; c < nb; c += kScanTile) {
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      const int j = k * kScanThreads + threadIdx.x;
+      s_v[j] = (c + j < nb) ? block_sums[c + j] : 0u;
+    }
+    __syncthreads();
+    uint32_t loc[kScanItems];
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      loc[k] = s_v[threadIdx.x * kScanItems + k];
+      acc += loc[k];
+    }
     uint32_t tot;
-    const uint32_t ex = block_excl_scan256(x, tot, s_tmp);
-    if (i < nb) block_sums[i] = carry + ex;
+    uint32_t ex = carry + block_excl_scan256(acc, tot, s_tmp);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      s_v[threadIdx.x * kScanItems + k] = ex;
+      ex += loc[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      const int j = k * kScanThreads + threadIdx.x;
+      if (c + j < nb) block_sums[c + j] = s_v[j];
+    }
     carry += tot;
+    __syncthreads();  // s_v is refilled by the next chunk
   }
   if (threadIdx.x == 0) {
     if (total_out) *total_out = int64_t(carry);
