@@ -827,15 +827,26 @@ __device__ inline void stage_sh_needed(const Views& V, const ChainIn& I, int g0,
   __syncthreads();
   const int rows = (I.n - g0 < T) ? I.n - g0 : T;
   const float4* src = reinterpret_cast<const float4*>(I.sh + size_t(g0) * F);
-  for (int i = threadIdx.x; i < rows * (F / 4); i += T) {
+  // a thread's float4s are i = t + u * T, u < 12 (rows <= T): every load is
+  // issued before the first LDS write, so their latencies overlap
+  constexpr int U = F / 4;
+  float4 q[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int i = int(threadIdx.x) + u * T;
+    if (i < rows * U && s_need[(4 * i) / F]) q[u] = src[i];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int i = int(threadIdx.x) + u * T;
     const int f = 4 * i, row = f / F, k = f - row * F;
-    if (!s_need[row]) continue;
-    const float4 q = src[i];
-    float* d = s_buf + row * kRow + k;
-    d[0] = q.x;
-    d[1] = q.y;
-    d[2] = q.z;
-    d[3] = q.w;
+    if (i < rows * U && s_need[row]) {
+      float* d = s_buf + row * kRow + k;
+      d[0] = q[u].x;
+      d[1] = q[u].y;
+      d[2] = q[u].z;
+      d[3] = q[u].w;
+    }
   }
   __syncthreads();
 }

@@ -220,17 +220,28 @@ __device__ __forceinline__ Gauss3 load_gauss(const Views& V, int g, const float*
 // whose s_need entry is zero are skipped (left unread).
 __device__ __forceinline__ void stage_sh(float* s_sh, const float* __restrict__ sh, int g0,
                                          int rows, const int* s_need) {
-  constexpr int F = GS_SH_COEFFS * 3;
+  constexpr int F = GS_SH_COEFFS * 3, U = F / 4;  // 12 float4 per row
   const float4* src = reinterpret_cast<const float4*>(sh + size_t(g0) * F);
-  for (int i = threadIdx.x; i < rows * (F / 4); i += kPreThreads) {
+  // a thread's float4s are i = t + u * kPreThreads, u < U (rows <= kPreThreads):
+  // all its loads are issued before the first LDS write, so their latencies
+  // overlap instead of adding up
+  float4 q[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int i = threadIdx.x + u * kPreThreads;
+    if (i < rows * U && (!s_need || s_need[(4 * i) / F])) q[u] = src[i];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int i = threadIdx.x + u * kPreThreads;
     const int f = 4 * i, row = f / F, k = f - row * F;
-    if (s_need && !s_need[row]) continue;
-    const float4 q = src[i];
-    float* d = s_sh + row * kShStride + k;
-    d[0] = q.x;
-    d[1] = q.y;
-    d[2] = q.z;
-    d[3] = q.w;
+    if (i < rows * U && (!s_need || s_need[row])) {
+      float* d = s_sh + row * kShStride + k;
+      d[0] = q[u].x;
+      d[1] = q[u].y;
+      d[2] = q[u].z;
+      d[3] = q[u].w;
+    }
   }
 }
 
