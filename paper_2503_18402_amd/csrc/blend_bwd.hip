@@ -967,23 +967,49 @@ __global__ __launch_bounds__(kCA) __attribute__((amdgpu_waves_per_eu(3))) void k
   const AdamCoef C{A.b1, A.b2, A.eps, s_c[0], s_c[1]};
   if (g < I.n && d_mean2d_abs) d_mean2d_abs[g] = O.m2abs;
   if (g < I.n && upd) {
+    // every value is loaded before the first store (the groups are distinct
+    // arrays), so the loads' latencies overlap
+    float pm[3], mm[3], vm[3], ps[3], ms[3], vs[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const int j = 3 * g + k;
-      adam_one(A.p[0][j], O.dm[k], A.m[0][j], A.v[0][j], lr[0], C);
-      adam_one(A.p[1][j], O.dls[k], A.m[1][j], A.v[1][j], lr[1], C);
+      pm[k] = A.p[0][j];
+      mm[k] = A.m[0][j];
+      vm[k] = A.v[0][j];
+      ps[k] = A.p[1][j];
+      ms[k] = A.m[1][j];
+      vs[k] = A.v[1][j];
     }
     float4 p4 = reinterpret_cast<float4*>(A.p[2])[g];
     float4 m4 = reinterpret_cast<float4*>(A.m[2])[g];
     float4 v4 = reinterpret_cast<float4*>(A.v[2])[g];
+    float po = A.p[3][g], mo = A.m[3][g], vo = A.v[3][g];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      adam_one(pm[k], O.dm[k], mm[k], vm[k], lr[0], C);
+      adam_one(ps[k], O.dls[k], ms[k], vs[k], lr[1], C);
+    }
     adam_one(p4.x, O.dq.x, m4.x, v4.x, lr[2], C);
     adam_one(p4.y, O.dq.y, m4.y, v4.y, lr[2], C);
     adam_one(p4.z, O.dq.z, m4.z, v4.z, lr[2], C);
     adam_one(p4.w, O.dq.w, m4.w, v4.w, lr[2], C);
+    adam_one(po, O.dlogit, mo, vo, lr[3], C);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int j = 3 * g + k;
+      A.p[0][j] = pm[k];
+      A.m[0][j] = mm[k];
+      A.v[0][j] = vm[k];
+      A.p[1][j] = ps[k];
+      A.m[1][j] = ms[k];
+      A.v[1][j] = vs[k];
+    }
     reinterpret_cast<float4*>(A.p[2])[g] = p4;
     reinterpret_cast<float4*>(A.m[2])[g] = m4;
     reinterpret_cast<float4*>(A.v[2])[g] = v4;
-    adam_one(A.p[3][g], O.dlogit, A.m[3][g], A.v[3][g], lr[3], C);
+    A.p[3][g] = po;
+    A.m[3][g] = mo;
+    A.v[3][g] = vo;
   }
   // SH: the block's contiguous slab of 48 values per Gaussian, float4 per lane
   const int g0 = blockIdx.x * kCA;
