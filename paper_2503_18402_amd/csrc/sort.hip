@@ -18,18 +18,24 @@
 //   3. bucket: every pair stores the 64-bit sort key
 //              (bits(depth_f32) << 32) | Gaussian index at its tile's first
 //              slot plus its rank: no atomics;
-//   4. sort:   one block per tile sorts its keys with a bitonic network in LDS
-//              (lists longer than one LDS chunk also run the network's long
-//              strides through global memory) and writes the values, and the
-//              keys when asked for.
+//   4. sort:   each tile's keys are sorted by a bitonic network and the
+//              values written (and the keys when asked for): lists of up to
+//              512 keys by one wave in registers, up to 2048 by a 256-thread
+//              block in registers with LDS exchanges for the strides that
+//              cross waves, longer ones by a 1024-thread block in LDS (lists
+//              longer than one LDS chunk also run the network's long strides
+//              through global memory).
 // The slot order after step 3 depends on atomic timing; after step 4 it does
-// not.  Blocks whose views have few tiles (low resolutions, thousands of pairs
-// per tile) count in LDS first and reserve one slot range per touched tile in
-// step 3 instead, through a cursor that starts after the tile's ranked pairs.
-// The counters, cursors and first slots live in the caller's ranges array
-// (during steps 1-3: ranges[2t] = ranked count, then first slot; ranges[2t+1]
-// = LDS-counted count, then cursor, then end), so the workspace holds the
-// bucketed keys, the ranks, the offsets' block sums and three counts.
+// not.  A block whose pairs fall on at most 2048 tiles it can index (all tiles
+// of its views at low resolutions, where every tile collects thousands of
+// pairs; or the bounding rectangle of its footprints' tiles, when its
+// Gaussians sit close together in space) counts in LDS first and reserves one
+// slot range per touched tile in step 3 instead, through a cursor that starts
+// after the tile's ranked pairs.  The counters, cursors and first slots live in
+// the caller's ranges array (during steps 1-3: ranges[2t] = ranked count, then
+// first slot; ranges[2t+1] = LDS-counted count, then cursor, then end), so the
+// workspace holds the bucketed keys, the ranks, the offsets' block sums and
+// four counts.
 //
 // The pair expansion spreads each wave's pairs evenly over its 64 lanes, so a
 // Gaussian with a footprint of thousands of tiles does not serialise on one lane.
