@@ -152,8 +152,9 @@ gs_status gs_bin_sort(int32_t n_views, const gs_camera* cams, const gs_raster_cf
  *   capacity_pairs: 0 .. GS_BIN_SORT_NOALLOC_MAX_PAIRS (2^22), and
  *   n_views * n: at most GS_BIN_SORT_NOALLOC_MAX_ITEMS (2^23); larger values
  *     return GS_ERR_CAPACITY and enqueue nothing.  The array holds 12 bytes
- *     per pair of that maximum plus 4 bytes per 256 items and 256 bytes
- *     (48.1 MiB) on every GPU the library runs on, until the process ends.
+ *     per pair of that maximum plus 4 bytes per 256 items, 64 KiB of tile
+ *     counters and 256 bytes (48.2 MiB) on every GPU the library runs on,
+ *     until the process ends.
  *   The call allocates nothing (no hipMalloc, no hipFree).  Its first call on
  *   a device looks up that device's copy of the array with the device
  *   current; the current device must be the one `stream` belongs to.

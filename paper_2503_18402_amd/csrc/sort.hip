@@ -251,10 +251,20 @@ __device__ inline BlockSpan block_span(const Items& S, int rounds, int agg_bins)
   return b;
 }
 
+// The counter an LDS-counting block reserves through for global tile t: with
+// `copies` (launches of at most kAggBins tiles, where the same few hundred
+// counters receive one atomic from nearly every block) one of kXcds copies,
+// chosen by the block, so each copy sees an eighth of those atomics; else the
+// tile's ranges[2t + 1].
+__device__ __forceinline__ uint32_t* agg_counter(uint32_t* ranges, uint32_t* copies, uint32_t t) {
+  return copies ? copies + (blockIdx.x % kXcds) * kAggBins + t : ranges + 2 * size_t(t) + 1;
+}
+
 __global__ __launch_bounds__(kXT) void k_tile_count(Items S, int rounds, int agg_bins,
                                                     const uint32_t* __restrict__ block_pos,
                                                     int64_t cap, uint32_t* __restrict__ ranges,
-                                                    uint32_t* __restrict__ rank) {
+                                                    uint32_t* __restrict__ rank,
+                                                    uint32_t* __restrict__ copies) {
   extern __shared__ uint32_t s_bins[];
   const BlockSpan B = block_span(S, rounds, agg_bins);
   if (B.mode) {
@@ -265,7 +275,7 @@ __global__ __launch_bounds__(kXT) void k_tile_count(Items S, int rounds, int agg
         atomicAdd(&s_bins[B.bin(t, xy)], 1u);
       });
     for (int b = threadIdx.x; b < B.span; b += kXT)
-      if (s_bins[b]) atomicAdd(&ranges[2 * size_t(B.tile_of(b)) + 1], s_bins[b]);
+      if (s_bins[b]) atomicAdd(agg_counter(ranges, copies, B.tile_of(b)), s_bins[b]);
   } else {
     // the returned count is the pair's rank among its tile's ranked pairs
     uint32_t pos = block_pos[blockIdx.x];
@@ -286,6 +296,7 @@ __global__ __launch_bounds__(kXT) void k_bucket(Items S, int rounds, int agg_bin
                                                 const uint32_t* __restrict__ block_pos,
                                                 const uint32_t* __restrict__ rank,
                                                 uint32_t* __restrict__ ranges,
+                                                uint32_t* __restrict__ copies,
                                                 uint64_t* __restrict__ bucket) {
   extern __shared__ uint32_t s_bins[];
   if (*n_eff == 0) return;  // capacity overflow (or no pairs): nothing to place
@@ -299,7 +310,7 @@ __global__ __launch_bounds__(kXT) void k_bucket(Items S, int rounds, int agg_bin
       });
     for (int b = threadIdx.x; b < B.span; b += kXT) {
       const uint32_t k = s_bins[b];
-      if (k) s_bins[b] = atomicAdd(&ranges[2 * size_t(B.tile_of(b)) + 1], k);
+      if (k) s_bins[b] = atomicAdd(agg_counter(ranges, copies, B.tile_of(b)), k);
     }
     __syncthreads();
     for (int64_t c = B.i0; c < B.i1; c += kXT)
@@ -315,11 +326,12 @@ __global__ __launch_bounds__(kXT) void k_bucket(Items S, int rounds, int agg_bin
   }
 }
 
-// One block: with c_t = ranges[2t] (ranked pairs) + ranges[2t+1] (pairs of
-// LDS-counting blocks), ranges[2t] = exclusive prefix of c (the tile's first
-// slot) and ranges[2t+1] = that prefix plus the ranked pairs (where the
-// LDS-counting blocks' cursor starts); the pair total, and whether it fits
-// the capacity.  Sums are 64-bit, so an
+// One block: with c_t = ranges[2t] (ranked pairs) + the pairs of LDS-counting
+// blocks (ranges[2t+1], or the sum of the tile's kXcds counter copies),
+// ranges[2t] = exclusive prefix of c (the tile's first slot) and ranges[2t+1]
+// = that prefix plus the ranked pairs (where the LDS-counting blocks' cursor
+// starts; with copies, copy x's cursor starts after copies 0..x-1's pairs);
+// the pair total, and whether it fits the capacity.  Sums are 64-bit, so an
 // overflowing total is always detected.
 constexpr int kTS = 1024;
 constexpr int kTSItems = 8;
@@ -334,7 +346,8 @@ __device__ inline uint64_t wave_incl_scan64(uint64_t x) {
   return x;
 }
 
-__global__ __launch_bounds__(kTS) void k_tile_scan(uint32_t* __restrict__ ranges, int n_tiles,
+__global__ __launch_bounds__(kTS) void k_tile_scan(uint32_t* __restrict__ ranges,
+                                                   uint32_t* __restrict__ copies, int n_tiles,
                                                    int64_t cap, int64_t* __restrict__ n_tot,
                                                    int64_t* __restrict__ n_eff,
                                                    int64_t* __restrict__ n_long,
@@ -350,7 +363,16 @@ __global__ __launch_bounds__(kTS) void k_tile_scan(uint32_t* __restrict__ ranges
 #pragma unroll
     for (int k = 0; k < kTSItems; ++k) {
       cr[k] = (i0 + k < n_tiles) ? ranges[2 * size_t(i0 + k)] : 0u;
-      c[k] = cr[k] + ((i0 + k < n_tiles) ? ranges[2 * size_t(i0 + k) + 1] : 0u);
+      uint32_t agg = 0u;
+      if (i0 + k < n_tiles) {
+        if (copies) {
+#pragma unroll
+          for (int x = 0; x < kXcds; ++x) agg += copies[x * kAggBins + i0 + k];
+        } else {
+          agg = ranges[2 * size_t(i0 + k) + 1];
+        }
+      }
+      c[k] = cr[k] + agg;
       s += c[k];
     }
     const uint64_t inc = wave_incl_scan64(s);
@@ -370,6 +392,15 @@ __global__ __launch_bounds__(kTS) void k_tile_scan(uint32_t* __restrict__ ranges
       if (i0 + k < n_tiles) {
         ranges[2 * size_t(i0 + k)] = uint32_t(ex);
         ranges[2 * size_t(i0 + k) + 1] = uint32_t(ex + cr[k]);
+        if (copies) {
+          uint32_t cur = uint32_t(ex + cr[k]);
+#pragma unroll
+          for (int x = 0; x < kXcds; ++x) {
+            const uint32_t a = copies[x * kAggBins + i0 + k];
+            copies[x * kAggBins + i0 + k] = cur;
+            cur += a;
+          }
+        }
       }
       ex += c[k];
     }
@@ -722,19 +753,25 @@ __global__ __launch_bounds__(kBigThreads) void k_tile_sort_big(
   }
 }
 
+// value into p[0, count) and q[0, count_q)
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int64_t count,
-                                                  uint32_t value) {
+                                                  uint32_t value, uint32_t* __restrict__ q,
+                                                  int64_t count_q) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
        i += int64_t(gridDim.x) * blockDim.x)
     p[i] = value;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count_q;
+       i += int64_t(gridDim.x) * blockDim.x)
+    q[i] = value;
 }
 
 struct WsLayout {
-  size_t cnt, bucket, rank, bpos, total;
+  size_t cnt, copies, bucket, rank, bpos, total;
   WsLayout(int64_t m, int64_t cap) {
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
     cnt = take(8 * 4);
+    copies = take(4 * size_t(kXcds) * kAggBins);
     bucket = take(8 * size_t(cap));
     rank = take(4 * size_t(cap));
     bpos = take(4 * (size_t((m + kXT - 1) / kXT) + 1));  // per expansion block
@@ -749,7 +786,7 @@ struct WsLayout {
 // device address comes from hipGetSymbolAddress, once per device.
 constexpr size_t align256c(size_t x) { return (x + 255) & ~size_t(255); }
 constexpr size_t kNoAllocBytes =
-    256 + align256c(8 * size_t(GS_BIN_SORT_NOALLOC_MAX_PAIRS)) +
+    256 + align256c(4 * size_t(kXcds) * kAggBins) + align256c(8 * size_t(GS_BIN_SORT_NOALLOC_MAX_PAIRS)) +
     align256c(4 * size_t(GS_BIN_SORT_NOALLOC_MAX_PAIRS)) +
     align256c(4 * (size_t(GS_BIN_SORT_NOALLOC_MAX_ITEMS + kXT - 1) / kXT + 1));
 static __device__ __align__(256) char scratch[kNoAllocBytes];
@@ -813,6 +850,7 @@ hipError_t launch_bin_sort(const Views& V, int n, const char* proj, int64_t cap,
   uint64_t* bucket = reinterpret_cast<uint64_t*>(ws + W.bucket);
   uint32_t* rank = reinterpret_cast<uint32_t*>(ws + W.rank);
   uint32_t* bpos = reinterpret_cast<uint32_t*>(ws + W.bpos);
+  uint32_t* copies_ws = reinterpret_cast<uint32_t*>(ws + W.copies);
   const ProjLayout L(n);
   Items S{};
   int min_view_tiles = 1 << 30;
@@ -845,8 +883,12 @@ hipError_t launch_bin_sort(const Views& V, int n, const char* proj, int64_t cap,
   const int agg_bins = kAggBins;
   const unsigned xb = unsigned((S.m + int64_t(kXT) * rounds - 1) / (int64_t(kXT) * rounds));
 
+  // launches of at most kAggBins tiles spread the LDS-counting blocks'
+  // reservation atomics over kXcds counter copies
+  uint32_t* copies = (T <= kAggBins) ? copies_ws : nullptr;
+  const int64_t nc = copies ? int64_t(kXcds) * kAggBins : 0;
   GS_LAUNCH("k_fill_u32", k_fill_u32, dim3(unsigned(nr / 256 + 1 < 4096 ? nr / 256 + 1 : 4096)),
-            dim3(256), 0, st, ranges, nr, 0u);
+            dim3(256), 0, st, ranges, nr, 0u, copies, nc);
   if (xb > 0) {
     // index-order positions of each block's first pair (only blocks that rank
     // their pairs read them: none when every view has at most agg_bins tiles)
@@ -856,13 +898,13 @@ hipError_t launch_bin_sort(const Views& V, int n, const char* proj, int64_t cap,
                 Count{nullptr, int64_t(xb) * kScanTile}, nullptr, nullptr);
     }
     GS_LAUNCH("k_tile_count", k_tile_count, dim3(xb), dim3(kXT), agg_lds, st, S, rounds, agg_bins,
-              bpos, cap, ranges, rank);
+              bpos, cap, ranges, rank, copies);
   }
-  GS_LAUNCH("k_tile_scan", k_tile_scan, dim3(1), dim3(kTS), 0, st, ranges, T, cap, n_tot, n_eff,
-            n_long, n_mid, n_pairs_dev);
+  GS_LAUNCH("k_tile_scan", k_tile_scan, dim3(1), dim3(kTS), 0, st, ranges, copies, T, cap, n_tot,
+            n_eff, n_long, n_mid, n_pairs_dev);
   if (xb > 0)
     GS_LAUNCH("k_bucket", k_bucket, dim3(xb), dim3(kXT), agg_lds, st, S, rounds, agg_bins, n_eff,
-              bpos, rank, ranges, bucket);
+              bpos, rank, ranges, copies, bucket);
   GS_LAUNCH("k_tile_sort_wave", k_tile_sort_wave, dim3(unsigned((T + 3) / 4)), dim3(256), 0, st,
             T, n_tot, n_eff, n_mid, n_long, bucket, vals, keys, ranges);
   GS_LAUNCH("k_tile_sort_mid", k_tile_sort_mid, dim3(unsigned(T < kMidBlocks ? T : kMidBlocks)),
