@@ -160,9 +160,11 @@ __device__ __forceinline__ void bwd_step(BwdPix<TILE>& P, const BwdStage& S, int
   const float4 r1 = S.r1[k];
   const float cb = S.b[k];
   const float lo = r1.y;  // log2 of the blending opacity
+  // -0 is the identity of float addition (+0 is not: +0 + -0 = +0), so the
+  // first group's products need no add
   float acc[kG];
 #pragma unroll
-  for (int c = 0; c < kG; ++c) acc[c] = 0.0f;
+  for (int c = 0; c < kG; ++c) acc[c] = -0.0f;
   bool hit = false;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
