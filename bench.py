@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--level", type=int, default=1, choices=(1, 2, 4, 8),
                     help="with --profile-steps: profile the step at this downscale level "
                          "of the headline view")
+    ap.add_argument("--sparse-adam", action="store_true",
+                    help="with --profile-steps: profile the step with sparse Adam")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--training-only", action="store_true",
@@ -94,8 +96,9 @@ def log(msg):
 
 def main():
     args = parse()
-    if args.level != 1 and not args.profile_steps:
-        print("--level is for profiling runs (--profile-steps)", file=sys.stderr)
+    if (args.level != 1 or args.sparse_adam) and not args.profile_steps:
+        print("--level and --sparse-adam are for profiling runs (--profile-steps)",
+              file=sys.stderr)
         sys.exit(2)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path would shard "
@@ -134,7 +137,8 @@ def main():
     tparams = raster.to_device(tscene, dev)
     target = raster.render(tparams, [cam], tile=args.tile).image.clone()
     del tparams
-    pipe = raster.Pipeline(params, [cam], target, tile=args.tile, lds_batch=args.lds_batch)
+    pipe = raster.Pipeline(params, [cam], target, tile=args.tile, lds_batch=args.lds_batch,
+                           sparse_adam=args.sparse_adam)
     stream = torch.cuda.current_stream()
     W, H = cam.width, cam.height
 
