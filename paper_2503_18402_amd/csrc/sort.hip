@@ -479,21 +479,76 @@ __device__ __forceinline__ void cx(uint64_t& a, uint64_t& b) {
   b = y;
 }
 
-__device__ __forceinline__ uint64_t shfl_xor64(uint64_t x, int mask) {
-  const uint32_t lo = uint32_t(__shfl_xor(int(uint32_t(x)), mask, 64));
-  const uint32_t hi = uint32_t(__shfl_xor(int(uint32_t(x >> 32)), mask, 64));
+// lane l reads lane l ^ M.  Within a row of 16 lanes the exchange runs on the
+// DPP path of the VALU (xor 1, 2, 3: quad permutes; 7, 15: half-row and row
+// mirrors), within 32 lanes as a swizzle (xor 4, 8, 16, 31), otherwise as a
+// permute through the LDS crossbar
+template <int M>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t x) {
+  const int v = int(x);
+  if constexpr (M == 1) return uint32_t(__builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true));
+  else if constexpr (M == 2) return uint32_t(__builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true));
+  else if constexpr (M == 3) return uint32_t(__builtin_amdgcn_update_dpp(0, v, 0x1B, 0xF, 0xF, true));
+  else if constexpr (M == 7) return uint32_t(__builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, true));
+  else if constexpr (M == 15) return uint32_t(__builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, true));
+  else if constexpr (M < 32) return uint32_t(__builtin_amdgcn_ds_swizzle(v, (M << 10) | 0x1F));
+  else return uint32_t(__shfl_xor(v, M, 64));
+}
+
+template <int M>
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t x) {
+  const uint32_t lo = xor_lane<M>(uint32_t(x));
+  const uint32_t hi = xor_lane<M>(uint32_t(x >> 32));
   return (uint64_t(hi) << 32) | lo;
 }
 
 // lanes whose stride bit is clear hold the lower element and keep the minimum
-__device__ __forceinline__ void cross_step(uint64_t (&k)[8], int mask, bool lower, bool mirror) {
+template <int M>
+__device__ __forceinline__ void cross_step_m(uint64_t (&k)[8], bool lower, bool mirror) {
   uint64_t p[8];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) p[r] = shfl_xor64(k[mirror ? 7 - r : r], mask);
+  for (int r = 0; r < 8; ++r) p[r] = shfl_xor64<M>(k[mirror ? 7 - r : r]);
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const bool lt = p[r] < k[r];
     k[r] = (lower == lt) ? p[r] : k[r];
+  }
+}
+
+// the same step with a runtime mask, every exchange through the LDS crossbar
+// (the block-wide network below measured faster with it than with the
+// dispatch over exchange paths)
+__device__ __forceinline__ void cross_step_perm(uint64_t (&k)[8], int mask, bool lower,
+                                                bool mirror) {
+  uint64_t p[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const uint64_t x = k[mirror ? 7 - r : r];
+    const uint32_t lo = uint32_t(__shfl_xor(int(uint32_t(x)), mask, 64));
+    const uint32_t hi = uint32_t(__shfl_xor(int(uint32_t(x >> 32)), mask, 64));
+    p[r] = (uint64_t(hi) << 32) | lo;
+  }
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const bool lt = p[r] < k[r];
+    k[r] = (lower == lt) ? p[r] : k[r];
+  }
+}
+
+// the lane masks the networks use: 2^j for plain steps, 2^j - 1 for mirrors
+__device__ __forceinline__ void cross_step(uint64_t (&k)[8], int mask, bool lower, bool mirror) {
+  switch (mask) {  // wave-uniform
+    case 1: cross_step_m<1>(k, lower, mirror); break;
+    case 2: cross_step_m<2>(k, lower, mirror); break;
+    case 3: cross_step_m<3>(k, lower, mirror); break;
+    case 4: cross_step_m<4>(k, lower, mirror); break;
+    case 7: cross_step_m<7>(k, lower, mirror); break;
+    case 8: cross_step_m<8>(k, lower, mirror); break;
+    case 15: cross_step_m<15>(k, lower, mirror); break;
+    case 16: cross_step_m<16>(k, lower, mirror); break;
+    case 31: cross_step_m<31>(k, lower, mirror); break;
+    case 32: cross_step_m<32>(k, lower, mirror); break;
+    default: cross_step_m<63>(k, lower, mirror); break;
   }
 }
 
@@ -567,7 +622,7 @@ __device__ inline void block_reg_sort(uint64_t (&k)[8], uint32_t len, uint64_t* 
       } else if (h == 4) {
         cx(k[0], k[7]); cx(k[1], k[6]); cx(k[2], k[5]); cx(k[3], k[4]);
       } else {
-        cross_step(k, int(2 * h / 8 - 1), (lane & int(h / 8)) == 0, true);
+        cross_step_perm(k, int(2 * h / 8 - 1), (lane & int(h / 8)) == 0, true);
       }
     }
     for (uint32_t d = h >> 1; d > 0; d >>= 1) {
@@ -575,7 +630,7 @@ __device__ inline void block_reg_sort(uint64_t (&k)[8], uint32_t len, uint64_t* 
         lds_step(d, d);
       } else if (idle) {
       } else if (d >= 8u) {
-        cross_step(k, int(d / 8), (lane & int(d / 8)) == 0, false);
+        cross_step_perm(k, int(d / 8), (lane & int(d / 8)) == 0, false);
       } else if (d == 4) {
         cx(k[0], k[4]); cx(k[1], k[5]); cx(k[2], k[6]); cx(k[3], k[7]);
       } else if (d == 2) {
