@@ -1076,64 +1076,61 @@ struct BwdWs {
 // Gaussians of neighbouring tiles then meet in one L2).  Which block takes
 // which tile changes no result.
 
-// one 1024-thread block; every thread of the block calls it
-__device__ void tile_order_block(const RViews& RV, const uint32_t* __restrict__ ranges,
-                                 uint32_t* __restrict__ order) {
-  const int n_tiles = RV.total_tiles;
-  auto cost = [&](int i) { return ranges[2 * i + 1] - ranges[2 * i]; };
-  __shared__ uint32_t s_hist[kXcds][256], s_off[kXcds][256], s_max;
+// The balanced order of XCD x's share: its n_x tiles (the ones xcd_tile gives
+// blocks x, x + 8, ...) ranked into 256 buckets of list length, heaviest first
+// (bucket width from the share's longest list), and dealt by order_block.  One
+// 1024-thread block per XCD share; every thread of the block calls it.
+__device__ void tile_order_xcd(const RViews& RV, const uint32_t* __restrict__ ranges,
+                               uint32_t* __restrict__ order, int x) {
+  const int n_x = RV.xcd_off[x][RV.n_views];  // tiles (and blocks) of XCD x
+  auto tile = [&](int idx) { return xcd_tile(idx * kXcds + x, RV); };
+  auto cost = [&](int t) { return ranges[2 * t + 1] - ranges[2 * t]; };
+  __shared__ uint32_t s_hist[256], s_off[256], s_max;
   const int tid = threadIdx.x;
-  for (int i = tid; i < kXcds * 256; i += 1024) (&s_hist[0][0])[i] = 0u;
+  if (tid < 256) s_hist[tid] = 0u;
   if (tid == 0) s_max = 0u;
   __syncthreads();
   uint32_t mx = 0;
-  for (int i = tid; i < n_tiles; i += 1024) mx = max(mx, cost(i));
+  for (int idx = tid; idx < n_x; idx += 1024) mx = max(mx, cost(tile(idx)));
   atomicMax(&s_max, mx);
   __syncthreads();
   const uint64_t top = uint64_t(s_max) + 1u;
   auto bucket = [&](uint32_t c) { return 255u - uint32_t(uint64_t(c) * 256u / top); };
-  for (int i = tid; i < n_tiles; i += 1024) {
-    int idx;
-    const int x = xcd_of_tile(i, RV, idx);
-    atomicAdd(&s_hist[x][bucket(cost(i))], 1u);
-  }
+  for (int idx = tid; idx < n_x; idx += 1024) atomicAdd(&s_hist[bucket(cost(tile(idx)))], 1u);
   __syncthreads();
-  // exclusive scan of each XCD's 256 bucket counts: wave w of the first eight
-  // scans XCD w's histogram, four values per lane
-  const int lane = tid & 63, w = tid >> 6;
-  if (w < kXcds) {
+  // exclusive scan of the 256 bucket counts by the first wave, four per lane
+  if (tid < 64) {
     uint32_t v[4], sum = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      v[k] = s_hist[w][4 * lane + k];
+      v[k] = s_hist[4 * tid + k];
       sum += v[k];
     }
     uint32_t inc = sum;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
       const uint32_t y = __shfl_up(inc, d, 64);
-      if (lane >= d) inc += y;
+      if (tid >= d) inc += y;
     }
     uint32_t ex = inc - sum;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      s_off[w][4 * lane + k] = ex;
+      s_off[4 * tid + k] = ex;
       ex += v[k];
     }
   }
   __syncthreads();
-  for (int i = tid; i < n_tiles; i += 1024) {
-    int idx;
-    const int x = xcd_of_tile(i, RV, idx);
-    const int n_x = RV.xcd_off[x][RV.n_views];  // tiles (and blocks) of XCD x
-    const int r = int(atomicAdd(&s_off[x][bucket(cost(i))], 1u));  // rank, heaviest first
-    order[order_block(r, n_x) * kXcds + x] = uint32_t(i);
+  for (int idx = tid; idx < n_x; idx += 1024) {
+    const int t = tile(idx);
+    const int r = int(atomicAdd(&s_off[bucket(cost(t))], 1u));  // rank, heaviest first
+    order[order_block(r, n_x) * kXcds + x] = uint32_t(t);
   }
 }
 
-// Blocks 1.. clear the pair slots [0, min(total, cap)); block 0 meanwhile
-// writes the backward's tile order when `order` is set and, for the backward
-// fused with Adam, advances the device step count (`step_dev`) once.
+// Blocks kXcds.. clear the pair slots [0, min(total, cap)); blocks 0..kXcds-1
+// meanwhile write the backward's tile order when `order` is set (block x the
+// order of XCD x's share) and block 0, for the backward fused with Adam,
+// advances the device step count (`step_dev`) once.
 constexpr int kZeroBlocks = 512;
 __global__ __launch_bounds__(1024) void k_zero_pairs(float* __restrict__ p,
                                                      const int64_t* __restrict__ total,
@@ -1141,15 +1138,15 @@ __global__ __launch_bounds__(1024) void k_zero_pairs(float* __restrict__ p,
                                                      const uint32_t* __restrict__ ranges,
                                                      uint32_t* __restrict__ order,
                                                      int32_t* __restrict__ step_dev) {
-  if (blockIdx.x == 0) {
-    if (step_dev && threadIdx.x == 0) *step_dev += 1;
-    if (order) tile_order_block(RV, ranges, order);
+  if (blockIdx.x < unsigned(kXcds)) {
+    if (blockIdx.x == 0 && step_dev && threadIdx.x == 0) *step_dev += 1;
+    if (order) tile_order_xcd(RV, ranges, order, int(blockIdx.x));
     return;
   }
   const int64_t np = (*total < cap) ? *total : cap;
   const int64_t m = np * kG;
-  for (int64_t i = int64_t(blockIdx.x - 1) * blockDim.x + threadIdx.x; i < m;
-       i += int64_t(gridDim.x - 1) * blockDim.x)
+  for (int64_t i = int64_t(blockIdx.x - kXcds) * blockDim.x + threadIdx.x; i < m;
+       i += int64_t(gridDim.x - kXcds) * blockDim.x)
     p[i] = 0.0f;
 }
 
@@ -1210,8 +1207,8 @@ hipError_t bwd_to_planes(const Views& V, int n, const gs_raster_cfg& cfg, const 
   uint32_t* order = nullptr;
   if (T > 0 && !split_long_lists(RV, cfg.tile) && size_t(4) * kG * size_t(M) >= 4 * T)
     order = reinterpret_cast<uint32_t*>(ws + B.g2d);
-  GS_LAUNCH("k_zero_pairs", k_zero_pairs, dim3(1 + kZeroBlocks), dim3(1024), 0, st, pairs, total,
-            cap, RV, ranges, order, step_dev);
+  GS_LAUNCH("k_zero_pairs", k_zero_pairs, dim3(kXcds + kZeroBlocks), dim3(1024), 0, st, pairs,
+            total, cap, RV, ranges, order, step_dev);
   if (V.total_tiles > 0) {
     const dim3 grid(unsigned(V.total_tiles));
     switch (cfg.tile) {
