@@ -308,9 +308,21 @@ __global__ __launch_bounds__(kXT) void k_bucket(Items S, int rounds, int agg_bin
       for_each_pair(S, c, 0u, [&](uint32_t t, uint64_t, uint32_t, uint32_t xy) {
         atomicAdd(&s_bins[B.bin(t, xy)], 1u);
       });
-    for (int b = threadIdx.x; b < B.span; b += kXT) {
-      const uint32_t k = s_bins[b];
-      if (k) s_bins[b] = atomicAdd(agg_counter(ranges, copies, B.tile_of(b)), k);
+    // a thread's bins are b = t + u kXT, u < kAggBins / kXT: all their
+    // reservation atomics are issued before the first result is used, so the
+    // returns' latencies overlap
+    constexpr int kU = kAggBins / kXT;
+    uint32_t got[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int b = int(threadIdx.x) + u * kXT;
+      const uint32_t k = b < B.span ? s_bins[b] : 0u;
+      got[u] = k ? atomicAdd(agg_counter(ranges, copies, B.tile_of(b)), k) : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int b = int(threadIdx.x) + u * kXT;
+      if (b < B.span && s_bins[b]) s_bins[b] = got[u];
     }
     __syncthreads();
     for (int64_t c = B.i0; c < B.i1; c += kXT)
