@@ -137,10 +137,13 @@ gs_status gs_preprocess(int32_t n_views, const gs_camera* cams, const gs_raster_
  *     total_tiles = sum over views of ceil(W/tile) * ceil(H/tile).
  *   n_pairs_dev [1] i64: number of pairs, always written.  If it exceeds
  *     capacity_pairs, keys/vals/ranges are NOT valid: grow and call again.
+ *   proj: the records of gs_preprocess; the call also writes into it, for
+ *     gs_render_bwd, each (view, Gaussian)'s first pair position in index
+ *     order (the exclusive prefix of the tile counts) and the pair total.
  * ------------------------------------------------------------------------- */
 size_t gs_bin_sort_workspace_bytes(int32_t n_views, int32_t n, int64_t capacity_pairs);
 gs_status gs_bin_sort(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
-                      int32_t n, const void* proj, int64_t capacity_pairs, void* ws,
+                      int32_t n, void* proj, int64_t capacity_pairs, void* ws,
                       size_t ws_bytes, uint64_t* keys, uint32_t* vals, uint32_t* ranges,
                       int64_t* n_pairs_dev, void* stream);
 
@@ -166,7 +169,7 @@ gs_status gs_bin_sort(int32_t n_views, const gs_camera* cams, const gs_raster_cf
 #define GS_BIN_SORT_NOALLOC_MAX_PAIRS (1 << 22)
 #define GS_BIN_SORT_NOALLOC_MAX_ITEMS (1 << 23)
 gs_status gs_bin_sort_noalloc(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
-                              int32_t n, const void* proj, int64_t capacity_pairs,
+                              int32_t n, void* proj, int64_t capacity_pairs,
                               uint64_t* keys, uint32_t* vals, uint32_t* ranges,
                               int64_t* n_pairs_dev, void* stream);
 
@@ -191,7 +194,7 @@ gs_status gs_filter3d_variance(int32_t n_views, const gs_camera* cams, int32_t n
  * gs_bin_sort, with its own workspace size. */
 size_t gs_bin_sort_radix_workspace_bytes(int32_t n_views, int32_t n, int64_t capacity_pairs);
 gs_status gs_bin_sort_radix(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
-                            int32_t n, const void* proj, int64_t capacity_pairs, void* ws,
+                            int32_t n, void* proj, int64_t capacity_pairs, void* ws,
                             size_t ws_bytes, uint64_t* keys, uint32_t* vals, uint32_t* ranges,
                             int64_t* n_pairs_dev, void* stream);
 
@@ -266,8 +269,9 @@ gs_status gs_render_fwd_l1(int32_t n_views, const gs_camera* cams, const gs_rast
  * stored.  Per (tile, Gaussian) gradients land in a deterministic per-pair
  * slot of the workspace (no float atomics); they are summed per Gaussian and
  * view, then chained to the 3D parameters and summed over views.
- *   Inputs: the parameters given to gs_preprocess, its proj, the ranges/vals
- *   of gs_bin_sort (which must not have overflowed), the forward's final_T
+ *   Inputs: the parameters given to gs_preprocess, its proj as the binning
+ *   left it (any gs_bin_sort* call records the pair offsets there), the
+ *   ranges/vals of that binning (which must not have overflowed), the forward's final_T
  *   and last_contrib, and dL_dimage (same layout as image).
  *   Outputs: d_means [n,3], d_log_scales [n,3], d_quats [n,4] (16-byte
  *   aligned), d_opacity_logits [n], d_sh [n,16,3], d_mean2d_abs [n] (nullable:

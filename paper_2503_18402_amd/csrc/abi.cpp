@@ -209,7 +209,7 @@ size_t gs_bin_sort_workspace_bytes(int32_t n_views, int32_t n, int64_t capacity_
 }
 
 gs_status gs_bin_sort(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
-                      int32_t n, const void* proj, int64_t capacity_pairs, void* ws,
+                      int32_t n, void* proj, int64_t capacity_pairs, void* ws,
                       size_t ws_bytes, uint64_t* keys, uint32_t* vals, uint32_t* ranges,
                       int64_t* n_pairs_dev, void* stream) {
   Views V;
@@ -219,12 +219,12 @@ gs_status gs_bin_sort(int32_t n_views, const gs_camera* cams, const gs_raster_cf
     return GS_ERR_ARG;
   if (ws_bytes < bin_sort_ws_bytes(n_views, n, capacity_pairs)) return GS_ERR_CAPACITY;
   if (!aligned16(ws) || (n > 0 && !aligned16(proj))) return GS_ERR_ARG;
-  return from_hip(launch_bin_sort(V, n, static_cast<const char*>(proj), capacity_pairs, ws, keys,
+  return from_hip(launch_bin_sort(V, n, static_cast<char*>(proj), capacity_pairs, ws, keys,
                                   vals, ranges, n_pairs_dev, as_stream(stream)));
 }
 
 gs_status gs_bin_sort_noalloc(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
-                              int32_t n, const void* proj, int64_t capacity_pairs,
+                              int32_t n, void* proj, int64_t capacity_pairs,
                               uint64_t* keys, uint32_t* vals, uint32_t* ranges,
                               int64_t* n_pairs_dev, void* stream) {
   Views V;
@@ -236,7 +236,7 @@ gs_status gs_bin_sort_noalloc(int32_t n_views, const gs_camera* cams, const gs_r
   if (!ranges || !n_pairs_dev || (n > 0 && !proj) || (capacity_pairs > 0 && !vals))
     return GS_ERR_ARG;
   if (n > 0 && !aligned16(proj)) return GS_ERR_ARG;
-  return from_hip(launch_bin_sort_noalloc(V, n, static_cast<const char*>(proj), capacity_pairs,
+  return from_hip(launch_bin_sort_noalloc(V, n, static_cast<char*>(proj), capacity_pairs,
                                           keys, vals, ranges, n_pairs_dev, as_stream(stream)));
 }
 
@@ -270,7 +270,7 @@ size_t gs_bin_sort_radix_workspace_bytes(int32_t n_views, int32_t n, int64_t cap
 }
 
 gs_status gs_bin_sort_radix(int32_t n_views, const gs_camera* cams, const gs_raster_cfg* cfg,
-                            int32_t n, const void* proj, int64_t capacity_pairs, void* ws,
+                            int32_t n, void* proj, int64_t capacity_pairs, void* ws,
                             size_t ws_bytes, uint64_t* keys, uint32_t* vals, uint32_t* ranges,
                             int64_t* n_pairs_dev, void* stream) {
   Views V;
@@ -280,7 +280,7 @@ gs_status gs_bin_sort_radix(int32_t n_views, const gs_camera* cams, const gs_ras
     return GS_ERR_ARG;
   if (ws_bytes < bin_sort_radix_ws_bytes(n_views, n, capacity_pairs)) return GS_ERR_CAPACITY;
   if (!aligned16(ws) || (n > 0 && !aligned16(proj))) return GS_ERR_ARG;
-  return from_hip(launch_bin_sort_radix(V, n, static_cast<const char*>(proj), capacity_pairs, ws,
+  return from_hip(launch_bin_sort_radix(V, n, static_cast<char*>(proj), capacity_pairs, ws,
                                         keys, vals, ranges, n_pairs_dev, as_stream(stream)));
 }
 

@@ -16,7 +16,6 @@
 // the sigmoid and the SH colour back to the parameters, accumulating over
 // views in registers before one read-modify-write of the outputs.
 #include "blend_common.hpp"
-#include "scan.hpp"
 
 namespace gsk {
 namespace {
@@ -229,7 +228,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd(
     RViews RV, int n, const char* __restrict__ proj, size_t stride,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const float* __restrict__ final_T, const uint32_t* __restrict__ last_contrib,
-    const float* __restrict__ dL_dimage, const uint32_t* __restrict__ grad_off,
+    const float* __restrict__ dL_dimage, size_t goff_off,
     float* __restrict__ pair_grad, int64_t cap, float bg0, float bg1, float bg2, int skip_long,
     const uint32_t* __restrict__ order) {
   __shared__ float4 s_r0[BATCH];
@@ -251,7 +250,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd(
   bwd_load_pixels<TILE>(P, RV, v, tx, ty, lane, final_T, last_contrib, dL_dimage, bg0, bg1, bg2);
   const uint32_t stop = min(start + P.mylast, end);
   const float4* rec = reinterpret_cast<const float4*>(proj + size_t(v) * stride);
-  const uint32_t* goff = grad_off + size_t(v) * n;
+  const uint32_t* goff = reinterpret_cast<const uint32_t*>(proj + size_t(v) * stride + goff_off);
   const float px0 = float(lane & 7) + 0.5f, py0 = float(lane >> 3) + 0.5f;
 
   for (uint32_t bend = stop; bend > start;) {
@@ -289,7 +288,7 @@ __global__ __launch_bounds__(64 * kLongWaves) void k_blend_bwd_long(
     RViews RV, int n, const char* __restrict__ proj, size_t stride,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const float* __restrict__ final_T, const uint32_t* __restrict__ last_contrib,
-    const float* __restrict__ dL_dimage, const uint32_t* __restrict__ grad_off,
+    const float* __restrict__ dL_dimage, size_t goff_off,
     float* __restrict__ pair_grad, int64_t cap, float bg0, float bg1, float bg2) {
   constexpr int GX = TileShape<TILE>::kGroupsX, Q = TileShape<TILE>::kGroups;
   __shared__ float4 s_r0[kLongWaves][kLongBatch];
@@ -318,7 +317,8 @@ __global__ __launch_bounds__(64 * kLongWaves) void k_blend_bwd_long(
     const int nch = int(want < uint32_t(kMaxChunks) ? want : uint32_t(kMaxChunks));
     const uint32_t ch = nch > 0 ? (len + uint32_t(nch) - 1) / uint32_t(nch) : 0u;
     const float4* rec = reinterpret_cast<const float4*>(proj + size_t(v) * stride);
-    const uint32_t* goff = grad_off + size_t(v) * n;
+    const uint32_t* goff =
+        reinterpret_cast<const uint32_t*>(proj + size_t(v) * stride + goff_off);
 
     // A. per chunk: product of (1 - alpha) and colour over the blended entries
     for (int c = wv; c < nch; c += kLongWaves) {
@@ -484,7 +484,7 @@ constexpr int kCoopSlots = 32;
 
 __global__ __launch_bounds__(256) void k_pair_sum(const char* __restrict__ proj, size_t stride,
                                                   size_t tt_off, int n, int64_t M,
-                                                  const uint32_t* __restrict__ grad_off,
+                                                  size_t goff_off,
                                                   const float* __restrict__ pair_grad,
                                                   int64_t cap, float* __restrict__ g2d) {
   const int lane = threadIdx.x & 63;
@@ -493,7 +493,7 @@ __global__ __launch_bounds__(256) void k_pair_sum(const char* __restrict__ proj,
   if (i < M) {
     const int64_t v = i / n, g = i - v * n;
     tt = reinterpret_cast<const uint32_t*>(proj + v * stride + tt_off)[g];
-    off = grad_off[i];
+    off = reinterpret_cast<const uint32_t*>(proj + v * stride + goff_off)[g];
     if (int64_t(off) + tt > cap) tt = 0u;  // pairs past the capacity have no slots
   }
   float s[kG];
@@ -1036,29 +1036,12 @@ __global__ __launch_bounds__(kCA) __attribute__((amdgpu_waves_per_eu(3))) void k
   }
 }
 
-struct TTSrc {  // tiles touched of item (view, Gaussian), index order
-  const char* proj;
-  size_t stride, tt_off;
-  int n;
-  __device__ uint32_t operator()(int64_t i) const {
-    const int64_t v = i / n, g = i - v * n;
-    return reinterpret_cast<const uint32_t*>(proj + v * stride + tt_off)[g];
-  }
-};
-struct GoffDst {
-  uint32_t* off;
-  __device__ void operator()(int64_t i, uint32_t pos, uint32_t) const { off[i] = pos; }
-};
-
 
 struct BwdWs {
-  size_t goff, bsum, total, g2d, pairs, bytes;
+  size_t g2d, pairs, bytes;
   BwdWs(int64_t M, int64_t cap) {
     size_t o = 0;
     auto take = [&](size_t b) { size_t r = o; o += align256(b); return r; };
-    goff = take(4 * M);
-    bsum = take(4 * scan_block_sums(M));
-    total = take(8);
     g2d = take(4 * kG * M);
     pairs = take(size_t(cap) * kG * 4);
     bytes = o;
@@ -1143,7 +1126,8 @@ __global__ __launch_bounds__(1024) void k_zero_pairs(float* __restrict__ p,
     if (order) tile_order_xcd(RV, ranges, order, int(blockIdx.x));
     return;
   }
-  const int64_t np = (*total < cap) ? *total : cap;
+  const int64_t tot = total ? *total : 0;
+  const int64_t np = (tot < cap) ? tot : cap;
   const int64_t m = np * kG;
   for (int64_t i = int64_t(blockIdx.x - kXcds) * blockDim.x + threadIdx.x; i < m;
        i += int64_t(gridDim.x - kXcds) * blockDim.x)
@@ -1154,7 +1138,7 @@ template <int TILE>
 void launch_bwd_tile(int batch, dim3 grid, const RViews& RV, int n, const char* proj,
                      size_t stride, const uint32_t* ranges, const uint32_t* vals,
                      const float* final_T, const uint32_t* last_contrib, const float* dL,
-                     const uint32_t* goff, float* pairs, int64_t cap, const float* bg,
+                     size_t goff, float* pairs, int64_t cap, const float* bg,
                      const uint32_t* order, hipStream_t st) {
   const dim3 block(64);
   // launches with few tiles hand long lists to the list-parallel kernel
@@ -1185,21 +1169,19 @@ size_t render_bwd_ws_bytes(int n_views, int n, int64_t cap) {
 
 namespace {
 
-// Everything before the chain rule: pair offsets, the backward blend into the
-// per-pair slots and their sums into the per-view 2D gradient planes.
+// Everything before the chain rule: the backward blend into the per-pair
+// slots and their sums into the per-view 2D gradient planes.
 hipError_t bwd_to_planes(const Views& V, int n, const gs_raster_cfg& cfg, const char* proj,
                          const uint32_t* ranges, const uint32_t* vals, const float* final_T,
                          const uint32_t* last_contrib, const float* dL_dimage, int64_t cap,
                          char* ws, float** g2d_out, int32_t* step_dev, hipStream_t st) {
   const int64_t M = int64_t(V.n_views) * n;
   const BwdWs B(M, cap);
-  uint32_t* goff = reinterpret_cast<uint32_t*>(ws + B.goff);
-  int64_t* total = reinterpret_cast<int64_t*>(ws + B.total);
   float* pairs = reinterpret_cast<float*>(ws + B.pairs);
   const ProjLayout L(n);
-  hipError_t e = scan_exclusive(TTSrc{proj, L.stride, L.tt, n}, GoffDst{goff}, Count{nullptr, M},
-                                M, reinterpret_cast<uint32_t*>(ws + B.bsum), total, nullptr, st);
-  if (e != hipSuccess) return e;
+  // the items' pair offsets and the pair total, recorded in proj by the binning
+  const size_t goff = L.goff;
+  const int64_t* total = proj ? reinterpret_cast<const int64_t*>(proj + L.total) : nullptr;
   // the balanced tile order (launches without list-parallel tiles), kept in the
   // 2D-gradient planes, which k_pair_sum writes only after the blend
   const RViews RV = make_rviews(V);
@@ -1227,8 +1209,9 @@ hipError_t bwd_to_planes(const Views& V, int n, const gs_raster_cfg& cfg, const 
     }
   }
   float* g2d = reinterpret_cast<float*>(ws + B.g2d);
-  GS_LAUNCH("k_pair_sum", k_pair_sum, dim3(unsigned((M + 255) / 256)), dim3(256), 0, st, proj,
-            L.stride, L.tt, n, M, goff, pairs, cap, g2d);
+  if (M > 0)
+    GS_LAUNCH("k_pair_sum", k_pair_sum, dim3(unsigned((M + 255) / 256)), dim3(256), 0, st, proj,
+              L.stride, L.tt, n, M, goff, pairs, cap, g2d);
   *g2d_out = g2d;
   return hipSuccess;
 }

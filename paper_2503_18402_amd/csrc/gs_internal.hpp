@@ -176,13 +176,19 @@ __device__ inline void adam_bias(const int32_t* step_dev, float b1, float b2, fl
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Per view: the records, tiles touched and colour-clamp flags (written by the
+// preprocess), then the index-order position of each item's first pair and,
+// in view 0's copy, the pair total as int64 (both written by the binning,
+// read by the backward).
 struct ProjLayout {
-  size_t rec, tt, flags, stride;
+  size_t rec, tt, flags, goff, total, stride;
   __host__ __device__ ProjLayout(int n) {
     rec = 0;
     tt = align256(size_t(n) * 48);
     flags = tt + align256(size_t(n) * 4);
-    stride = flags + align256(size_t(n) * 4);
+    goff = flags + align256(size_t(n) * 4);
+    total = goff + align256(size_t(n) * 4);
+    stride = total + 256;
   }
 };
 
@@ -229,14 +235,14 @@ hipError_t launch_preprocess(const Views& V, int n, int sh_degree, const float* 
                              hipStream_t st);
 
 size_t bin_sort_ws_bytes(int n_views, int n, int64_t cap);
-hipError_t launch_bin_sort(const Views& V, int n, const char* proj, int64_t cap, void* ws,
+hipError_t launch_bin_sort(const Views& V, int n, char* proj, int64_t cap, void* ws,
                            uint64_t* keys, uint32_t* vals, uint32_t* ranges,
                            int64_t* n_pairs_dev, hipStream_t st);
-hipError_t launch_bin_sort_noalloc(const Views& V, int n, const char* proj, int64_t cap,
+hipError_t launch_bin_sort_noalloc(const Views& V, int n, char* proj, int64_t cap,
                                    uint64_t* keys, uint32_t* vals, uint32_t* ranges,
                                    int64_t* n_pairs_dev, hipStream_t st);
 size_t bin_sort_radix_ws_bytes(int n_views, int n, int64_t cap);
-hipError_t launch_bin_sort_radix(const Views& V, int n, const char* proj, int64_t cap, void* ws,
+hipError_t launch_bin_sort_radix(const Views& V, int n, char* proj, int64_t cap, void* ws,
                                  uint64_t* keys, uint32_t* vals, uint32_t* ranges,
                                  int64_t* n_pairs_dev, hipStream_t st);
 

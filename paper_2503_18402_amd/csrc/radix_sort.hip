@@ -211,6 +211,24 @@ struct OffDst {
   uint32_t* off;
   __device__ void operator()(int64_t i, uint32_t pos, uint32_t) const { off[i] = pos; }
 };
+struct TTSrcItems {  // tiles touched of item i (index order)
+  const char* proj;
+  size_t stride, tt_off;
+  int n;
+  __device__ uint32_t operator()(int64_t i) const {
+    const int64_t v = i / n, g = i - v * n;
+    return reinterpret_cast<const uint32_t*>(proj + v * stride + tt_off)[g];
+  }
+};
+struct ProjGoffDst {  // item i's first pair position, into proj for the backward
+  char* proj;
+  size_t stride, goff_off;
+  int n;
+  __device__ void operator()(int64_t i, uint32_t pos, uint32_t) const {
+    const int64_t v = i / n, g = i - v * n;
+    reinterpret_cast<uint32_t*>(proj + v * stride + goff_off)[g] = pos;
+  }
+};
 
 struct TileInfo {  // per view: first global tile and grid width
   int32_t tile_base[GS_MAX_VIEWS];
@@ -318,7 +336,7 @@ size_t bin_sort_radix_ws_bytes(int n_views, int n, int64_t cap) {
   return WsLayout(int64_t(n_views) * n, cap).total;
 }
 
-hipError_t launch_bin_sort_radix(const Views& V, int n, const char* proj, int64_t cap, void* ws_,
+hipError_t launch_bin_sort_radix(const Views& V, int n, char* proj, int64_t cap, void* ws_,
                                  uint64_t* keys, uint32_t* vals, uint32_t* ranges,
                                  int64_t* n_pairs_dev, hipStream_t st) {
   const int64_t M = int64_t(V.n_views) * n;
@@ -332,6 +350,14 @@ hipError_t launch_bin_sort_radix(const Views& V, int n, const char* proj, int64_
   const ProjLayout L(n);
   hipError_t e;
 
+  // 0. the items' pair offsets in index order and the pair total, recorded in
+  // proj for the backward (the same values the bucket route records)
+  if (proj) {
+    e = scan_exclusive(TTSrcItems{proj, L.stride, L.tt, n},
+                       ProjGoffDst{proj, L.stride, L.goff, n}, Count{nullptr, M}, M, U(W.bsum),
+                       reinterpret_cast<int64_t*>(proj + L.total), nullptr, st);
+    if (e != hipSuccess) return e;
+  }
   // 1. compact the visible items: key = depth bits, value = item id
   e = scan_exclusive(VisSrc{proj, L.stride, L.tt, n},
                      VisDst{proj, L.stride, n, U(W.ikey0), U(W.ival0)}, Count{nullptr, M}, M,

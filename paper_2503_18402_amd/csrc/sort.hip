@@ -57,6 +57,8 @@ struct Items {  // the (view, Gaussian) items of a preprocess output
   TileInfo TI;
   const char* proj;
   size_t stride, tt_off;
+  char* goff_proj;  // non-null: record each item's first pair position (at goff_off)
+  size_t goff_off;
   int64_t m;  // n_views * n
   int n, tile;
 };
@@ -121,6 +123,11 @@ __device__ inline uint32_t for_each_pair(const Items& S, int64_t first, uint32_t
     const uint32_t t = s_wtot[w];
     wbase += (w < (threadIdx.x >> 6)) ? t : 0u;
     all += t;
+  }
+  if (S.goff_proj && i < S.m) {
+    const int64_t v = i / S.n, g = i - v * S.n;
+    reinterpret_cast<uint32_t*>(S.goff_proj + size_t(v) * S.stride + S.goff_off)[g] =
+        wbase + (inc - cnt);
   }
   for (uint32_t j = uint32_t(lane); j < total; j += 64) {
     // the item owning the wave's j-th pair: the first k with s_end[k] > j
@@ -270,8 +277,9 @@ __global__ __launch_bounds__(kXT) void k_tile_count(Items S, int rounds, int agg
   if (B.mode) {
     for (int b = threadIdx.x; b < B.span; b += kXT) s_bins[b] = 0u;
     __syncthreads();
+    uint32_t pos = block_pos[blockIdx.x];  // for the items' pair offsets
     for (int64_t c = B.i0; c < B.i1; c += kXT)
-      for_each_pair(S, c, 0u, [&](uint32_t t, uint64_t, uint32_t, uint32_t xy) {
+      pos += for_each_pair(S, c, pos, [&](uint32_t t, uint64_t, uint32_t, uint32_t xy) {
         atomicAdd(&s_bins[B.bin(t, xy)], 1u);
       });
     for (int b = threadIdx.x; b < B.span; b += kXT)
@@ -360,6 +368,7 @@ __device__ inline uint64_t wave_incl_scan64(uint64_t x) {
 
 __global__ __launch_bounds__(kTS) void k_tile_scan(uint32_t* __restrict__ ranges,
                                                    uint32_t* __restrict__ copies, int n_tiles,
+                                                   int64_t* __restrict__ proj_total,
                                                    int64_t cap, int64_t* __restrict__ n_tot,
                                                    int64_t* __restrict__ n_eff,
                                                    int64_t* __restrict__ n_long,
@@ -421,6 +430,7 @@ __global__ __launch_bounds__(kTS) void k_tile_scan(uint32_t* __restrict__ ranges
   if (threadIdx.x == 0) {
     const int64_t t = int64_t(carry);
     *n_tot = t;
+    if (proj_total) *proj_total = t;
     *n_eff = (t <= cap) ? t : 0;
     *n_pairs_user = t;
     *n_long = 0;  // set by the wave sort for lists it leaves to the larger tiers
@@ -887,7 +897,7 @@ size_t bin_sort_ws_bytes(int n_views, int n, int64_t cap) {
   return WsLayout(int64_t(n_views) * n, cap).total;
 }
 
-hipError_t launch_bin_sort_noalloc(const Views& V, int n, const char* proj, int64_t cap,
+hipError_t launch_bin_sort_noalloc(const Views& V, int n, char* proj, int64_t cap,
                                    uint64_t* keys, uint32_t* vals, uint32_t* ranges,
                                    int64_t* n_pairs_dev, hipStream_t st) {
   const int64_t m = int64_t(V.n_views) * n;
@@ -904,7 +914,7 @@ hipError_t launch_bin_sort_noalloc(const Views& V, int n, const char* proj, int6
   return launch_bin_sort(V, n, proj, cap, ws, keys, vals, ranges, n_pairs_dev, st);
 }
 
-hipError_t launch_bin_sort(const Views& V, int n, const char* proj, int64_t cap, void* ws_,
+hipError_t launch_bin_sort(const Views& V, int n, char* proj, int64_t cap, void* ws_,
                            uint64_t* keys, uint32_t* vals, uint32_t* ranges,
                            int64_t* n_pairs_dev, hipStream_t st) {
   const WsLayout W(int64_t(V.n_views) * n, cap);
@@ -930,6 +940,8 @@ hipError_t launch_bin_sort(const Views& V, int n, const char* proj, int64_t cap,
   S.proj = proj;
   S.stride = L.stride;
   S.tt_off = L.tt;
+  S.goff_proj = proj;  // the count pass records the items' pair offsets
+  S.goff_off = L.goff;
   S.m = int64_t(V.n_views) * n;
   S.n = n;
   S.tile = V.tile;
@@ -957,20 +969,22 @@ hipError_t launch_bin_sort(const Views& V, int n, const char* proj, int64_t cap,
   GS_LAUNCH("k_fill_u32", k_fill_u32, dim3(unsigned(nr / 256 + 1 < 4096 ? nr / 256 + 1 : 4096)),
             dim3(256), 0, st, ranges, nr, 0u, copies, nc);
   if (xb > 0) {
-    // index-order positions of each block's first pair (only blocks that rank
-    // their pairs read them: none when every view has at most agg_bins tiles)
-    if (T > agg_bins) {
-      GS_LAUNCH("k_tile_reduce", k_tile_reduce, dim3(xb), dim3(kXT), 0, st, S, rounds, bpos);
-      GS_LAUNCH("k_scan_spine", k_scan_spine, dim3(1), dim3(kScanThreads), 0, st, bpos,
-                Count{nullptr, int64_t(xb) * kScanTile}, nullptr, nullptr);
-    }
+    // index-order positions of each block's first pair: ranked pairs store
+    // their ranks there, and every item's pair offset (recorded in proj for
+    // the backward) follows from them
+    GS_LAUNCH("k_tile_reduce", k_tile_reduce, dim3(xb), dim3(kXT), 0, st, S, rounds, bpos);
+    GS_LAUNCH("k_scan_spine", k_scan_spine, dim3(1), dim3(kScanThreads), 0, st, bpos,
+              Count{nullptr, int64_t(xb) * kScanTile}, nullptr, nullptr);
     GS_LAUNCH("k_tile_count", k_tile_count, dim3(xb), dim3(kXT), agg_lds, st, S, rounds, agg_bins,
               bpos, cap, ranges, rank, copies);
   }
-  GS_LAUNCH("k_tile_scan", k_tile_scan, dim3(1), dim3(kTS), 0, st, ranges, copies, T, cap, n_tot,
-            n_eff, n_long, n_mid, n_pairs_dev);
+  int64_t* proj_total = proj ? reinterpret_cast<int64_t*>(proj + L.total) : nullptr;
+  GS_LAUNCH("k_tile_scan", k_tile_scan, dim3(1), dim3(kTS), 0, st, ranges, copies, T, proj_total,
+            cap, n_tot, n_eff, n_long, n_mid, n_pairs_dev);
+  Items Sb = S;
+  Sb.goff_proj = nullptr;
   if (xb > 0)
-    GS_LAUNCH("k_bucket", k_bucket, dim3(xb), dim3(kXT), agg_lds, st, S, rounds, agg_bins, n_eff,
+    GS_LAUNCH("k_bucket", k_bucket, dim3(xb), dim3(kXT), agg_lds, st, Sb, rounds, agg_bins, n_eff,
               bpos, rank, ranges, copies, bucket);
   GS_LAUNCH("k_tile_sort_wave", k_tile_sort_wave, dim3(unsigned((T + 3) / 4)), dim3(256), 0, st,
             T, n_tot, n_eff, n_mid, n_long, bucket, vals, keys, ranges);

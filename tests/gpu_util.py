@@ -19,10 +19,11 @@ def align256(x: int) -> int:
 
 def decode_proj(frame, view: int = 0, tile: int | None = None) -> dict:
     """Per-Gaussian records of one view, in the documented layout of the
-    projected-record buffer (rec: 3 float4, then tiles touched, then flags);
-    the record holds log2 of the opacity."""
+    projected-record buffer (rec: 3 float4, then tiles touched, then flags,
+    then the first pair position binning writes, then the pair total in a
+    256-byte slot); the record holds log2 of the opacity."""
     n = frame.n
-    stride = align256(48 * n) + 2 * align256(4 * n)
+    stride = align256(48 * n) + 3 * align256(4 * n) + 256
     raw = frame.proj.cpu().numpy()[view * stride:(view + 1) * stride]
     rec = raw[:48 * n].view(np.float32).reshape(n, 12)
     tt_off = align256(48 * n)
