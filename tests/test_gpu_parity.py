@@ -247,6 +247,29 @@ def test_batched_views_equal_plain():
             np.max(err / (scale["d_" + name] + 1e-30))))
 
 
+def test_one_view_and_several_view_preprocess_records_equal():
+    """The one-view preprocess (each lane loads its own SH row) and the
+    several-view form (rows staged once through LDS for all views) write the
+    same records: every word of a Gaussian with a footprint, and the tile
+    count, box and depth of every Gaussian (a Gaussian without a footprint has
+    no colour the later calls read)."""
+    sc, _ = scenes.small_scene()
+    base = scenes.orbit_cameras(4, 3.0, 128, 96, 120.0)
+    cams = [base[0], scenes.downscale(base[1], 2), base[2], scenes.downscale(base[3], 4)]
+    _, fb, _ = U.run(sc, cams, upstream=None, want_keys=False)
+    for k, c in enumerate(cams):
+        _, fp, _ = U.run(sc, [c], upstream=None, want_keys=False)
+        b, p = U.decode_proj(fb, view=k), U.decode_proj(fp)
+        assert np.array_equal(b["tt"], p["tt"]), k
+        assert np.array_equal(b["px_box"], p["px_box"]), k
+        assert np.array_equal(b["depth"].view(np.uint32), p["depth"].view(np.uint32)), k
+        live = p["tt"] > 0
+        assert live.sum() > 100, k
+        for name in ("mean2d", "conic", "opacity", "rgb"):
+            assert np.array_equal(b[name][live], p[name][live]), (k, name)
+        assert np.array_equal(b["flags"][live], p["flags"][live]), k
+
+
 def test_multiview_grads_match_oracle_sum():
     sc, _ = scenes.small_scene()
     sc = scenes.subset(sc, slice(0, 2000))
