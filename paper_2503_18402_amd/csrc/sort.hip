@@ -755,17 +755,20 @@ __global__ __launch_bounds__(kMidThreads) void k_tile_sort_mid(
 }
 
 // Longer lists: 1024-thread blocks, each striding over the tiles (a block
-// needs most of a CU's LDS, so one block per tile would serialise on empty
+// needs much of a CU's LDS, so one block per tile would serialise on empty
 // tiles), with LDS chunks of kChunk keys.  A list of at most kChunk keys is
 // sorted in LDS (block_reg_sort over the block's 16 waves measured slower
 // here: 0.070 against 0.058 ms at 1M Gaussians, 200x133, tile 8).  A longer one is sorted in place in the bucket: each chunk is
 // sorted in LDS, then for every further merge size the strides >= kChunk run on
 // global memory and the shorter ones per chunk in LDS.  (All waves of a block
 // share one CU, whose L1 keeps the block's global writes coherent across the
-// barriers.)
-constexpr int kChunk = 16384;
+// barriers.)  The 64 KB chunk lets two blocks share a CU, so 512 blocks take
+// all of a low-resolution view's long lists at once; with 16384-key chunks one
+// block held a CU, and the 425 lists of 1M Gaussians at 200x133 (tile 8) took
+// two rounds of 256 blocks (sorts 96 -> 80 us, the same keys).
+constexpr int kChunk = 8192;
 constexpr int kBigThreads = 1024;
-constexpr int kBigBlocks = 256;
+constexpr int kBigBlocks = 512;
 
 __device__ inline void sort_long(uint64_t* s, uint64_t* a, uint32_t n) {
   const uint32_t len = pow2_ceil(n);

@@ -79,11 +79,11 @@ def test_bin_sort_properties(small):
                 assert r[t, 0] == 0 and r[t, 1] == 0
 
 
-@pytest.mark.parametrize("n,longest", [(1500, 512), (3000, 2048), (40000, 16384)])
+@pytest.mark.parametrize("n,longest", [(1500, 512), (3000, 2048), (12000, 8192), (40000, 16384)])
 def test_bin_sort_long_lists(n, longest):
     """Tile lists longer than the one-wave register sort (512 keys), than the
-    256-thread LDS sort (2048 keys) and than one LDS chunk (16384 keys, sorted
-    through global memory): still the exact (tile, depth, index) order of the
+    256-thread LDS sort (2048 keys) and than one LDS chunk (8192 keys, sorted
+    through global memory; two chunks and more): still the exact (tile, depth, index) order of the
     oracle's binning.  A quarter of the Gaussians share their mean, hence their
     depth, with another one, so ties are broken by index."""
     sc = scenes.make_scene(n, seed=41, mean_range=0.2, ls_mu=-3.0, ls_sigma=0.2)
