@@ -736,9 +736,10 @@ __global__ __launch_bounds__(256) void k_tile_sort_wave(
 // Lists of kWaveKeys+1 .. kSmall keys: 256-thread blocks striding over the
 // tiles, 8 keys per lane in registers (block_reg_sort: LDS only for the
 // strides that cross waves; 0.046 -> 0.029 ms against the network in LDS at
-// 1M Gaussians, 200x133, tile 8).
+// 1M Gaussians, 200x133, tile 8).  Up to 2048 blocks: at 400x266 (1700 tiles)
+// every tile then has its own block (binning 161 -> 153 us against 1024 blocks).
 constexpr int kMidThreads = 256;
-constexpr int kMidBlocks = 1024;
+constexpr int kMidBlocks = 2048;
 
 __global__ __launch_bounds__(kMidThreads) void k_tile_sort_mid(
     int n_tiles, const int64_t* __restrict__ n_eff, const int64_t* __restrict__ n_mid,
