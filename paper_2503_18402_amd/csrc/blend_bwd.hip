@@ -481,7 +481,26 @@ __device__ inline void sh_dir_grad(float x, float y, float z, int deg, const flo
 // wave: lane-strided coalesced loads, then the fixed-order register reduction,
 // so the wave never waits on one lane's long serial loop.
 constexpr int kCoopSlots = 32;
-constexpr int kSumSlots = 8;  // slots a lane loads per step
+
+// U consecutive slots from slot k of an item with tt slots added to s in
+// order (a slot past the last reloads slot k); returns the next slot
+template <int U>
+__device__ __forceinline__ uint32_t sum_slots(const float* __restrict__ pg, uint32_t k,
+                                              uint32_t tt, float* s) {
+  float x[U][kG];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const float* q = pg + size_t(k + u < tt ? k + u : k) * kG;
+#pragma unroll
+    for (int c = 0; c < kG; ++c) x[u][c] = q[c];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (k + u < tt)
+#pragma unroll
+      for (int c = 0; c < kG; ++c) s[c] += x[u][c];
+  return k + U;
+}
 
 __global__ __launch_bounds__(256) void k_pair_sum(const char* __restrict__ proj, size_t stride,
                                                   size_t tt_off, int n, int64_t M,
@@ -502,24 +521,18 @@ __global__ __launch_bounds__(256) void k_pair_sum(const char* __restrict__ proj,
   for (int c = 0; c < kG; ++c) s[c] = 0.0f;
   const bool coop = tt > uint32_t(kCoopSlots);
   if (!coop) {
-    // eight slots' loads in flight per step (a lane past its last slot reloads
-    // slot k, which exists); the sums still add slot after slot in order.
-    // Eight against four: 33.5 -> 31 us at 1M Gaussians, 1600x1064 (85 VGPRs);
-    // two: 54 us
+    // several slots' loads in flight per step (a lane past its last slot
+    // reloads slot k, which exists); the sums still add slot after slot in
+    // order.  A lane with more than four slots left loads eight, else four:
+    // 32 us at 1M Gaussians, 1600x1064, and 17 us at 200x133 (tile 8), against
+    // 34 / 18 us with four per step and 31 / 20 us with eight (whose unused
+    // loads and registers cost where items have one or two slots)
     const float* pg = pair_grad + size_t(off) * kG;
-    for (uint32_t k = 0; k < tt; k += kSumSlots) {
-      float x[kSumSlots][kG];
-#pragma unroll
-      for (int u = 0; u < kSumSlots; ++u) {
-        const float* q = pg + size_t(k + u < tt ? k + u : k) * kG;
-#pragma unroll
-        for (int c = 0; c < kG; ++c) x[u][c] = q[c];
-      }
-#pragma unroll
-      for (int u = 0; u < kSumSlots; ++u)
-        if (k + u < tt)
-#pragma unroll
-          for (int c = 0; c < kG; ++c) s[c] += x[u][c];
+    for (uint32_t k = 0; k < tt;) {
+      if (tt - k > 4u)
+        k = sum_slots<8>(pg, k, tt, s);
+      else
+        k = sum_slots<4>(pg, k, tt, s);
     }
   }
   // the wave's long items, one after the other (all lanes take part)
